@@ -1,0 +1,149 @@
+/*
+ * lmfr.h -- C ABI of the MI355X (gfx950) implementation of the implicit
+ * Weiss-Smith-preconditioned flux reconstruction (FR/CPR) method for low-Mach
+ * compressible Navier-Stokes flow on static or deforming quadrilateral meshes
+ * (Wang & Yu, arXiv:1903.06304).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Unknowns are the primitive variables q^p = (p, u, v, T) (paper Sec. 2.2) at
+ *    (p+1)^2 Gauss-Legendre solution points per quadrilateral element.
+ *  - State-sized arrays are DEVICE pointers owned by the caller, FP64, layout
+ *    [4][n_elem][Np], var-major, Np = (order+1)^2, solution point (i, j) at index
+ *    i + (order+1)*j, i along xi.  Residual rows are the conservation equations
+ *    (mass, x-momentum, y-momentum, energy) in the units of dq^c/dt.
+ *  - Element faces: 0 (xi=-1), 1 (xi=+1), 2 (eta=-1), 3 (eta=+1).  Face point k
+ *    runs along the face (eta index on faces 0/1, xi index on faces 2/3).
+ *  - Geometry: isoparametric Gauss-Lobatto nodes of degree geom_order, node (a, b)
+ *    at a + (geom_order+1)*b, arrays [2][n_elem][(geom_order+1)^2] (x then y).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All calls are
+ *    asynchronous on it unless stated otherwise.
+ *  - No exceptions cross the ABI: every call returns an fr_status; the text of
+ *    the last failure on the calling thread is returned by fr_last_error().
+ *  - Memory: the context allocates its tables and workspaces in fr_create,
+ *    fr_set_geometry and (Krylov workspace) the first fr_bdf2_step with a given
+ *    Krylov dimension; residual, JVP, VJP and preconditioner calls allocate nothing.
+ */
+#ifndef LMFR_H
+#define LMFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_ctx_s* fr_ctx;
+
+typedef enum {
+    FR_OK = 0,
+    FR_EINVAL = -1,        /* invalid argument (null pointer, size, range) */
+    FR_EHIP = -2,          /* HIP runtime error (text in fr_last_error) */
+    FR_ENOMEM = -3,        /* device allocation failed */
+    FR_ENONFINITE = -4,    /* NaN/Inf met in a residual or Krylov norm */
+    FR_ENOCONV = -5,       /* Newton or GMRES did not reach its tolerance */
+    FR_EUNSUPPORTED = -6   /* order or geometry outside what is built */
+} fr_status;
+
+typedef enum { FR_FP64 = 0, FR_FP32 = 1, FR_BF16 = 2 } fr_prec;
+
+/* Physical and discretisation parameters (paper Sec. 2.1 non-dimensionalisation:
+ * R = 1/(gamma mach_ref^2), Cp = 1/((gamma-1) mach_ref^2), k = mu Cp / prandtl;
+ * Sec. 2.2 Eq. (eps_nonmove)/(eps_move): eps = min(1, max(kappa mach_inf, Ma))). */
+typedef struct {
+    int32_t order;        /* solution degree p, 1..4 */
+    int32_t geom_order;   /* degree of the geometry nodes, 1..4 */
+    int32_t n_elem;
+    int32_t viscous;      /* 0: Euler, 1: Navier-Stokes (BR2 viscous fluxes) */
+    int32_t moving;       /* 1: grid velocities present (deforming / moving mesh) */
+    double gamma, mach_ref, reynolds, prandtl, mu, kappa, mach_inf;
+} fr_params;
+
+/* Options of one BDF2 dual-time step (paper Sec. 3.2, Eq. unsteady_pre_discretized_3). */
+typedef struct {
+    double dt;            /* physical time step */
+    double inv_dtau;      /* 1/dtau of the pseudo-time term (paper: dtau = 1e20) */
+    double tol_pseudo;    /* stop when Res_m / Res_0 <= tol_pseudo (mass-row 2-norm) */
+    double tol_res;       /* GMRES relative tolerance ||b - A x|| <= tol_res ||b|| */
+    double tol_abs;       /* also stop when Res_m <= tol_abs (round-off floor) */
+    int32_t krylov;       /* restart length m */
+    int32_t max_lin_it;   /* GMRES iteration cap per Newton step */
+    int32_t max_newton;   /* Newton (pseudo-time) iteration cap */
+    int32_t jac_lag;      /* refresh the block-Jacobi blocks when m % jac_lag == 0 */
+    int32_t prec;         /* fr_prec of the stored preconditioner blocks */
+} fr_step_opts;
+
+typedef struct {
+    int32_t newton_its, gmres_its, converged;
+    double res0, res_final;
+} fr_step_stats;
+
+/* Create a context for one mesh.  h_nbr/h_nbr_face/h_flip are HOST arrays [n_elem][4]:
+ * neighbour element, neighbour's local face and point-order reversal (NULL = none)
+ * across each face (periodic meshes only: every face has a neighbour).
+ * Returns FR_EUNSUPPORTED for order or geom_order outside 1..4. */
+fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h_nbr_face,
+                    const int8_t* h_flip, fr_ctx* out);
+
+/* Geometry of the mesh at the time level where the residual is evaluated (paper
+ * Sec. 2.3, metrics of the map x(xi, eta, t) and grid velocity v_g = dx/dt):
+ * xg, vg are DEVICE arrays [2][n_elem][(geom_order+1)^2]; vg NULL for static meshes
+ * (required when the context was created with moving = 1).  Computes and keeps the
+ * metric terms at solution and flux points; the face vector of each interface is
+ * computed once, from its owner side, and shared by both sides. */
+fr_status fr_set_geometry(fr_ctx ctx, const double* xg, const double* vg, void* stream);
+
+/* R(q): the FR/CPR residual of paper Eq. (cpr_ns) with the moving-mesh terms of
+ * Eq. (unsteady_pre_mov_pdomain), preconditioned Rusanov common flux (Eq. Rosanov),
+ * BR2 common gradient and Radau correction functions.  q, R: [4][E][Np]. */
+fr_status fr_residual(fr_ctx ctx, const double* q, double* R, void* stream);
+
+/* Exact Jacobian-vector product Jv = (dR/dq^p) v (forward tangent of the residual);
+ * R_or_null receives R(q) when non-NULL.  All arrays [4][E][Np]. */
+fr_status fr_jvp(fr_ctx ctx, const double* q, const double* v, double* Jv, double* R_or_null,
+                 void* stream);
+
+/* Vector-Jacobian product JTw = (dR/dq^p)^T w (reverse / adjoint of the residual),
+ * gather-formulated and deterministic.  All arrays [4][E][Np]. */
+fr_status fr_vjp(fr_ctx ctx, const double* q, const double* w, double* JTw, void* stream);
+
+/* Operator of the BDF2 Newton system, paper Eq. (unsteady_pre_discretized_3):
+ * Av = inv_dtau Gamma v + c_time M v - (dR/dq) v, pointwise Gamma and M at q. */
+fr_status fr_bdf_operator(fr_ctx ctx, const double* q, const double* v, double c_time,
+                          double inv_dtau, double* Av, void* stream);
+
+/* Element-block-Jacobi preconditioner: P_e = inv_dtau Gamma_e + c_time M_e - dR_e/dq_e,
+ * the true diagonal block of the Newton operator (own-state dependence through the
+ * faces included), assembled on the device, factored (partial pivoting) and stored
+ * as an explicit inverse in precision `prec` (FP32/BF16 with FP32 accumulation).
+ * c_time = 3/(2 dt) for BDF2, 1/dt for BDF1.  Kept in the context for the apply. */
+fr_status fr_block_jacobi_factor(fr_ctx ctx, const double* q, double c_time, double inv_dtau,
+                                 int32_t prec, void* stream);
+
+/* z = P^-1 r with the last factored blocks; r, z [4][E][Np] (may not alias). */
+fr_status fr_block_jacobi_apply(fr_ctx ctx, const double* r, double* z, void* stream);
+
+/* Copy the assembled (unfactored) FP64 blocks of the last fr_block_jacobi_factor to
+ * the DEVICE array blk [E][4Np][4Np], row-major (row = v*Np + s).  Only available
+ * when the context keeps them (fr_block_jacobi_factor with keep = 1 via fr_set_option). */
+fr_status fr_get_blocks(fr_ctx ctx, double* blk, void* stream);
+
+/* One BDF2 dual-time Newton step (BDF1 when q_nm1 is NULL): q holds q^n on entry and
+ * q^{n+1} on return.  Newton starts from q^n (paper Sec. 3.2); each Newton step solves
+ * the Eq. (unsteady_pre_discretized_3) system with restarted, right-preconditioned
+ * FP64 GMRES and the element-block-Jacobi preconditioner (refreshed every jac_lag steps).
+ * Synchronises `stream` once per GMRES iteration and Newton step.  h_stats: HOST,
+ * may be NULL.  Returns FR_ENOCONV (state still updated) when max_newton is reached. */
+fr_status fr_bdf2_step(fr_ctx ctx, double* q, const double* q_nm1, const fr_step_opts* opts,
+                       fr_step_stats* h_stats, void* stream);
+
+/* Options: "keep_blocks" (0/1: keep the FP64 blocks for fr_get_blocks). */
+fr_status fr_set_option(fr_ctx ctx, const char* name, int64_t value);
+
+const char* fr_last_error(void);
+void fr_destroy(fr_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMFR_H */

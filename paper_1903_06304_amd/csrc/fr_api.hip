@@ -1,0 +1,509 @@
+// C ABI of the lmfr library: context, operator tables, residual / JVP / VJP entry
+// points, the element-block-Jacobi preconditioner, and the BDF2 dual-time Newton step
+// with restarted, right-preconditioned FP64 GMRES (classical Gram-Schmidt with
+// re-orthogonalisation) driven from the host.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fr_internal.hpp"
+
+// ----------------------------------------------------------------------------- errors
+static thread_local std::string g_err;
+void fr_set_error(const std::string& s) { g_err = s; }
+extern "C" const char* fr_last_error(void) { return g_err.c_str(); }
+
+#define FR_TRY(x)                              \
+    do {                                       \
+        fr_status st_ = (x);                   \
+        if (st_ != FR_OK) return st_;          \
+    } while (0)
+
+static fr_status bad(const char* msg) { fr_set_error(msg); return FR_EINVAL; }
+
+// ----------------------------------------------------------------------------- 1-D tables
+namespace {
+
+// Legendre P_n and P_n' at x (three-term recurrence)
+void leg(int nn, double x, double& P, double& dP) {
+    double a = 1.0, b = x;
+    if (nn == 0) { P = 1.0; dP = 0.0; return; }
+    for (int k = 2; k <= nn; ++k) { double c = ((2 * k - 1) * x * b - (k - 1) * a) / k; a = b; b = c; }
+    P = b;
+    dP = nn * (x * b - a) / (x * x - 1.0);
+}
+
+// Gauss-Legendre points (Newton from Chebyshev guesses) and weights
+void gl_nodes(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(n); w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = -std::cos(M_PI * (2 * i + 1) / (2.0 * n));
+        for (int it = 0; it < 60; ++it) {
+            double P, dP; leg(n, z, P, dP);
+            double dz = P / dP; z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        double P, dP; leg(n, z, P, dP);
+        x[i] = z; w[i] = 2.0 / ((1.0 - z * z) * dP * dP);
+    }
+}
+
+// Gauss-Lobatto points: +-1 and the roots of P'_{m-1} (Newton on P'_{m-1})
+void gll_nodes(int m, std::vector<double>& x) {
+    x.resize(m);
+    x[0] = -1.0; x[m - 1] = 1.0;
+    const int N = m - 1;
+    for (int i = 1; i < N; ++i) {
+        double z = -std::cos(M_PI * i / N);
+        for (int it = 0; it < 60; ++it) {
+            double P, dP; leg(N, z, P, dP);
+            // (1 - z^2) P'' = 2 z P' - N (N+1) P
+            double d2P = (2.0 * z * dP - N * (N + 1) * P) / (1.0 - z * z);
+            double dz = dP / d2P; z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        x[i] = z;
+    }
+}
+
+// barycentric weights of a node set
+std::vector<double> bary(const std::vector<double>& x) {
+    std::vector<double> b(x.size(), 1.0);
+    for (size_t a = 0; a < x.size(); ++a)
+        for (size_t m = 0; m < x.size(); ++m)
+            if (m != a) b[a] /= (x[a] - x[m]);
+    return b;
+}
+
+// Lagrange values and derivatives of the basis on nodes x at point z
+void lag_eval(const std::vector<double>& x, const std::vector<double>& bw, double z, double* L, double* dL) {
+    const int n = (int)x.size();
+    for (int a = 0; a < n; ++a) {
+        if (z == x[a]) {
+            // z is a node: values are a Kronecker delta, derivatives the differentiation row
+            for (int c = 0; c < n; ++c) L[c] = (c == a) ? 1.0 : 0.0;
+            double diag = 0.0;
+            for (int c = 0; c < n; ++c) {
+                if (c == a) continue;
+                dL[c] = (bw[c] / bw[a]) / (x[a] - x[c]);
+                diag -= dL[c];
+            }
+            dL[a] = diag;
+            return;
+        }
+    }
+    double den = 0.0;
+    for (int a = 0; a < n; ++a) den += bw[a] / (z - x[a]);
+    for (int a = 0; a < n; ++a) {
+        L[a] = (bw[a] / (z - x[a])) / den;
+        double s = 0.0;
+        for (int m = 0; m < n; ++m) if (m != a) s += 1.0 / (z - x[m]);
+        dL[a] = L[a] * s;
+    }
+}
+
+void build_tables(fr_ctx c) {
+    const int n = c->n, m = c->m;
+    std::vector<double> x, w;
+    gl_nodes(n, x, w);
+    std::vector<double> bw = bary(x);
+    memset(&c->op, 0, sizeof(OpTab));
+    double L[FR_MAXN], dL[FR_MAXN];
+    for (int i = 0; i < n; ++i) {
+        lag_eval(x, bw, x[i], L, dL);
+        for (int a = 0; a < n; ++a) c->op.D[i * n + a] = dL[a];
+    }
+    lag_eval(x, bw, -1.0, L, dL);
+    for (int a = 0; a < n; ++a) c->op.lamL[a] = L[a];
+    lag_eval(x, bw, 1.0, L, dL);
+    for (int a = 0; a < n; ++a) c->op.lamR[a] = L[a];
+    // Radau correction functions (g_L right Radau, g_R left Radau) have nodal slopes
+    // -l_i(-1)/w_i and l_i(+1)/w_i on the Gauss-Legendre points
+    for (int i = 0; i < n; ++i) {
+        c->op.gamL[i] = -c->op.lamL[i] / w[i];
+        c->op.gamR[i] = c->op.lamR[i] / w[i];
+    }
+    // geometry basis on Gauss-Lobatto nodes of degree m-1
+    std::vector<double> g;
+    gll_nodes(m, g);
+    std::vector<double> gb = bary(g);
+    memset(&c->gt, 0, sizeof(GeoTab));
+    c->gt.m = m;
+    for (int i = 0; i < n; ++i) {
+        lag_eval(g, gb, x[i], L, dL);
+        for (int a = 0; a < m; ++a) { c->gt.Ls[i * m + a] = L[a]; c->gt.dLs[i * m + a] = dL[a]; }
+    }
+    lag_eval(g, gb, -1.0, L, dL);
+    for (int a = 0; a < m; ++a) c->gt.dLm[a] = dL[a];
+    lag_eval(g, gb, 1.0, L, dL);
+    for (int a = 0; a < m; ++a) c->gt.dLp[a] = dL[a];
+}
+
+template <class T>
+fr_status dalloc(T** p, size_t count) {
+    if (*p) return FR_OK;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T) + 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        fr_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return FR_ENOMEM;
+    }
+    return FR_OK;
+}
+
+void dfree(void* p) { if (p) (void)hipFree(p); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- context
+extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h_nbr_face,
+                               const int8_t* h_flip, fr_ctx* out) {
+    if (!prm || !h_nbr || !h_nbr_face || !out) return bad("fr_create: null argument");
+    *out = nullptr;
+    if (prm->order < 1 || prm->order > 4 || prm->geom_order < 1 || prm->geom_order > 4) {
+        fr_set_error("fr_create: order and geom_order must be in 1..4");
+        return FR_EUNSUPPORTED;
+    }
+    if (prm->n_elem <= 0 || prm->n_elem >= (1 << 27)) return bad("fr_create: n_elem out of range");
+    if (!(prm->gamma > 1.0) || !(prm->mach_ref > 0.0) || !(prm->prandtl > 0.0) || !(prm->mach_inf >= 0.0) ||
+        !(prm->kappa >= 0.0))
+        return bad("fr_create: invalid physical parameters");
+    if (prm->viscous && !(prm->reynolds > 0.0)) return bad("fr_create: reynolds must be positive");
+    const int E = prm->n_elem;
+    std::vector<int32_t> packed((size_t)E * 4);
+    for (int e = 0; e < E; ++e)
+        for (int f = 0; f < 4; ++f) {
+            const int nb = h_nbr[e * 4 + f], nf = h_nbr_face[e * 4 + f];
+            const int fl = h_flip ? (h_flip[e * 4 + f] != 0) : 0;
+            if (nb < 0 || nb >= E || nf < 0 || nf > 3) return bad("fr_create: neighbour table out of range");
+            if (h_nbr[nb * 4 + nf] != e || h_nbr_face[nb * 4 + nf] != f)
+                return bad("fr_create: neighbour table is not symmetric");
+            if (nb == e && nf == f) return bad("fr_create: a face cannot neighbour itself");
+            packed[(size_t)e * 4 + f] = nb * 8 + nf * 2 + fl;
+        }
+    fr_ctx c = new fr_ctx_s();
+    c->prm = *prm;
+    c->p = prm->order; c->n = c->p + 1; c->Np = c->n * c->n;
+    c->pg = prm->geom_order; c->m = c->pg + 1; c->E = E;
+    const double g = prm->gamma, Ma = prm->mach_ref;
+    PhysConst& pc = c->pc;
+    pc.gam = g;
+    pc.Rg = 1.0 / (g * Ma * Ma);
+    pc.Cp = 1.0 / ((g - 1.0) * Ma * Ma);
+    pc.inv_gm1 = 1.0 / (g - 1.0);
+    pc.gRg = g * pc.Rg;
+    pc.inv_Cp = 1.0 / pc.Cp;
+    pc.inv_Rg = 1.0 / pc.Rg;
+    pc.mu_re = prm->viscous ? prm->mu / prm->reynolds : 0.0;
+    pc.kc_re = prm->viscous ? prm->mu * pc.Cp / prm->prandtl / prm->reynolds : 0.0;
+    pc.eps_min = prm->kappa * prm->mach_inf;
+    pc.br2 = 0.5 * c->n * c->n;
+    build_tables(c);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; fr_set_error("no HIP device"); return FR_EHIP; }
+    const size_t EN = (size_t)E * c->Np, FE = (size_t)E * 4 * c->n;
+    fr_status st = FR_OK;
+    if ((st = dalloc(&c->d_nbr, (size_t)E * 4)) != FR_OK ||
+        (st = dalloc(&c->d_gsp, NGSP * EN)) != FR_OK ||
+        (st = dalloc(&c->d_gfp, NGFP * FE)) != FR_OK ||
+        (st = dalloc(&c->d_trace, FE * 10 * 2)) != FR_OK ||
+        (st = dalloc(&c->d_trace0, FE * 10)) != FR_OK ||
+        (st = dalloc(&c->d_scal, (size_t)SC_TOTAL)) != FR_OK) {
+        fr_destroy(c);
+        return st;
+    }
+    if (hipHostMalloc((void**)&c->h_scal, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        c->h_scal = nullptr;
+        fr_destroy(c);
+        fr_set_error("hipHostMalloc failed");
+        return FR_ENOMEM;
+    }
+    if (hipMemcpy(c->d_nbr, packed.data(), packed.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        fr_destroy(c);
+        fr_set_error("copy of the neighbour table failed");
+        return FR_EHIP;
+    }
+    *out = c;
+    return FR_OK;
+}
+
+extern "C" void fr_destroy(fr_ctx c) {
+    if (!c) return;
+    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_trace); dfree(c->d_trace0);
+    dfree(c->d_blk); dfree(c->d_inv); dfree(c->d_blk_keep); dfree(c->d_scal);
+    dfree(c->d_V); dfree(c->d_w); dfree(c->d_vj);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    delete c;
+}
+
+extern "C" fr_status fr_set_option(fr_ctx c, const char* name, int64_t value) {
+    if (!c || !name) return bad("fr_set_option: null argument");
+    if (!strcmp(name, "keep_blocks")) { c->keep_blocks = value != 0; return FR_OK; }
+    return bad("fr_set_option: unknown option");
+}
+
+extern "C" fr_status fr_set_geometry(fr_ctx c, const double* xg, const double* vg, void* stream) {
+    if (!c || !xg) return bad("fr_set_geometry: null argument");
+    if (c->prm.moving && !vg) return bad("fr_set_geometry: moving mesh needs grid velocities");
+    FR_TRY(launch_geometry(c, xg, c->prm.moving ? vg : nullptr, (hipStream_t)stream));
+    c->geometry_set = true;
+    return FR_OK;
+}
+
+static fr_status ready(fr_ctx c) {
+    if (!c) return bad("null context");
+    if (!c->geometry_set) return bad("fr_set_geometry has not been called");
+    return FR_OK;
+}
+
+extern "C" fr_status fr_residual(fr_ctx c, const double* q, double* R, void* stream) {
+    FR_TRY(ready(c));
+    if (!q || !R) return bad("fr_residual: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    FR_TRY(launch_traces(c, q, nullptr, c->d_trace, 0, s));
+    KArgs a{};
+    a.E = c->E; a.q = q; a.tr = c->d_trace; a.out = R;
+    return launch_residual(c, MODE_R, a, s);
+}
+
+extern "C" fr_status fr_jvp(fr_ctx c, const double* q, const double* v, double* Jv, double* R_or_null, void* stream) {
+    FR_TRY(ready(c));
+    if (!q || !v || !Jv) return bad("fr_jvp: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    FR_TRY(launch_traces(c, q, v, c->d_trace, 1, s));
+    KArgs a{};
+    a.E = c->E; a.q = q; a.v = v; a.tr = c->d_trace; a.out = Jv; a.out2 = R_or_null;
+    return launch_residual(c, MODE_JVP, a, s);
+}
+
+extern "C" fr_status fr_bdf_operator(fr_ctx c, const double* q, const double* v, double c_time, double inv_dtau,
+                                     double* Av, void* stream) {
+    FR_TRY(ready(c));
+    if (!q || !v || !Av) return bad("fr_bdf_operator: null argument");
+    hipStream_t s = (hipStream_t)stream;
+    FR_TRY(launch_traces(c, q, v, c->d_trace, 1, s));
+    KArgs a{};
+    a.E = c->E; a.q = q; a.v = v; a.tr = c->d_trace; a.out = Av; a.c_time = c_time; a.inv_dtau = inv_dtau;
+    return launch_residual(c, MODE_AOP, a, s);
+}
+
+extern "C" fr_status fr_vjp(fr_ctx c, const double* q, const double* w, double* JTw, void* stream) {
+    FR_TRY(ready(c));
+    if (!q || !w || !JTw) return bad("fr_vjp: null argument");
+    return launch_vjp(c, q, w, JTw, (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_block_jacobi_factor(fr_ctx c, const double* q, double c_time, double inv_dtau, int32_t prec,
+                                            void* stream) {
+    FR_TRY(ready(c));
+    if (!q) return bad("fr_block_jacobi_factor: null argument");
+    if (prec < FR_FP64 || prec > FR_BF16) return bad("fr_block_jacobi_factor: unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nb = 4 * (size_t)c->Np, nbb = (size_t)c->E * nb * nb;
+    FR_TRY(dalloc(&c->d_blk, nbb));
+    if (!c->d_inv) FR_TRY(dalloc((double**)&c->d_inv, nbb));   // sized for FP64, reused by any precision
+    FR_TRY(launch_block_assembly(c, q, c_time, inv_dtau, s));
+    if (c->keep_blocks) {
+        FR_TRY(dalloc(&c->d_blk_keep, nbb));
+        FR_HIP(hipMemcpyAsync(c->d_blk_keep, c->d_blk, nbb * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    FR_TRY(launch_block_invert(c, prec, s));
+    // a zero pivot leaves a flag; reading it synchronises once per refresh
+    FR_HIP(hipMemcpyAsync(c->h_scal + 1024, c->d_scal + SC_STATUS, sizeof(int), hipMemcpyDeviceToHost, s));
+    FR_HIP(hipStreamSynchronize(s));
+    int flag;
+    memcpy(&flag, c->h_scal + 1024, sizeof(int));
+    if (flag) {
+        c->inv_prec = -1;
+        fr_set_error("fr_block_jacobi_factor: singular element block");
+        return FR_ENOCONV;
+    }
+    return FR_OK;
+}
+
+extern "C" fr_status fr_block_jacobi_apply(fr_ctx c, const double* r, double* z, void* stream) {
+    FR_TRY(ready(c));
+    if (!r || !z) return bad("fr_block_jacobi_apply: null argument");
+    if (r == z) return bad("fr_block_jacobi_apply: r and z may not alias");
+    return launch_block_apply(c, r, z, (hipStream_t)stream);
+}
+
+// blocks as assembled (column-major per element) -> caller's array row-major
+namespace {
+__global__ void k_transpose_blocks(size_t E, int nb, const double* __restrict__ src, double* __restrict__ dst) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t nn = (size_t)nb * nb;
+    if (t >= E * nn) return;
+    const size_t e = t / nn, rc = t % nn, col = rc / nb, row = rc % nb;
+    dst[e * nn + row * nb + col] = src[t];
+}
+}  // namespace
+
+extern "C" fr_status fr_get_blocks(fr_ctx c, double* blk, void* stream) {
+    FR_TRY(ready(c));
+    if (!blk) return bad("fr_get_blocks: null argument");
+    if (!c->d_blk_keep) return bad("fr_get_blocks: enable keep_blocks before fr_block_jacobi_factor");
+    const int nb = 4 * c->Np;
+    const size_t tot = (size_t)c->E * nb * nb;
+    hipLaunchKernelGGL(k_transpose_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       (size_t)c->E, nb, c->d_blk_keep, blk);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+// ----------------------------------------------------------------------------- GMRES
+namespace {
+
+struct Gm {
+    int its = 0;
+    double rel = 0.0;
+};
+
+// work vectors inside d_w: 0: b, 1: R, 2: Q^n, 3: Q^{n-1}, 4: r, 5: w, 6: z, 7: dq
+enum { WB = 0, WR, WQN, WQNM1, WRES, WW, WZ, WDQ, NWORK };
+
+fr_status ensure_krylov(fr_ctx c, int m) {
+    if (c->kry_m >= m && c->d_V) return FR_OK;
+    dfree(c->d_V); c->d_V = nullptr;
+    FR_TRY(dalloc(&c->d_V, (size_t)(m + 1) * c->N()));
+    c->kry_m = m;
+    if (!c->d_w) FR_TRY(dalloc(&c->d_w, (size_t)NWORK * c->N()));
+    return FR_OK;
+}
+
+double* wv(fr_ctx c, int i) { return c->d_w + (size_t)i * c->N(); }
+
+// 2-norm of the first N entries of x (synchronises)
+fr_status norm2(fr_ctx c, size_t N, const double* x, double& out, hipStream_t s) {
+    FR_TRY(la_dots(c, N, x, 1, x, c->d_scal + SC_NRM, s));
+    FR_HIP(hipMemcpyAsync(c->h_scal, c->d_scal + SC_NRM, sizeof(double), hipMemcpyDeviceToHost, s));
+    FR_HIP(hipStreamSynchronize(s));
+    out = std::sqrt(c->h_scal[0]);
+    return FR_OK;
+}
+
+// Solve (inv_dtau Gamma + c_time M - J(q)) x = b with right preconditioning by the
+// factored element blocks.  x0 = 0; stops on ||b - A x|| <= tol ||b|| (true residual at
+// each restart, Arnoldi estimate inside a cycle) or after max_it iterations.
+fr_status gmres(fr_ctx c, const double* q, const double* b, double* x, int m, double tol, int max_it, double ct,
+                double idt, Gm& out, hipStream_t s) {
+    const size_t N = c->N();
+    double* V = c->d_V;
+    double* r = wv(c, WRES);
+    double* w = wv(c, WW);
+    double* z = wv(c, WZ);
+    double* d_h1 = c->d_scal + SC_H1;
+    double* d_h2 = c->d_scal + SC_H2;
+    double* d_nrm = c->d_scal + SC_NRM;
+    double* d_y = c->d_scal + SC_Y;
+    FR_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
+    double bn;
+    FR_TRY(norm2(c, N, b, bn, s));
+    out = Gm{};
+    if (bn == 0.0) return FR_OK;
+    if (!std::isfinite(bn)) { fr_set_error("non-finite right-hand side"); return FR_ENONFINITE; }
+    FR_HIP(hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double beta = bn;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+    while (out.its < max_it) {
+        FR_TRY(la_scale_copy(N, 1.0 / beta, r, V, s));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        bool done = false;
+        for (; j < m && out.its < max_it; ++j) {
+            double* vj = V + (size_t)j * N;
+            FR_TRY(launch_block_apply(c, vj, z, s));
+            FR_TRY(fr_bdf_operator(c, q, z, ct, idt, w, s));
+            // classical Gram-Schmidt, applied twice
+            FR_TRY(la_dots(c, N, V, j + 1, w, d_h1, s));
+            FR_TRY(la_update(c, w, V, j + 1, d_h1, s));
+            FR_TRY(la_dots(c, N, V, j + 1, w, d_h2, s));
+            FR_TRY(la_update(c, w, V, j + 1, d_h2, s));
+            FR_TRY(la_dots(c, N, w, 1, w, d_nrm, s));
+            FR_HIP(hipMemcpyAsync(c->h_scal, d_h1, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
+            FR_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->h_scal[i] + c->h_scal[64 + i];
+            const double hn = std::sqrt(c->h_scal[128]);
+            if (!std::isfinite(hn)) { fr_set_error("non-finite Arnoldi vector"); return FR_ENONFINITE; }
+            H[(size_t)(j + 1) * m + j] = hn;
+            if (hn > 0.0) FR_TRY(la_scale_copy(N, 1.0 / hn, w, V + (size_t)(j + 1) * N, s));
+            for (int i = 0; i < j; ++i) {
+                const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+            }
+            const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
+            const double den = std::hypot(a0, a1);
+            cs[j] = den == 0.0 ? 1.0 : a0 / den;
+            sn[j] = den == 0.0 ? 0.0 : a1 / den;
+            H[(size_t)j * m + j] = cs[j] * a0 + sn[j] * a1;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            out.its++;
+            if (std::fabs(g[j + 1]) <= tol * bn || hn == 0.0) { ++j; done = true; break; }
+        }
+        (void)done;
+        // y = H^-1 g (upper triangular), x += P^-1 (V y)
+        for (int i = j - 1; i >= 0; --i) {
+            double sacc = g[i];
+            for (int k = i + 1; k < j; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+            y[i] = sacc / H[(size_t)i * m + i];
+        }
+        memcpy(c->h_scal + 256, y.data(), j * sizeof(double));
+        FR_HIP(hipMemcpyAsync(d_y, c->h_scal + 256, j * sizeof(double), hipMemcpyHostToDevice, s));
+        FR_TRY(la_combine(N, V, j, d_y, w, s));
+        FR_TRY(launch_block_apply(c, w, z, s));
+        FR_TRY(la_axpy(N, 1.0, z, x, s));
+        // true residual r = b - A x
+        FR_TRY(fr_bdf_operator(c, q, x, ct, idt, w, s));
+        FR_TRY(la_scale_copy(N, 1.0, b, r, s));
+        FR_TRY(la_axpy(N, -1.0, w, r, s));
+        FR_TRY(norm2(c, N, r, beta, s));   // synchronises, so h_scal may be reused
+        out.rel = beta / bn;
+        if (!std::isfinite(beta)) { fr_set_error("non-finite GMRES residual"); return FR_ENONFINITE; }
+        if (beta <= tol * bn) break;
+    }
+    return FR_OK;
+}
+
+}  // namespace
+
+extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q, const double* q_nm1, const fr_step_opts* o,
+                                  fr_step_stats* h_stats, void* stream) {
+    FR_TRY(ready(c));
+    if (!q || !o) return bad("fr_bdf2_step: null argument");
+    if (!(o->dt > 0.0) || o->krylov < 1 || o->krylov > 60 || o->max_lin_it < 1 || o->max_newton < 0 || o->jac_lag < 1)
+        return bad("fr_bdf2_step: invalid options");
+    hipStream_t s = (hipStream_t)stream;
+    FR_TRY(ensure_krylov(c, o->krylov));
+    const size_t N = c->N(), EN = (size_t)c->E * c->Np;
+    const double a0 = q_nm1 ? 1.5 : 1.0, a1 = q_nm1 ? -2.0 : -1.0, a2 = q_nm1 ? 0.5 : 0.0;
+    const double ct = a0 / o->dt;
+    FR_TRY(launch_cons(c, q, wv(c, WQN), s));
+    if (q_nm1) FR_TRY(launch_cons(c, q_nm1, wv(c, WQNM1), s));
+    fr_step_stats st{0, 0, 0, 0.0, 0.0};
+    fr_status ret = FR_OK;
+    for (int m = 0;; ++m) {
+        FR_TRY(fr_residual(c, q, wv(c, WR), s));
+        FR_TRY(launch_bdf_rhs(c, q, wv(c, WQN), q_nm1 ? wv(c, WQNM1) : nullptr, wv(c, WR), a0, a1, a2, o->dt,
+                              wv(c, WB), s));
+        double res;
+        FR_TRY(norm2(c, EN, wv(c, WB), res, s));   // mass rows
+        if (!std::isfinite(res)) { fr_set_error("non-finite nonlinear residual"); ret = FR_ENONFINITE; break; }
+        if (m == 0) st.res0 = res;
+        st.res_final = res;
+        if (res <= o->tol_abs || res <= o->tol_pseudo * st.res0) { st.converged = 1; break; }
+        if (m >= o->max_newton) { ret = FR_ENOCONV; fr_set_error("Newton iteration limit reached"); break; }
+        if (m % o->jac_lag == 0) FR_TRY(fr_block_jacobi_factor(c, q, ct, o->inv_dtau, o->prec, s));
+        Gm gm;
+        FR_TRY(gmres(c, q, wv(c, WB), wv(c, WDQ), o->krylov, o->tol_res, o->max_lin_it, ct, o->inv_dtau, gm, s));
+        st.gmres_its += gm.its;
+        FR_TRY(la_axpy(N, 1.0, wv(c, WDQ), q, s));
+        st.newton_its++;
+    }
+    if (h_stats) *h_stats = st;
+    return ret;
+}

@@ -1,0 +1,175 @@
+// Pointwise physics of the preconditioned FR/CPR residual (device + host inline),
+// templated on the scalar type (double or Dual<K>).
+//
+//  - non-dimensional Navier-Stokes fluxes, paper Sec. 2.1 Eqs. (convection),
+//    (diffusion), (shear_stress); total flux f = f_inv - f_vis
+//  - M = dq^c/dq^p and the Weiss-Smith matrix Gamma (rho_p -> Theta),
+//    Sec. 2.2 Eqs. (jacobian), (preconditioning), (theta); both applied in the
+//    compact row form  r0 = a dp + rho_T dT,  r1 = u r0 + rho du,  r2 = v r0 + rho dv,
+//    r3 = h r0 - dp + rho (u du + v dv) + rho Cp dT  with a = rho_p (M) or Theta (Gamma)
+//  - reference velocity U_r = eps c, eps = min(1, max(kappa Ma_inf, Ma)), Ma from
+//    v - v_g, Eqs. (eps_nonmove), (eps_move)
+//  - preconditioned Rusanov flux, Eq. (Rosanov), with |lambda|max = |u_n'| + c' of
+//    Eqs. (eigenvalues), (eigenvalues_para) (alpha = (1 - eps^2)/2 because
+//    beta U_r^2 = eps^2 for an ideal gas), moving-face normal flux of Sec. 3.1
+//  - BR2 common gradient (Sec. 3.1) with the face-local Radau lifting evaluated at
+//    the face: r = ((p+1)^2/2)(|S|/|J|_f)(q^com - q) n_out on each side.
+#pragma once
+#include "fr_scalar.hpp"
+
+struct PhysConst {
+    double gam, Rg, Cp, inv_gm1, gRg, inv_Cp, inv_Rg;
+    double mu_re, kc_re;      // mu/Re, (mu Cp/Pr)/Re
+    double eps_min;           // kappa * Ma_inf
+    double br2;               // (p+1)^2 / 2
+};
+
+// q^c = (rho, rho u, rho v, E), E = p/(gamma-1) + rho |v|^2 / 2, rho = p/(R T)
+template <class T>
+FR_HD void fr_cons(const PhysConst& c, const T* q, T* qc) {
+    T rho = q[0] * c.inv_Rg / q[3];
+    qc[0] = rho;
+    qc[1] = rho * q[1];
+    qc[2] = rho * q[2];
+    qc[3] = q[0] * c.inv_gm1 + 0.5 * rho * (q[1] * q[1] + q[2] * q[2]);
+}
+
+// Total physical flux (f, g) = (f_inv - f_vis, g_inv - g_vis) and q^c at a point.
+// gu, gv, gT: (d/dx, d/dy) of u, v, T.
+template <class T, bool VISC>
+FR_HD void fr_point_flux(const PhysConst& c, const T* q, const T* gu, const T* gv, const T* gT,
+                         T* f, T* g, T* qc) {
+    fr_cons(c, q, qc);
+    const T& p = q[0]; const T& u = q[1]; const T& v = q[2];
+    T Ep = qc[3] + p;
+    f[0] = qc[1];
+    f[1] = qc[1] * u + p;
+    f[2] = qc[1] * v;
+    f[3] = Ep * u;
+    g[0] = qc[2];
+    g[1] = qc[2] * u;
+    g[2] = qc[2] * v + p;
+    g[3] = Ep * v;
+    if (VISC) {
+        // tau/Re with mu constant; heat flux k grad T / Re
+        T div = gu[0] + gv[1];
+        T txx = c.mu_re * (2.0 * gu[0] - (2.0 / 3.0) * div);
+        T tyy = c.mu_re * (2.0 * gv[1] - (2.0 / 3.0) * div);
+        T txy = c.mu_re * (gu[1] + gv[0]);
+        f[1] = f[1] - txx;
+        f[2] = f[2] - txy;
+        f[3] = f[3] - (u * txx + v * txy + c.kc_re * gT[0]);
+        g[1] = g[1] - txy;
+        g[2] = g[2] - tyy;
+        g[3] = g[3] - (u * txy + v * tyy + c.kc_re * gT[1]);
+    }
+}
+
+// eps of the preconditioner from the velocity relative to the grid and the sound speed
+template <class T>
+FR_HD T fr_eps(const PhysConst& c, const T& urel, const T& vrel, const T& cs) {
+    T Ma = ssqrt(urel * urel + vrel * vrel) / cs;
+    return smin(cst<T>(1.0), smax(cst<T>(c.eps_min), Ma));
+}
+
+// out = (a-row matrix) * dq with a = rho_p (M) or Theta (Gamma); state q.
+template <class T, class V>
+FR_HD void fr_gm_apply(const PhysConst& c, const T& a, const T& rho, const T& rhoT, const T& h,
+                       const T* q, const V* dq, V* out) {
+    V r0 = a * dq[0] + rhoT * dq[3];
+    out[0] = r0;
+    out[1] = q[1] * r0 + rho * dq[1];
+    out[2] = q[2] * r0 + rho * dq[2];
+    out[3] = h * r0 - dq[0] + rho * (q[1] * dq[1] + q[2] * dq[2]) + (rho * c.Cp) * dq[3];
+}
+
+// Time-term operator at a solution point: out = inv_dtau Gamma(q) x + c_time M(q) x.
+template <class T, class V>
+FR_HD void fr_time_apply(const PhysConst& c, const T* q, double ug, double vg, double inv_dtau,
+                         double c_time, const V* x, V* out) {
+    T rho = q[0] * c.inv_Rg / q[3];
+    T rhoT = -rho / q[3];
+    T rhop = c.inv_Rg / q[3];
+    T cs = ssqrt(c.gRg * q[3]);
+    T eps = fr_eps(c, q[1] - ug, q[2] - vg, cs);
+    T Ur = eps * cs;
+    T theta = 1.0 / (Ur * Ur) + c.inv_Cp / q[3];
+    T h = c.Cp * q[3] + 0.5 * (q[1] * q[1] + q[2] * q[2]);
+    V a[4], b[4];
+    fr_gm_apply(c, theta, rho, rhoT, h, q, x, a);
+    fr_gm_apply(c, rhop, rho, rhoT, h, q, x, b);
+    for (int r = 0; r < 4; ++r) out[r] = inv_dtau * a[r] + c_time * b[r];
+}
+
+// Normal inviscid flux through a moving face: f n_x + g n_y - (v_g . n) q^c
+template <class T>
+FR_HD void fr_normal_flux(const PhysConst& c, const T* q, double nx, double ny, double vgn, T* fn) {
+    T qc[4];
+    fr_cons(c, q, qc);
+    T un = q[1] * nx + q[2] * ny;
+    T unr = un - vgn;
+    fn[0] = qc[0] * unr;
+    fn[1] = qc[1] * unr + q[0] * nx;
+    fn[2] = qc[2] * unr + q[0] * ny;
+    fn[3] = qc[3] * unr + q[0] * un;
+}
+
+// Common normal flux at one face point, normal n = outward normal of the own ('-') side.
+//   qm, qp : primitive states of the own side and of the neighbour
+//   gm, gp : uncorrected gradient traces (ux, uy, vx, vy, Tx, Ty) of both sides
+//   Smag   : |S| of the face vector; JfL, JfR : |J| of each side at the point
+// Outputs fn (common normal flux for n) and dqh = q^com - q^- for (u, v, T).
+template <class T, bool VISC>
+FR_HD void fr_common_flux(const PhysConst& c, const T* qm, const T* qp, const T* gm, const T* gp,
+                          double nx, double ny, double Smag, double JfL, double JfR,
+                          double ug, double vg, T* fn, T* dqh) {
+    const double vgn = ug * nx + vg * ny;
+    T fL[4], fR[4];
+    fr_normal_flux(c, qm, nx, ny, vgn, fL);
+    fr_normal_flux(c, qp, nx, ny, vgn, fR);
+    T qb[4], dq[4];
+    for (int r = 0; r < 4; ++r) {
+        qb[r] = 0.5 * (qm[r] + qp[r]);
+        dq[r] = qp[r] - qm[r];
+    }
+    T rho = qb[0] * c.inv_Rg / qb[3];
+    T cs = ssqrt(c.gRg * qb[3]);
+    T ur = qb[1] - ug, vr = qb[2] - vg;
+    T eps = fr_eps(c, ur, vr, cs);
+    T Ur = eps * cs;
+    T Ur2 = Ur * Ur;
+    T theta = 1.0 / Ur2 + c.inv_Cp / qb[3];
+    T rhoT = -rho / qb[3];
+    T h = c.Cp * qb[3] + 0.5 * (qb[1] * qb[1] + qb[2] * qb[2]);
+    T gd[4];
+    fr_gm_apply(c, theta, rho, rhoT, h, qb, dq, gd);
+    T un = ur * nx + vr * ny;
+    T alpha = 0.5 * (1.0 - eps * eps);
+    T unp = un * (1.0 - alpha);
+    T cp = ssqrt(alpha * alpha * un * un + Ur2);
+    T lam = sabs(unp) + cp;
+    T hl = 0.5 * lam;
+    for (int r = 0; r < 4; ++r) fn[r] = 0.5 * (fL[r] + fR[r]) - hl * gd[r];
+    if (VISC) {
+        // grad q^com = 1/2 (g^- + g^+) + 1/4 (cL + cR) (q^+ - q^-) n
+        const double cc = 0.25 * c.br2 * Smag * (1.0 / JfL + 1.0 / JfR);
+        T ux = 0.5 * (gm[0] + gp[0]) + (cc * nx) * dq[1];
+        T uy = 0.5 * (gm[1] + gp[1]) + (cc * ny) * dq[1];
+        T vx = 0.5 * (gm[2] + gp[2]) + (cc * nx) * dq[2];
+        T vy = 0.5 * (gm[3] + gp[3]) + (cc * ny) * dq[2];
+        T Tx = 0.5 * (gm[4] + gp[4]) + (cc * nx) * dq[3];
+        T Ty = 0.5 * (gm[5] + gp[5]) + (cc * ny) * dq[3];
+        T div = ux + vy;
+        T txx = c.mu_re * (2.0 * ux - (2.0 / 3.0) * div);
+        T tyy = c.mu_re * (2.0 * vy - (2.0 / 3.0) * div);
+        T txy = c.mu_re * (uy + vx);
+        T tnx = txx * nx + txy * ny;
+        T tny = txy * nx + tyy * ny;
+        fn[1] = fn[1] - tnx;
+        fn[2] = fn[2] - tny;
+        fn[3] = fn[3] - (qb[1] * tnx + qb[2] * tny + c.kc_re * (Tx * nx + Ty * ny));
+        dqh[0] = 0.5 * dq[1];
+        dqh[1] = 0.5 * dq[2];
+        dqh[2] = 0.5 * dq[3];
+    }
+}

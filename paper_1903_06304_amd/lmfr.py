@@ -1,0 +1,236 @@
+"""Python binding of the lmfr C ABI (include/lmfr.h): argument marshalling only.
+
+Every step of the residual, its derivatives, the preconditioner and the BDF2 step
+runs in the HIP kernels of liblmfr.so; PyTorch provides device memory and streams.
+Loading fails loudly when the library is missing or no HIP device is present.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblmfr.so")
+_lib = None
+
+FR_OK, FR_EINVAL, FR_EHIP, FR_ENOMEM, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FR_FP64, FR_FP32, FR_BF16 = 0, 1, 2
+PREC = {"fp64": FR_FP64, "fp32": FR_FP32, "bf16": FR_BF16}
+
+# every symbol declared in include/lmfr.h
+EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "fr_bdf_operator",
+           "fr_block_jacobi_factor", "fr_block_jacobi_apply", "fr_get_blocks", "fr_bdf2_step",
+           "fr_set_option", "fr_last_error", "fr_destroy"]
+
+
+class FRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lmfr status {status}: {msg}")
+        self.status = status
+
+
+class fr_params(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("geom_order", ctypes.c_int32), ("n_elem", ctypes.c_int32),
+                ("viscous", ctypes.c_int32), ("moving", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("mach_ref", ctypes.c_double), ("reynolds", ctypes.c_double),
+                ("prandtl", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("mach_inf", ctypes.c_double)]
+
+
+class fr_step_opts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("inv_dtau", ctypes.c_double), ("tol_pseudo", ctypes.c_double),
+                ("tol_res", ctypes.c_double), ("tol_abs", ctypes.c_double), ("krylov", ctypes.c_int32),
+                ("max_lin_it", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("jac_lag", ctypes.c_int32),
+                ("prec", ctypes.c_int32)]
+
+
+class fr_step_stats(ctypes.Structure):
+    _fields_ = [("newton_its", ctypes.c_int32), ("gmres_its", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double)]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblmfr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"lmfr HIP library not built: {path} (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, dp = ctypes.c_void_p, ctypes.c_void_p
+    L.fr_create.argtypes = [ctypes.POINTER(fr_params), vp, vp, vp, ctypes.POINTER(ctypes.c_void_p)]
+    L.fr_set_geometry.argtypes = [vp, dp, dp, vp]
+    L.fr_residual.argtypes = [vp, dp, dp, vp]
+    L.fr_jvp.argtypes = [vp, dp, dp, dp, dp, vp]
+    L.fr_vjp.argtypes = [vp, dp, dp, dp, vp]
+    L.fr_bdf_operator.argtypes = [vp, dp, dp, ctypes.c_double, ctypes.c_double, dp, vp]
+    L.fr_block_jacobi_factor.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
+    L.fr_block_jacobi_apply.argtypes = [vp, dp, dp, vp]
+    L.fr_get_blocks.argtypes = [vp, dp, vp]
+    L.fr_bdf2_step.argtypes = [vp, dp, dp, ctypes.POINTER(fr_step_opts), ctypes.POINTER(fr_step_stats), vp]
+    L.fr_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+    L.fr_last_error.restype = ctypes.c_char_p
+    L.fr_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("fr_last_error", "fr_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != FR_OK:
+        raise FRError(st, load_library().fr_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A discretisation context: mesh connectivity, geometry and physical parameters."""
+
+    def __init__(self, prm, nbr, nbr_face, flip=None, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("lmfr needs a HIP device")
+        L = load_library()
+        self.device = torch.device(device)
+        p = fr_params(int(prm.order), int(prm.geom_order), int(prm.n_elem), int(bool(prm.viscous)),
+                      int(bool(prm.moving)), float(prm.gamma), float(prm.mach_ref), float(prm.reynolds),
+                      float(prm.prandtl), float(prm.mu), float(prm.kappa), float(prm.mach_inf))
+        self._nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        self._nbf = np.ascontiguousarray(nbr_face, dtype=np.int32)
+        self._flip = None if flip is None else np.ascontiguousarray(flip, dtype=np.int8)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.fr_create(ctypes.byref(p), self._nbr.ctypes.data_as(ctypes.c_void_p),
+                               self._nbf.ctypes.data_as(ctypes.c_void_p),
+                               None if self._flip is None else self._flip.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(h)))
+        self.h = h
+        self.prm = prm
+        self.E = int(prm.n_elem)
+        self.Np = (int(prm.order) + 1) ** 2
+        self.shape = (4, self.E, self.Np)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                load_library().fr_destroy(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def _dev(self, x):
+        if x is None:
+            return None
+        t = torch.as_tensor(x, dtype=torch.float64, device=self.device)
+        return t.contiguous()
+
+    def _state(self, x):
+        t = self._dev(x)
+        if tuple(t.shape) != self.shape and t.numel() != 4 * self.E * self.Np:
+            raise ValueError(f"state of shape {tuple(t.shape)}, expected {self.shape}")
+        return t.view(self.shape)
+
+    def set_geometry(self, xg, vg=None):
+        self._xg = self._dev(xg)
+        self._vg = self._dev(vg)
+        _check(load_library().fr_set_geometry(self.h, _ptr(self._xg), _ptr(self._vg), _stream()))
+
+    def set_option(self, name: str, value: int):
+        _check(load_library().fr_set_option(self.h, name.encode(), int(value)))
+
+    def residual(self, q, out=None):
+        q = self._state(q)
+        R = torch.empty_like(q) if out is None else out
+        _check(load_library().fr_residual(self.h, _ptr(q), _ptr(R), _stream()))
+        return R
+
+    def jvp(self, q, v, want_residual=False):
+        q, v = self._state(q), self._state(v)
+        Jv = torch.empty_like(q)
+        R = torch.empty_like(q) if want_residual else None
+        _check(load_library().fr_jvp(self.h, _ptr(q), _ptr(v), _ptr(Jv), _ptr(R), _stream()))
+        return (Jv, R) if want_residual else Jv
+
+    def vjp(self, q, w):
+        q, w = self._state(q), self._state(w)
+        out = torch.empty_like(q)
+        _check(load_library().fr_vjp(self.h, _ptr(q), _ptr(w), _ptr(out), _stream()))
+        return out
+
+    def bdf_operator(self, q, v, c_time, inv_dtau):
+        q, v = self._state(q), self._state(v)
+        out = torch.empty_like(q)
+        _check(load_library().fr_bdf_operator(self.h, _ptr(q), _ptr(v), float(c_time), float(inv_dtau),
+                                              _ptr(out), _stream()))
+        return out
+
+    def block_jacobi_factor(self, q, c_time, inv_dtau, prec="fp64"):
+        q = self._state(q)
+        _check(load_library().fr_block_jacobi_factor(self.h, _ptr(q), float(c_time), float(inv_dtau),
+                                                     PREC[prec] if isinstance(prec, str) else int(prec),
+                                                     _stream()))
+
+    def block_jacobi_apply(self, r):
+        r = self._state(r)
+        z = torch.empty_like(r)
+        _check(load_library().fr_block_jacobi_apply(self.h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def get_blocks(self):
+        nb = 4 * self.Np
+        out = torch.empty((self.E, nb, nb), dtype=torch.float64, device=self.device)
+        _check(load_library().fr_get_blocks(self.h, _ptr(out), _stream()))
+        return out
+
+    def bdf2_step(self, q, q_nm1, dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=100,
+                  max_newton=100, jac_lag=2, inv_dtau=1e-20, tol_abs=0.0, prec="fp64", check=True):
+        """One BDF2 step in place on q (a float64 device tensor); returns the stats dict."""
+        q = self._state(q)
+        qn1 = None if q_nm1 is None else self._state(q_nm1)
+        o = fr_step_opts(float(dt), float(inv_dtau), float(tol_pseudo), float(tol_res), float(tol_abs),
+                         int(krylov), int(max_lin_it), int(max_newton), int(jac_lag),
+                         PREC[prec] if isinstance(prec, str) else int(prec))
+        st = fr_step_stats()
+        rc = load_library().fr_bdf2_step(self.h, _ptr(q), _ptr(qn1), ctypes.byref(o), ctypes.byref(st), _stream())
+        if check and rc not in (FR_OK, FR_ENOCONV):
+            _check(rc)
+        return dict(rc=rc, newton_its=st.newton_its, gmres_its=st.gmres_its, converged=st.converged,
+                    res0=st.res0, res_final=st.res_final)
+
+
+class FRResidual(torch.autograd.Function):
+    """R(q) with exact derivatives: forward = fr_residual, backward = fr_vjp, jvp = fr_jvp."""
+
+    @staticmethod
+    def forward(q, ctx_fr):
+        return ctx_fr.residual(q)
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        q, ctx_fr = inputs
+        ctx.save_for_backward(q)
+        ctx.fr = ctx_fr
+        ctx.q_fwd = q
+
+    @staticmethod
+    def backward(ctx, w):
+        (q,) = ctx.saved_tensors
+        return ctx.fr.vjp(q, w.contiguous()), None
+
+    @staticmethod
+    def jvp(ctx, v, _):
+        return ctx.fr.jvp(ctx.q_fwd, v.contiguous())
+
+
+def residual(q, ctx_fr):
+    return FRResidual.apply(q, ctx_fr)

@@ -1,0 +1,100 @@
+"""Shared test helpers: scales for residual parity and case construction."""
+import numpy as np
+
+from paper_1903_06304_amd import inputs as I
+
+
+def flux_scale(geo, prm, q):
+    """S_c per row: the scale of the terms summed into row c of R.
+
+    Round-off in R is proportional to the magnitudes of the summed terms, not to R
+    (a plain relative error is ill-posed at low Mach number).  Per point the terms are
+    the fluxes |f_c| + |g_c| + |v_g||q^c_c| and the Rusanov dissipation
+    |lambda|max (|Gamma~| |q|)_c, whose pressure part Theta |p| is large at low Mach; they
+    enter through the chain-rule metrics (max |grad xi|) and the 1-D operators
+    (absolute row sum of D plus the two Radau lifts of a direction)."""
+    p, u, v, T = q
+    Rg, Cp = prm.gas_constant, prm.cp
+    rho = p / (Rg * T)
+    E = p / (prm.gamma - 1) + 0.5 * rho * (u * u + v * v)
+    f = np.stack([rho * u, rho * u * u + p, rho * u * v, (E + p) * u])
+    g = np.stack([rho * v, rho * u * v, rho * v * v + p, (E + p) * v])
+    qc = np.stack([rho, rho * u, rho * v, E])
+    vg = np.hypot(geo["ug"], geo["vg"])
+    c = np.sqrt(prm.gamma * Rg * T)
+    eps = np.minimum(1.0, np.maximum(prm.kappa * prm.mach_inf, np.hypot(u - geo["ug"], v - geo["vg"]) / c))
+    Ur = eps * c
+    theta = 1.0 / Ur ** 2 + 1.0 / (Cp * T)
+    h = Cp * T + 0.5 * (u * u + v * v)
+    r0 = theta * np.abs(p) + rho
+    gq = np.stack([r0, np.abs(u) * r0 + rho * np.abs(u), np.abs(v) * r0 + rho * np.abs(v),
+                   h * r0 + np.abs(p) + rho * (u * u + v * v) + rho * Cp * T])
+    lam = np.abs(u) + np.abs(v) + vg + c
+    terms = np.abs(f) + np.abs(g) + vg * np.abs(qc) + lam * gq
+    gm = np.max(np.sqrt(np.maximum(geo["xix"] ** 2 + geo["xiy"] ** 2, geo["etx"] ** 2 + geo["ety"] ** 2)))
+    n = prm.order + 1
+    x, w = np.polynomial.legendre.leggauss(n)
+    V = np.polynomial.legendre.legvander(x, n - 1)
+    Dm = np.polynomial.legendre.legvander(x, n - 1)
+    dV = np.stack([np.polynomial.legendre.legval(x, np.polynomial.legendre.legder(np.eye(n)[k]))
+                   if n > 1 else np.zeros(n) for k in range(n)], axis=1)
+    D = dV @ np.linalg.inv(V)
+    lamL = np.polynomial.legendre.legvander(np.array([-1.0]), n - 1)[0] @ np.linalg.inv(Dm)
+    op = np.max(np.abs(D).sum(axis=1)) + 2.0 * np.max(np.abs(lamL / w))
+    return np.max(terms, axis=(1, 2)) * gm * op
+
+
+def row_errors(a, b):
+    """Per-row max abs difference of two [4][E][Np] arrays."""
+    return np.max(np.abs(np.asarray(a) - np.asarray(b)).reshape(4, -1), axis=1)
+
+
+def normwise_rel(a, b):
+    """Per-row ||a - b|| / ||b||."""
+    a = np.asarray(a).reshape(4, -1)
+    b = np.asarray(b).reshape(4, -1)
+    return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+
+
+def small_cases():
+    """Small meshes of every kind, sized so several workgroups and a ragged tail occur."""
+    out = []
+    c1 = I.config_c1(nx=8)
+    out.append(("c1_euler_p2_8x8", c1.prm, c1.mesh, c1.q, 0.0))
+    for p in (1, 2, 3, 4):
+        mesh = I.Mesh(7, 5, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
+        q = I.taylor_green(mesh, prm)
+        out.append((f"ns_curved_p{p}_7x5", prm, mesh, q, 0.0))
+    for p in (2, 3):
+        mesh = I.Mesh(6, 9, p, (0.0, 2.0, 0.0, 2.0), I.map_deforming(0.05), moving=True)
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.01, reynolds=100.0, viscous=True,
+                       moving=True, kappa=1.0)
+        q = I.uniform_flow(mesh, prm)
+        rng = np.random.default_rng(3)
+        du, dv = I.random_solenoidal_velocity(mesh, rng, rms=1e-3)
+        q[1] += du
+        q[2] += dv
+        out.append((f"ns_deforming_p{p}_6x9", prm, mesh, q, 0.13))
+    mesh = I.Mesh(5, 4, 3, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+    prm = I.Params(order=3, n_elem=mesh.E, mach_ref=0.3, reynolds=50.0, viscous=True, kappa=1.0)
+    out.append(("ns_curved_p3_ma0.3", prm, mesh, I.taylor_green(mesh, prm), 0.0))
+    for p in (1, 2, 3, 4):
+        # randomised states: O(1) jumps between elements and temperature variation, so every
+        # term (dissipation, BR2, heat flux) is exercised and R is as large as its terms
+        mov = p % 2 == 0
+        mapping = I.map_deforming(0.05, np.pi) if mov else I.map_curved(0.1)
+        mesh = I.Mesh(5, 6, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), mapping, moving=mov)
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.2, reynolds=50.0, viscous=True, moving=mov,
+                       kappa=1.0)
+        rng = np.random.default_rng(40 + p)
+        q = I.uniform_flow(mesh, prm)
+        q[0] *= 1 + 0.05 * rng.standard_normal(q[0].shape)
+        q[1] += 0.3 * rng.standard_normal(q[1].shape)
+        q[2] += 0.3 * rng.standard_normal(q[2].shape)
+        q[3] *= 1 + 0.03 * rng.standard_normal(q[3].shape)
+        out.append((f"ns_random_p{p}", prm, mesh, q, 0.21 if mov else 0.0))
+    mesh = I.Mesh(5, 6, 2, (0.0, 10.0, 0.0, 10.0), I.map_vortex_motion(0.5, 1.0, 0.1, 0.1), moving=True)
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.1, moving=True, kappa=0.0)
+    out.append(("euler_moving_p2", prm, mesh, I.isentropic_vortex(mesh, prm, xy=mesh.solution_points(0.1)), 0.1))
+    return out

@@ -1,0 +1,106 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry point that
+include/lmfr.h declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1903_06304_amd import lmfr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lmfr.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fr_[a-z0-9_]+)\s*\(", src)))
+
+
+def _lib():
+    if not os.path.exists(lmfr.LIB_PATH):
+        pytest.skip("liblmfr.so not built")
+    return lmfr.load_library()
+
+
+def test_header_declares_expected_entry_points():
+    decl = _declared()
+    for name in ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp",
+                 "fr_block_jacobi_factor", "fr_block_jacobi_apply", "fr_bdf2_step", "fr_last_error",
+                 "fr_destroy"]:
+        assert name in decl
+    assert sorted(lmfr.EXPORTS) == decl
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _params(order=2, E=4):
+    return lmfr.fr_params(order, order, E, 1, 0, 1.4, 0.1, 100.0, 0.72, 1.0, 1.0, 0.1)
+
+
+def _table(nx=2, ny=2):
+    from paper_1903_06304_amd import inputs as I
+    m = I.Mesh(nx, ny, 1)
+    return m.connectivity()
+
+
+def _create(prm, nbr, nbf):
+    L = _lib()
+    h = ctypes.c_void_p()
+    st = L.fr_create(ctypes.byref(prm), nbr.ctypes.data_as(ctypes.c_void_p),
+                     nbf.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h))
+    return st, h
+
+
+def test_create_rejects_unsupported_order():
+    nbr, nbf, _ = _table()
+    st, h = _create(_params(order=5), nbr, nbf)
+    assert st == lmfr.FR_EUNSUPPORTED and not h.value
+    assert b"order" in _lib().fr_last_error()
+    st, _ = _create(_params(order=0), nbr, nbf)
+    assert st == lmfr.FR_EUNSUPPORTED
+
+
+def test_create_rejects_bad_tables_and_parameters():
+    nbr, nbf, _ = _table()
+    bad = nbr.copy(); bad[0, 0] = 99
+    st, _ = _create(_params(), bad, nbf)
+    assert st == lmfr.FR_EINVAL
+    nbr3, nbf3, _ = _table(3, 3)
+    asym = nbr3.copy(); asym[0, 1] = asym[0, 0]
+    st, _ = _create(_params(E=9), asym, nbf3)
+    assert st == lmfr.FR_EINVAL
+    prm = _params(); prm.mach_ref = -1.0
+    st, _ = _create(prm, nbr, nbf)
+    assert st == lmfr.FR_EINVAL
+    prm = _params(); prm.n_elem = 0
+    st, _ = _create(prm, nbr, nbf)
+    assert st == lmfr.FR_EINVAL
+
+
+def test_null_arguments_rejected():
+    L = _lib()
+    assert L.fr_create(None, None, None, None, None) == lmfr.FR_EINVAL
+    assert L.fr_residual(None, None, None, None) == lmfr.FR_EINVAL
+    assert L.fr_jvp(None, None, None, None, None, None) == lmfr.FR_EINVAL
+    assert L.fr_vjp(None, None, None, None, None) == lmfr.FR_EINVAL
+    assert L.fr_bdf2_step(None, None, None, None, None, None) == lmfr.FR_EINVAL
+    assert L.fr_block_jacobi_apply(None, None, None, None) == lmfr.FR_EINVAL
+    L.fr_destroy(None)
+
+
+def test_binding_refuses_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("device present")
+    from paper_1903_06304_amd import inputs as I
+    c = I.config_c1(nx=2)
+    nbr, nbf, flip = c.connectivity()
+    with pytest.raises(RuntimeError):
+        lmfr.Context(c.prm, nbr, nbf, flip)

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Bars (written here, derived in the design notes):
+  * R: per row, max |R_gpu - R_oracle| <= 1e-12 * S_c (S_c the scale of the summed terms);
+  * JVP / BDF operator: per-row normwise relative error <= 1e-12;
+  * element blocks: max abs error <= 1e-12 * max |block|;
+  * block apply: FP64 1e-10 relative; FP32 / BF16 within their storage precision;
+  * BDF2 step (FP64 blocks): converged states agree to 1e-8 relative per variable.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.oracle import Oracle  # noqa: E402
+from paper_1903_06304_amd import inputs as I  # noqa: E402
+
+from helpers import flux_scale, normwise_rel, row_errors, small_cases  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _lmfr():
+    from paper_1903_06304_amd import lmfr
+    return lmfr
+
+
+def _pair(prm, mesh, t=0.0):
+    lmfr = _lmfr()
+    xg, vg = mesh.nodes(t)
+    o = Oracle(prm, mesh, xg, vg)
+    nbr, nbf, flip = mesh.connectivity()
+    g = lmfr.Context(prm, nbr, nbf, flip)
+    g.set_geometry(xg, vg)
+    return o, g
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_residual_parity(case):
+    name, prm, mesh, q, t = case
+    print(f"[parity] residual {name} E={mesh.E}", flush=True)
+    o, g = _pair(prm, mesh, t)
+    R = g.residual(_dev(q)).cpu().numpy()
+    Ro = o.residual(q)
+    S = flux_scale(o.geometry(), prm, q)
+    err = row_errors(R, Ro)
+    print("  err/S", err / S, " plain rel", normwise_rel(R, Ro), flush=True)
+    assert np.all(err <= 1e-12 * S), (name, err / S)
+    if "random" in name:
+        # R is as large as its terms here, so a plain relative bar is meaningful
+        assert np.all(normwise_rel(R, Ro) <= 1e-12), normwise_rel(R, Ro)
+
+
+def test_residual_parity_c2_full():
+    c = I.config_c2()
+    print(f"[parity] residual C2 full E={c.mesh.E}", flush=True)
+    o, g = _pair(c.prm, c.mesh)
+    R = g.residual(_dev(c.q)).cpu().numpy()
+    Ro = o.residual(c.q)
+    S = flux_scale(o.geometry(), c.prm, c.q)
+    err = row_errors(R, Ro)
+    assert np.all(err <= 1e-12 * S), err / S
+    print("  plain rel", normwise_rel(R, Ro), flush=True)
+
+
+def test_residual_deterministic_and_free_stream():
+    c = I.config_c3(nx=16, perturbed=False)
+    o, g = _pair(c.prm, c.mesh, 0.07)
+    q = _dev(c.q)
+    R1 = g.residual(q)
+    R2 = g.residual(q)
+    assert torch.equal(R1, R2)
+    S = flux_scale(o.geometry(), c.prm, c.q)
+    assert np.all(np.max(np.abs(R1.cpu().numpy()).reshape(4, -1), axis=1) <= 1e-13 * S)
+
+
+def _offset_tg(c):
+    # Taylor-Green's odd symmetry puts averaged normal velocities exactly at the kink of
+    # |lambda|max; derivative parity uses a state moved off it.
+    q = c.q.copy()
+    q[1] += 0.05
+    q[2] -= 0.03
+    return q
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_jvp_parity(case):
+    name, prm, mesh, q, t = case
+    print(f"[parity] jvp {name}", flush=True)
+    if "curved" in name:
+        q = q.copy(); q[1] += 0.05; q[2] -= 0.03
+    o, g = _pair(prm, mesh, t)
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(q.shape)
+    Jv, R = g.jvp(_dev(q), _dev(v), want_residual=True)
+    Jo = o.jvp(q, v)
+    assert np.all(normwise_rel(Jv.cpu().numpy(), Jo) <= 1e-12), normwise_rel(Jv.cpu().numpy(), Jo)
+    S = flux_scale(o.geometry(), prm, q)
+    assert np.all(row_errors(R.cpu().numpy(), o.residual(q)) <= 1e-12 * S)
+
+
+def test_jvp_parity_c2_full():
+    c = I.config_c2()
+    q = _offset_tg(c)
+    o, g = _pair(c.prm, c.mesh)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(q.shape)
+    Jv = g.jvp(_dev(q), _dev(v)).cpu().numpy()
+    Jo = o.jvp(q, v)
+    err = normwise_rel(Jv, Jo)
+    print("[parity] jvp C2 full", err, flush=True)
+    assert np.all(err <= 1e-12), err
+
+
+def test_bdf_operator_parity():
+    c = I.config_c3(nx=4, p=2)
+    o, g = _pair(c.prm, c.mesh, 0.05)
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal(c.q.shape)
+    ct, idt = 150.0, 0.37
+    Av = g.bdf_operator(_dev(c.q), _dev(v), ct, idt).cpu().numpy()
+    # oracle: time terms from its blocks' diagonal point matrices, J v by complex step
+    B0 = o.blocks(c.q, 0.0, 0.0)
+    Bt = o.blocks(c.q, ct, idt)
+    E, Np = o.E, o.Np
+    ref = -o.jvp(c.q, v)
+    for e in range(E):
+        T = Bt[e] - B0[e]
+        ve = v[:, e, :].reshape(-1)
+        ref[:, e, :] += (T @ ve).reshape(4, Np)
+    err = normwise_rel(Av, ref)
+    assert np.all(err <= 1e-12), err
+
+
+@pytest.mark.parametrize("nx,ny,p,kind", [(3, 3, 2, "curved"), (1, 3, 1, "curved"), (2, 3, 2, "deforming"),
+                                          (4, 3, 3, "curved"), (3, 2, 4, "curved")])
+def test_blocks_parity(nx, ny, p, kind):
+    print(f"[parity] blocks {nx}x{ny} p={p} {kind}", flush=True)
+    if kind == "curved":
+        mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
+        q = I.taylor_green(mesh, prm); q[1] += 0.05; q[2] -= 0.03
+        t = 0.0
+    else:
+        mesh = I.Mesh(nx, ny, p, (0.0, 2.0, 0.0, 2.0), I.map_deforming(0.05), moving=True)
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, moving=True,
+                       kappa=1.0)
+        q = I.uniform_flow(mesh, prm)
+        rng = np.random.default_rng(5)
+        du, dv = I.random_solenoidal_velocity(mesh, rng, rms=0.2)
+        q[1] += du; q[2] += dv
+        t = 0.1
+    o, g = _pair(prm, mesh, t)
+    g.set_option("keep_blocks", 1)
+    ct, idt = 150.0, 1e-3
+    g.block_jacobi_factor(_dev(q), ct, idt, "fp64")
+    B = g.get_blocks().cpu().numpy()
+    Bo = o.blocks(q, ct, idt)
+    err = np.max(np.abs(B - Bo)) / np.max(np.abs(Bo))
+    assert err <= 1e-12, err
+    # apply in each precision vs a dense solve with the oracle's blocks
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(q.shape)
+    E, Np = mesh.E, (p + 1) ** 2
+    zref = np.zeros_like(r)
+    for e in range(E):
+        zref[:, e, :] = np.linalg.solve(Bo[e], r[:, e, :].reshape(-1)).reshape(4, Np)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-3), ("bf16", 5e-1)):
+        g.block_jacobi_factor(_dev(q), ct, idt, prec)
+        z = g.block_jacobi_apply(_dev(r)).cpu().numpy()
+        rel = np.linalg.norm(z - zref) / np.linalg.norm(zref)
+        print(f"  apply {prec}: rel {rel:.2e}", flush=True)
+        assert rel <= tol, (prec, rel)
+
+
+def test_bdf2_step_parity_c1():
+    c = I.config_c1(nx=4)
+    o, g = _pair(c.prm, c.mesh)
+    kw = dict(tol_pseudo=1e-10, tol_res=1e-9, krylov=20, max_lin_it=200, max_newton=20)
+    qo, sto = o.bdf2_step(c.q, c.q_nm1, c.dt, **kw)
+    qg = _dev(c.q)
+    st = g.bdf2_step(qg, _dev(c.q_nm1), c.dt, **kw)
+    torch.cuda.synchronize()
+    print("[parity] bdf2 c1", st, sto, flush=True)
+    assert st["converged"] == 1 and sto["converged"] == 1
+    qg = qg.cpu().numpy()
+    scale = np.max(np.abs(qo), axis=(1, 2))
+    assert np.all(row_errors(qg, qo) <= 1e-8 * scale), row_errors(qg, qo) / scale
+
+
+def test_bdf2_step_deforming_free_stream():
+    c = I.config_c3(nx=6, p=2, perturbed=False)
+    o, g = _pair(c.prm, c.mesh, 0.05)
+    q = _dev(c.q)
+    st = g.bdf2_step(q, q.clone(), 0.01, krylov=10, tol_abs=1e-9 * c.prm.gas_constant)
+    torch.cuda.synchronize()
+    assert st["converged"] == 1
+    d = (q.cpu().numpy() - c.q) / np.max(np.abs(c.q), axis=(1, 2))[:, None, None]
+    assert np.max(np.abs(d)) < 1e-13
