@@ -1,0 +1,211 @@
+"""Benchmark of the FR/CPR hot path on one MI355X.
+
+Workload: 2-D Navier-Stokes, p = 3, 256 x 256 affine periodic quads on [0, 2 pi]^2,
+Ma = 0.05, Re = 1000, seeded smooth random fields (4.19M DOF, FP64) -- the
+configuration on which the mixed- vs plain-precision BDF2 comparison is defined.
+
+One timed step = one pass of the hot path over that input:
+  * NR residual evaluations (rotating through buffer sets larger than the 256 MB
+    Infinity Cache, so inputs and outputs stream from HBM),
+  * NJ JVPs and NV VJPs,
+  * one BDF2 dual-time step (Newton to Res_m/Res_0 <= 1e-8, GMRES(30), tol_res 1e-6)
+    with FP64 element blocks ("plain"), and the same step with FP32 and BF16 blocks.
+`value` = DOF-residual evaluations per second of the residual (the metric's first
+half); the BDF2 step times (second half) are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--order", type=int, default=3)
+    ap.add_argument("--nr", type=int, default=40, help="residual evaluations per step")
+    ap.add_argument("--nj", type=int, default=10, help="JVP evaluations per step")
+    ap.add_argument("--dt", type=float, default=1e-3, help="physical time step of the BDF2 step")
+    ap.add_argument("--max-lin-it", type=int, default=200)
+    ap.add_argument("--precs", default="fp64,fp32,bf16")
+    ap.add_argument("--no-bdf2", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20, help="oracle residual evaluations timed")
+    return ap.parse_args()
+
+
+def algorithmic_bytes_residual(E, p, moving=False):
+    """Minimal FP64 words of one residual: q in, R out, 5 Np metrics, 8 n face words
+    (+2 Np, +4 n grid-velocity words on moving meshes) per element."""
+    n = p + 1
+    Np = n * n
+    words = 13 * Np + 8 * n + ((2 * Np + 4 * n) if moving else 0)
+    return 8.0 * words * E
+
+
+def algorithmic_bytes_jvp(E, p):
+    n = p + 1
+    Np = n * n
+    return 8.0 * (17 * Np + 8 * n) * E
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in the "
+                                   "design notes but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1903_06304_amd import inputs as I
+    from paper_1903_06304_amd import lmfr
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    case = I.config_c4(nx=args.nx, p=args.order)
+    mesh, prm = case.mesh, case.prm
+    E, Np = mesh.E, mesh.Np
+    dof = 4 * E * Np
+    nbr, nbf, flip = mesh.connectivity()
+    xg, vg = mesh.nodes()
+    ctx = lmfr.Context(prm, nbr, nbf, flip)
+    ctx.set_geometry(xg, vg)
+    q0 = torch.tensor(case.q, device=dev)
+    # rotating input/output sets: > 512 MB in total so the residual streams from HBM
+    state_bytes = q0.numel() * 8
+    nsets = max(2, int(np.ceil(512e6 / (2 * state_bytes))))
+    rng = np.random.default_rng(11)
+    qs = [q0 * (1.0 + 1e-3 * torch.tensor(rng.standard_normal(q0.shape), device=dev)) for _ in range(nsets)]
+    Rs = [torch.empty_like(q0) for _ in range(nsets)]
+    vdir = torch.tensor(rng.standard_normal(q0.shape), device=dev)
+    Jv = torch.empty_like(q0)
+    stream = torch.cuda.current_stream()
+
+    # BDF2 start: one BDF1 step gives (q^n, q^{n-1}); every timed step restarts from it
+    bdf_kw = dict(tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=args.max_lin_it, max_newton=20,
+                  jac_lag=2, inv_dtau=1e-20)
+    q_nm1 = q0.clone()
+    q_n = q0.clone()
+    if not args.no_bdf2:
+        st0 = ctx.bdf2_step(q_n, None, args.dt, **bdf_kw)
+        torch.cuda.synchronize()
+        print(f"[bench] BDF1 start step {st0}", file=sys.stderr, flush=True)
+
+    precs = args.precs.split(",")
+
+    def one_step(record):
+        ev = {}
+        t0 = torch.cuda.Event(enable_timing=True); t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for k in range(args.nr):
+            i = k % nsets
+            ctx.residual(qs[i], out=Rs[i])
+        t1.record(stream)
+        ev["res"] = (t0, t1)
+        t2 = torch.cuda.Event(enable_timing=True); t3 = torch.cuda.Event(enable_timing=True)
+        t2.record(stream)
+        for k in range(args.nj):
+            Jv.copy_(ctx.jvp(qs[k % nsets], vdir))
+        t3.record(stream)
+        ev["jvp"] = (t2, t3)
+        stats = {}
+        if not args.no_bdf2:
+            for pr in precs:
+                qw = q_n.clone()
+                a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                st = ctx.bdf2_step(qw, q_nm1, args.dt, prec=pr, **bdf_kw)
+                b.record(stream)
+                ev["bdf2_" + pr] = (a, b)
+                stats[pr] = (st, qw)
+        if record is not None:
+            record.append((ev, stats))
+
+    for w in range(args.warmup):
+        one_step(None)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup step {w} done", file=sys.stderr, flush=True)
+    records = []
+    t_start = time.perf_counter()
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        one_step(records)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+
+    def mean_ms(key):
+        return float(np.mean([r[0][key][0].elapsed_time(r[0][key][1]) for r in records]))
+
+    res_ms = mean_ms("res") / args.nr          # per residual evaluation
+    jvp_ms = mean_ms("jvp") / args.nj
+    value = dof / (res_ms * 1e-3)
+    alg_b = algorithmic_bytes_residual(E, args.order)
+    achieved = alg_b / (res_ms * 1e-3) / 1e9
+    out = {
+        "metric": "DOF-residual evals/s (p=3 FP64) + wall time per BDF2 step to 1e-8, mixed vs plain",
+        "value": value,
+        "unit": "DOF-residual evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded smooth random fields)",
+        "config": {"workload": f"NS p={args.order} {args.nx}x{args.nx} affine periodic [0,2pi]^2, Ma=0.05, "
+                               f"Re=1000, seeded random fields", "dof": dof, "elements": E,
+                   "residuals_per_step": args.nr, "jvps_per_step": args.nj, "buffer_sets": nsets},
+        "residual_ms": res_ms,
+        "jvp_ms": jvp_ms,
+        "jvp_dof_per_s": dof / (jvp_ms * 1e-3),
+        "roofline": {"bound": "hbm", "kernel": "fr_residual (k_traces + k_residual)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": alg_b},
+    }
+    if not args.no_bdf2:
+        bd = {}
+        for pr in precs:
+            st, qw = records[-1][1][pr]
+            bd[pr] = {"ms": mean_ms("bdf2_" + pr), "newton_its": st["newton_its"], "gmres_its": st["gmres_its"],
+                      "converged": st["converged"], "res_ratio": st["res_final"] / max(st["res0"], 1e-300)}
+        ref = records[-1][1]["fp64"][1]
+        for pr in [x for x in precs if x != "fp64"]:
+            d = (records[-1][1][pr][1] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
+            bd[pr]["max_rel_diff_vs_fp64"] = float(d.max())
+            bd[pr]["speedup_vs_fp64"] = bd["fp64"]["ms"] / bd[pr]["ms"]
+        out["bdf2_step"] = bd
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(case, nsample):
+    """The serial FP64 oracle timed on this host on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle.oracle import Oracle
+    o = Oracle(case.prm, case.mesh)
+    o.residual(case.q)
+    t = time.perf_counter()
+    for _ in range(nsample):
+        o.residual(case.q)
+    dt = time.perf_counter() - t
+    dof = 4 * case.mesh.E * case.mesh.Np
+    return {"value": dof * nsample / dt, "unit": "DOF-residual evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nsample} serial residual evaluations of the full workload ({dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

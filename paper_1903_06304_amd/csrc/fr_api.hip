@@ -376,7 +376,7 @@ double* wv(fr_ctx c, int i) { return c->d_w + (size_t)i * c->N(); }
 
 // 2-norm of the first N entries of x (synchronises)
 fr_status norm2(fr_ctx c, size_t N, const double* x, double& out, hipStream_t s) {
-    FR_TRY(la_dots(c, N, x, 1, x, c->d_scal + SC_NRM, s));
+    FR_TRY(la_krylov(c, N, x, 0, nullptr, 0, x, nullptr, true, c->d_scal + SC_NRM, s));
     FR_HIP(hipMemcpyAsync(c->h_scal, c->d_scal + SC_NRM, sizeof(double), hipMemcpyDeviceToHost, s));
     FR_HIP(hipStreamSynchronize(s));
     out = std::sqrt(c->h_scal[0]);
@@ -417,11 +417,9 @@ fr_status gmres(fr_ctx c, const double* q, const double* b, double* x, int m, do
             FR_TRY(launch_block_apply(c, vj, z, s));
             FR_TRY(fr_bdf_operator(c, q, z, ct, idt, w, s));
             // classical Gram-Schmidt, applied twice
-            FR_TRY(la_dots(c, N, V, j + 1, w, d_h1, s));
-            FR_TRY(la_update(c, w, V, j + 1, d_h1, s));
-            FR_TRY(la_dots(c, N, V, j + 1, w, d_h2, s));
-            FR_TRY(la_update(c, w, V, j + 1, d_h2, s));
-            FR_TRY(la_dots(c, N, w, 1, w, d_nrm, s));
+            FR_TRY(la_krylov(c, N, V, 0, nullptr, j + 1, w, nullptr, false, d_h1, s));     // h1 = V^T w
+            FR_TRY(la_krylov(c, N, V, j + 1, d_h1, j + 1, w, w, false, d_h2, s));        // w -= V h1; h2 = V^T w
+            FR_TRY(la_krylov(c, N, V, j + 1, d_h2, 0, w, w, true, d_nrm, s));            // w -= V h2; |w|^2
             FR_HIP(hipMemcpyAsync(c->h_scal, d_h1, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
             FR_HIP(hipStreamSynchronize(s));
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->h_scal[i] + c->h_scal[64 + i];

@@ -105,7 +105,9 @@ fr_status launch_block_invert(fr_ctx c, int prec, hipStream_t s);
 fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s);
 // dots of the first N entries; V_i = V + i * c->N()
 fr_status la_dots(fr_ctx c, size_t N, const double* V, int nv, const double* w, double* d_out, hipStream_t s);
-fr_status la_update(fr_ctx c, double* w, const double* V, int nv, const double* d_coef, hipStream_t s);
+// w_out = w_in - sum_{i<nv_upd} coef_i V_i; d_out[i] = V_i . w_out (i < nv_dot); d_out[nv_dot] = |w_out|^2
+fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
+                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s);
 fr_status la_axpy(size_t N, double a, const double* x, double* y, hipStream_t s);
 fr_status la_scale_copy(size_t N, double a, const double* x, double* y, hipStream_t s);
 fr_status la_norm2(size_t N, const double* x, double* d_out, double* scratch, hipStream_t s);

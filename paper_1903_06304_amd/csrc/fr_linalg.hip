@@ -139,47 +139,67 @@ __global__ void __launch_bounds__(256) k_block_apply(int E, int Np, const Tin* _
     z[(row / Np) * EN + (size_t)e * Np + (row % Np)] = acc;
 }
 
-// ------------------------------------------------------------------ reductions
-// partial[b][i] = sum over this block's stripe of V_i . w   (i < nv)
-__global__ void __launch_bounds__(RED_THREADS) k_dots_partial(size_t N, const double* __restrict__ V, size_t ldv, int nv,
-                                                              const double* __restrict__ w, double* __restrict__ partial) {
-    __shared__ double red[RED_THREADS / 64][MAXV];
-    double acc[MAXV];
-    for (int i = 0; i < nv; ++i) acc[i] = 0.0;
+// ------------------------------------------------------------------ Krylov reductions
+// One streaming pass over the basis V (vectors V_i = V + i*ldv):
+//   w_new = w_in - sum_{i < nv_upd} coef[i] V_i           (written to w_out when nv_upd > 0)
+//   partial[b][i] = sum over this block's stripe of V_i . w_new   (i < nv_dot)
+//   partial[b][nv_dot] = stripe sum of w_new . w_new               (want_norm)
+// NVM bounds nv_upd and nv_dot so the accumulators stay in registers.
+template <int NVM>
+__global__ void __launch_bounds__(RED_THREADS) k_krylov(size_t N, const double* __restrict__ V, size_t ldv, int nv_upd,
+                                                        const double* __restrict__ coef, int nv_dot,
+                                                        const double* w_in, double* w_out, int want_norm,
+                                                        double* __restrict__ partial) {
+    __shared__ double red[RED_THREADS / 64][NVM + 1];
+    double cf[NVM], acc[NVM];
+    double nacc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NVM; ++i) {
+        cf[i] = (i < nv_upd) ? coef[i] : 0.0;
+        acc[i] = 0.0;
+    }
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        const double wt = w[t];
-        for (int i = 0; i < nv; ++i) acc[i] += V[i * ldv + t] * wt;
+        double wt = w_in[t];
+#pragma unroll
+        for (int i = 0; i < NVM; ++i)
+            if (i < nv_upd) wt -= cf[i] * V[i * ldv + t];
+        if (nv_upd > 0) w_out[t] = wt;
+#pragma unroll
+        for (int i = 0; i < NVM; ++i)
+            if (i < nv_dot) acc[i] += V[i * ldv + t] * wt;
+        nacc += wt * wt;
     }
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-    for (int i = 0; i < nv; ++i) {
-        double s = acc[i];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) red[wid][i] = s;
+#pragma unroll
+    for (int i = 0; i < NVM + 1; ++i) {
+        const bool live = (i < nv_dot) || (i == nv_dot && want_norm);
+        if (!live) continue;
+        double v = (i < nv_dot) ? acc[i] : nacc;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[wid][i] = v;
     }
     __syncthreads();
-    if (threadIdx.x < nv) {
-        double s = 0.0;
-        for (int k = 0; k < RED_THREADS / 64; ++k) s += red[k][threadIdx.x];
-        partial[(size_t)blockIdx.x * MAXV + threadIdx.x] = s;
+    const int nout = nv_dot + (want_norm ? 1 : 0);
+    if ((int)threadIdx.x < nout) {
+        double v = 0.0;
+        for (int k = 0; k < RED_THREADS / 64; ++k) v += red[k][threadIdx.x];
+        partial[(size_t)blockIdx.x * MAXV + threadIdx.x] = v;
     }
 }
 
-__global__ void k_dots_final(int nblocks, int nv, const double* __restrict__ partial, double* __restrict__ out) {
-    const int i = threadIdx.x;
-    if (i >= nv) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * MAXV + i];
-    out[i] = s;
-}
-
-// w -= sum_i coef[i] V_i
-__global__ void k_update(size_t N, double* __restrict__ w, const double* __restrict__ V, size_t ldv, int nv,
-                         const double* __restrict__ coef) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        double s = w[t];
-        for (int i = 0; i < nv; ++i) s -= coef[i] * V[i * ldv + t];
-        w[t] = s;
+// out[i] = sum over blocks of partial[b][i]; one workgroup per output, fixed-order tree
+__global__ void __launch_bounds__(256) k_final(int nblocks, const double* __restrict__ partial, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * MAXV + i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // out = sum_i y[i] V_i
@@ -297,21 +317,32 @@ fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s
     return FR_OK;
 }
 
-fr_status la_dots(fr_ctx c, size_t N, const double* V, int nv, const double* w, double* d_out, hipStream_t s) {
-    if (nv > MAXV) { fr_set_error("too many vectors in multi-dot"); return FR_EINVAL; }
+fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
+                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s) {
+    const int nmax = nv_upd > nv_dot ? nv_upd : nv_dot;
+    if (nmax > MAXV - 1) { fr_set_error("too many Krylov vectors"); return FR_EINVAL; }
     double* partial = c->d_scal + SC_PART;
-    hipLaunchKernelGGL(k_dots_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, N, V, c->N(), nv, w, partial);
+    const size_t ldv = c->N();
+    const int wn = want_norm ? 1 : 0;
+#define FR_KRY(NVM) hipLaunchKernelGGL(k_krylov<NVM>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, N, V, ldv, nv_upd, \
+                                       d_coef, nv_dot, w_in, w_out, wn, partial)
+    if (nmax <= 1) FR_KRY(1);
+    else if (nmax <= 8) FR_KRY(8);
+    else if (nmax <= 16) FR_KRY(16);
+    else if (nmax <= 32) FR_KRY(32);
+    else FR_KRY(63);
+#undef FR_KRY
     FR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(MAXV), 0, s, RED_BLOCKS, nv, partial, d_out);
-    FR_HIP(hipGetLastError());
+    const int nout = nv_dot + wn;
+    if (nout > 0) {
+        hipLaunchKernelGGL(k_final, dim3(nout), dim3(256), 0, s, RED_BLOCKS, partial, d_out);
+        FR_HIP(hipGetLastError());
+    }
     return FR_OK;
 }
 
-fr_status la_update(fr_ctx c, double* w, const double* V, int nv, const double* d_coef, hipStream_t s) {
-    const size_t N = c->N();
-    hipLaunchKernelGGL(k_update, dim3(grid_for(N, 256)), dim3(256), 0, s, N, w, V, N, nv, d_coef);
-    FR_HIP(hipGetLastError());
-    return FR_OK;
+fr_status la_dots(fr_ctx c, size_t N, const double* V, int nv, const double* w, double* d_out, hipStream_t s) {
+    return la_krylov(c, N, V, 0, nullptr, nv, w, nullptr, false, d_out, s);
 }
 
 fr_status la_combine(size_t N, const double* V, int nv, const double* d_y, double* out, hipStream_t s) {
