@@ -204,3 +204,43 @@ def test_bdf2_step_deforming_free_stream():
     assert st["converged"] == 1
     d = (q.cpu().numpy() - c.q) / np.max(np.abs(c.q), axis=(1, 2))[:, None, None]
     assert np.max(np.abs(d)) < 1e-13
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_vjp_parity(case):
+    """J^T w against the oracle's per-DOF complex-step adjoint, plus the adjoint identity."""
+    name, prm, mesh, q, t = case
+    print(f"[parity] vjp {name}", flush=True)
+    if "curved" in name:
+        q = q.copy(); q[1] += 0.05; q[2] -= 0.03
+    o, g = _pair(prm, mesh, t)
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal(q.shape)
+    v = rng.standard_normal(q.shape)
+    JTw = g.vjp(_dev(q), _dev(w)).cpu().numpy()
+    ref = o.vjp_dofs(q, w, np.arange(q.size)).reshape(q.shape)
+    err = normwise_rel(JTw, ref)
+    assert np.all(err <= 1e-12), err
+    Jv = g.jvp(_dev(q), _dev(v)).cpu().numpy()
+    lhs, rhs = np.dot(w.ravel(), Jv.ravel()), np.dot(JTw.ravel(), v.ravel())
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(w.ravel() * Jv.ravel()).sum()
+
+
+def test_vjp_parity_c2_sampled():
+    c = I.config_c2()
+    q = _offset_tg(c)
+    o, g = _pair(c.prm, c.mesh)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal(q.shape)
+    JTw = g.vjp(_dev(q), _dev(w)).cpu().numpy().ravel()
+    dofs = rng.choice(q.size, 400, replace=False)
+    ref = o.vjp_dofs(q, w, dofs)
+    err = np.max(np.abs(JTw[dofs] - ref)) / np.max(np.abs(ref))
+    print("[parity] vjp C2 sampled", err, flush=True)
+    assert err <= 1e-12, err
+    # autograd: backward of the FRResidual function is the VJP
+    from paper_1903_06304_amd import lmfr
+    qt = _dev(q).requires_grad_(True)
+    R = lmfr.residual(qt, g)
+    R.backward(_dev(w))
+    assert torch.equal(qt.grad.reshape(-1).cpu(), torch.tensor(JTw))
