@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--dt", type=float, default=1e-3, help="physical time step of the BDF2 step")
     ap.add_argument("--max-lin-it", type=int, default=200)
     ap.add_argument("--precs", default="fp64,fp32,bf16")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-bdf2", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20, help="oracle residual evaluations timed")
@@ -132,6 +134,14 @@ def main():
         if record is not None:
             record.append((ev, stats))
 
+    if args.copy_calib:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     for w in range(args.warmup):
         one_step(None)
         torch.cuda.synchronize()

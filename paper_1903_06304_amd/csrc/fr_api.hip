@@ -167,6 +167,11 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         return FR_EUNSUPPORTED;
     }
     if (prm->n_elem <= 0 || prm->n_elem >= (1 << 27)) return bad("fr_create: n_elem out of range");
+    {
+        // kernels index state arrays with 32-bit offsets: 4 * n_elem * (p+1)^2 < 2^31
+        const long long np1 = prm->order + 1;
+        if (4LL * prm->n_elem * np1 * np1 >= (1LL << 31)) return bad("fr_create: state arrays above 2^31 entries");
+    }
     if (!(prm->gamma > 1.0) || !(prm->mach_ref > 0.0) || !(prm->prandtl > 0.0) || !(prm->mach_inf >= 0.0) ||
         !(prm->kappa >= 0.0))
         return bad("fr_create: invalid physical parameters");
@@ -260,32 +265,26 @@ static fr_status ready(fr_ctx c) {
 extern "C" fr_status fr_residual(fr_ctx c, const double* q, double* R, void* stream) {
     FR_TRY(ready(c));
     if (!q || !R) return bad("fr_residual: null argument");
-    hipStream_t s = (hipStream_t)stream;
-    FR_TRY(launch_traces(c, q, nullptr, c->d_trace, 0, s));
     KArgs a{};
-    a.E = c->E; a.q = q; a.tr = c->d_trace; a.out = R;
-    return launch_residual(c, MODE_R, a, s);
+    a.E = c->E; a.q = q; a.out = R;
+    return launch_residual(c, MODE_R, a, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_jvp(fr_ctx c, const double* q, const double* v, double* Jv, double* R_or_null, void* stream) {
     FR_TRY(ready(c));
     if (!q || !v || !Jv) return bad("fr_jvp: null argument");
-    hipStream_t s = (hipStream_t)stream;
-    FR_TRY(launch_traces(c, q, v, c->d_trace, 1, s));
     KArgs a{};
-    a.E = c->E; a.q = q; a.v = v; a.tr = c->d_trace; a.out = Jv; a.out2 = R_or_null;
-    return launch_residual(c, MODE_JVP, a, s);
+    a.E = c->E; a.q = q; a.v = v; a.out = Jv; a.out2 = R_or_null;
+    return launch_residual(c, MODE_JVP, a, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_bdf_operator(fr_ctx c, const double* q, const double* v, double c_time, double inv_dtau,
                                      double* Av, void* stream) {
     FR_TRY(ready(c));
     if (!q || !v || !Av) return bad("fr_bdf_operator: null argument");
-    hipStream_t s = (hipStream_t)stream;
-    FR_TRY(launch_traces(c, q, v, c->d_trace, 1, s));
     KArgs a{};
-    a.E = c->E; a.q = q; a.v = v; a.tr = c->d_trace; a.out = Av; a.c_time = c_time; a.inv_dtau = inv_dtau;
-    return launch_residual(c, MODE_AOP, a, s);
+    a.E = c->E; a.q = q; a.v = v; a.out = Av; a.c_time = c_time; a.inv_dtau = inv_dtau;
+    return launch_residual(c, MODE_AOP, a, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_vjp(fr_ctx c, const double* q, const double* w, double* JTw, void* stream) {

@@ -27,8 +27,10 @@ struct GeoTab {
 
 // Field indices of the per-solution-point geometry array gsp[NGSP][E][Np]
 enum { G_XIX = 0, G_XIY, G_ETX, G_ETY, G_IJ, G_UG, G_VG, NGSP };
-// Field indices of the per-side geometry array gfp[NGFP][E][4][n]
-enum { F_SX = 0, F_SY, F_JF, F_UG, F_VG, NGFP };
+// Field indices of the per-side geometry array gfp[NGFP][E][4][n]: unit outward normal,
+// signed scale sc = sign * |S| (the element-oriented face vector is sc * n), BR2
+// coefficient cc = (p+1)^2/8 |S| (1/|J|^- + 1/|J|^+), grid velocity at the face point
+enum { F_NX = 0, F_NY, F_SC, F_CC, F_UG, F_VG, NGFP };
 
 struct Geo {
     const double* sp;     // [NGSP][E][Np]

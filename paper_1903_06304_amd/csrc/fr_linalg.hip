@@ -259,12 +259,11 @@ unsigned grid_for(size_t N, int bs) {
 
 // ----------------------------------------------------------------------------- launchers
 fr_status launch_block_assembly(fr_ctx c, const double* q, double c_time, double inv_dtau, hipStream_t s) {
-    // value traces of every element, then one seeded column per launch
-    fr_status st = launch_traces(c, q, nullptr, c->d_trace0, 0, s);
-    if (st != FR_OK) return st;
+    // one seeded column of every element's block per launch
+    fr_status st = FR_OK;
     const int nb = 4 * c->Np;
     KArgs a{};
-    a.E = c->E; a.q = q; a.v = nullptr; a.tr = c->d_trace0; a.out = c->d_blk;
+    a.E = c->E; a.q = q; a.v = nullptr; a.out = c->d_blk;
     a.c_time = c_time; a.inv_dtau = inv_dtau;
     for (int col = 0; col < nb; ++col) {
         a.seed0 = col;

@@ -17,6 +17,8 @@
 #pragma once
 #include "fr_scalar.hpp"
 
+#define FR_DEV __device__ __forceinline__
+
 struct PhysConst {
     double gam, Rg, Cp, inv_gm1, gRg, inv_Cp, inv_Rg;
     double mu_re, kc_re;      // mu/Re, (mu Cp/Pr)/Re
@@ -26,8 +28,8 @@ struct PhysConst {
 
 // q^c = (rho, rho u, rho v, E), E = p/(gamma-1) + rho |v|^2 / 2, rho = p/(R T)
 template <class T>
-FR_HD void fr_cons(const PhysConst& c, const T* q, T* qc) {
-    T rho = q[0] * c.inv_Rg / q[3];
+FR_DEV void fr_cons(const PhysConst& c, const T* q, T* qc) {
+    T rho = q[0] * c.inv_Rg * rcp(q[3]);
     qc[0] = rho;
     qc[1] = rho * q[1];
     qc[2] = rho * q[2];
@@ -37,7 +39,7 @@ FR_HD void fr_cons(const PhysConst& c, const T* q, T* qc) {
 // Total physical flux (f, g) = (f_inv - f_vis, g_inv - g_vis) and q^c at a point.
 // gu, gv, gT: (d/dx, d/dy) of u, v, T.
 template <class T, bool VISC>
-FR_HD void fr_point_flux(const PhysConst& c, const T* q, const T* gu, const T* gv, const T* gT,
+FR_DEV void fr_point_flux(const PhysConst& c, const T* q, const T* gu, const T* gv, const T* gT,
                          T* f, T* g, T* qc) {
     fr_cons(c, q, qc);
     const T& p = q[0]; const T& u = q[1]; const T& v = q[2];
@@ -67,14 +69,14 @@ FR_HD void fr_point_flux(const PhysConst& c, const T* q, const T* gu, const T* g
 
 // eps of the preconditioner from the velocity relative to the grid and the sound speed
 template <class T>
-FR_HD T fr_eps(const PhysConst& c, const T& urel, const T& vrel, const T& cs) {
-    T Ma = ssqrt(urel * urel + vrel * vrel) / cs;
+FR_DEV T fr_eps(const PhysConst& c, const T& urel, const T& vrel, const T& cs) {
+    T Ma = ssqrt(urel * urel + vrel * vrel) * rcp(cs);
     return smin(cst<T>(1.0), smax(cst<T>(c.eps_min), Ma));
 }
 
 // out = (a-row matrix) * dq with a = rho_p (M) or Theta (Gamma); state q.
 template <class T, class V>
-FR_HD void fr_gm_apply(const PhysConst& c, const T& a, const T& rho, const T& rhoT, const T& h,
+FR_DEV void fr_gm_apply(const PhysConst& c, const T& a, const T& rho, const T& rhoT, const T& h,
                        const T* q, const V* dq, V* out) {
     V r0 = a * dq[0] + rhoT * dq[3];
     out[0] = r0;
@@ -85,15 +87,16 @@ FR_HD void fr_gm_apply(const PhysConst& c, const T& a, const T& rho, const T& rh
 
 // Time-term operator at a solution point: out = inv_dtau Gamma(q) x + c_time M(q) x.
 template <class T, class V>
-FR_HD void fr_time_apply(const PhysConst& c, const T* q, double ug, double vg, double inv_dtau,
+FR_DEV void fr_time_apply(const PhysConst& c, const T* q, double ug, double vg, double inv_dtau,
                          double c_time, const V* x, V* out) {
-    T rho = q[0] * c.inv_Rg / q[3];
-    T rhoT = -rho / q[3];
-    T rhop = c.inv_Rg / q[3];
+    T iT = rcp(q[3]);
+    T rho = q[0] * c.inv_Rg * iT;
+    T rhoT = -rho * iT;
+    T rhop = c.inv_Rg * iT;
     T cs = ssqrt(c.gRg * q[3]);
     T eps = fr_eps(c, q[1] - ug, q[2] - vg, cs);
     T Ur = eps * cs;
-    T theta = 1.0 / (Ur * Ur) + c.inv_Cp / q[3];
+    T theta = rcp(Ur * Ur) + c.inv_Cp * iT;
     T h = c.Cp * q[3] + 0.5 * (q[1] * q[1] + q[2] * q[2]);
     V a[4], b[4];
     fr_gm_apply(c, theta, rho, rhoT, h, q, x, a);
@@ -103,7 +106,7 @@ FR_HD void fr_time_apply(const PhysConst& c, const T* q, double ug, double vg, d
 
 // Normal inviscid flux through a moving face: f n_x + g n_y - (v_g . n) q^c
 template <class T>
-FR_HD void fr_normal_flux(const PhysConst& c, const T* q, double nx, double ny, double vgn, T* fn) {
+FR_DEV void fr_normal_flux(const PhysConst& c, const T* q, double nx, double ny, double vgn, T* fn) {
     T qc[4];
     fr_cons(c, q, qc);
     T un = q[1] * nx + q[2] * ny;
@@ -115,31 +118,30 @@ FR_HD void fr_normal_flux(const PhysConst& c, const T* q, double nx, double ny, 
 }
 
 // Common normal flux at one face point, normal n = outward normal of the own ('-') side.
-//   qm, qp : primitive states of the own side and of the neighbour
-//   gm, gp : uncorrected gradient traces (ux, uy, vx, vy, Tx, Ty) of both sides
-//   Smag   : |S| of the face vector; JfL, JfR : |J| of each side at the point
-// Outputs fn (common normal flux for n) and dqh = q^com - q^- for (u, v, T).
-template <class T, bool VISC>
-FR_HD void fr_common_flux(const PhysConst& c, const T* qm, const T* qp, const T* gm, const T* gp,
-                          double nx, double ny, double Smag, double JfL, double JfR,
-                          double ug, double vg, T* fn, T* dqh) {
+// Inviscid part: qm, qp are the primitive states of the own side and of the neighbour;
+// returns fn (preconditioned Rusanov flux for n) and dq = q^+ - q^-.
+template <class T>
+FR_DEV void fr_common_inviscid(const PhysConst& c, const T* qm, const T* qp, double nx, double ny,
+                               double ug, double vg, T* fn, T* dq) {
     const double vgn = ug * nx + vg * ny;
     T fL[4], fR[4];
     fr_normal_flux(c, qm, nx, ny, vgn, fL);
     fr_normal_flux(c, qp, nx, ny, vgn, fR);
-    T qb[4], dq[4];
+    T qb[4];
     for (int r = 0; r < 4; ++r) {
         qb[r] = 0.5 * (qm[r] + qp[r]);
         dq[r] = qp[r] - qm[r];
+        fn[r] = 0.5 * (fL[r] + fR[r]);
     }
-    T rho = qb[0] * c.inv_Rg / qb[3];
+    T iT = rcp(qb[3]);
+    T rho = qb[0] * c.inv_Rg * iT;
     T cs = ssqrt(c.gRg * qb[3]);
     T ur = qb[1] - ug, vr = qb[2] - vg;
     T eps = fr_eps(c, ur, vr, cs);
     T Ur = eps * cs;
     T Ur2 = Ur * Ur;
-    T theta = 1.0 / Ur2 + c.inv_Cp / qb[3];
-    T rhoT = -rho / qb[3];
+    T theta = rcp(Ur2) + c.inv_Cp * iT;
+    T rhoT = -rho * iT;
     T h = c.Cp * qb[3] + 0.5 * (qb[1] * qb[1] + qb[2] * qb[2]);
     T gd[4];
     fr_gm_apply(c, theta, rho, rhoT, h, qb, dq, gd);
@@ -149,27 +151,32 @@ FR_HD void fr_common_flux(const PhysConst& c, const T* qm, const T* qp, const T*
     T cp = ssqrt(alpha * alpha * un * un + Ur2);
     T lam = sabs(unp) + cp;
     T hl = 0.5 * lam;
-    for (int r = 0; r < 4; ++r) fn[r] = 0.5 * (fL[r] + fR[r]) - hl * gd[r];
-    if (VISC) {
-        // grad q^com = 1/2 (g^- + g^+) + 1/4 (cL + cR) (q^+ - q^-) n
-        const double cc = 0.25 * c.br2 * Smag * (1.0 / JfL + 1.0 / JfR);
-        T ux = 0.5 * (gm[0] + gp[0]) + (cc * nx) * dq[1];
-        T uy = 0.5 * (gm[1] + gp[1]) + (cc * ny) * dq[1];
-        T vx = 0.5 * (gm[2] + gp[2]) + (cc * nx) * dq[2];
-        T vy = 0.5 * (gm[3] + gp[3]) + (cc * ny) * dq[2];
-        T Tx = 0.5 * (gm[4] + gp[4]) + (cc * nx) * dq[3];
-        T Ty = 0.5 * (gm[5] + gp[5]) + (cc * ny) * dq[3];
-        T div = ux + vy;
-        T txx = c.mu_re * (2.0 * ux - (2.0 / 3.0) * div);
-        T tyy = c.mu_re * (2.0 * vy - (2.0 / 3.0) * div);
-        T txy = c.mu_re * (uy + vx);
-        T tnx = txx * nx + txy * ny;
-        T tny = txy * nx + tyy * ny;
-        fn[1] = fn[1] - tnx;
-        fn[2] = fn[2] - tny;
-        fn[3] = fn[3] - (qb[1] * tnx + qb[2] * tny + c.kc_re * (Tx * nx + Ty * ny));
-        dqh[0] = 0.5 * dq[1];
-        dqh[1] = 0.5 * dq[2];
-        dqh[2] = 0.5 * dq[3];
-    }
+    for (int r = 0; r < 4; ++r) fn[r] = fn[r] - hl * gd[r];
+}
+
+// Viscous part (subtracted from fn): f_vis(q^com, grad q^com) . n with the BR2 common
+// gradient grad q^com = (g^- + g^+)/2 + cc (q^+ - q^-) n  (cc = (p+1)^2/8 |S| (1/|J|^- + 1/|J|^+),
+// the face-local Radau liftings of both sides evaluated at the face);
+// gm, gp: uncorrected gradient traces (ux, uy, vx, vy, Tx, Ty); qcu, qcv: q^com velocity.
+// Returns dqh = q^com - q^- for (u, v, T).
+template <class T>
+FR_DEV void fr_common_viscous(const PhysConst& c, const T* dq, const T& qcu, const T& qcv, const T* gm,
+                              const T* gp, double nx, double ny, double cc, T* fn, T* dqh) {
+    T ux = 0.5 * (gm[0] + gp[0]) + (cc * nx) * dq[1];
+    T uy = 0.5 * (gm[1] + gp[1]) + (cc * ny) * dq[1];
+    T vx = 0.5 * (gm[2] + gp[2]) + (cc * nx) * dq[2];
+    T vy = 0.5 * (gm[3] + gp[3]) + (cc * ny) * dq[2];
+    T Tn = 0.5 * ((gm[4] + gp[4]) * nx + (gm[5] + gp[5]) * ny) + cc * dq[3];
+    T div = ux + vy;
+    T txx = c.mu_re * (2.0 * ux - (2.0 / 3.0) * div);
+    T tyy = c.mu_re * (2.0 * vy - (2.0 / 3.0) * div);
+    T txy = c.mu_re * (uy + vx);
+    T tnx = txx * nx + txy * ny;
+    T tny = txy * nx + tyy * ny;
+    fn[1] = fn[1] - tnx;
+    fn[2] = fn[2] - tny;
+    fn[3] = fn[3] - (qcu * tnx + qcv * tny + c.kc_re * Tn);
+    dqh[0] = 0.5 * dq[1];
+    dqh[1] = 0.5 * dq[2];
+    dqh[2] = 0.5 * dq[3];
 }

@@ -17,9 +17,19 @@ struct Dual {
 FR_HD double val(double x) { return x; }
 template <int K> FR_HD double val(const Dual<K>& x) { return x.v; }
 
-template <class T> struct ScalarTraits { static constexpr int K = 0; };
-template <int K> struct ScalarTraits<Dual<K>> { static constexpr int K_ = K; static constexpr int K__ = K; };
-template <class T> constexpr int nlanes() { return 0; }
+// ---- reciprocal: hardware estimate refined by two Newton steps (error well below 1 ulp
+// of the quantities it feeds; replaces the much longer IEEE division sequence)
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ double rcp(double x) { return frcp(x); }
+template <int K> __device__ __forceinline__ Dual<K> rcp(const Dual<K>& a) { Dual<K> r; r.v = frcp(a.v);
+    const double s = -r.v * r.v;
+#pragma unroll
+    for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * s; return r; }
 
 template <int K> FR_HD Dual<K> mkconst(double a) { Dual<K> r; r.v = a;
 #pragma unroll
@@ -38,8 +48,9 @@ template <int K> FR_HD Dual<K> operator-(const Dual<K>& a) { Dual<K> r; r.v = -a
 template <int K> FR_HD Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) { Dual<K> r; r.v = a.v * b.v;
 #pragma unroll
     for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
-template <int K> FR_HD Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) { Dual<K> r; r.v = a.v / b.v;
-    const double ib = 1.0 / b.v;
+template <int K> __device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) { Dual<K> r;
+    const double ib = frcp(b.v);
+    r.v = a.v * ib;
 #pragma unroll
     for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib; return r; }
 template <int K> FR_HD Dual<K> operator+(const Dual<K>& a, double b) { Dual<K> r = a; r.v += b; return r; }

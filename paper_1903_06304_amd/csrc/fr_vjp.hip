@@ -104,7 +104,7 @@ __device__ void normal_flux_rev(const PhysConst& c, const double* q, double nx, 
 // outputs the adjoints of qm, qp (4 each) and gm, gp (6 each)
 template <bool VISC>
 __device__ void common_flux_rev(const PhysConst& c, const double* qm, const double* qp, const double* gm,
-                                const double* gp, double nx, double ny, double Smag, double JfL, double JfR,
+                                const double* gp, double nx, double ny, double cc,
                                 double ug, double vg, const double* afn, const double* adqh, double* aqm,
                                 double* aqp, double* agm, double* agp) {
     const double vgn = ug * nx + vg * ny;
@@ -143,7 +143,6 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
     double a_qb[4] = {0, 0, 0, 0}, a_dq[4] = {0, 0, 0, 0};
     for (int r = 0; r < 6; ++r) { agm[r] = 0.0; agp[r] = 0.0; }
     if (VISC) {
-        const double cc = 0.25 * c.br2 * Smag * (1.0 / JfL + 1.0 / JfR);
         const double ux = 0.5 * (gm[0] + gp[0]) + (cc * nx) * dq[1];
         const double uy = 0.5 * (gm[1] + gp[1]) + (cc * ny) * dq[1];
         const double vx = 0.5 * (gm[2] + gp[2]) + (cc * nx) * dq[2];
@@ -235,13 +234,17 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
 template <int P, bool VISC, bool MOV>
 __global__ void __launch_bounds__((Sz<P>::threads))
 k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, const double* __restrict__ tr,
-           double* __restrict__ out, double* __restrict__ aside, OpTab op, PhysConst pc, Geo g) {
+           double* __restrict__ out, double* __restrict__ aside, OpTab op_in, PhysConst pc, Geo g) {
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT, EPB = Sz<P>::EPB;
     constexpr int NTV = VISC ? 10 : 4;
     __shared__ double s_q[EPB][4][Np];
     __shared__ double s_a[EPB][24][Np];      // scratch fields at solution points
     __shared__ double s_f[EPB][NF][10];      // per flux point scratch
     __shared__ double s_S[EPB][NF][4];       // Sx, Sy, S.vg, scale sg|S|
+    __shared__ OpTab sop;                    // operator tables (lane-dependent indexing in LDS)
+    for (int t = threadIdx.x; t < (int)(sizeof(OpTab) / sizeof(double)); t += blockDim.x)
+        reinterpret_cast<double*>(&sop)[t] = reinterpret_cast<const double*>(&op_in)[t];
+    const OpTab& op = sop;
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
     const int e = blockIdx.x * EPB + el;
     const bool act = e < E;
@@ -273,7 +276,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     __syncthreads();
     // ---- forward: traces and the common solution (dqh) at flux points
     double qm[4], qp[4], gm[6], gp[6];
-    double nx = 0, ny = 0, Smag = 0, JfL = 1, JfR = 1, ugf = 0, vgf = 0, sc = 0;
+    double nx = 0, ny = 0, cc = 0, ugf = 0, vgf = 0, sc = 0;
     int f = 0, k = 0;
     if (isF) {
         f = lt / n; k = lt % n;
@@ -295,18 +298,12 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         for (int v = 0; v < 4; ++v) qp[v] = src[(size_t)v * n + k2];
         for (int c = 0; c < 6; ++c) gp[c] = VISC ? src[(size_t)(4 + c) * n + k2] : 0.0;
         const size_t sid = (size_t)e * NF + lt;
-        const double Sx = g.fp[F_SX * FE + sid], Sy = g.fp[F_SY * FE + sid];
-        JfL = g.fp[F_JF * FE + sid];
-        JfR = g.fp[F_JF * FE + (size_t)nb * NF + nf * n + k2];
+        nx = g.fp[F_NX * FE + sid]; ny = g.fp[F_NY * FE + sid];
+        sc = g.fp[F_SC * FE + sid]; cc = g.fp[F_CC * FE + sid];
         ugf = MOV ? g.fp[F_UG * FE + sid] : 0.0;
         vgf = MOV ? g.fp[F_VG * FE + sid] : 0.0;
-        const double sg = (f & 1) ? 1.0 : -1.0;
-        const double Ox = sg * Sx, Oy = sg * Sy;
-        Smag = sqrt(Ox * Ox + Oy * Oy);
-        nx = Ox / Smag; ny = Oy / Smag;
-        sc = sg * Smag;
-        s_S[el][lt][0] = Sx; s_S[el][lt][1] = Sy;
-        s_S[el][lt][2] = MOV ? (Sx * ugf + Sy * vgf) : 0.0;
+        s_S[el][lt][0] = sc * nx; s_S[el][lt][1] = sc * ny;
+        s_S[el][lt][2] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;
         s_S[el][lt][3] = sc;
         if (VISC) for (int c = 0; c < 3; ++c) s_f[el][lt][c] = 0.5 * (qp[c + 1] - qm[c + 1]);   // dqh
     }
@@ -429,7 +426,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         double afn[4];
         for (int v = 0; v < 4; ++v) afn[v] = sc * aDF[v];
         double aqm[4], aqp[4], agm[6], agp[6];
-        common_flux_rev<VISC>(pc, qm, qp, gm, gp, nx, ny, Smag, JfL, JfR, ugf, vgf, afn, adqh, aqm, aqp, agm, agp);
+        common_flux_rev<VISC>(pc, qm, qp, gm, gp, nx, ny, cc, ugf, vgf, afn, adqh, aqm, aqp, agm, agp);
         double* dst = aside + ((size_t)(e * 4 + f) * NTV) * n;
         for (int v = 0; v < 4; ++v) dst[(size_t)v * n + k] = aqp[v];
         if (VISC) for (int c = 0; c < 6; ++c) dst[(size_t)(4 + c) * n + k] = agp[c];
@@ -470,11 +467,15 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
 // ---------------------------------------------------------------- kernel 3: gather from neighbours
 template <int P, bool VISC>
 __global__ void __launch_bounds__((Sz<P>::threads))
-k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, OpTab op, Geo g) {
+k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, OpTab op_in, Geo g) {
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT, EPB = Sz<P>::EPB;
     constexpr int NTV = VISC ? 10 : 4;
     __shared__ double s_f[EPB][NF][10];
     __shared__ double s_d[EPB][6][Np];
+    __shared__ OpTab sop;
+    for (int t = threadIdx.x; t < (int)(sizeof(OpTab) / sizeof(double)); t += blockDim.x)
+        reinterpret_cast<double*>(&sop)[t] = reinterpret_cast<const double*>(&op_in)[t];
+    const OpTab& op = sop;
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
     const int e = blockIdx.x * EPB + el;
     const bool act = e < E;
