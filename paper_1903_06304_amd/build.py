@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblmfr.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["fr_api.hip", "fr_kernels.hip", "fr_vjp.hip", "fr_linalg.hip"]
+SOURCES = ["fr_api.hip", "fr_kernels.hip", "fr_vjp.hip", "fr_linalg.hip", "fr_gmres.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

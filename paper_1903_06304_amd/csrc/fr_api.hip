@@ -237,7 +237,11 @@ extern "C" void fr_destroy(fr_ctx c) {
     if (!c) return;
     dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_trace); dfree(c->d_trace0);
     dfree(c->d_blk); dfree(c->d_inv); dfree(c->d_blk_keep); dfree(c->d_scal);
-    dfree(c->d_V); dfree(c->d_w); dfree(c->d_vj);
+    gmres_release(c);
+    if (c->ws) (void)hipStreamDestroy(c->ws);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    dfree(c->d_V); dfree(c->d_w); dfree(c->d_vj); dfree(c->d_qw); dfree(c->d_gs); dfree(c->d_gi);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     delete c;
 }
@@ -245,6 +249,7 @@ extern "C" void fr_destroy(fr_ctx c) {
 extern "C" fr_status fr_set_option(fr_ctx c, const char* name, int64_t value) {
     if (!c || !name) return bad("fr_set_option: null argument");
     if (!strcmp(name, "keep_blocks")) { c->keep_blocks = value != 0; return FR_OK; }
+    if (!strcmp(name, "graph")) { c->use_graph = value != 0; gmres_release(c); return FR_OK; }
     return bad("fr_set_option: unknown option");
 }
 
@@ -351,23 +356,29 @@ extern "C" fr_status fr_get_blocks(fr_ctx c, double* blk, void* stream) {
     return FR_OK;
 }
 
-// ----------------------------------------------------------------------------- GMRES
+// ----------------------------------------------------------------------------- Newton / BDF2
 namespace {
 
-struct Gm {
-    int its = 0;
-    double rel = 0.0;
-};
-
-// work vectors inside d_w: 0: b, 1: R, 2: Q^n, 3: Q^{n-1}, 4: r, 5: w, 6: z, 7: dq
+// work vectors inside d_w: 0: b, 1: R, 2: Q^n, 3: Q^{n-1}, 4-6: GMRES (r, w, z), 7: dq
 enum { WB = 0, WR, WQN, WQNM1, WRES, WW, WZ, WDQ, NWORK };
 
 fr_status ensure_krylov(fr_ctx c, int m) {
-    if (c->kry_m >= m && c->d_V) return FR_OK;
-    dfree(c->d_V); c->d_V = nullptr;
-    FR_TRY(dalloc(&c->d_V, (size_t)(m + 1) * c->N()));
-    c->kry_m = m;
+    if (c->kry_m < m || !c->d_V) {
+        gmres_release(c);
+        dfree(c->d_V); c->d_V = nullptr;
+        dfree(c->d_gs); c->d_gs = nullptr;
+        FR_TRY(dalloc(&c->d_V, (size_t)(m + 1) * c->N()));
+        FR_TRY(dalloc(&c->d_gs, gmres_state_doubles(m)));
+        c->kry_m = m;
+    }
     if (!c->d_w) FR_TRY(dalloc(&c->d_w, (size_t)NWORK * c->N()));
+    if (!c->d_qw) FR_TRY(dalloc(&c->d_qw, c->N()));
+    if (!c->d_gi) FR_TRY(dalloc(&c->d_gi, (size_t)8));
+    if (!c->ws) {
+        FR_HIP(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking));
+        FR_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        FR_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    }
     return FR_OK;
 }
 
@@ -382,103 +393,26 @@ fr_status norm2(fr_ctx c, size_t N, const double* x, double& out, hipStream_t s)
     return FR_OK;
 }
 
-// Solve (inv_dtau Gamma + c_time M - J(q)) x = b with right preconditioning by the
-// factored element blocks.  x0 = 0; stops on ||b - A x|| <= tol ||b|| (true residual at
-// each restart, Arnoldi estimate inside a cycle) or after max_it iterations.
-fr_status gmres(fr_ctx c, const double* q, const double* b, double* x, int m, double tol, int max_it, double ct,
-                double idt, Gm& out, hipStream_t s) {
-    const size_t N = c->N();
-    double* V = c->d_V;
-    double* r = wv(c, WRES);
-    double* w = wv(c, WW);
-    double* z = wv(c, WZ);
-    double* d_h1 = c->d_scal + SC_H1;
-    double* d_h2 = c->d_scal + SC_H2;
-    double* d_nrm = c->d_scal + SC_NRM;
-    double* d_y = c->d_scal + SC_Y;
-    FR_HIP(hipMemsetAsync(x, 0, N * sizeof(double), s));
-    double bn;
-    FR_TRY(norm2(c, N, b, bn, s));
-    out = Gm{};
-    if (bn == 0.0) return FR_OK;
-    if (!std::isfinite(bn)) { fr_set_error("non-finite right-hand side"); return FR_ENONFINITE; }
-    FR_HIP(hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    double beta = bn;
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
-    while (out.its < max_it) {
-        FR_TRY(la_scale_copy(N, 1.0 / beta, r, V, s));
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int j = 0;
-        bool done = false;
-        for (; j < m && out.its < max_it; ++j) {
-            double* vj = V + (size_t)j * N;
-            FR_TRY(launch_block_apply(c, vj, z, s));
-            FR_TRY(fr_bdf_operator(c, q, z, ct, idt, w, s));
-            // classical Gram-Schmidt, applied twice
-            FR_TRY(la_krylov(c, N, V, 0, nullptr, j + 1, w, nullptr, false, d_h1, s));     // h1 = V^T w
-            FR_TRY(la_krylov(c, N, V, j + 1, d_h1, j + 1, w, w, false, d_h2, s));        // w -= V h1; h2 = V^T w
-            FR_TRY(la_krylov(c, N, V, j + 1, d_h2, 0, w, w, true, d_nrm, s));            // w -= V h2; |w|^2
-            FR_HIP(hipMemcpyAsync(c->h_scal, d_h1, 129 * sizeof(double), hipMemcpyDeviceToHost, s));
-            FR_HIP(hipStreamSynchronize(s));
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->h_scal[i] + c->h_scal[64 + i];
-            const double hn = std::sqrt(c->h_scal[128]);
-            if (!std::isfinite(hn)) { fr_set_error("non-finite Arnoldi vector"); return FR_ENONFINITE; }
-            H[(size_t)(j + 1) * m + j] = hn;
-            if (hn > 0.0) FR_TRY(la_scale_copy(N, 1.0 / hn, w, V + (size_t)(j + 1) * N, s));
-            for (int i = 0; i < j; ++i) {
-                const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
-            }
-            const double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
-            const double den = std::hypot(a0, a1);
-            cs[j] = den == 0.0 ? 1.0 : a0 / den;
-            sn[j] = den == 0.0 ? 0.0 : a1 / den;
-            H[(size_t)j * m + j] = cs[j] * a0 + sn[j] * a1;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            out.its++;
-            if (std::fabs(g[j + 1]) <= tol * bn || hn == 0.0) { ++j; done = true; break; }
-        }
-        (void)done;
-        // y = H^-1 g (upper triangular), x += P^-1 (V y)
-        for (int i = j - 1; i >= 0; --i) {
-            double sacc = g[i];
-            for (int k = i + 1; k < j; ++k) sacc -= H[(size_t)i * m + k] * y[k];
-            y[i] = sacc / H[(size_t)i * m + i];
-        }
-        memcpy(c->h_scal + 256, y.data(), j * sizeof(double));
-        FR_HIP(hipMemcpyAsync(d_y, c->h_scal + 256, j * sizeof(double), hipMemcpyHostToDevice, s));
-        FR_TRY(la_combine(N, V, j, d_y, w, s));
-        FR_TRY(launch_block_apply(c, w, z, s));
-        FR_TRY(la_axpy(N, 1.0, z, x, s));
-        // true residual r = b - A x
-        FR_TRY(fr_bdf_operator(c, q, x, ct, idt, w, s));
-        FR_TRY(la_scale_copy(N, 1.0, b, r, s));
-        FR_TRY(la_axpy(N, -1.0, w, r, s));
-        FR_TRY(norm2(c, N, r, beta, s));   // synchronises, so h_scal may be reused
-        out.rel = beta / bn;
-        if (!std::isfinite(beta)) { fr_set_error("non-finite GMRES residual"); return FR_ENONFINITE; }
-        if (beta <= tol * bn) break;
-    }
-    return FR_OK;
-}
-
 }  // namespace
 
-extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q, const double* q_nm1, const fr_step_opts* o,
+extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q_io, const double* q_nm1, const fr_step_opts* o,
                                   fr_step_stats* h_stats, void* stream) {
     FR_TRY(ready(c));
-    if (!q || !o) return bad("fr_bdf2_step: null argument");
-    if (!(o->dt > 0.0) || o->krylov < 1 || o->krylov > 60 || o->max_lin_it < 1 || o->max_newton < 0 || o->jac_lag < 1)
+    if (!q_io || !o) return bad("fr_bdf2_step: null argument");
+    if (!(o->dt > 0.0) || o->krylov < 1 || o->krylov > 60 || o->max_lin_it < 1 || o->max_newton < 0 || o->jac_lag < 1 ||
+        o->prec < FR_FP64 || o->prec > FR_BF16)
         return bad("fr_bdf2_step: invalid options");
-    hipStream_t s = (hipStream_t)stream;
     FR_TRY(ensure_krylov(c, o->krylov));
+    // the step runs on the context stream, ordered after and before the caller's stream
+    hipStream_t cs = (hipStream_t)stream;
+    FR_HIP(hipEventRecord(c->ev_in, cs));
+    FR_HIP(hipStreamWaitEvent(c->ws, c->ev_in, 0));
+    hipStream_t s = c->ws;
     const size_t N = c->N(), EN = (size_t)c->E * c->Np;
     const double a0 = q_nm1 ? 1.5 : 1.0, a1 = q_nm1 ? -2.0 : -1.0, a2 = q_nm1 ? 0.5 : 0.0;
     const double ct = a0 / o->dt;
+    double* q = c->d_qw;   // Newton iterate in a context-owned buffer
+    FR_HIP(hipMemcpyAsync(q, q_io, N * sizeof(double), hipMemcpyDeviceToDevice, s));
     FR_TRY(launch_cons(c, q, wv(c, WQN), s));
     if (q_nm1) FR_TRY(launch_cons(c, q_nm1, wv(c, WQNM1), s));
     fr_step_stats st{0, 0, 0, 0.0, 0.0};
@@ -495,12 +429,16 @@ extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q, const double* q_nm1, cons
         if (res <= o->tol_abs || res <= o->tol_pseudo * st.res0) { st.converged = 1; break; }
         if (m >= o->max_newton) { ret = FR_ENOCONV; fr_set_error("Newton iteration limit reached"); break; }
         if (m % o->jac_lag == 0) FR_TRY(fr_block_jacobi_factor(c, q, ct, o->inv_dtau, o->prec, s));
-        Gm gm;
-        FR_TRY(gmres(c, q, wv(c, WB), wv(c, WDQ), o->krylov, o->tol_res, o->max_lin_it, ct, o->inv_dtau, gm, s));
+        GmresResult gm;
+        FR_TRY(gmres_device(c, q, wv(c, WB), wv(c, WDQ), o->krylov, o->tol_res, o->max_lin_it, ct, o->inv_dtau,
+                            o->prec, gm, s));
         st.gmres_its += gm.its;
         FR_TRY(la_axpy(N, 1.0, wv(c, WDQ), q, s));
         st.newton_its++;
     }
+    FR_HIP(hipMemcpyAsync(q_io, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    FR_HIP(hipEventRecord(c->ev_out, s));
+    FR_HIP(hipStreamWaitEvent(cs, c->ev_out, 0));
     if (h_stats) *h_stats = st;
     return ret;
 }

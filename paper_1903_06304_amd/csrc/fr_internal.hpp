@@ -49,6 +49,7 @@ struct KArgs {
     double* out2;         // R (JVP) or NULL
     double c_time, inv_dtau;
     int seed0;            // first seeded column (block mode)
+    const int* skip;      // device flag: non-zero => the launch does nothing (finished GMRES cycle)
 };
 
 struct fr_ctx_s {
@@ -77,6 +78,16 @@ struct fr_ctx_s {
     double* d_V = nullptr;          // [(m+1)][N]
     double* d_w = nullptr;          // [N] x 6 work vectors
     double* d_vj = nullptr;         // [vjp adjoint trace buffer]
+    double* d_qw = nullptr;         // Newton iterate (ctx-owned so captured graphs stay valid)
+    double* d_gs = nullptr;         // device GMRES state (Hessenberg, rotations, scalars)
+    int* d_gi = nullptr;            // device GMRES counters and flags
+    bool use_graph = true;
+    hipStream_t ws = nullptr;       // context stream of the BDF2 step (capturable, default priority)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    void* graph_exec = nullptr;     // hipGraphExec_t of one GMRES(m) cycle
+    double graph_ct = 0, graph_idt = 0;
+    int graph_m = 0, graph_prec = -1;
+    double graph_tol = 0;
     size_t N() const { return (size_t)4 * E * Np; }
 };
 
@@ -104,12 +115,13 @@ fr_status launch_vjp(fr_ctx c, const double* q, const double* w, double* out, hi
 // linear algebra (fr_linalg.hip)
 fr_status launch_block_assembly(fr_ctx c, const double* q, double c_time, double inv_dtau, hipStream_t s);
 fr_status launch_block_invert(fr_ctx c, int prec, hipStream_t s);
-fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s);
+fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s, const int* skip = nullptr);
 // dots of the first N entries; V_i = V + i * c->N()
 fr_status la_dots(fr_ctx c, size_t N, const double* V, int nv, const double* w, double* d_out, hipStream_t s);
 // w_out = w_in - sum_{i<nv_upd} coef_i V_i; d_out[i] = V_i . w_out (i < nv_dot); d_out[nv_dot] = |w_out|^2
 fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
-                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s);
+                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s,
+                    const int* skip = nullptr);
 fr_status la_axpy(size_t N, double a, const double* x, double* y, hipStream_t s);
 fr_status la_scale_copy(size_t N, double a, const double* x, double* y, hipStream_t s);
 fr_status la_norm2(size_t N, const double* x, double* d_out, double* scratch, hipStream_t s);
@@ -117,3 +129,10 @@ fr_status launch_bdf_rhs(fr_ctx c, const double* q, const double* Qn, const doub
                          double a0, double a1, double a2, double dt, double* b, hipStream_t s);
 fr_status launch_cons(fr_ctx c, const double* q, double* Qc, hipStream_t s);
 fr_status la_combine(size_t N, const double* V, int nv, const double* d_y, double* out, hipStream_t s);
+
+// device GMRES (fr_gmres.hip)
+struct GmresResult { int its; double rel; };
+fr_status gmres_device(fr_ctx c, const double* q, const double* b, double* x, int m, double tol, int max_it,
+                       double ct, double idt, int prec, GmresResult& out, hipStream_t s);
+void gmres_release(fr_ctx c);
+size_t gmres_state_doubles(int m);

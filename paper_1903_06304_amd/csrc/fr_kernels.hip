@@ -313,6 +313,7 @@ k_fused(KArgs a, OpTab op, PhysConst pc, Geo g) {
     __shared__ double s_D[n * n];       // operator tables (lane-dependent indexing goes to LDS)
     __shared__ double s_lam[2][n], s_gam[2][n];
 
+    if (a.skip && *a.skip) return;   // uniform: a finished GMRES cycle replays as no-ops
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
     if (threadIdx.x < n) {

@@ -122,8 +122,10 @@ __global__ void __launch_bounds__(256) k_block_invert(int E, int nb, const doubl
 // z_e = Ainv_e r_e; state layout [4][E][Np], block row/col index v*Np + s
 template <class Tin>
 __global__ void __launch_bounds__(256) k_block_apply(int E, int Np, const Tin* __restrict__ inv,
-                                                     const double* __restrict__ r, double* __restrict__ z) {
+                                                     const double* __restrict__ r, double* __restrict__ z,
+                                                     const int* skip) {
     extern __shared__ double rs[];
+    if (skip && *skip) return;
     const int nb = 4 * Np;
     const int epb = blockDim.x / nb;
     const int el = threadIdx.x / nb, row = threadIdx.x % nb;
@@ -149,8 +151,9 @@ template <int NVM>
 __global__ void __launch_bounds__(RED_THREADS) k_krylov(size_t N, const double* __restrict__ V, size_t ldv, int nv_upd,
                                                         const double* __restrict__ coef, int nv_dot,
                                                         const double* w_in, double* w_out, int want_norm,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, const int* skip) {
     __shared__ double red[RED_THREADS / 64][NVM + 1];
+    if (skip && *skip) return;
     double cf[NVM], acc[NVM];
     double nacc = 0.0;
 #pragma unroll
@@ -188,8 +191,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_krylov(size_t N, const double* 
 }
 
 // out[i] = sum over blocks of partial[b][i]; one workgroup per output, fixed-order tree
-__global__ void __launch_bounds__(256) k_final(int nblocks, const double* __restrict__ partial, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_final(int nblocks, const double* __restrict__ partial, double* __restrict__ out,
+                                               const int* skip) {
     __shared__ double red[256];
+    if (skip && *skip) return;
     const int i = blockIdx.x;
     double v = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * MAXV + i];
@@ -300,16 +305,16 @@ fr_status launch_block_invert(fr_ctx c, int prec, hipStream_t s) {
     return FR_OK;
 }
 
-fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s) {
+fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s, const int* skip) {
     const int nb = 4 * c->Np;
     const int epb = 256 / nb;
     const int threads = epb * nb;
     const unsigned grid = (unsigned)((c->E + epb - 1) / epb);
     const size_t lds = (size_t)threads * sizeof(double);
     switch (c->inv_prec) {
-        case FR_FP64: hipLaunchKernelGGL(k_block_apply<double>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const double*)c->d_inv, r, z); break;
-        case FR_FP32: hipLaunchKernelGGL(k_block_apply<float>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const float*)c->d_inv, r, z); break;
-        case FR_BF16: hipLaunchKernelGGL(k_block_apply<uint16_t>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const uint16_t*)c->d_inv, r, z); break;
+        case FR_FP64: hipLaunchKernelGGL(k_block_apply<double>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const double*)c->d_inv, r, z, skip); break;
+        case FR_FP32: hipLaunchKernelGGL(k_block_apply<float>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const float*)c->d_inv, r, z, skip); break;
+        case FR_BF16: hipLaunchKernelGGL(k_block_apply<uint16_t>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const uint16_t*)c->d_inv, r, z, skip); break;
         default: fr_set_error("preconditioner not factored"); return FR_EINVAL;
     }
     FR_HIP(hipGetLastError());
@@ -317,14 +322,15 @@ fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s
 }
 
 fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
-                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s) {
+                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s,
+                    const int* skip) {
     const int nmax = nv_upd > nv_dot ? nv_upd : nv_dot;
     if (nmax > MAXV - 1) { fr_set_error("too many Krylov vectors"); return FR_EINVAL; }
     double* partial = c->d_scal + SC_PART;
     const size_t ldv = c->N();
     const int wn = want_norm ? 1 : 0;
 #define FR_KRY(NVM) hipLaunchKernelGGL(k_krylov<NVM>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, N, V, ldv, nv_upd, \
-                                       d_coef, nv_dot, w_in, w_out, wn, partial)
+                                       d_coef, nv_dot, w_in, w_out, wn, partial, skip)
     if (nmax <= 1) FR_KRY(1);
     else if (nmax <= 8) FR_KRY(8);
     else if (nmax <= 16) FR_KRY(16);
@@ -334,7 +340,7 @@ fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const doubl
     FR_HIP(hipGetLastError());
     const int nout = nv_dot + wn;
     if (nout > 0) {
-        hipLaunchKernelGGL(k_final, dim3(nout), dim3(256), 0, s, RED_BLOCKS, partial, d_out);
+        hipLaunchKernelGGL(k_final, dim3(nout), dim3(256), 0, s, RED_BLOCKS, partial, d_out, skip);
         FR_HIP(hipGetLastError());
     }
     return FR_OK;

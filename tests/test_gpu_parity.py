@@ -244,3 +244,30 @@ def test_vjp_parity_c2_sampled():
     R = lmfr.residual(qt, g)
     R.backward(_dev(w))
     assert torch.equal(qt.grad.reshape(-1).cpu(), torch.tensor(JTw))
+
+
+def test_bdf2_graph_replay_matches_eager():
+    """The captured GMRES cycle, replayed over several Newton/BDF2 steps with eager work and
+    synchronisations in between, reproduces the uncaptured launches bit for bit."""
+    c = I.config_c1(nx=4)
+    results = {}
+    for use_graph in (0, 1):
+        o, g = _pair(c.prm, c.mesh)
+        g.set_option("graph", use_graph)
+        q = _dev(c.q)
+        qm1 = _dev(c.q_nm1)
+        hist = []
+        for step in range(3):
+            qn = q.clone()
+            st = g.bdf2_step(q, qm1, c.dt, tol_pseudo=1e-10, tol_res=1e-9, krylov=8, max_lin_it=200)
+            torch.cuda.synchronize()
+            assert st["converged"] == 1, st
+            R = g.residual(q)        # eager work between replays
+            torch.cuda.synchronize()
+            hist.append((q.clone(), st["gmres_its"], R.clone()))
+            qm1 = qn
+        results[use_graph] = hist
+    for (qa, ia, Ra), (qb, ib, Rb) in zip(results[0], results[1]):
+        assert ia == ib
+        assert torch.equal(qa, qb)
+        assert torch.equal(Ra, Rb)
