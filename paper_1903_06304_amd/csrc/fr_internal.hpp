@@ -93,7 +93,7 @@ struct fr_ctx_s {
 
 // layout of the reduction scratch d_scal (doubles)
 enum { SC_H1 = 0, SC_H2 = 64, SC_NRM = 128, SC_Y = 192, SC_STATUS = 256, SC_PART = 320,
-       SC_TOTAL = 320 + 512 * 64 };
+       SC_TOTAL = 320 + 2048 * 64 };
 
 // error handling
 void fr_set_error(const std::string& s);

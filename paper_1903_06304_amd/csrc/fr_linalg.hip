@@ -14,7 +14,7 @@
 
 namespace {
 
-constexpr int RED_BLOCKS = 512;   // first-stage partial sums per reduction
+constexpr int RED_BLOCKS = 2048;  // first-stage partial sums per reduction (8 workgroups per CU)
 constexpr int RED_THREADS = 256;
 constexpr int MAXV = 64;          // max vectors in one multi-dot
 
@@ -142,51 +142,74 @@ __global__ void __launch_bounds__(256) k_block_apply(int E, int Np, const Tin* _
 }
 
 // ------------------------------------------------------------------ Krylov reductions
-// One streaming pass over the basis V (vectors V_i = V + i*ldv):
-//   w_new = w_in - sum_{i < nv_upd} coef[i] V_i           (written to w_out when nv_upd > 0)
-//   partial[b][i] = sum over this block's stripe of V_i . w_new   (i < nv_dot)
-//   partial[b][nv_dot] = stripe sum of w_new . w_new               (want_norm)
-// NVM bounds nv_upd and nv_dot so the accumulators stay in registers.
-template <int NVM>
-__global__ void __launch_bounds__(RED_THREADS) k_krylov(size_t N, const double* __restrict__ V, size_t ldv, int nv_upd,
-                                                        const double* __restrict__ coef, int nv_dot,
-                                                        const double* w_in, double* w_out, int want_norm,
-                                                        double* __restrict__ partial, const int* skip) {
-    __shared__ double red[RED_THREADS / 64][NVM + 1];
+// Dot products V_i . w for i in [8*blockIdx.y, 8*blockIdx.y + 8) ∩ [0, nv), plus |w|^2 in slot
+// nv when want_norm (chunk 0 only): per-block partial sums partial[b][i].
+__global__ void __launch_bounds__(RED_THREADS) k_dots8(size_t N, const double* __restrict__ V, size_t ldv, int nv,
+                                                       const double* __restrict__ w, int want_norm,
+                                                       double* __restrict__ partial, const int* skip) {
+    __shared__ double red[RED_THREADS / 64][9];
     if (skip && *skip) return;
-    double cf[NVM], acc[NVM];
+    const int i0 = blockIdx.y * 8;
+    const int cnt = nv - i0 < 8 ? nv - i0 : 8;
+    const bool nrm = want_norm && blockIdx.y == 0;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double nacc = 0.0;
-#pragma unroll
-    for (int i = 0; i < NVM; ++i) {
-        cf[i] = (i < nv_upd) ? coef[i] : 0.0;
-        acc[i] = 0.0;
-    }
+    const double* Vc = V + (size_t)i0 * ldv;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        double wt = w_in[t];
+        const double wt = w[t];
 #pragma unroll
-        for (int i = 0; i < NVM; ++i)
-            if (i < nv_upd) wt -= cf[i] * V[i * ldv + t];
-        if (nv_upd > 0) w_out[t] = wt;
-#pragma unroll
-        for (int i = 0; i < NVM; ++i)
-            if (i < nv_dot) acc[i] += V[i * ldv + t] * wt;
-        nacc += wt * wt;
+        for (int i = 0; i < 8; ++i)
+            if (i < cnt) acc[i] += Vc[i * ldv + t] * wt;
+        if (nrm) nacc += wt * wt;
     }
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
 #pragma unroll
-    for (int i = 0; i < NVM + 1; ++i) {
-        const bool live = (i < nv_dot) || (i == nv_dot && want_norm);
+    for (int i = 0; i < 9; ++i) {
+        const bool live = (i < cnt) || (i == 8 && nrm);
         if (!live) continue;
-        double v = (i < nv_dot) ? acc[i] : nacc;
+        double v = (i < 8) ? acc[i] : nacc;
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
         if (lane == 0) red[wid][i] = v;
     }
     __syncthreads();
-    const int nout = nv_dot + (want_norm ? 1 : 0);
-    if ((int)threadIdx.x < nout) {
+    const int k = threadIdx.x;
+    if (k < cnt || (k == 8 && nrm)) {
         double v = 0.0;
-        for (int k = 0; k < RED_THREADS / 64; ++k) v += red[k][threadIdx.x];
-        partial[(size_t)blockIdx.x * MAXV + threadIdx.x] = v;
+        for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q][k];
+        partial[(size_t)blockIdx.x * MAXV + (k < 8 ? i0 + k : nv)] = v;
+    }
+}
+
+// w_out = w_in - sum_{i < nv} coef[i] V_i, and partial |w_out|^2 in slot 0 when want_norm
+__global__ void __launch_bounds__(RED_THREADS) k_update(size_t N, const double* __restrict__ V, size_t ldv, int nv,
+                                                        const double* __restrict__ coef, const double* w_in,
+                                                        double* w_out, int want_norm, double* __restrict__ partial,
+                                                        const int* skip) {
+    __shared__ double cf[MAXV];
+    __shared__ double red[RED_THREADS / 64];
+    if (skip && *skip) return;
+    if ((int)threadIdx.x < MAXV) cf[threadIdx.x] = ((int)threadIdx.x < nv) ? coef[threadIdx.x] : 0.0;
+    __syncthreads();
+    double nacc = 0.0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
+        double wt = w_in[t];
+        int i = 0;
+        for (; i + 4 <= nv; i += 4)
+            wt -= cf[i] * V[i * ldv + t] + cf[i + 1] * V[(i + 1) * ldv + t] + cf[i + 2] * V[(i + 2) * ldv + t] +
+                  cf[i + 3] * V[(i + 3) * ldv + t];
+        for (; i < nv; ++i) wt -= cf[i] * V[i * ldv + t];
+        w_out[t] = wt;
+        nacc += wt * wt;
+    }
+    if (!want_norm) return;
+    const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+    for (int off = 32; off > 0; off >>= 1) nacc += __shfl_down(nacc, off, 64);
+    if (lane == 0) red[wid] = nacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q];
+        partial[(size_t)blockIdx.x * MAXV] = v;
     }
 }
 
@@ -324,21 +347,30 @@ fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s
 fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
                     const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s,
                     const int* skip) {
-    const int nmax = nv_upd > nv_dot ? nv_upd : nv_dot;
-    if (nmax > MAXV - 1) { fr_set_error("too many Krylov vectors"); return FR_EINVAL; }
+    if (nv_upd > MAXV - 1 || nv_dot > MAXV - 1) { fr_set_error("too many Krylov vectors"); return FR_EINVAL; }
     double* partial = c->d_scal + SC_PART;
     const size_t ldv = c->N();
-    const int wn = want_norm ? 1 : 0;
-#define FR_KRY(NVM) hipLaunchKernelGGL(k_krylov<NVM>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, N, V, ldv, nv_upd, \
-                                       d_coef, nv_dot, w_in, w_out, wn, partial, skip)
-    if (nmax <= 1) FR_KRY(1);
-    else if (nmax <= 8) FR_KRY(8);
-    else if (nmax <= 16) FR_KRY(16);
-    else if (nmax <= 32) FR_KRY(32);
-    else FR_KRY(63);
-#undef FR_KRY
+    const double* w = w_in;
+    if (nv_upd > 0) {
+        // the norm of the updated vector rides on the update pass when no dots follow
+        const int nrm = (want_norm && nv_dot == 0) ? 1 : 0;
+        hipLaunchKernelGGL(k_update, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, N, V, ldv, nv_upd, d_coef, w_in, w_out,
+                           nrm, partial, skip);
+        FR_HIP(hipGetLastError());
+        w = w_out;
+        if (nv_dot == 0) {
+            if (nrm) {
+                hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, RED_BLOCKS, partial, d_out, skip);
+                FR_HIP(hipGetLastError());
+            }
+            return FR_OK;
+        }
+    }
+    const int chunks = nv_dot > 0 ? (nv_dot + 7) / 8 : 1;
+    hipLaunchKernelGGL(k_dots8, dim3(RED_BLOCKS, chunks), dim3(RED_THREADS), 0, s, N, V, ldv, nv_dot, w,
+                       want_norm ? 1 : 0, partial, skip);
     FR_HIP(hipGetLastError());
-    const int nout = nv_dot + wn;
+    const int nout = nv_dot + (want_norm ? 1 : 0);
     if (nout > 0) {
         hipLaunchKernelGGL(k_final, dim3(nout), dim3(256), 0, s, RED_BLOCKS, partial, d_out, skip);
         FR_HIP(hipGetLastError());
