@@ -20,9 +20,11 @@
  *    asynchronous on it unless stated otherwise.
  *  - No exceptions cross the ABI: every call returns an fr_status; the text of
  *    the last failure on the calling thread is returned by fr_last_error().
- *  - Memory: the context allocates its tables and workspaces in fr_create,
- *    fr_set_geometry and (Krylov workspace) the first fr_bdf2_step with a given
- *    Krylov dimension; residual, JVP, VJP and preconditioner calls allocate nothing.
+ *  - Memory: a context allocates its tables and workspaces in fr_create, the
+ *    element blocks in its first fr_block_jacobi_factor (or step), and the Krylov
+ *    workspace in its first fr_bdf2_step with a given Krylov dimension; a batch does
+ *    the same in fr_batch_create and its first step.  Residual, JVP, VJP, apply and
+ *    repeated step calls allocate nothing.
  */
 #ifndef LMFR_H
 #define LMFR_H
@@ -34,6 +36,7 @@ extern "C" {
 #endif
 
 typedef struct fr_ctx_s* fr_ctx;
+typedef struct fr_batch_s* fr_batch;
 
 typedef enum {
     FR_OK = 0,
@@ -132,13 +135,63 @@ fr_status fr_get_blocks(fr_ctx ctx, double* blk, void* stream);
  * q^{n+1} on return.  Newton starts from q^n (paper Sec. 3.2); each Newton step solves
  * the Eq. (unsteady_pre_discretized_3) system with restarted, right-preconditioned
  * FP64 GMRES and the element-block-Jacobi preconditioner (refreshed every jac_lag steps).
- * Synchronises `stream` once per GMRES iteration and Newton step.  h_stats: HOST,
+ * Synchronises once per GMRES restart cycle and Newton step.  h_stats: HOST,
  * may be NULL.  Returns FR_ENOCONV (state still updated) when max_newton is reached. */
 fr_status fr_bdf2_step(fr_ctx ctx, double* q, const double* q_nm1, const fr_step_opts* opts,
                        fr_step_stats* h_stats, void* stream);
 
-/* Options: "keep_blocks" (0/1: keep the FP64 blocks for fr_get_blocks). */
+/* Options: "keep_blocks" (0/1: keep the FP64 blocks for fr_get_blocks), "graph" (0/1:
+ * replay each GMRES restart cycle from a captured hipGraph, default 1). */
 fr_status fr_set_option(fr_ctx ctx, const char* name, int64_t value);
+
+/* Choose the launch shape (workgroup width: elements per workgroup, and persistent grid
+ * size) of the residual, JVP and Newton-operator kernels by timing the candidates on the
+ * device with a free-stream state; block-column assembly takes the Newton operator's
+ * shape.  cache_path (may be NULL): text file of earlier choices keyed by GPU
+ * architecture, order, viscous/moving flags, mode and element-count bucket; entries
+ * found there are used without timing, new ones are appended.  Synchronises `stream`.
+ * The choice affects speed only: every shape computes the same values bit for bit. */
+fr_status fr_autotune(fr_ctx ctx, const char* cache_path, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Batches: many independent cases (meshes of different sizes and orders, different
+ * Mach and Reynolds numbers, static or deforming) advanced together.  Every launch of
+ * the hot path covers all cases: cases of one (order, viscous, moving) kind share one
+ * persistent launch of the fused residual kernel over a ragged tile list, and the
+ * Krylov kernels reduce per case over one concatenated vector.  Each case keeps its
+ * own Newton and GMRES convergence through per-case flags on the device; each GMRES
+ * restart cycle of the whole batch is one captured hipGraph replay. */
+
+/* Create a batch over n contexts (each created and given its geometry as usual; the
+ * batch does not own them and they must outlive it).  A context may appear once. */
+fr_status fr_batch_create(const fr_ctx* ctxs, int32_t n, fr_batch* out);
+void fr_batch_destroy(fr_batch batch);
+
+/* Layout of the batch's concatenated state vectors: *n_total entries; case c's
+ * [4][E_c][Np_c] array starts at offsets[c] (HOST array [n], may be NULL); the gaps
+ * between cases are padding the kernels neither read into results nor write. */
+fr_status fr_batch_layout(fr_batch batch, int64_t* n_total, int64_t* offsets);
+
+/* Residual / JVP of every case on concatenated DEVICE arrays laid out as reported by
+ * fr_batch_layout (q, v in; R, Jv out; padding of the outputs is left untouched). */
+fr_status fr_batch_residual(fr_batch batch, const double* q, double* R, void* stream);
+fr_status fr_batch_jvp(fr_batch batch, const double* q, const double* v, double* Jv, void* stream);
+
+/* One BDF2 (BDF1 where q_nm1[c] is NULL or q_nm1 itself is NULL) dual-time step of
+ * every case: q[c] (DEVICE, [4][E_c][Np_c]) holds q^n on entry and q^{n+1} on return.
+ * opts[c]: per-case dt, inv_dtau and tolerances; krylov, max_lin_it, max_newton,
+ * jac_lag and prec must agree across the batch.  h_stats: HOST [n] or NULL.  Cases
+ * that converge leave the iteration while the others continue.  Synchronises once per
+ * GMRES restart cycle and Newton iteration.  Returns FR_ENONFINITE or FR_ENOCONV when
+ * a case failed (fr_last_error names the first); the other cases are still advanced. */
+fr_status fr_batch_bdf2_step(fr_batch batch, double* const* q, const double* const* q_nm1,
+                             const fr_step_opts* opts, fr_step_stats* h_stats, void* stream);
+
+/* Options: "graph" (0/1) as for a context. */
+fr_status fr_batch_set_option(fr_batch batch, const char* name, int64_t value);
+
+/* fr_autotune for every launch group of the batch. */
+fr_status fr_batch_autotune(fr_batch batch, const char* cache_path, void* stream);
 
 const char* fr_last_error(void);
 void fr_destroy(fr_ctx ctx);

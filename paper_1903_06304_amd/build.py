@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblmfr.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["fr_api.hip", "fr_kernels.hip", "fr_vjp.hip", "fr_linalg.hip", "fr_gmres.hip"]
+SOURCES = ["fr_fused_p3.hip", "fr_fused_p4.hip", "fr_fused_p2.hip", "fr_fused_p1.hip", "fr_api.hip",
+           "fr_kernels.hip", "fr_vjp.hip", "fr_linalg.hip", "fr_gmres.hip", "fr_solver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -35,7 +36,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]

@@ -1,7 +1,7 @@
 // C ABI of the lmfr library: context, operator tables, residual / JVP / VJP entry
-// points, the element-block-Jacobi preconditioner, and the BDF2 dual-time Newton step
-// with restarted, right-preconditioned FP64 GMRES (classical Gram-Schmidt with
-// re-orthogonalisation) driven from the host.
+// points, the element-block-Jacobi preconditioner, the BDF2 dual-time Newton step, and
+// batches of cases advanced together.  A context's own entry points run through its
+// one-case solver; a batch is a solver over many contexts.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,12 +14,6 @@
 static thread_local std::string g_err;
 void fr_set_error(const std::string& s) { g_err = s; }
 extern "C" const char* fr_last_error(void) { return g_err.c_str(); }
-
-#define FR_TRY(x)                              \
-    do {                                       \
-        fr_status st_ = (x);                   \
-        if (st_ != FR_OK) return st_;          \
-    } while (0)
 
 static fr_status bad(const char* msg) { fr_set_error(msg); return FR_EINVAL; }
 
@@ -141,20 +135,6 @@ void build_tables(fr_ctx c) {
     for (int a = 0; a < m; ++a) c->gt.dLp[a] = dL[a];
 }
 
-template <class T>
-fr_status dalloc(T** p, size_t count) {
-    if (*p) return FR_OK;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T) + 16);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        fr_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
-        return FR_ENOMEM;
-    }
-    return FR_OK;
-}
-
-void dfree(void* p) { if (p) (void)hipFree(p); }
-
 }  // namespace
 
 // ----------------------------------------------------------------------------- context
@@ -212,22 +192,20 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
     if ((st = dalloc(&c->d_nbr, (size_t)E * 4)) != FR_OK ||
         (st = dalloc(&c->d_gsp, NGSP * EN)) != FR_OK ||
         (st = dalloc(&c->d_gfp, NGFP * FE)) != FR_OK ||
-        (st = dalloc(&c->d_trace, FE * 10 * 2)) != FR_OK ||
-        (st = dalloc(&c->d_trace0, FE * 10)) != FR_OK ||
-        (st = dalloc(&c->d_scal, (size_t)SC_TOTAL)) != FR_OK) {
+        (st = dalloc(&c->d_trace, FE * 10)) != FR_OK ||
+        (st = dalloc(&c->d_vj, FE * 10)) != FR_OK) {
         fr_destroy(c);
         return st;
-    }
-    if (hipHostMalloc((void**)&c->h_scal, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        c->h_scal = nullptr;
-        fr_destroy(c);
-        fr_set_error("hipHostMalloc failed");
-        return FR_ENOMEM;
     }
     if (hipMemcpy(c->d_nbr, packed.data(), packed.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
         fr_destroy(c);
         fr_set_error("copy of the neighbour table failed");
         return FR_EHIP;
+    }
+    c->self = new Solver();
+    if ((st = solver_init(*c->self, &c, 1)) != FR_OK) {
+        fr_destroy(c);
+        return st;
     }
     *out = c;
     return FR_OK;
@@ -235,21 +213,16 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
 
 extern "C" void fr_destroy(fr_ctx c) {
     if (!c) return;
-    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_trace); dfree(c->d_trace0);
-    dfree(c->d_blk); dfree(c->d_inv); dfree(c->d_blk_keep); dfree(c->d_scal);
-    gmres_release(c);
-    if (c->ws) (void)hipStreamDestroy(c->ws);
-    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
-    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
-    dfree(c->d_V); dfree(c->d_w); dfree(c->d_vj); dfree(c->d_qw); dfree(c->d_gs); dfree(c->d_gi);
-    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->self) { solver_free(*c->self); delete c->self; }
+    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_trace); dfree(c->d_vj);
     delete c;
 }
 
 extern "C" fr_status fr_set_option(fr_ctx c, const char* name, int64_t value) {
     if (!c || !name) return bad("fr_set_option: null argument");
-    if (!strcmp(name, "keep_blocks")) { c->keep_blocks = value != 0; return FR_OK; }
-    if (!strcmp(name, "graph")) { c->use_graph = value != 0; gmres_release(c); return FR_OK; }
+    Solver& sv = *c->self;
+    if (!strcmp(name, "keep_blocks")) { sv.keep_blocks = value != 0; return FR_OK; }
+    if (!strcmp(name, "graph")) { sv.use_graph = value != 0; gmres_release(sv); return FR_OK; }
     return bad("fr_set_option: unknown option");
 }
 
@@ -267,29 +240,31 @@ static fr_status ready(fr_ctx c) {
     return FR_OK;
 }
 
+static KArgs plain_args(const double* q, const double* v, double* out, double* out2) {
+    KArgs a{};
+    a.q = q; a.v = v; a.out = out; a.out2 = out2;
+    return a;
+}
+
 extern "C" fr_status fr_residual(fr_ctx c, const double* q, double* R, void* stream) {
     FR_TRY(ready(c));
     if (!q || !R) return bad("fr_residual: null argument");
-    KArgs a{};
-    a.E = c->E; a.q = q; a.out = R;
-    return launch_residual(c, MODE_R, a, (hipStream_t)stream);
+    return solver_fused(*c->self, MODE_R, plain_args(q, nullptr, R, nullptr), (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_jvp(fr_ctx c, const double* q, const double* v, double* Jv, double* R_or_null, void* stream) {
     FR_TRY(ready(c));
     if (!q || !v || !Jv) return bad("fr_jvp: null argument");
-    KArgs a{};
-    a.E = c->E; a.q = q; a.v = v; a.out = Jv; a.out2 = R_or_null;
-    return launch_residual(c, MODE_JVP, a, (hipStream_t)stream);
+    return solver_fused(*c->self, MODE_JVP, plain_args(q, v, Jv, R_or_null), (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_bdf_operator(fr_ctx c, const double* q, const double* v, double c_time, double inv_dtau,
                                      double* Av, void* stream) {
     FR_TRY(ready(c));
     if (!q || !v || !Av) return bad("fr_bdf_operator: null argument");
-    KArgs a{};
-    a.E = c->E; a.q = q; a.v = v; a.out = Av; a.c_time = c_time; a.inv_dtau = inv_dtau;
-    return launch_residual(c, MODE_AOP, a, (hipStream_t)stream);
+    KArgs a = plain_args(q, v, Av, nullptr);
+    a.c_time = c_time; a.inv_dtau = inv_dtau;
+    return solver_fused(*c->self, MODE_AOP, a, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_vjp(fr_ctx c, const double* q, const double* w, double* JTw, void* stream) {
@@ -303,23 +278,21 @@ extern "C" fr_status fr_block_jacobi_factor(fr_ctx c, const double* q, double c_
     FR_TRY(ready(c));
     if (!q) return bad("fr_block_jacobi_factor: null argument");
     if (prec < FR_FP64 || prec > FR_BF16) return bad("fr_block_jacobi_factor: unknown precision");
+    Solver& sv = *c->self;
     hipStream_t s = (hipStream_t)stream;
-    const size_t nb = 4 * (size_t)c->Np, nbb = (size_t)c->E * nb * nb;
-    FR_TRY(dalloc(&c->d_blk, nbb));
-    if (!c->d_inv) FR_TRY(dalloc((double**)&c->d_inv, nbb));   // sized for FP64, reused by any precision
-    FR_TRY(launch_block_assembly(c, q, c_time, inv_dtau, s));
-    if (c->keep_blocks) {
-        FR_TRY(dalloc(&c->d_blk_keep, nbb));
-        FR_HIP(hipMemcpyAsync(c->d_blk_keep, c->d_blk, nbb * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    FR_TRY(launch_block_invert(c, prec, s));
-    // a zero pivot leaves a flag; reading it synchronises once per refresh
-    FR_HIP(hipMemcpyAsync(c->h_scal + 1024, c->d_scal + SC_STATUS, sizeof(int), hipMemcpyDeviceToHost, s));
+    FR_TRY(solver_ensure_blocks(sv));
+    KArgs a{};
+    a.c_time = c_time; a.inv_dtau = inv_dtau;
+    FR_TRY(launch_block_assembly(sv, q, a, s));
+    if (sv.keep_blocks) FR_HIP(hipMemcpyAsync(sv.d_blk_keep, sv.d_blk, sv.Btot * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // a zero pivot marks the case status; reading it synchronises once per refresh
+    FR_HIP(hipMemsetAsync(sv.d_gi, 0, GI_STRIDE * sizeof(int), s));
+    FR_TRY(launch_block_invert(sv, prec, nullptr, s));
+    int* flags = reinterpret_cast<int*>(sv.h_pin);
+    FR_HIP(hipMemcpyAsync(flags, sv.d_gi, GI_STRIDE * sizeof(int), hipMemcpyDeviceToHost, s));
     FR_HIP(hipStreamSynchronize(s));
-    int flag;
-    memcpy(&flag, c->h_scal + 1024, sizeof(int));
-    if (flag) {
-        c->inv_prec = -1;
+    if (flags[GI_STATUS] == 3) {
+        sv.inv_prec = -1;
         fr_set_error("fr_block_jacobi_factor: singular element block");
         return FR_ENOCONV;
     }
@@ -330,7 +303,7 @@ extern "C" fr_status fr_block_jacobi_apply(fr_ctx c, const double* r, double* z,
     FR_TRY(ready(c));
     if (!r || !z) return bad("fr_block_jacobi_apply: null argument");
     if (r == z) return bad("fr_block_jacobi_apply: r and z may not alias");
-    return launch_block_apply(c, r, z, (hipStream_t)stream);
+    return launch_block_apply(*c->self, r, z, nullptr, 0, (hipStream_t)stream);
 }
 
 // blocks as assembled (column-major per element) -> caller's array row-major
@@ -347,98 +320,97 @@ __global__ void k_transpose_blocks(size_t E, int nb, const double* __restrict__ 
 extern "C" fr_status fr_get_blocks(fr_ctx c, double* blk, void* stream) {
     FR_TRY(ready(c));
     if (!blk) return bad("fr_get_blocks: null argument");
-    if (!c->d_blk_keep) return bad("fr_get_blocks: enable keep_blocks before fr_block_jacobi_factor");
+    const Solver& sv = *c->self;
+    if (!sv.d_blk_keep) return bad("fr_get_blocks: enable keep_blocks before fr_block_jacobi_factor");
     const int nb = 4 * c->Np;
     const size_t tot = (size_t)c->E * nb * nb;
     hipLaunchKernelGGL(k_transpose_blocks, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       (size_t)c->E, nb, c->d_blk_keep, blk);
+                       (size_t)c->E, nb, sv.d_blk_keep, blk);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
-
-// ----------------------------------------------------------------------------- Newton / BDF2
-namespace {
-
-// work vectors inside d_w: 0: b, 1: R, 2: Q^n, 3: Q^{n-1}, 4-6: GMRES (r, w, z), 7: dq
-enum { WB = 0, WR, WQN, WQNM1, WRES, WW, WZ, WDQ, NWORK };
-
-fr_status ensure_krylov(fr_ctx c, int m) {
-    if (c->kry_m < m || !c->d_V) {
-        gmres_release(c);
-        dfree(c->d_V); c->d_V = nullptr;
-        dfree(c->d_gs); c->d_gs = nullptr;
-        FR_TRY(dalloc(&c->d_V, (size_t)(m + 1) * c->N()));
-        FR_TRY(dalloc(&c->d_gs, gmres_state_doubles(m)));
-        c->kry_m = m;
-    }
-    if (!c->d_w) FR_TRY(dalloc(&c->d_w, (size_t)NWORK * c->N()));
-    if (!c->d_qw) FR_TRY(dalloc(&c->d_qw, c->N()));
-    if (!c->d_gi) FR_TRY(dalloc(&c->d_gi, (size_t)8));
-    if (!c->ws) {
-        FR_HIP(hipStreamCreateWithFlags(&c->ws, hipStreamNonBlocking));
-        FR_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
-        FR_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-    }
-    return FR_OK;
-}
-
-double* wv(fr_ctx c, int i) { return c->d_w + (size_t)i * c->N(); }
-
-// 2-norm of the first N entries of x (synchronises)
-fr_status norm2(fr_ctx c, size_t N, const double* x, double& out, hipStream_t s) {
-    FR_TRY(la_krylov(c, N, x, 0, nullptr, 0, x, nullptr, true, c->d_scal + SC_NRM, s));
-    FR_HIP(hipMemcpyAsync(c->h_scal, c->d_scal + SC_NRM, sizeof(double), hipMemcpyDeviceToHost, s));
-    FR_HIP(hipStreamSynchronize(s));
-    out = std::sqrt(c->h_scal[0]);
-    return FR_OK;
-}
-
-}  // namespace
 
 extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q_io, const double* q_nm1, const fr_step_opts* o,
                                   fr_step_stats* h_stats, void* stream) {
     FR_TRY(ready(c));
     if (!q_io || !o) return bad("fr_bdf2_step: null argument");
-    if (!(o->dt > 0.0) || o->krylov < 1 || o->krylov > 60 || o->max_lin_it < 1 || o->max_newton < 0 || o->jac_lag < 1 ||
-        o->prec < FR_FP64 || o->prec > FR_BF16)
-        return bad("fr_bdf2_step: invalid options");
-    FR_TRY(ensure_krylov(c, o->krylov));
-    // the step runs on the context stream, ordered after and before the caller's stream
-    hipStream_t cs = (hipStream_t)stream;
-    FR_HIP(hipEventRecord(c->ev_in, cs));
-    FR_HIP(hipStreamWaitEvent(c->ws, c->ev_in, 0));
-    hipStream_t s = c->ws;
-    const size_t N = c->N(), EN = (size_t)c->E * c->Np;
-    const double a0 = q_nm1 ? 1.5 : 1.0, a1 = q_nm1 ? -2.0 : -1.0, a2 = q_nm1 ? 0.5 : 0.0;
-    const double ct = a0 / o->dt;
-    double* q = c->d_qw;   // Newton iterate in a context-owned buffer
-    FR_HIP(hipMemcpyAsync(q, q_io, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    FR_TRY(launch_cons(c, q, wv(c, WQN), s));
-    if (q_nm1) FR_TRY(launch_cons(c, q_nm1, wv(c, WQNM1), s));
-    fr_step_stats st{0, 0, 0, 0.0, 0.0};
-    fr_status ret = FR_OK;
-    for (int m = 0;; ++m) {
-        FR_TRY(fr_residual(c, q, wv(c, WR), s));
-        FR_TRY(launch_bdf_rhs(c, q, wv(c, WQN), q_nm1 ? wv(c, WQNM1) : nullptr, wv(c, WR), a0, a1, a2, o->dt,
-                              wv(c, WB), s));
-        double res;
-        FR_TRY(norm2(c, EN, wv(c, WB), res, s));   // mass rows
-        if (!std::isfinite(res)) { fr_set_error("non-finite nonlinear residual"); ret = FR_ENONFINITE; break; }
-        if (m == 0) st.res0 = res;
-        st.res_final = res;
-        if (res <= o->tol_abs || res <= o->tol_pseudo * st.res0) { st.converged = 1; break; }
-        if (m >= o->max_newton) { ret = FR_ENOCONV; fr_set_error("Newton iteration limit reached"); break; }
-        if (m % o->jac_lag == 0) FR_TRY(fr_block_jacobi_factor(c, q, ct, o->inv_dtau, o->prec, s));
-        GmresResult gm;
-        FR_TRY(gmres_device(c, q, wv(c, WB), wv(c, WDQ), o->krylov, o->tol_res, o->max_lin_it, ct, o->inv_dtau,
-                            o->prec, gm, s));
-        st.gmres_its += gm.its;
-        FR_TRY(la_axpy(N, 1.0, wv(c, WDQ), q, s));
-        st.newton_its++;
+    double* qs[1] = {q_io};
+    const double* qm[1] = {q_nm1};
+    return solver_step(*c->self, qs, qm, o, h_stats, (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_autotune(fr_ctx c, const char* cache_path, void* stream) {
+    FR_TRY(ready(c));
+    return solver_autotune(*c->self, cache_path, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------------------------- batches
+extern "C" fr_status fr_batch_create(const fr_ctx* ctxs, int32_t n, fr_batch* out) {
+    if (!ctxs || !out || n < 1) return bad("fr_batch_create: invalid argument");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return bad("fr_batch_create: null context");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return bad("fr_batch_create: a context appears twice");
     }
-    FR_HIP(hipMemcpyAsync(q_io, q, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    FR_HIP(hipEventRecord(c->ev_out, s));
-    FR_HIP(hipStreamWaitEvent(cs, c->ev_out, 0));
-    if (h_stats) *h_stats = st;
-    return ret;
+    fr_batch b = new fr_batch_s();
+    fr_status st = solver_init(b->sv, ctxs, n);
+    if (st != FR_OK) {
+        solver_free(b->sv);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return FR_OK;
+}
+
+extern "C" void fr_batch_destroy(fr_batch b) {
+    if (!b) return;
+    solver_free(b->sv);
+    delete b;
+}
+
+extern "C" fr_status fr_batch_layout(fr_batch b, int64_t* n_total, int64_t* offsets) {
+    if (!b || !n_total) return bad("fr_batch_layout: null argument");
+    *n_total = (int64_t)b->sv.Ntot;
+    if (offsets)
+        for (int c = 0; c < b->sv.n; ++c) offsets[c] = (int64_t)b->sv.off[c];
+    return FR_OK;
+}
+
+static fr_status batch_ready(fr_batch b) {
+    if (!b) return bad("null batch");
+    for (fr_ctx c : b->sv.cs)
+        if (!c->geometry_set) return bad("fr_set_geometry has not been called for every case");
+    return FR_OK;
+}
+
+extern "C" fr_status fr_batch_residual(fr_batch b, const double* q, double* R, void* stream) {
+    FR_TRY(batch_ready(b));
+    if (!q || !R) return bad("fr_batch_residual: null argument");
+    return solver_fused(b->sv, MODE_R, plain_args(q, nullptr, R, nullptr), (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_batch_jvp(fr_batch b, const double* q, const double* v, double* Jv, void* stream) {
+    FR_TRY(batch_ready(b));
+    if (!q || !v || !Jv) return bad("fr_batch_jvp: null argument");
+    return solver_fused(b->sv, MODE_JVP, plain_args(q, v, Jv, nullptr), (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_batch_bdf2_step(fr_batch b, double* const* q, const double* const* q_nm1,
+                                        const fr_step_opts* opts, fr_step_stats* h_stats, void* stream) {
+    FR_TRY(batch_ready(b));
+    if (!q || !opts) return bad("fr_batch_bdf2_step: null argument");
+    return solver_step(b->sv, q, q_nm1, opts, h_stats, (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_batch_set_option(fr_batch b, const char* name, int64_t value) {
+    if (!b || !name) return bad("fr_batch_set_option: null argument");
+    if (!strcmp(name, "graph")) { b->sv.use_graph = value != 0; gmres_release(b->sv); return FR_OK; }
+    return bad("fr_batch_set_option: unknown option");
+}
+
+extern "C" fr_status fr_batch_autotune(fr_batch b, const char* cache_path, void* stream) {
+    FR_TRY(batch_ready(b));
+    return solver_autotune(b->sv, cache_path, (hipStream_t)stream);
 }

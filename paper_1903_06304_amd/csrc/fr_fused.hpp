@@ -1,0 +1,503 @@
+// Fused per-element FR/CPR residual kernel for gfx950, shared by the per-order
+// translation units (fr_fused_p1..p4.hip).  One kernel produces, by mode,
+//   R      the residual (paper Eq. cpr_ns with the moving-mesh terms),
+//   JVP    the exact forward tangent Jv (and optionally R),
+//   AOP    the Newton operator  Av = inv_dtau Gamma v + c_time M v - Jv,
+//   BLK    one seeded column of every element's diagonal block of that operator.
+//
+// Work mapping: a workgroup tile holds EPB elements of one case; each element owns
+// NT = max(Np, 4n) lanes, lane `lt` acting as solution point lt (lt < Np) and as flux
+// point lt (lt < 4n, face lt/n, point lt%n).  Element data live in LDS between the
+// stages:
+//   1. own state and the four neighbour states      [solution points]
+//   2. uncorrected chain-rule gradient               [solution points]
+//   3. own and neighbour traces, common flux         [flux points]  Eq. (Rosanov), BR2
+//   4. corrected gradient, fluxes f, g, q^c          [solution points]
+//   5. F^num - F^loc at the flux points              [flux points]  Eq. (norm_f_2)
+//   6. chain-rule divergence, moving-mesh terms, Radau lift -> output
+// The grid is persistent and XCD-aware: workgroup b runs on XCD b % 8 and walks the
+// tiles of a contiguous eighth of the tile list, so an element and its face
+// neighbours (whose states are re-read here) are mostly served by the same L2.
+// Tiles of many cases (a batch) form one list; a tile finds its case by binary search
+// over the group's tile prefix and reads the case's metrics, offsets and constants
+// from its descriptor.
+#pragma once
+#include "fr_internal.hpp"
+
+namespace fused {
+
+template <int P>
+struct Sz {
+    static constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = (Np > NF ? Np : NF);
+};
+
+// elements per workgroup for a workgroup width of LANES
+template <int P, int LANES>
+struct Shape {
+    static constexpr int NT = Sz<P>::NT;
+    static constexpr int EPB = (LANES / NT) > 0 ? (LANES / NT) : 1;
+    static constexpr int threads = EPB * NT;
+};
+
+__device__ __forceinline__ int line_pt(int n, int f, int k, int a) {
+    return f < 2 ? a + n * k : k + n * a;
+}
+
+template <int MODE, int K> struct ModeT { using T = Dual<K>; };
+template <int K> struct ModeT<MODE_R, K> { using T = double; };
+
+// own state with the tangent the mode asks for: JVP/AOP carry v; block mode seeds the
+// unit column seed0 (+k)
+template <class T> struct Seed;
+template <> struct Seed<double> {
+    __device__ static double load(const KArgs& a, const double* q, const double*, unsigned gid, int) { return q[gid]; }
+};
+template <int K> struct Seed<Dual<K>> {
+    __device__ static Dual<K> load(const KArgs& a, const double* q, const double* v, unsigned gid, int col) {
+        Dual<K> r; r.v = q[gid];
+        if (v) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) r.d[k] = v[gid];
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) r.d[k] = (col == a.seed0 + k) ? 1.0 : 0.0;
+        }
+        return r;
+    }
+};
+
+// neighbour state: block mode seeds only when the neighbour is the element itself
+// (periodic single-element rows)
+template <class T> struct NbLoad;
+template <> struct NbLoad<double> {
+    __device__ static double load(const KArgs&, const double* q, const double*, unsigned gid, int, bool) { return q[gid]; }
+};
+template <int K> struct NbLoad<Dual<K>> {
+    __device__ static Dual<K> load(const KArgs& a, const double* q, const double* v, unsigned gid, int col, bool self) {
+        Dual<K> r; r.v = q[gid];
+        if (v) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) r.d[k] = v[gid];
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) r.d[k] = (self && col == a.seed0 + k) ? 1.0 : 0.0;
+        }
+        return r;
+    }
+};
+
+// (q^- + q^+)/2 of one variable, recomputed from the own trace and the jump
+template <class T>
+__device__ __forceinline__ T am_avg(const T* sv, const double* lam, int f, int k, const T& jump, int n) {
+    T acc = cst<T>(0.0);
+    for (int b = 0; b < n; ++b) acc = acc + lam[b] * sv[line_pt(n, f, k, b)];
+    return acc + 0.5 * jump;
+}
+
+// Values that are uniform across the workgroup but loaded from memory that the kernel
+// also writes to are moved to scalar registers explicitly (the compiler cannot prove
+// that they are not clobbered between tiles, so it keeps them in vector registers).
+__device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ unsigned long long rfl(unsigned long long x) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double rfl(double x) {
+    return __longlong_as_double((long long)rfl((unsigned long long)__double_as_longlong(x)));
+}
+template <class T> __device__ __forceinline__ T* rfl(T* p) {
+    return reinterpret_cast<T*>(rfl((unsigned long long)reinterpret_cast<uintptr_t>(p)));
+}
+
+// the descriptor of a case, in scalar registers
+__device__ __forceinline__ CaseDev load_case(const CaseDev* p) {
+    CaseDev c;
+    c.E = rfl(p->E);
+    c.Np = rfl(p->Np);
+    c.off = rfl(p->off);
+    c.boff = rfl(p->boff);
+    c.g.sp = rfl(p->g.sp);
+    c.g.fp = rfl(p->g.fp);
+    c.g.nbr = rfl(p->g.nbr);
+    const PhysConst& s = p->pc;
+    PhysConst& d = c.pc;
+    d.gam = rfl(s.gam); d.Rg = rfl(s.Rg); d.Cp = rfl(s.Cp); d.inv_gm1 = rfl(s.inv_gm1); d.gRg = rfl(s.gRg);
+    d.inv_Cp = rfl(s.inv_Cp); d.inv_Rg = rfl(s.inv_Rg); d.mu_re = rfl(s.mu_re); d.kc_re = rfl(s.kc_re);
+    d.eps_min = rfl(s.eps_min); d.br2 = rfl(s.br2);
+    return c;
+}
+
+// member of a group that owns tile t (binary search over the tile prefix), uniform
+__device__ __forceinline__ int find_member(const GroupArgs& ga, int t) {
+    int lo = 0, hi = ga.nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rfl(ga.pfx[mid]) <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// first tile of the range walked by this workgroup, and the end of that range
+__device__ __forceinline__ void xcd_range(int ntiles, int& t0, int& tend, int& stride) {
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int t8 = (ntiles + 7) >> 3;
+    t0 = xcd * t8 + slot;
+    tend = min((xcd + 1) * t8, ntiles);
+    stride = per;
+}
+
+template <int P, bool VISC, bool MOV, int MODE, int K, int LANES>
+__global__ void __launch_bounds__((Shape<P, LANES>::threads))
+k_fused(GroupArgs ga, KArgs a, OpTab op) {
+    using T = typename ModeT<MODE, K>::T;
+    constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
+    constexpr int EPB = Shape<P, LANES>::EPB;
+    constexpr int NW = MOV ? 12 : 8;
+    static_assert(NW <= 16, "flux fields alias the neighbour staging area");
+    __shared__ T s_q[EPB][4][Np];
+    __shared__ T s_n[EPB][16][Np];      // neighbour states [face*4 + var]; later f, g (, q^c)
+    __shared__ T s_g[EPB][VISC ? 6 : 1][Np];
+    __shared__ T s_F[EPB][NF][4];       // F^num, then F^num - F^loc
+    __shared__ T s_dq[EPB][NF][VISC ? 3 : 1];
+    __shared__ double s_S[EPB][NF][3];  // element-oriented S, S . v_g
+    __shared__ double s_D[n * n];       // operator tables (lane-dependent indexing goes to LDS)
+    __shared__ double s_lam[2][n], s_gam[2][n];
+
+    const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
+    if (threadIdx.x < n) {
+        s_lam[0][threadIdx.x] = op.lamL[threadIdx.x]; s_lam[1][threadIdx.x] = op.lamR[threadIdx.x];
+        s_gam[0][threadIdx.x] = op.gamL[threadIdx.x]; s_gam[1][threadIdx.x] = op.gamR[threadIdx.x];
+    }
+    const int i = lt % n, j = lt / n;
+    int tile, tend, tstride;
+    xcd_range(ga.ntiles, tile, tend, tstride);
+    for (; tile < tend; tile += tstride) {
+        // ---- the tile's case (uniform across the workgroup)
+        const int lo = find_member(ga, tile);
+        const int cid = rfl(ga.ids[lo]);
+        if (a.flags && rfl(a.flags[cid * GI_STRIDE + a.flag])) continue;
+        const CaseDev cd = load_case(ga.cases + cid);
+        const PhysConst& pc = cd.pc;
+        const Geo g = cd.g;
+        const int E = cd.E;
+        const int e = (tile - rfl(ga.pfx[lo])) * EPB + el;
+        const bool act = e < E;
+        const unsigned EN = (unsigned)E * Np;   // state arrays hold < 2^31 entries (checked at creation)
+        const double* q = a.q + cd.off;
+        const double* v = a.v ? a.v + cd.off : nullptr;
+        __syncthreads();   // the previous tile's readers of s_n / s_F are done
+        // ---- stage 1: own state and neighbour states into LDS
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) s_q[el][vv][lt] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + lt);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int nb = g.nbr[e * 4 + f] >> 3;
+                const unsigned nid = (unsigned)nb * Np + lt;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv)
+                    s_n[el][f * 4 + vv][lt] = NbLoad<T>::load(a, q, v, vv * EN + nid, vv * Np + lt, nb == e);
+            }
+        }
+        __syncthreads();
+        // ---- stage 2: own uncorrected gradient (kept in LDS only)
+        if (VISC && act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            const double xix = g.sp[G_XIX * EN + id], xiy = g.sp[G_XIY * EN + id];
+            const double etx = g.sp[G_ETX * EN + id], ety = g.sp[G_ETY * EN + id];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T dxi = cst<T>(0.0), deta = cst<T>(0.0);
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    dxi = dxi + s_D[i * n + b] * s_q[el][c + 1][b + n * j];
+                    deta = deta + s_D[j * n + b] * s_q[el][c + 1][i + n * b];
+                }
+                s_g[el][2 * c][lt] = xix * dxi + etx * deta;
+                s_g[el][2 * c + 1][lt] = xiy * dxi + ety * deta;
+            }
+        }
+        __syncthreads();
+        // ---- stage 3: own and neighbour traces, common flux at the flux points
+        if (act && lt < NF) {
+            const int f = lt / n, k = lt % n;
+            const int pk = g.nbr[e * 4 + f];
+            const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
+            const double* lam = s_lam[f & 1];
+            const double* lamn = s_lam[nf & 1];
+            const unsigned FE = (unsigned)E * NF;
+            const unsigned sid = (unsigned)e * NF + lt;
+            const double nx = g.fp[F_NX * FE + sid], ny = g.fp[F_NY * FE + sid];
+            const double sc = g.fp[F_SC * FE + sid];
+            const double ugf = MOV ? g.fp[F_UG * FE + sid] : 0.0;
+            const double vgf = MOV ? g.fp[F_VG * FE + sid] : 0.0;
+            T fn[4], dq[4];
+            {
+                T qm[4], qp[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    T am = cst<T>(0.0), ap = cst<T>(0.0);
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        am = am + lam[b] * s_q[el][vv][line_pt(n, f, k, b)];
+                        ap = ap + lamn[b] * s_n[el][f * 4 + vv][line_pt(n, nf, k2, b)];
+                    }
+                    qm[vv] = am;
+                    qp[vv] = ap;
+                }
+                fr_common_inviscid<T>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
+            }
+            if (VISC) {
+                T gm[6], gp[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    T am = cst<T>(0.0);
+#pragma unroll
+                    for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[el][c][line_pt(n, f, k, b)];
+                    gm[c] = am;
+                    gp[c] = cst<T>(0.0);
+                }
+                // neighbour's uncorrected gradient along the line through its face point, traced
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const int sp = line_pt(n, nf, k2, b);
+                    const int is = sp % n, js = sp / n;
+                    const unsigned gid = (unsigned)nb * Np + sp;
+                    const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
+                    const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        T dxi = cst<T>(0.0), deta = cst<T>(0.0);
+#pragma unroll
+                        for (int m = 0; m < n; ++m) {
+                            dxi = dxi + s_D[is * n + m] * s_n[el][f * 4 + c + 1][m + n * js];
+                            deta = deta + s_D[js * n + m] * s_n[el][f * 4 + c + 1][is + n * m];
+                        }
+                        gp[2 * c] = gp[2 * c] + lamn[b] * (xix * dxi + etx * deta);
+                        gp[2 * c + 1] = gp[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
+                    }
+                }
+                // q^com velocity = average of the two traces = q^- + dq/2
+                const T qcu = am_avg<T>(s_q[el][1], lam, f, k, dq[1], n);
+                const T qcv = am_avg<T>(s_q[el][2], lam, f, k, dq[2], n);
+                T dqh[3];
+                fr_common_viscous<T>(pc, dq, qcu, qcv, gm, gp, nx, ny, g.fp[F_CC * FE + sid], fn, dqh);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s_dq[el][lt][c] = dqh[c];
+            }
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) s_F[el][lt][vv] = sc * fn[vv];
+            s_S[el][lt][0] = sc * nx;                                  // element-oriented S
+            s_S[el][lt][1] = sc * ny;
+            s_S[el][lt][2] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;   // S . v_g
+        }
+        __syncthreads();
+
+        // ---- stage 4: corrected gradient, pointwise fluxes (into the staging area)
+        T (*s_w)[Np] = s_n[el];
+        T qs[4];
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            const double ij = g.sp[G_IJ * EN + id];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[el][vv][lt];
+            T gu[2], gv[2], gT[2];
+            if (VISC) {
+#pragma unroll
+                for (int d = 0; d < 2; ++d) { gu[d] = s_g[el][d][lt]; gv[d] = s_g[el][2 + d][lt]; gT[d] = s_g[el][4 + d][lt]; }
+                const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
+                const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
+                T* gr[3] = {gu, gv, gT};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    T cx = (s_S[el][fp0][0] * gL_i) * s_dq[el][fp0][c] + (s_S[el][fp1][0] * gR_i) * s_dq[el][fp1][c]
+                         + (s_S[el][fp2][0] * gL_j) * s_dq[el][fp2][c] + (s_S[el][fp3][0] * gR_j) * s_dq[el][fp3][c];
+                    T cy = (s_S[el][fp0][1] * gL_i) * s_dq[el][fp0][c] + (s_S[el][fp1][1] * gR_i) * s_dq[el][fp1][c]
+                         + (s_S[el][fp2][1] * gL_j) * s_dq[el][fp2][c] + (s_S[el][fp3][1] * gR_j) * s_dq[el][fp3][c];
+                    gr[c][0] = gr[c][0] + ij * cx;
+                    gr[c][1] = gr[c][1] + ij * cy;
+                }
+            }
+            T fl[4], gl[4], qc[4];
+            fr_point_flux<T, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                s_w[vv][lt] = fl[vv];
+                s_w[4 + vv][lt] = gl[vv];
+                if (MOV) s_w[8 + vv][lt] = qc[vv];
+            }
+        }
+        __syncthreads();
+
+        // ---- stage 5: F^num - F^loc, F^loc = S.(Pi f, Pi g) - (S.v_g) Pi q^c
+        if (act && lt < NF) {
+            const int f = lt / n, k = lt % n;
+            const double* lam = s_lam[f & 1];
+            const double Sx = s_S[el][lt][0], Sy = s_S[el][lt][1], Svg = s_S[el][lt][2];
+#pragma unroll 1
+            for (int vv = 0; vv < 4; ++vv) {
+                T acc = cst<T>(0.0);
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const int sp = line_pt(n, f, k, b);
+                    T w = Sx * s_w[vv][sp] + Sy * s_w[4 + vv][sp];
+                    if (MOV) w = w - Svg * s_w[8 + vv][sp];
+                    acc = acc + lam[b] * w;
+                }
+                s_F[el][lt][vv] = s_F[el][lt][vv] - acc;
+            }
+        }
+        __syncthreads();
+
+        // ---- stage 6: divergence + moving-mesh terms + Radau lift, one variable at a time
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            double geo[NGSP] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < (MOV ? NGSP : G_UG); ++c) geo[c] = g.sp[c * EN + id];
+            const double axi = MOV ? geo[G_UG] * geo[G_XIX] + geo[G_VG] * geo[G_XIY] : 0.0;
+            const double aet = MOV ? geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY] : 0.0;
+            double ct = a.c_time, idt = a.inv_dtau;
+            if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
+            double tt[4] = {0.0, 0.0, 0.0, 0.0};   // time terms (Newton operator)
+            if constexpr (MODE == MODE_AOP) {
+                double qv[4], x[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) { qv[vv] = qs[vv].v; x[vv] = qs[vv].d[0]; }
+                fr_time_apply<double, double>(pc, qv, geo[G_UG], geo[G_VG], idt, ct, x, tt);
+            }
+            double* out = a.out + ((MODE == MODE_BLK) ? cd.boff : cd.off);
+#pragma unroll 1
+            for (int vv = 0; vv < 4; ++vv) {
+                T dfx = cst<T>(0.0), dfe = cst<T>(0.0), dgx = cst<T>(0.0), dge = cst<T>(0.0);
+                T dqx = cst<T>(0.0), dqe = cst<T>(0.0);
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const double Dx = s_D[i * n + b], De = s_D[j * n + b];
+                    dfx = dfx + Dx * s_w[vv][b + n * j];
+                    dgx = dgx + Dx * s_w[4 + vv][b + n * j];
+                    dfe = dfe + De * s_w[vv][i + n * b];
+                    dge = dge + De * s_w[4 + vv][i + n * b];
+                    if (MOV) {
+                        dqx = dqx + Dx * s_w[8 + vv][b + n * j];
+                        dqe = dqe + De * s_w[8 + vv][i + n * b];
+                    }
+                }
+                T vol = geo[G_XIX] * dfx + geo[G_ETX] * dfe + geo[G_XIY] * dgx + geo[G_ETY] * dge;
+                if (MOV) vol = vol - axi * dqx - aet * dqe;
+                T cor = s_gam[0][i] * s_F[el][0 * n + j][vv] + s_gam[1][i] * s_F[el][1 * n + j][vv]
+                      + s_gam[0][j] * s_F[el][2 * n + i][vv] + s_gam[1][j] * s_F[el][3 * n + i][vv];
+                const T R = -(vol + geo[G_IJ] * cor);
+                if constexpr (MODE == MODE_R) {
+                    out[vv * EN + id] = val(R);
+                } else if constexpr (MODE == MODE_JVP) {
+                    out[vv * EN + id] = R.d[0];
+                    if (a.out2) a.out2[cd.off + vv * EN + id] = R.v;
+                } else if constexpr (MODE == MODE_AOP) {
+                    const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                    out[vv * EN + id] = ttv - R.d[0];
+                } else {
+                    // block columns seed0..seed0+K-1 of element e, column-major [E][nb][nb]
+                    constexpr int nbk = 4 * Np;
+                    double* blk = out + (size_t)e * nbk * nbk;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const int col = a.seed0 + k;
+                        if (col < nbk) blk[(size_t)col * nbk + vv * Np + lt] = -R.d[k];
+                    }
+                }
+            }
+            if constexpr (MODE == MODE_BLK) {
+                // time terms on the diagonal point block of the seeded columns
+                constexpr int nbk = 4 * Np;
+                double* blk = out + (size_t)e * nbk * nbk;
+                double qv[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) qv[vv] = qs[vv].v;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int col = a.seed0 + k;
+                    if (col < nbk && col % Np == lt) {
+                        double x[4] = {0.0, 0.0, 0.0, 0.0}, t4[4];
+                        x[col / Np] = 1.0;
+                        fr_time_apply<double, double>(pc, qv, geo[G_UG], geo[G_VG], idt, ct, x, t4);
+#pragma unroll
+                        for (int vv = 0; vv < 4; ++vv) blk[(size_t)col * nbk + vv * Np + lt] += t4[vv];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// grid of a launch: one workgroup per tile by default, else the tuned persistent size;
+// always a multiple of 8 (the XCD count) so every XCD walks an equal tile range
+inline unsigned grid_of(int ntiles, int grid) {
+    long long g = grid > 0 ? grid : ntiles;
+    g = ((g + 7) / 8) * 8;
+    if (g < 8) g = 8;
+    return (unsigned)g;
+}
+
+template <int P, bool VISC, bool MOV, int MODE, int LANES>
+fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, hipStream_t s) {
+    using SH = Shape<P, LANES>;
+    GroupArgs ga;
+    ga.cases = sv.d_cases;
+    ga.ids = gr.d_ids;
+    ga.pfx = gr.tile_pfx(SH::EPB);
+    ga.nmem = (int)gr.ids.size();
+    ga.ntiles = gr.ntiles(SH::EPB);
+    if (!ga.pfx) { fr_set_error("tile prefix missing for this workgroup shape"); return FR_EINVAL; }
+    if (ga.ntiles == 0) return FR_OK;
+    const OpTab& op = sv.cs[gr.ids[0]]->op;
+    hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s,
+                       ga, a, op);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { fr_set_error(std::string("k_fused launch: ") + hipGetErrorString(e)); return FR_EHIP; }
+    return FR_OK;
+}
+
+// workgroup widths built per mode: plain doubles 64/128/256 lanes, dual numbers 64/128
+template <int P, bool VISC, bool MOV, int MODE>
+fr_status run_lanes(const Solver& sv, const Group& gr, const KArgs& a, const Tune& t, hipStream_t s) {
+    constexpr bool dual = MODE != MODE_R;
+    const int lanes = t.lanes > 0 ? t.lanes : (dual ? 64 : 128);
+    switch (lanes) {
+        case 64: return run<P, VISC, MOV, MODE, 64>(sv, gr, a, t.grid, s);
+        case 128: return run<P, VISC, MOV, MODE, 128>(sv, gr, a, t.grid, s);
+        case 256:
+            if constexpr (!dual) return run<P, VISC, MOV, MODE, 256>(sv, gr, a, t.grid, s);
+            break;
+    }
+    fr_set_error("unsupported workgroup width");
+    return FR_EINVAL;
+}
+
+template <int P, bool VISC, bool MOV>
+fr_status run_mode(const Solver& sv, const Group& gr, int mode, const KArgs& a, const Tune& t, hipStream_t s) {
+    switch (mode) {
+        case MODE_R: return run_lanes<P, VISC, MOV, MODE_R>(sv, gr, a, t, s);
+        case MODE_JVP: return run_lanes<P, VISC, MOV, MODE_JVP>(sv, gr, a, t, s);
+        case MODE_AOP: return run_lanes<P, VISC, MOV, MODE_AOP>(sv, gr, a, t, s);
+        case MODE_BLK: return run_lanes<P, VISC, MOV, MODE_BLK>(sv, gr, a, t, s);
+    }
+    fr_set_error("unknown residual mode");
+    return FR_EINVAL;
+}
+
+}  // namespace fused
+
+#define FR_FUSED_INSTANTIATE(P)                                                                          \
+    template <>                                                                                          \
+    fr_status launch_fused_p<P>(const Solver& sv, const Group& gr, int mode, const KArgs& a, const Tune& t, \
+                                hipStream_t s) {                                                         \
+        if (gr.visc)                                                                                     \
+            return gr.mov ? fused::run_mode<P, true, true>(sv, gr, mode, a, t, s)                         \
+                          : fused::run_mode<P, true, false>(sv, gr, mode, a, t, s);                       \
+        return gr.mov ? fused::run_mode<P, false, true>(sv, gr, mode, a, t, s)                            \
+                      : fused::run_mode<P, false, false>(sv, gr, mode, a, t, s);                          \
+    }

@@ -1,0 +1,4 @@
+// Fused residual / JVP / Newton-operator / block-column kernels for order p = 2.
+#include "fr_fused.hpp"
+
+FR_FUSED_INSTANTIATE(2)

@@ -1,14 +1,19 @@
-// Restarted, right-preconditioned FP64 GMRES(m) with its small dense state on the device.
+// Restarted, right-preconditioned FP64 GMRES(m) and the BDF2 dual-time Newton loop for
+// every case of a solver at once, with the small dense state of each case (Hessenberg
+// matrix, Givens rotations, least-squares right-hand side, counters) on the device.
 //
-// One restart cycle is a fixed sequence of launches:
-//   cycle init (g = beta e1, V_0 = r / beta) |
+// One restart cycle is a fixed sequence of launches over all cases:
+//   cycle init (per case: idle test, g = beta e1, V_0 = r / beta) |
 //   m x [ z = P^-1 V_j ; w = A z ; classical Gram-Schmidt twice (3 streaming passes) ;
 //         Givens update of column j and of g, convergence test ; V_{j+1} = w / h_{j+1,j} ] |
 //   y = H^-1 g ; x += P^-1 (V y) ; r = b - A x ; beta = |r|
-// The Givens kernel raises a device flag when |g_{j+1}| <= tol |b| (or on breakdown or
-// the iteration cap); every later launch of the cycle reads the flag and returns at once.
-// The sequence therefore contains no host decision and is captured once into a hipGraph
-// and replayed; the host synchronises once per cycle to read beta and the counters.
+// Per-case flags decide which cases a launch touches: a case whose Arnoldi process has
+// stopped (|g_{j+1}| <= tol |b|, breakdown, iteration cap) is skipped by the rest of the
+// cycle's Arnoldi launches; a case that did not start the cycle is skipped by its update
+// too.  The sequence holds no host decision, so it is captured once into a hipGraph and
+// replayed; the host synchronises once per cycle to read one "needs another cycle" flag
+// per case.  The Newton loop (paper Sec. 3.2) keeps per-case convergence on the device
+// as well and synchronises once per Newton iteration.
 #include <cmath>
 #include <cstring>
 
@@ -16,42 +21,92 @@
 
 namespace {
 
-// layout of d_gs (doubles) for restart length m
+// layout of one case's GMRES state (doubles) for restart length m
 struct GsLayout {
     int m, H, CS, SN, G, Y, H1, H2, NRM, BN, BETA, INVHN, SCALE0, total;
-    explicit GsLayout(int m_) : m(m_) {
+    __host__ __device__ explicit GsLayout(int m_) : m(m_) {
         H = 0;
         CS = H + (m + 1) * m;
         SN = CS + m;
         G = SN + m;
         Y = G + m + 1;
         H1 = Y + m;
-        H2 = H1 + 64;
-        NRM = H2 + 64;
-        BN = NRM + 64;
+        H2 = H1 + MAXV;
+        NRM = H2 + MAXV;
+        BN = NRM + 8;
         BETA = BN + 1;
         INVHN = BETA + 1;
         SCALE0 = INVHN + 1;
-        total = SCALE0 + 1;
+        total = ((SCALE0 + 1 + 7) / 8) * 8;
     }
 };
-enum { GI_DONE = 0, GI_CYC, GI_TOTAL, GI_MAXIT, GI_TOTAL_INT };
 
-// g = beta e1, counters of the cycle reset, scale of V_0
-__global__ void k_cycle_init(int m, double* gs, int* gi, GsLayout L) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double beta = gs[L.BETA];
-    for (int i = 0; i <= m; ++i) gs[L.G + i] = 0.0;
-    gs[L.G] = beta;
-    gs[L.SCALE0] = beta > 0.0 ? 1.0 / beta : 0.0;
+struct Ctl {
+    double* gs;
+    int gs_stride;
+    int* gi;
+    const CaseStep* step;
+    double* sum;
+    int n;
+};
+
+__device__ __forceinline__ int case_index() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
+// start of a solve: counters and flags of the solve
+__global__ void k_gm_start(Ctl k, int maxit) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    int* gi = k.gi + c * GI_STRIDE;
+    gi[GI_TOTAL] = 0;
     gi[GI_CYC] = 0;
-    gi[GI_DONE] = (beta > 0.0 && gi[GI_TOTAL] < gi[GI_MAXIT]) ? 0 : 1;
+    gi[GI_MAXIT] = maxit;
+    gi[GI_DONE] = 1;
+    gi[GI_IDLE] = 1;
 }
 
-// column j of the Hessenberg matrix, Givens rotations, convergence flag
-__global__ void k_givens(int j, int m, double tol, double* gs, int* gi, GsLayout L) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// beta = bn = |b|
+__global__ void k_gm_norm0(Ctl k, int m) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    if (k.gi[c * GI_STRIDE + GI_NDONE]) return;
+    const GsLayout L(m);
+    double* gs = k.gs + (size_t)c * k.gs_stride;
+    const double b = sqrt(gs[L.NRM]);
+    gs[L.BN] = b;
+    gs[L.BETA] = b;
+}
+
+// the case's test for another cycle (also used by the host through the summary)
+__device__ __forceinline__ bool wants_cycle(const int* gi, double beta, double bn, double tol) {
+    return !gi[GI_NDONE] && isfinite(beta) && beta > 0.0 && beta > tol * bn && gi[GI_TOTAL] < gi[GI_MAXIT];
+}
+
+// per case: does it take part in this cycle?  g = beta e1, scale of V_0
+__global__ void k_cycle_init(Ctl k, int m) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    const GsLayout L(m);
+    double* gs = k.gs + (size_t)c * k.gs_stride;
+    int* gi = k.gi + c * GI_STRIDE;
+    const double beta = gs[L.BETA], bn = gs[L.BN];
+    const bool run = wants_cycle(gi, beta, bn, k.step[c].tol_res);
+    gi[GI_IDLE] = run ? 0 : 1;
+    gi[GI_DONE] = run ? 0 : 1;
+    gi[GI_CYC] = 0;
+    if (!run) return;
+    for (int i = 0; i <= m; ++i) gs[L.G + i] = 0.0;
+    gs[L.G] = beta;
+    gs[L.SCALE0] = 1.0 / beta;
+}
+
+// column j of each case's Hessenberg matrix, Givens rotations, convergence flag
+__global__ void k_givens(Ctl k, int j, int m) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    int* gi = k.gi + c * GI_STRIDE;
     if (gi[GI_DONE]) return;
+    const GsLayout L(m);
+    double* gs = k.gs + (size_t)c * k.gs_stride;
     double* H = gs + L.H;
     double* cs = gs + L.CS;
     double* sn = gs + L.SN;
@@ -75,168 +130,257 @@ __global__ void k_givens(int j, int m, double tol, double* gs, int* gi, GsLayout
     gi[GI_CYC] = j + 1;
     gi[GI_TOTAL] += 1;
     gs[L.INVHN] = hn > 0.0 ? 1.0 / hn : 0.0;
-    const bool conv = fabs(g[j + 1]) <= tol * gs[L.BN];
+    const bool conv = fabs(g[j + 1]) <= k.step[c].tol_res * gs[L.BN];
     if (conv || !(hn > 0.0) || !isfinite(hn) || gi[GI_TOTAL] >= gi[GI_MAXIT] || j == m - 1) gi[GI_DONE] = 1;
 }
 
 // y = H^-1 g on the iterations of this cycle
-__global__ void k_backsub(int m, double* gs, const int* gi, GsLayout L) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_backsub(Ctl k, int m) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    const int* gi = k.gi + c * GI_STRIDE;
+    if (gi[GI_IDLE]) return;
+    const GsLayout L(m);
+    double* gs = k.gs + (size_t)c * k.gs_stride;
     const int jd = gi[GI_CYC];
     const double* H = gs + L.H;
     double* y = gs + L.Y;
     for (int i = jd - 1; i >= 0; --i) {
         double s = gs[L.G + i];
-        for (int k = i + 1; k < jd; ++k) s -= H[i * m + k] * y[k];
+        for (int q = i + 1; q < jd; ++q) s -= H[i * m + q] * y[q];
         y[i] = s / H[i * m + i];
     }
     for (int i = jd; i < m; ++i) y[i] = 0.0;
 }
 
-// out = scale * in, scale read on the device; skipped when *skip != 0
-__global__ void k_scale_dev(size_t N, const double* __restrict__ in, double* __restrict__ out, const double* scale,
-                            const int* skip) {
-    if (skip && *skip) return;
-    const double a = *scale;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x)
-        out[t] = a * in[t];
+// beta = |r| after the update; a non-finite beta retires the case; summary for the host
+__global__ void k_cycle_end(Ctl k, int m) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    const GsLayout L(m);
+    double* gs = k.gs + (size_t)c * k.gs_stride;
+    int* gi = k.gi + c * GI_STRIDE;
+    if (!gi[GI_IDLE]) {
+        const double beta = sqrt(gs[L.NRM]);
+        gs[L.BETA] = beta;
+        if (!isfinite(beta)) { gi[GI_STATUS] = 1; gi[GI_NDONE] = 1; }
+    }
+    double* s = k.sum + (size_t)c * SUM_STRIDE;
+    s[S_BN] = gs[L.BN];
+    s[S_BETA] = gs[L.BETA];
+    s[S_TOTAL] = gi[GI_TOTAL];
+    s[S_MORE] = (!gi[GI_IDLE] && gi[GI_CYC] > 0 && wants_cycle(gi, gs[L.BETA], gs[L.BN], k.step[c].tol_res)) ? 1.0 : 0.0;
 }
 
-// out = sum_{i < count} y_i V_i
-__global__ void k_combine_dev(size_t N, const double* __restrict__ V, size_t ldv, const double* __restrict__ y,
-                              const int* count, double* __restrict__ out) {
-    const int nv = *count;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int i = 0; i < nv; ++i) s += y[i] * V[i * ldv + t];
-        out[t] = s;
+// GMRES iterations of this Newton step into the case's total
+__global__ void k_gm_finish(Ctl k) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    k.sum[(size_t)c * SUM_STRIDE + S_GMRES] += k.gi[c * GI_STRIDE + GI_TOTAL];
+}
+
+// ---- chunk-walking vector kernels (every chunk belongs to one case)
+struct Vec {
+    const int* chunk_case;
+    int nchunks;
+    const int* gi;
+    int flag;   // skip flag
+};
+
+#define FR_CHUNKS(vc, ...)                                                                                \
+    for (int ch = blockIdx.x; ch < (vc).nchunks; ch += gridDim.x) {                                       \
+        const int c = (vc).chunk_case[ch];                                                                 \
+        if ((vc).gi[c * GI_STRIDE + (vc).flag]) continue;                                                  \
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x) { \
+            __VA_ARGS__                                                                                    \
+        }                                                                                                  \
+    }
+
+// out = s_c * in, s_c = gs[c * stride + field]
+__global__ void k_scale_case(Vec vc, const double* __restrict__ in, double* __restrict__ out, const double* gs,
+                             int stride, int field) {
+    for (int ch = blockIdx.x; ch < vc.nchunks; ch += gridDim.x) {
+        const int c = vc.chunk_case[ch];
+        if (vc.gi[c * GI_STRIDE + vc.flag]) continue;
+        const double a = gs[(size_t)c * stride + field];
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x)
+            out[t] = a * in[t];
     }
 }
 
-// x += z ; r = b - w
-__global__ void k_add(size_t N, const double* __restrict__ z, double* __restrict__ x) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x)
-        x[t] += z[t];
-}
-__global__ void k_sub(size_t N, const double* __restrict__ b, const double* __restrict__ w, double* __restrict__ r) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x)
-        r[t] = b[t] - w[t];
-}
-__global__ void k_fill(size_t N, double v, double* __restrict__ x) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x)
-        x[t] = v;
-}
-// beta = sqrt(|r|^2) (and bn = beta on the first call of a solve)
-__global__ void k_sqrt_to(const double* in, double* beta, double* bn) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double b = sqrt(*in);
-    *beta = b;
-    if (bn) *bn = b;
-}
-__global__ void k_set_int(int* p, int v0, int v1, int v2, int v3) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    p[0] = v0; p[1] = v1; p[2] = v2; p[3] = v3;
+// out = sum_{i < cyc_c} y_c[i] V_i
+__global__ void k_combine_case(Vec vc, const double* __restrict__ V, size_t ldv, const double* gs, int stride,
+                               int yfield, double* __restrict__ out) {
+    __shared__ double y[MAXV];
+    for (int ch = blockIdx.x; ch < vc.nchunks; ch += gridDim.x) {
+        const int c = vc.chunk_case[ch];
+        if (vc.gi[c * GI_STRIDE + vc.flag]) continue;
+        const int nv = vc.gi[c * GI_STRIDE + GI_CYC];
+        __syncthreads();
+        if ((int)threadIdx.x < MAXV) y[threadIdx.x] = (int)threadIdx.x < nv ? gs[(size_t)c * stride + yfield + threadIdx.x] : 0.0;
+        __syncthreads();
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x) {
+            double s = 0.0;
+            for (int i = 0; i < nv; ++i) s += y[i] * V[i * ldv + t];
+            out[t] = s;
+        }
+    }
 }
 
-unsigned gridN(size_t N) {
-    size_t g = (N + 255) / 256;
-    if (g > 4096) g = 4096;
-    return (unsigned)(g < 1 ? 1 : g);
+__global__ void k_add(Vec vc, const double* __restrict__ z, double* __restrict__ x) { FR_CHUNKS(vc, x[t] += z[t];) }
+__global__ void k_sub(Vec vc, const double* __restrict__ b, const double* __restrict__ w, double* __restrict__ r) {
+    FR_CHUNKS(vc, r[t] = b[t] - w[t];)
 }
+__global__ void k_fill(Vec vc, double v, double* __restrict__ x) { FR_CHUNKS(vc, x[t] = v;) }
+__global__ void k_copy(Vec vc, const double* __restrict__ a, double* __restrict__ b) { FR_CHUNKS(vc, b[t] = a[t];) }
 
-// work vectors of the solve inside d_w
-enum { WR = 4, WW = 5, WZ = 6 };
+unsigned vgrid(const Solver& sv) { return (unsigned)(sv.nchunks < 8192 ? sv.nchunks : 8192); }
+unsigned cgrid(const Solver& sv) { return (unsigned)((sv.n + 63) / 64); }
 
-fr_status bdf_op(fr_ctx c, const double* q, const double* v, double ct, double idt, double* Av, const int* skip,
-                 hipStream_t s) {
+Ctl ctl(const Solver& sv) { return Ctl{sv.d_gs, sv.gs_stride, sv.d_gi, sv.d_step, sv.d_sum, sv.n}; }
+Vec vec(const Solver& sv, int flag) { return Vec{sv.d_chunk_case, sv.nchunks, sv.d_gi, flag}; }
+
+double* wv(const Solver& sv, int i) { return sv.d_w + (size_t)i * sv.Ntot; }
+
+fr_status bdf_op(const Solver& sv, const double* q, const double* v, double* Av, int flag, hipStream_t s) {
     KArgs a{};
-    a.E = c->E; a.q = q; a.v = v; a.out = Av; a.c_time = ct; a.inv_dtau = idt; a.skip = skip;
-    return launch_residual(c, MODE_AOP, a, s);
+    a.q = q; a.v = v; a.out = Av; a.cstep = sv.d_step; a.flags = sv.d_gi; a.flag = flag;
+    return solver_fused(sv, MODE_AOP, a, s);
 }
 
 // the launches of one cycle (enqueued eagerly or under capture)
-fr_status enqueue_cycle(fr_ctx c, const double* q, const double* b, double* x, int m, double tol, double ct,
-                        double idt, hipStream_t s) {
-    const size_t N = c->N();
+fr_status enqueue_cycle(Solver& sv, int m, hipStream_t s) {
+    const size_t N = sv.Ntot;
     const GsLayout L(m);
-    double* V = c->d_V;
-    double* r = c->d_w + (size_t)WR * N;
-    double* w = c->d_w + (size_t)WW * N;
-    double* z = c->d_w + (size_t)WZ * N;
-    double* gs = c->d_gs;
-    int* gi = c->d_gi;
-    const int* done = gi + GI_DONE;
-    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, s, m, gs, gi, L);
+    const double* q = sv.d_q;
+    const double* b = wv(sv, WB);
+    double* x = wv(sv, WDQ);
+    double* r = wv(sv, WRES);
+    double* w = wv(sv, WW);
+    double* z = wv(sv, WZ);
+    double* V = sv.d_V;
+    double* gs = sv.d_gs;
+    const int gst = sv.gs_stride;
+    const Ctl k = ctl(sv);
+    hipLaunchKernelGGL(k_cycle_init, dim3(cgrid(sv)), dim3(64), 0, s, k, m);
     FR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_scale_dev, dim3(gridN(N)), dim3(256), 0, s, N, r, V, gs + L.SCALE0, done);
+    hipLaunchKernelGGL(k_scale_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_DONE), r, V, gs, gst, L.SCALE0);
     FR_HIP(hipGetLastError());
     for (int j = 0; j < m; ++j) {
         double* vj = V + (size_t)j * N;
-        fr_status st;
-        if ((st = launch_block_apply(c, vj, z, s, done)) != FR_OK) return st;
-        if ((st = bdf_op(c, q, z, ct, idt, w, done, s)) != FR_OK) return st;
-        if ((st = la_krylov(c, N, V, 0, nullptr, j + 1, w, nullptr, false, gs + L.H1, s, done)) != FR_OK) return st;
-        if ((st = la_krylov(c, N, V, j + 1, gs + L.H1, j + 1, w, w, false, gs + L.H2, s, done)) != FR_OK) return st;
-        if ((st = la_krylov(c, N, V, j + 1, gs + L.H2, 0, w, w, true, gs + L.NRM, s, done)) != FR_OK) return st;
-        hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, j, m, tol, gs, gi, L);
+        FR_TRY(launch_block_apply(sv, vj, z, sv.d_gi, GI_DONE, s));
+        FR_TRY(bdf_op(sv, q, z, w, GI_DONE, s));
+        FR_TRY(la_krylov(sv, V, N, 0, nullptr, 0, j + 1, w, nullptr, false, false, gs + L.H1, gst, sv.d_gi, GI_DONE, s));
+        FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, j + 1, w, w, false, false, gs + L.H2, gst, sv.d_gi, GI_DONE, s));
+        FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H2, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi, GI_DONE, s));
+        hipLaunchKernelGGL(k_givens, dim3(cgrid(sv)), dim3(64), 0, s, k, j, m);
         FR_HIP(hipGetLastError());
         if (j + 1 < m) {
-            hipLaunchKernelGGL(k_scale_dev, dim3(gridN(N)), dim3(256), 0, s, N, w, V + (size_t)(j + 1) * N,
-                               gs + L.INVHN, done);
+            hipLaunchKernelGGL(k_scale_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_DONE), w,
+                               V + (size_t)(j + 1) * N, gs, gst, L.INVHN);
             FR_HIP(hipGetLastError());
         }
     }
-    hipLaunchKernelGGL(k_backsub, dim3(1), dim3(64), 0, s, m, gs, gi, L);
+    hipLaunchKernelGGL(k_backsub, dim3(cgrid(sv)), dim3(64), 0, s, k, m);
     FR_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_combine_dev, dim3(gridN(N)), dim3(256), 0, s, N, V, N, gs + L.Y, gi + GI_CYC, w);
+    hipLaunchKernelGGL(k_combine_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_IDLE), V, N, gs, gst, L.Y, w);
     FR_HIP(hipGetLastError());
-    fr_status st;
-    if ((st = launch_block_apply(c, w, z, s, nullptr)) != FR_OK) return st;
-    hipLaunchKernelGGL(k_add, dim3(gridN(N)), dim3(256), 0, s, N, z, x);
+    FR_TRY(launch_block_apply(sv, w, z, sv.d_gi, GI_IDLE, s));
+    hipLaunchKernelGGL(k_add, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_IDLE), z, x);
     FR_HIP(hipGetLastError());
-    if ((st = bdf_op(c, q, x, ct, idt, w, nullptr, s)) != FR_OK) return st;
-    hipLaunchKernelGGL(k_sub, dim3(gridN(N)), dim3(256), 0, s, N, b, w, r);
+    FR_TRY(bdf_op(sv, q, x, w, GI_IDLE, s));
+    hipLaunchKernelGGL(k_sub, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_IDLE), b, w, r);
     FR_HIP(hipGetLastError());
-    if ((st = la_krylov(c, N, r, 0, nullptr, 0, r, nullptr, true, gs + L.NRM, s, nullptr)) != FR_OK) return st;
-    hipLaunchKernelGGL(k_sqrt_to, dim3(1), dim3(64), 0, s, gs + L.NRM, gs + L.BETA, (double*)nullptr);
+    FR_TRY(la_krylov(sv, r, N, 0, nullptr, 0, 0, r, nullptr, true, false, gs + L.NRM, gst, sv.d_gi, GI_IDLE, s));
+    hipLaunchKernelGGL(k_cycle_end, dim3(cgrid(sv)), dim3(64), 0, s, k, m);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
+// ---- Newton-level kernels
+__global__ void k_step_init(Ctl k) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    int* gi = k.gi + c * GI_STRIDE;
+    for (int f = 0; f < GI_STRIDE; ++f) gi[f] = 0;
+    double* s = k.sum + (size_t)c * SUM_STRIDE;
+    for (int f = 0; f < SUM_STRIDE; ++f) s[f] = 0.0;
+}
+
+// per case: Newton test on the mass-row norm of b (in the NRM slot)
+__global__ void k_newton_check(Ctl k, int m, int it) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    int* gi = k.gi + c * GI_STRIDE;
+    double* s = k.sum + (size_t)c * SUM_STRIDE;
+    if (gi[GI_NDONE]) return;
+    const GsLayout L(m);
+    const double rr = sqrt(k.gs[(size_t)c * k.gs_stride + L.NRM]);
+    if (it == 0) s[S_RES0] = rr;
+    s[S_RES] = rr;
+    s[S_NEWTON] = it;
+    const CaseStep& st = k.step[c];
+    if (!isfinite(rr)) { gi[GI_STATUS] = 1; gi[GI_NDONE] = 1; return; }
+    if (rr <= st.tol_abs || rr <= st.tol_pseudo * s[S_RES0]) { gi[GI_CONV] = 1; gi[GI_NDONE] = 1; return; }
+    if (it >= st.max_newton) { gi[GI_STATUS] = 2; gi[GI_NDONE] = 1; }
+}
+
+// a singular block (status 3) takes its case out of the iteration; flags to the summary
+__global__ void k_after_factor(Ctl k) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    int* gi = k.gi + c * GI_STRIDE;
+    if (gi[GI_STATUS] == 3) gi[GI_NDONE] = 1;
+}
+
+__global__ void k_publish(Ctl k) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    const int* gi = k.gi + c * GI_STRIDE;
+    double* s = k.sum + (size_t)c * SUM_STRIDE;
+    s[S_NDONE] = gi[GI_NDONE];
+    s[S_CONV] = gi[GI_CONV];
+    s[S_STATUS] = gi[GI_STATUS];
+}
+
+__global__ void k_axpy_case(Vec vc, const double* __restrict__ dq, double* __restrict__ q) {
+    FR_CHUNKS(vc, q[t] += dq[t];)
+}
+
 }  // namespace
 
-void gmres_release(fr_ctx c) {
-    if (c->graph_exec) {
-        (void)hipGraphExecDestroy((hipGraphExec_t)c->graph_exec);
-        c->graph_exec = nullptr;
+size_t gmres_state_doubles(int m) { return (size_t)GsLayout(m).total; }
+
+void gmres_release(Solver& sv) {
+    if (sv.graph_exec) {
+        (void)hipGraphExecDestroy((hipGraphExec_t)sv.graph_exec);
+        sv.graph_exec = nullptr;
     }
 }
 
-fr_status gmres_device(fr_ctx c, const double* q, const double* b, double* x, int m, double tol, int max_it,
-                       double ct, double idt, int prec, GmresResult& out, hipStream_t s) {
-    const size_t N = c->N();
+// GMRES on every case still in the Newton iteration: A dq = b with b = WB, dq = WDQ
+fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
     const GsLayout L(m);
-    double* gs = c->d_gs;
-    int* gi = c->d_gi;
-    double* r = c->d_w + (size_t)WR * N;
-    // x = 0, r = b, beta = bn = |b|, counters
-    hipLaunchKernelGGL(k_fill, dim3(gridN(N)), dim3(256), 0, s, N, 0.0, x);
+    const Ctl k = ctl(sv);
+    hipLaunchKernelGGL(k_gm_start, dim3(cgrid(sv)), dim3(64), 0, s, k, max_it);
     FR_HIP(hipGetLastError());
-    FR_HIP(hipMemcpyAsync(r, b, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-    fr_status st = la_krylov(c, N, b, 0, nullptr, 0, b, nullptr, true, gs + L.NRM, s, nullptr);
-    if (st != FR_OK) return st;
-    hipLaunchKernelGGL(k_sqrt_to, dim3(1), dim3(64), 0, s, gs + L.NRM, gs + L.BETA, gs + L.BN);
-    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, gi, 0, 0, 0, max_it);
+    hipLaunchKernelGGL(k_fill, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_NDONE), 0.0, wv(sv, WDQ));
+    FR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_copy, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_NDONE), wv(sv, WB), wv(sv, WRES));
+    FR_HIP(hipGetLastError());
+    FR_TRY(la_krylov(sv, wv(sv, WB), sv.Ntot, 0, nullptr, 0, 0, wv(sv, WB), nullptr, true, false, sv.d_gs + L.NRM,
+                     sv.gs_stride, sv.d_gi, GI_NDONE, s));
+    hipLaunchKernelGGL(k_gm_norm0, dim3(cgrid(sv)), dim3(64), 0, s, k, m);
     FR_HIP(hipGetLastError());
 
-    const bool graph = c->use_graph;
-    if (graph && (!c->graph_exec || c->graph_m != m || c->graph_ct != ct || c->graph_idt != idt ||
-                  c->graph_prec != prec || c->graph_tol != tol)) {
-        gmres_release(c);
-        // capture one cycle (all buffers are context-owned; the key is what the launches bake in)
+    const bool graph = sv.use_graph;
+    if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec)) {
+        gmres_release(sv);
+        // capture one cycle (all buffers are solver-owned; tolerances, time coefficients and
+        // caps are read on the device, so the graph depends on m and the block precision only)
         hipGraph_t gr;
         FR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        fr_status cst = enqueue_cycle(c, q, b, x, m, tol, ct, idt, s);
+        fr_status cst = enqueue_cycle(sv, m, s);
         hipError_t ee = hipStreamEndCapture(s, &gr);
         if (cst != FR_OK) { if (ee == hipSuccess) (void)hipGraphDestroy(gr); return cst; }
         FR_HIP(ee);
@@ -244,31 +388,73 @@ fr_status gmres_device(fr_ctx c, const double* q, const double* b, double* x, in
         hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         FR_HIP(ie);
-        c->graph_exec = ex;
-        c->graph_m = m; c->graph_ct = ct; c->graph_idt = idt; c->graph_prec = prec;
-        c->graph_tol = tol;
+        sv.graph_exec = ex;
+        sv.graph_m = m;
+        sv.graph_prec = prec;
     }
-    out.its = 0;
-    out.rel = 0.0;
-    for (int cycle = 0;; ++cycle) {
+    double* hs = sv.h_pin;
+    for (;;) {
         if (graph) {
-            FR_HIP(hipGraphLaunch((hipGraphExec_t)c->graph_exec, s));
+            FR_HIP(hipGraphLaunch((hipGraphExec_t)sv.graph_exec, s));
         } else {
-            st = enqueue_cycle(c, q, b, x, m, tol, ct, idt, s);
-            if (st != FR_OK) return st;
+            FR_TRY(enqueue_cycle(sv, m, s));
         }
-        FR_HIP(hipMemcpyAsync(c->h_scal + 2048, gs + L.BN, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        FR_HIP(hipMemcpyAsync(c->h_scal + 2052, gi, GI_TOTAL_INT * sizeof(int), hipMemcpyDeviceToHost, s));
+        FR_HIP(hipMemcpyAsync(hs, sv.d_sum, (size_t)sv.n * SUM_STRIDE * sizeof(double), hipMemcpyDeviceToHost, s));
         FR_HIP(hipStreamSynchronize(s));
-        const double bn = c->h_scal[2048], beta = c->h_scal[2049];
-        int ic[GI_TOTAL_INT];
-        memcpy(ic, c->h_scal + 2052, sizeof(ic));
-        out.its = ic[GI_TOTAL];
-        out.rel = bn > 0.0 ? beta / bn : 0.0;
-        if (!std::isfinite(beta)) { fr_set_error("non-finite GMRES residual"); return FR_ENONFINITE; }
-        if (bn == 0.0 || beta <= tol * bn || ic[GI_TOTAL] >= max_it || ic[GI_CYC] == 0) break;
+        bool more = false;
+        for (int c = 0; c < sv.n; ++c) more |= hs[(size_t)c * SUM_STRIDE + S_MORE] != 0.0;
+        if (!more) break;
     }
+    hipLaunchKernelGGL(k_gm_finish, dim3(cgrid(sv)), dim3(64), 0, s, k);
+    FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
-size_t gmres_state_doubles(int m) { return (size_t)GsLayout(m).total; }
+// The BDF2 (BDF1 for cases without q^{n-1}) dual-time Newton iteration of every case,
+// paper Sec. 3.2, Eq. (unsteady_pre_discretized_3): the iterate and Q^n, Q^{n-1} are in
+// the solver's vectors (WQN, WQNM1 hold the states on entry; converted here).
+fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
+    const Ctl k = ctl(sv);
+    const GsLayout L(o->krylov);
+    hipLaunchKernelGGL(k_step_init, dim3(cgrid(sv)), dim3(64), 0, s, k);
+    FR_HIP(hipGetLastError());
+    FR_TRY(launch_cons(sv, sv.d_q, wv(sv, WQN), sv.d_gi, s));
+    FR_TRY(launch_cons_nm1(sv, wv(sv, WQNM1), s));
+    double* hs = sv.h_pin;
+    for (int it = 0;; ++it) {
+        KArgs a{};
+        a.q = sv.d_q; a.out = wv(sv, WR); a.flags = sv.d_gi; a.flag = GI_NDONE;
+        FR_TRY(solver_fused(sv, MODE_R, a, s));
+        FR_TRY(launch_bdf_rhs(sv, sv.d_q, wv(sv, WQN), wv(sv, WQNM1), wv(sv, WR), wv(sv, WB), sv.d_gi, s));
+        FR_TRY(la_krylov(sv, wv(sv, WB), sv.Ntot, 0, nullptr, 0, 0, wv(sv, WB), nullptr, true, true, sv.d_gs + L.NRM,
+                         sv.gs_stride, sv.d_gi, GI_NDONE, s));
+        hipLaunchKernelGGL(k_newton_check, dim3(cgrid(sv)), dim3(64), 0, s, k, o->krylov, it);
+        FR_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_publish, dim3(cgrid(sv)), dim3(64), 0, s, k);
+        FR_HIP(hipGetLastError());
+        FR_HIP(hipMemcpyAsync(hs, sv.d_sum, (size_t)sv.n * SUM_STRIDE * sizeof(double), hipMemcpyDeviceToHost, s));
+        FR_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int c = 0; c < sv.n; ++c) any |= hs[(size_t)c * SUM_STRIDE + S_NDONE] == 0.0;
+        if (!any) break;
+        if (it % o->jac_lag == 0) {
+            KArgs b{};
+            b.cstep = sv.d_step; b.flags = sv.d_gi; b.flag = GI_NDONE;
+            FR_TRY(launch_block_assembly(sv, sv.d_q, b, s));
+            if (sv.keep_blocks) {
+                FR_HIP(hipMemcpyAsync(sv.d_blk_keep, sv.d_blk, sv.Btot * sizeof(double), hipMemcpyDeviceToDevice, s));
+            }
+            FR_TRY(launch_block_invert(sv, o->prec, sv.d_gi, s));
+            hipLaunchKernelGGL(k_after_factor, dim3(cgrid(sv)), dim3(64), 0, s, k);
+            FR_HIP(hipGetLastError());
+        }
+        FR_TRY(gmres_device(sv, o->krylov, o->prec, o->max_lin_it, s));
+        hipLaunchKernelGGL(k_axpy_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_NDONE), wv(sv, WDQ), sv.d_q);
+        FR_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_publish, dim3(cgrid(sv)), dim3(64), 0, s, k);
+    FR_HIP(hipGetLastError());
+    FR_HIP(hipMemcpyAsync(hs, sv.d_sum, (size_t)sv.n * SUM_STRIDE * sizeof(double), hipMemcpyDeviceToHost, s));
+    FR_HIP(hipStreamSynchronize(s));
+    return FR_OK;
+}

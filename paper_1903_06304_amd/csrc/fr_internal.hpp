@@ -40,17 +40,92 @@ struct Geo {
 
 enum FrMode { MODE_R = 0, MODE_JVP = 1, MODE_AOP = 2, MODE_BLK = 3 };
 
-struct KArgs {
-    int E;
-    const double* q;      // state [4][E][Np]
-    const double* v;      // tangent direction (JVP / AOP)
-    const double* tr;     // neighbour traces [E][4][NTV][n] of the scalar type
-    double* out;          // R, Jv, Av, or block column base
-    double* out2;         // R (JVP) or NULL
-    double c_time, inv_dtau;
-    int seed0;            // first seeded column (block mode)
-    const int* skip;      // device flag: non-zero => the launch does nothing (finished GMRES cycle)
+// Device view of one case (one mesh) of a solver.  A solver concatenates the state
+// vectors [4][E][Np] of its cases, each starting at a multiple of CHUNK doubles, and
+// the element blocks [E][nb][nb] of its cases.
+struct CaseDev {
+    int E, Np;
+    unsigned long long off;    // first entry of the case's state vector
+    unsigned long long boff;   // first entry of the case's element blocks
+    Geo g;
+    PhysConst pc;
 };
+
+// Per-case scalars of one dual-time step (written by the host before the step).
+struct CaseStep {
+    double ct, idt;             // c_time (a0/dt) and inv_dtau of the Newton operator
+    double inv_dt, a0, a1, a2;  // BDF coefficients: a0 q^c(q) + a1 Q^n + a2 Q^{n-1}
+    double tol_res, tol_pseudo, tol_abs;
+    int has_nm1, max_newton;
+};
+
+// per-case summary published to the host: sum[case * SUM_STRIDE + field]
+enum { S_BN = 0, S_BETA, S_TOTAL, S_MORE,      // GMRES: |b|, |r|, iterations, wants another cycle
+       S_RES0, S_RES, S_NEWTON, S_GMRES,       // Newton: Res_0, Res_m, iterations, GMRES iterations
+       S_NDONE, S_CONV, S_STATUS, SUM_STRIDE = 16 };
+
+// work vectors of a step inside Solver::d_w
+enum { WB = 0, WR, WQN, WQNM1, WRES, WW, WZ, WDQ, NWORK };
+
+// per-case integer state of a step: gi[case * GI_STRIDE + field]
+enum { GI_DONE = 0,   // Arnoldi of the current cycle stopped (skip flag of the cycle's kernels)
+       GI_CYC,        // iterations of the current cycle
+       GI_TOTAL,      // GMRES iterations of the current Newton step
+       GI_MAXIT,      // GMRES iteration cap
+       GI_IDLE,       // the case takes no part in the current cycle (skip flag of its update)
+       GI_NDONE,      // the case has left the Newton iteration (skip flag of everything)
+       GI_STATUS,     // 0 running/converged, 1 non-finite, 2 iteration limit, 3 singular block
+       GI_CONV,       // Newton converged
+       GI_STRIDE };
+
+// Arguments of the fused residual kernels.  State-sized pointers are bases of the
+// concatenated vectors (per-case offsets come from CaseDev).
+struct KArgs {
+    const double* q;      // state
+    const double* v;      // tangent direction (JVP / AOP)
+    double* out;          // R, Jv, Av, or the block assembly buffer (block mode)
+    double* out2;         // R (JVP) or NULL
+    double c_time, inv_dtau;   // time-term coefficients when cstep is NULL
+    const CaseStep* cstep;     // per-case coefficients (solver steps) or NULL
+    int seed0;            // first seeded column (block mode)
+    const int* flags;     // per-case flags (gi layout) or NULL
+    int flag;             // which flag skips a case
+};
+
+// tiles of one launch group (cases of one order / viscous / moving combination)
+struct GroupArgs {
+    const CaseDev* cases;
+    const int* ids;       // case index of each group member
+    const int* pfx;       // first tile of each member, [nmem + 1]
+    int nmem;
+    int ntiles;
+};
+
+// launch shape of the fused kernel: workgroup width (lanes) and persistent grid size
+struct Tune {
+    int lanes = 0;        // 0: default of the variant
+    int grid = 0;         // 0: one workgroup per tile
+};
+
+struct Group {
+    int p, visc, mov;
+    std::vector<int> ids;
+    int* d_ids = nullptr;
+    std::vector<std::pair<int, int*>> pfx;   // tile width (elements) -> device prefix
+    std::vector<long long> elems;            // elements of each member
+    Tune tune[4];                            // per mode
+    const int* tile_pfx(int epb) const {
+        for (auto& x : pfx) if (x.first == epb) return x.second;
+        return nullptr;
+    }
+    int ntiles(int epb) const {
+        long long t = 0;
+        for (long long e : elems) t += (e + epb - 1) / epb;
+        return (int)t;
+    }
+};
+
+struct Solver;
 
 struct fr_ctx_s {
     fr_params prm;
@@ -59,41 +134,63 @@ struct fr_ctx_s {
     OpTab op;
     GeoTab gt;
     int device;
-    bool keep_blocks = false;
     bool geometry_set = false;
     // device storage
     int32_t* d_nbr = nullptr;       // packed [E][4]
     double* d_gsp = nullptr;        // [NGSP][E][Np]
     double* d_gfp = nullptr;        // [NGFP][E][4n]
-    double* d_trace = nullptr;      // neighbour traces, sized for Dual<KBLK>
-    double* d_trace0 = nullptr;     // value-only traces (block assembly)
-    double* d_blk = nullptr;        // [E][nb][nb] FP64 assembly buffer (column-major per element)
-    void* d_inv = nullptr;          // [E][nb][nb] inverse blocks in the stored precision
-    int inv_prec = -1;
-    double* d_blk_keep = nullptr;
-    double* d_scal = nullptr;       // small reduction scratch, layout SC_* below
-    double* h_scal = nullptr;       // pinned host mirror
-    // Krylov workspace
-    int kry_m = 0;
-    double* d_V = nullptr;          // [(m+1)][N]
-    double* d_w = nullptr;          // [N] x 6 work vectors
-    double* d_vj = nullptr;         // [vjp adjoint trace buffer]
-    double* d_qw = nullptr;         // Newton iterate (ctx-owned so captured graphs stay valid)
-    double* d_gs = nullptr;         // device GMRES state (Hessenberg, rotations, scalars)
-    int* d_gi = nullptr;            // device GMRES counters and flags
-    bool use_graph = true;
-    hipStream_t ws = nullptr;       // context stream of the BDF2 step (capturable, default priority)
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    void* graph_exec = nullptr;     // hipGraphExec_t of one GMRES(m) cycle
-    double graph_ct = 0, graph_idt = 0;
-    int graph_m = 0, graph_prec = -1;
-    double graph_tol = 0;
+    double* d_trace = nullptr;      // neighbour traces (adjoint path)
+    double* d_vj = nullptr;         // adjoint trace buffer
+    Solver* self = nullptr;         // one-case solver of the context's own entry points
     size_t N() const { return (size_t)4 * E * Np; }
 };
 
-// layout of the reduction scratch d_scal (doubles)
-enum { SC_H1 = 0, SC_H2 = 64, SC_NRM = 128, SC_Y = 192, SC_STATUS = 256, SC_PART = 320,
-       SC_TOTAL = 320 + 2048 * 64 };
+// A solver: one or more cases advanced together (fr_batch, or the one-case solver of a
+// context).  Owns the concatenated work vectors, blocks and device GMRES state.
+struct Solver {
+    std::vector<fr_ctx> cs;
+    int n = 0;
+    std::vector<size_t> off, len, boff;    // state offset / padded length, block offset per case
+    size_t Ntot = 0, Btot = 0;
+    int nchunks = 0;
+    CaseDev* d_cases = nullptr;
+    int* d_chunk_case = nullptr;           // [nchunks]
+    int* d_case_chunk = nullptr;           // [n + 1] first chunk of each case
+    std::vector<Group> groups;
+    int device = 0;
+    // preconditioner
+    double* d_blk = nullptr;               // FP64 assembly buffer (column-major blocks)
+    void* d_inv = nullptr;                 // inverse blocks in the stored precision
+    int inv_prec = -1;
+    bool keep_blocks = false;
+    double* d_blk_keep = nullptr;
+    // step workspace
+    int kry_m = 0;
+    double* d_q = nullptr;                 // Newton iterate
+    double* d_w = nullptr;                 // NWORK vectors
+    double* d_V = nullptr;                 // (m+1) Krylov vectors
+    double* d_gs = nullptr;                // per-case GMRES state [n][gs_stride]
+    int gs_stride = 0;
+    int* d_gi = nullptr;                   // per-case flags [n][GI_STRIDE]
+    double* d_part = nullptr;              // reduction partials [nchunks][MAXV]
+    CaseStep* d_step = nullptr;            // [n]
+    double* d_sum = nullptr;               // per-case summary [n][SUM_STRIDE]
+    double* h_pin = nullptr;               // pinned host staging
+    size_t h_pin_doubles = 0;
+    hipStream_t ws = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    bool use_graph = true;
+    void* graph_exec = nullptr;
+    int graph_m = 0, graph_prec = -1;
+    size_t N(int c) const { return (size_t)4 * cs[c]->E * cs[c]->Np; }
+};
+
+struct fr_batch_s {
+    Solver sv;
+};
+
+constexpr int CHUNK = 4096;   // alignment of case vectors; unit of the segmented reductions
+constexpr int MAXV = 64;      // max vectors in one multi-dot
 
 // error handling
 void fr_set_error(const std::string& s);
@@ -106,33 +203,75 @@ void fr_set_error(const std::string& s);
         }                                                                            \
     } while (0)
 
-// launchers (fr_kernels.hip)
+#define FR_TRY(x)                              \
+    do {                                       \
+        fr_status st_ = (x);                   \
+        if (st_ != FR_OK) return st_;          \
+    } while (0)
+
+template <class T>
+fr_status dalloc(T** p, size_t count) {
+    if (*p) return FR_OK;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T) + 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        fr_set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return FR_ENOMEM;
+    }
+    return FR_OK;
+}
+inline void dfree(void* p) { if (p) (void)hipFree(p); }
+
+// geometry and traces (fr_kernels.hip)
 fr_status launch_geometry(fr_ctx c, const double* xg, const double* vg, hipStream_t s);
-fr_status launch_traces(fr_ctx c, const double* q, const double* v, double* trace, int lanes, hipStream_t s);
-fr_status launch_residual(fr_ctx c, int mode, const KArgs& a, hipStream_t s);
+fr_status launch_traces(fr_ctx c, const double* q, double* trace, hipStream_t s);
 fr_status launch_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s);
 
-// linear algebra (fr_linalg.hip)
-fr_status launch_block_assembly(fr_ctx c, const double* q, double c_time, double inv_dtau, hipStream_t s);
-fr_status launch_block_invert(fr_ctx c, int prec, hipStream_t s);
-fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s, const int* skip = nullptr);
-// dots of the first N entries; V_i = V + i * c->N()
-fr_status la_dots(fr_ctx c, size_t N, const double* V, int nv, const double* w, double* d_out, hipStream_t s);
-// w_out = w_in - sum_{i<nv_upd} coef_i V_i; d_out[i] = V_i . w_out (i < nv_dot); d_out[nv_dot] = |w_out|^2
-fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
-                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s,
-                    const int* skip = nullptr);
-fr_status la_axpy(size_t N, double a, const double* x, double* y, hipStream_t s);
-fr_status la_scale_copy(size_t N, double a, const double* x, double* y, hipStream_t s);
-fr_status la_norm2(size_t N, const double* x, double* d_out, double* scratch, hipStream_t s);
-fr_status launch_bdf_rhs(fr_ctx c, const double* q, const double* Qn, const double* Qnm1, const double* R,
-                         double a0, double a1, double a2, double dt, double* b, hipStream_t s);
-fr_status launch_cons(fr_ctx c, const double* q, double* Qc, hipStream_t s);
-fr_status la_combine(size_t N, const double* V, int nv, const double* d_y, double* out, hipStream_t s);
+// fused residual kernels of one group (fr_fused_p*.hip)
+fr_status launch_fused(const Solver& sv, const Group& gr, int mode, const KArgs& a, const Tune& t, hipStream_t s);
+template <int P>
+fr_status launch_fused_p(const Solver& sv, const Group& gr, int mode, const KArgs& a, const Tune& t, hipStream_t s);
+template <> fr_status launch_fused_p<1>(const Solver&, const Group&, int, const KArgs&, const Tune&, hipStream_t);
+template <> fr_status launch_fused_p<2>(const Solver&, const Group&, int, const KArgs&, const Tune&, hipStream_t);
+template <> fr_status launch_fused_p<3>(const Solver&, const Group&, int, const KArgs&, const Tune&, hipStream_t);
+template <> fr_status launch_fused_p<4>(const Solver&, const Group&, int, const KArgs&, const Tune&, hipStream_t);
+// every group of the solver with its tuned shape
+fr_status solver_fused(const Solver& sv, int mode, const KArgs& a, hipStream_t s);
+// tile widths (elements per workgroup) a group may be launched with
+std::vector<int> fused_tile_widths(int p);
+
+// solver set-up (fr_solver.hip)
+fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n);
+void solver_free(Solver& sv);
+fr_status solver_ensure_blocks(Solver& sv);
+fr_status solver_ensure_step(Solver& sv, int m);
+
+// preconditioner (fr_linalg.hip)
+fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s);
+fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s);
+fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s);
+// segmented reductions over the concatenated vectors: for every case c (not skipped),
+//   w_out = w_in - sum_{i<nv_upd} coef_c[i] V_i            (coef_c = coef + c * cstride)
+//   out_c[i] = V_i . w_out (i < nv_dot), out_c[nv_dot] = |w_out|^2 (want_norm)
+// (out_c = out + c * ostride); mass_only restricts the norm to the first E Np entries.
+fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, const double* coef, int cstride,
+                    int nv_dot, const double* w_in, double* w_out, bool want_norm, bool mass_only, double* out,
+                    int ostride, const int* flags, int flag, hipStream_t s);
+fr_status launch_bdf_rhs(const Solver& sv, const double* q, const double* Qn, const double* Qnm1, const double* R,
+                         double* b, const int* flags, hipStream_t s);
+fr_status launch_cons(const Solver& sv, const double* q, double* Qc, const int* flags, hipStream_t s);
+// q^c in place for the cases that have a q^{n-1}
+fr_status launch_cons_nm1(const Solver& sv, double* buf, hipStream_t s);
+int block_apply_width(int p);
 
 // device GMRES (fr_gmres.hip)
-struct GmresResult { int its; double rel; };
-fr_status gmres_device(fr_ctx c, const double* q, const double* b, double* x, int m, double tol, int max_it,
-                       double ct, double idt, int prec, GmresResult& out, hipStream_t s);
-void gmres_release(fr_ctx c);
 size_t gmres_state_doubles(int m);
+fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s);
+void gmres_release(Solver& sv);
+// Newton loop of a step: iterate in d_q, q^{n-1} states in WQNM1; leaves the per-case
+// summary in h_pin
+fr_status solver_newton(Solver& sv, const fr_step_opts* opts, hipStream_t s);
+// one dual-time step of every case (copies in and out of the caller's arrays)
+fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, const fr_step_opts* opts,
+                      fr_step_stats* stats, hipStream_t caller);
+fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s);

@@ -14,9 +14,18 @@
 
 namespace {
 
-constexpr int RED_BLOCKS = 2048;  // first-stage partial sums per reduction (8 workgroups per CU)
 constexpr int RED_THREADS = 256;
-constexpr int MAXV = 64;          // max vectors in one multi-dot
+constexpr int MAX_GRID = 8192;    // workgroups of the chunk-walking kernels
+
+// case of tile t of a group (binary search over the group's tile prefix); uniform
+__device__ __forceinline__ int tile_member(const GroupArgs& ga, int t) {
+    int lo = 0, hi = ga.nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ga.pfx[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 // ------------------------------------------------------------------ block inversion
 template <class Tout>
@@ -35,9 +44,12 @@ __device__ __forceinline__ double from_store(float x) { return (double)x; }
 __device__ __forceinline__ double from_store(uint16_t x) { return (double)__uint_as_float(((uint32_t)x) << 16); }
 
 // A is column-major in global (a[col*nb + row]); LDS holds it row-major with a padded stride.
+// One workgroup per element of a group (tile width 1); a zero pivot marks the case's
+// status (plain vector store) and leaves its inverse unwritten.
 template <class Tout>
-__global__ void __launch_bounds__(256) k_block_invert(int E, int nb, const double* __restrict__ blk,
-                                                      Tout* __restrict__ inv, int* __restrict__ status) {
+__global__ void __launch_bounds__(256) k_block_invert(GroupArgs ga, int nb, const double* __restrict__ blk,
+                                                      Tout* __restrict__ inv, int* __restrict__ gi,
+                                                      const int* __restrict__ flags) {
     extern __shared__ double lds[];
     const int ld = nb + 1;
     double* A = lds;                       // [nb][ld]
@@ -45,9 +57,14 @@ __global__ void __launch_bounds__(256) k_block_invert(int E, int nb, const doubl
     int* perm = (int*)(colk + nb);         // [nb]
     __shared__ int s_piv;
     __shared__ double s_pval;
-    const int e = blockIdx.x;
-    if (e >= E) return;
-    const double* src = blk + (size_t)e * nb * nb;
+    const int t = blockIdx.x;
+    if (t >= ga.ntiles) return;
+    const int lo = tile_member(ga, t);
+    const int cid = ga.ids[lo];
+    if (flags && flags[cid * GI_STRIDE + GI_NDONE]) return;
+    const CaseDev& cd = ga.cases[cid];
+    const int e = t - ga.pfx[lo];
+    const double* src = blk + cd.boff + (size_t)e * nb * nb;
     for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
         const int c = t / nb, r = t % nb;
         A[r * ld + c] = src[t];
@@ -73,7 +90,7 @@ __global__ void __launch_bounds__(256) k_block_invert(int E, int nb, const doubl
         const int pr = s_piv;
         const double pv = s_pval;
         if (pv == 0.0) {
-            if (threadIdx.x == 0) *status = 1;   // plain vector store
+            if (threadIdx.x == 0) gi[cid * GI_STRIDE + GI_STATUS] = 3;   // plain vector store
             return;   // uniform across the workgroup
         }
         if (pr != k) {
@@ -112,306 +129,363 @@ __global__ void __launch_bounds__(256) k_block_invert(int E, int nb, const doubl
         }
         __syncthreads();
     }
-    Tout* dst = inv + (size_t)e * nb * nb;
+    Tout* dst = inv + cd.boff + (size_t)e * nb * nb;
     for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
         const int c = t / nb, r = t % nb;
         dst[t] = to_store<Tout>(A[r * ld + c]);   // column-major inverse
     }
 }
 
-// z_e = Ainv_e r_e; state layout [4][E][Np], block row/col index v*Np + s
+// z_e = Ainv_e r_e for the elements of one group; state layout [4][E][Np] per case,
+// block row/col index v*Np + s; one thread per block row, tile width 256 / nb
 template <class Tin>
-__global__ void __launch_bounds__(256) k_block_apply(int E, int Np, const Tin* __restrict__ inv,
+__global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, int Np, const Tin* __restrict__ inv,
                                                      const double* __restrict__ r, double* __restrict__ z,
-                                                     const int* skip) {
+                                                     const int* __restrict__ flags, int flag) {
     extern __shared__ double rs[];
-    if (skip && *skip) return;
     const int nb = 4 * Np;
     const int epb = blockDim.x / nb;
+    const int t = blockIdx.x;
+    if (t >= ga.ntiles) return;
+    const int lo = tile_member(ga, t);
+    const int cid = ga.ids[lo];
+    if (flags && flags[cid * GI_STRIDE + flag]) return;
+    const CaseDev& cd = ga.cases[cid];
     const int el = threadIdx.x / nb, row = threadIdx.x % nb;
-    const int e = blockIdx.x * epb + el;
-    const bool act = (el < epb) && (e < E);
-    const size_t EN = (size_t)E * Np;
-    if (act) rs[el * nb + row] = r[(row / Np) * EN + (size_t)e * Np + (row % Np)];
+    const int e = (t - ga.pfx[lo]) * epb + el;
+    const bool act = (el < epb) && (e < cd.E);
+    const size_t EN = (size_t)cd.E * Np;
+    const size_t gid = cd.off + (row / Np) * EN + (size_t)e * Np + (row % Np);
+    if (act) rs[el * nb + row] = r[gid];
     __syncthreads();
     if (!act) return;
-    const Tin* A = inv + (size_t)e * nb * nb;
+    const Tin* A = inv + cd.boff + (size_t)e * nb * nb;
     double acc = 0.0;
     for (int c = 0; c < nb; ++c) acc += from_store(A[(size_t)c * nb + row]) * rs[el * nb + c];
-    z[(row / Np) * EN + (size_t)e * Np + (row % Np)] = acc;
+    z[gid] = acc;
 }
 
-// ------------------------------------------------------------------ Krylov reductions
-// Dot products V_i . w for i in [8*blockIdx.y, 8*blockIdx.y + 8) ∩ [0, nv), plus |w|^2 in slot
-// nv when want_norm (chunk 0 only): per-block partial sums partial[b][i].
-__global__ void __launch_bounds__(RED_THREADS) k_dots8(size_t N, const double* __restrict__ V, size_t ldv, int nv,
-                                                       const double* __restrict__ w, int want_norm,
-                                                       double* __restrict__ partial, const int* skip) {
+// ------------------------------------------------------------------ segmented Krylov reductions
+// The solver vectors are concatenations of per-case segments aligned to CHUNK doubles;
+// every chunk belongs to one case.  First stage: one partial sum per chunk and output;
+// second stage: per case, a fixed-order tree over its chunks (deterministic).
+struct ChunkArgs {
+    const CaseDev* cases;
+    const int* chunk_case;   // [nchunks]
+    const int* case_chunk;   // [ncase + 1]
+    int nchunks;
+    const int* flags;        // per-case skip flags or NULL
+    int flag;
+};
+
+__device__ __forceinline__ bool chunk_skipped(const ChunkArgs& ca, int c) {
+    return ca.flags && ca.flags[c * GI_STRIDE + ca.flag];
+}
+
+// Dot products V_i . w for i in [8*blockIdx.y, 8*blockIdx.y + 8) ∩ [0, nv), plus |w|^2 in
+// slot nv when want_norm (y-block 0 only; mass_only: first E Np entries of the case).
+__global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const double* __restrict__ V, size_t ldv, int nv,
+                                                       const double* __restrict__ w, int want_norm, int mass_only,
+                                                       double* __restrict__ partial) {
     __shared__ double red[RED_THREADS / 64][9];
-    if (skip && *skip) return;
     const int i0 = blockIdx.y * 8;
     const int cnt = nv - i0 < 8 ? nv - i0 : 8;
     const bool nrm = want_norm && blockIdx.y == 0;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double nacc = 0.0;
     const double* Vc = V + (size_t)i0 * ldv;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        const double wt = w[t];
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (i < cnt) acc[i] += Vc[i * ldv + t] * wt;
-        if (nrm) nacc += wt * wt;
-    }
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
+        const int c = ca.chunk_case[ch];
+        if (chunk_skipped(ca, c)) continue;
+        size_t lim = (size_t)ch * CHUNK + CHUNK;
+        if (mass_only) {
+            const CaseDev& cd = ca.cases[c];
+            const size_t m = cd.off + (size_t)cd.E * cd.Np;
+            lim = m < lim ? m : lim;
+        }
+        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double nacc = 0.0;
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
+            const double wt = w[t];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const bool live = (i < cnt) || (i == 8 && nrm);
-        if (!live) continue;
-        double v = (i < 8) ? acc[i] : nacc;
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) red[wid][i] = v;
-    }
-    __syncthreads();
-    const int k = threadIdx.x;
-    if (k < cnt || (k == 8 && nrm)) {
-        double v = 0.0;
-        for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q][k];
-        partial[(size_t)blockIdx.x * MAXV + (k < 8 ? i0 + k : nv)] = v;
+            for (int i = 0; i < 8; ++i)
+                if (i < cnt) acc[i] += Vc[i * ldv + t] * wt;
+            if (nrm && t < lim) nacc += wt * wt;
+        }
+        __syncthreads();   // red[] of the previous chunk consumed
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool live = (i < cnt) || (i == 8 && nrm);
+            if (!live) continue;
+            double v = (i < 8) ? acc[i] : nacc;
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[wid][i] = v;
+        }
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < cnt || (k == 8 && nrm)) {
+            double v = 0.0;
+            for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q][k];
+            partial[(size_t)ch * MAXV + (k < 8 ? i0 + k : nv)] = v;
+        }
     }
 }
 
-// w_out = w_in - sum_{i < nv} coef[i] V_i, and partial |w_out|^2 in slot 0 when want_norm
-__global__ void __launch_bounds__(RED_THREADS) k_update(size_t N, const double* __restrict__ V, size_t ldv, int nv,
-                                                        const double* __restrict__ coef, const double* w_in,
-                                                        double* w_out, int want_norm, double* __restrict__ partial,
-                                                        const int* skip) {
+// w_out = w_in - sum_{i < nv} coef_c[i] V_i (coef_c = coef + c * cstride), and the partial
+// |w_out|^2 in slot 0 when want_norm
+__global__ void __launch_bounds__(RED_THREADS) k_update(ChunkArgs ca, const double* __restrict__ V, size_t ldv, int nv,
+                                                        const double* __restrict__ coef, int cstride,
+                                                        const double* w_in, double* w_out, int want_norm,
+                                                        double* __restrict__ partial) {
     __shared__ double cf[MAXV];
     __shared__ double red[RED_THREADS / 64];
-    if (skip && *skip) return;
-    if ((int)threadIdx.x < MAXV) cf[threadIdx.x] = ((int)threadIdx.x < nv) ? coef[threadIdx.x] : 0.0;
-    __syncthreads();
-    double nacc = 0.0;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        double wt = w_in[t];
-        int i = 0;
-        for (; i + 4 <= nv; i += 4)
-            wt -= cf[i] * V[i * ldv + t] + cf[i + 1] * V[(i + 1) * ldv + t] + cf[i + 2] * V[(i + 2) * ldv + t] +
-                  cf[i + 3] * V[(i + 3) * ldv + t];
-        for (; i < nv; ++i) wt -= cf[i] * V[i * ldv + t];
-        w_out[t] = wt;
-        nacc += wt * wt;
-    }
-    if (!want_norm) return;
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-    for (int off = 32; off > 0; off >>= 1) nacc += __shfl_down(nacc, off, 64);
-    if (lane == 0) red[wid] = nacc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double v = 0.0;
-        for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q];
-        partial[(size_t)blockIdx.x * MAXV] = v;
+    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
+        const int c = ca.chunk_case[ch];
+        if (chunk_skipped(ca, c)) continue;
+        __syncthreads();   // cf[] / red[] of the previous chunk consumed
+        if ((int)threadIdx.x < MAXV) cf[threadIdx.x] = ((int)threadIdx.x < nv) ? coef[(size_t)c * cstride + threadIdx.x] : 0.0;
+        __syncthreads();
+        double nacc = 0.0;
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
+            double wt = w_in[t];
+            int i = 0;
+            for (; i + 4 <= nv; i += 4)
+                wt -= cf[i] * V[i * ldv + t] + cf[i + 1] * V[(i + 1) * ldv + t] + cf[i + 2] * V[(i + 2) * ldv + t] +
+                      cf[i + 3] * V[(i + 3) * ldv + t];
+            for (; i < nv; ++i) wt -= cf[i] * V[i * ldv + t];
+            w_out[t] = wt;
+            nacc += wt * wt;
+        }
+        if (!want_norm) continue;
+        for (int off = 32; off > 0; off >>= 1) nacc += __shfl_down(nacc, off, 64);
+        if (lane == 0) red[wid] = nacc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = 0.0;
+            for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q];
+            partial[(size_t)ch * MAXV] = v;
+        }
     }
 }
 
-// out[i] = sum over blocks of partial[b][i]; one workgroup per output, fixed-order tree
-__global__ void __launch_bounds__(256) k_final(int nblocks, const double* __restrict__ partial, double* __restrict__ out,
-                                               const int* skip) {
+// out_c[i] = sum over the chunks of case c of partial[chunk][i]; grid (ncase, nout)
+__global__ void __launch_bounds__(256) k_final(ChunkArgs ca, const double* __restrict__ partial,
+                                               double* __restrict__ out, int ostride) {
     __shared__ double red[256];
-    if (skip && *skip) return;
-    const int i = blockIdx.x;
+    const int c = blockIdx.x, i = blockIdx.y;
+    if (chunk_skipped(ca, c)) return;
+    const int c0 = ca.case_chunk[c], c1 = ca.case_chunk[c + 1];
     double v = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * MAXV + i];
+    for (int b = c0 + threadIdx.x; b < c1; b += blockDim.x) v += partial[(size_t)b * MAXV + i];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[i] = red[0];
+    if (threadIdx.x == 0) out[(size_t)c * ostride + i] = red[0];
 }
 
-// out = sum_i y[i] V_i
-__global__ void k_combine(size_t N, double* __restrict__ out, const double* __restrict__ V, size_t ldv, int nv,
-                          const double* __restrict__ y) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int i = 0; i < nv; ++i) s += y[i] * V[i * ldv + t];
-        out[t] = s;
+// ------------------------------------------------------------------ pointwise physics per case
+// Walk the chunks that hold solution points of the first variable of each case: point
+// t of case c covers entries v * E Np + t, v = 0..3.
+#define FR_POINT_LOOP(ca, ...)                                                                  \
+    for (int ch = blockIdx.x; ch < (ca).nchunks; ch += gridDim.x) {                             \
+        const int c = (ca).chunk_case[ch];                                                       \
+        if (chunk_skipped((ca), c)) continue;                                                    \
+        const CaseDev& cd = (ca).cases[c];                                                       \
+        const size_t EN = (size_t)cd.E * cd.Np;                                                  \
+        const size_t r0 = (size_t)ch * CHUNK - cd.off;                                           \
+        if (r0 >= EN) continue;                                                                  \
+        for (size_t t = r0 + threadIdx.x; t < r0 + CHUNK && t < EN; t += blockDim.x) {           \
+            const size_t base = cd.off + t;                                                      \
+            __VA_ARGS__                                                                          \
+        }                                                                                        \
     }
+
+// q^c of the state
+__global__ void k_cons(ChunkArgs ca, const double* __restrict__ q, double* __restrict__ Qc) {
+    FR_POINT_LOOP(ca, {
+        double qs[4], qc[4];
+        for (int v = 0; v < 4; ++v) qs[v] = q[base + v * EN];
+        fr_cons(cd.pc, qs, qc);
+        for (int v = 0; v < 4; ++v) Qc[base + v * EN] = qc[v];
+    })
 }
 
-__global__ void k_axpy(size_t N, double a, const double* __restrict__ x, double* __restrict__ y) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x)
-        y[t] += a * x[t];
+// b = R - (a0 q^c(q) + a1 Q^n + a2 Q^{n-1}) / dt with the case's BDF coefficients
+__global__ void k_bdf_rhs(ChunkArgs ca, const CaseStep* __restrict__ st, const double* __restrict__ q,
+                          const double* __restrict__ Qn, const double* __restrict__ Qnm1, const double* __restrict__ R,
+                          double* __restrict__ b) {
+    FR_POINT_LOOP(ca, {
+        const CaseStep& cs = st[c];
+        double qs[4], qc[4];
+        for (int v = 0; v < 4; ++v) qs[v] = q[base + v * EN];
+        fr_cons(cd.pc, qs, qc);
+        for (int v = 0; v < 4; ++v) {
+            double acc = cs.a0 * qc[v] + cs.a1 * Qn[base + v * EN];
+            if (cs.has_nm1) acc += cs.a2 * Qnm1[base + v * EN];
+            b[base + v * EN] = R[base + v * EN] - acc * cs.inv_dt;
+        }
+    })
 }
 
-__global__ void k_scale_copy(size_t N, double a, const double* __restrict__ x, double* __restrict__ y) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < N; t += (size_t)gridDim.x * blockDim.x)
-        y[t] = a * x[t];
+// q^c in place for the cases with a q^{n-1}
+__global__ void k_cons_nm1(ChunkArgs ca, const CaseStep* __restrict__ st, double* __restrict__ buf) {
+    FR_POINT_LOOP(ca, {
+        if (st[c].has_nm1) {
+            double qs[4], qc[4];
+            for (int v = 0; v < 4; ++v) qs[v] = buf[base + v * EN];
+            fr_cons(cd.pc, qs, qc);
+            for (int v = 0; v < 4; ++v) buf[base + v * EN] = qc[v];
+        }
+    })
 }
 
-// q^c of the state (per solution point)
-__global__ void k_cons(size_t EN, PhysConst pc, const double* __restrict__ q, double* __restrict__ Qc) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= EN) return;
-    double qs[4], qc[4];
-    for (int v = 0; v < 4; ++v) qs[v] = q[v * EN + t];
-    fr_cons(pc, qs, qc);
-    for (int v = 0; v < 4; ++v) Qc[v * EN + t] = qc[v];
+ChunkArgs chunk_args(const Solver& sv, const int* flags, int flag) {
+    ChunkArgs ca;
+    ca.cases = sv.d_cases;
+    ca.chunk_case = sv.d_chunk_case;
+    ca.case_chunk = sv.d_case_chunk;
+    ca.nchunks = sv.nchunks;
+    ca.flags = flags;
+    ca.flag = flag;
+    return ca;
 }
 
-// b = -(a0 q^c(q) + a1 Q^n + a2 Q^{n-1}) / dt + R
-__global__ void k_bdf_rhs(size_t EN, PhysConst pc, const double* __restrict__ q, const double* __restrict__ Qn,
-                          const double* __restrict__ Qnm1, const double* __restrict__ R, double a0, double a1, double a2,
-                          double idt, double* __restrict__ b) {
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= EN) return;
-    double qs[4], qc[4];
-    for (int v = 0; v < 4; ++v) qs[v] = q[v * EN + t];
-    fr_cons(pc, qs, qc);
-    for (int v = 0; v < 4; ++v) {
-        double acc = a0 * qc[v] + a1 * Qn[v * EN + t];
-        if (Qnm1) acc += a2 * Qnm1[v * EN + t];
-        b[v * EN + t] = R[v * EN + t] - acc * idt;
-    }
+unsigned chunk_grid(const Solver& sv) {
+    return (unsigned)(sv.nchunks < MAX_GRID ? sv.nchunks : MAX_GRID);
 }
 
-unsigned grid_for(size_t N, int bs) {
-    size_t g = (N + bs - 1) / bs;
-    if (g > 4096) g = 4096;
-    if (g < 1) g = 1;
-    return (unsigned)g;
+GroupArgs group_args(const Solver& sv, const Group& gr, int epb) {
+    GroupArgs ga;
+    ga.cases = sv.d_cases;
+    ga.ids = gr.d_ids;
+    ga.pfx = gr.tile_pfx(epb);
+    ga.nmem = (int)gr.ids.size();
+    ga.ntiles = gr.ntiles(epb);
+    return ga;
 }
 
 }  // namespace
 
 // ----------------------------------------------------------------------------- launchers
-fr_status launch_block_assembly(fr_ctx c, const double* q, double c_time, double inv_dtau, hipStream_t s) {
-    // one seeded column of every element's block per launch
-    fr_status st = FR_OK;
-    const int nb = 4 * c->Np;
-    KArgs a{};
-    a.E = c->E; a.q = q; a.v = nullptr; a.out = c->d_blk;
-    a.c_time = c_time; a.inv_dtau = inv_dtau;
-    for (int col = 0; col < nb; ++col) {
-        a.seed0 = col;
-        st = launch_residual(c, MODE_BLK, a, s);
-        if (st != FR_OK) return st;
+fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s) {
+    // one seeded column of every element's block per launch and group
+    KArgs a = base;
+    a.q = q; a.v = nullptr; a.out = sv.d_blk; a.out2 = nullptr;
+    for (const Group& gr : sv.groups) {
+        const int nb = 4 * (gr.p + 1) * (gr.p + 1);
+        for (int col = 0; col < nb; ++col) {
+            a.seed0 = col;
+            FR_TRY(launch_fused(sv, gr, MODE_BLK, a, gr.tune[MODE_BLK], s));
+        }
     }
     return FR_OK;
 }
 
-fr_status launch_block_invert(fr_ctx c, int prec, hipStream_t s) {
-    const int nb = 4 * c->Np;
-    const size_t lds = ((size_t)nb * (nb + 1) + nb) * sizeof(double) + nb * sizeof(int);
-    int* d_status = (int*)(c->d_scal + SC_STATUS);
-    FR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), s));
+template <class Tout>
+static fr_status invert_as(Solver& sv, const int* flags, hipStream_t s) {
+    for (const Group& gr : sv.groups) {
+        const int nb = 4 * (gr.p + 1) * (gr.p + 1);
+        const size_t lds = ((size_t)nb * (nb + 1) + nb) * sizeof(double) + nb * sizeof(int);
+        GroupArgs ga = group_args(sv, gr, 1);
+        if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
+        if (ga.ntiles == 0) continue;
+        FR_HIP(hipFuncSetAttribute((const void*)k_block_invert<Tout>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        hipLaunchKernelGGL(k_block_invert<Tout>, dim3(ga.ntiles), dim3(256), lds, s, ga, nb, sv.d_blk,
+                           (Tout*)sv.d_inv, sv.d_gi, flags);
+        FR_HIP(hipGetLastError());
+    }
+    return FR_OK;
+}
+
+fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s) {
     switch (prec) {
-        case FR_FP64:
-            FR_HIP(hipFuncSetAttribute((const void*)k_block_invert<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(k_block_invert<double>, dim3(c->E), dim3(256), lds, s, c->E, nb, c->d_blk, (double*)c->d_inv, d_status);
-            break;
-        case FR_FP32:
-            FR_HIP(hipFuncSetAttribute((const void*)k_block_invert<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(k_block_invert<float>, dim3(c->E), dim3(256), lds, s, c->E, nb, c->d_blk, (float*)c->d_inv, d_status);
-            break;
-        case FR_BF16:
-            FR_HIP(hipFuncSetAttribute((const void*)k_block_invert<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(k_block_invert<uint16_t>, dim3(c->E), dim3(256), lds, s, c->E, nb, c->d_blk, (uint16_t*)c->d_inv, d_status);
-            break;
-        default:
-            fr_set_error("unknown precision");
-            return FR_EINVAL;
+        case FR_FP64: FR_TRY(invert_as<double>(sv, flags, s)); break;
+        case FR_FP32: FR_TRY(invert_as<float>(sv, flags, s)); break;
+        case FR_BF16: FR_TRY(invert_as<uint16_t>(sv, flags, s)); break;
+        default: fr_set_error("unknown precision"); return FR_EINVAL;
     }
-    FR_HIP(hipGetLastError());
-    c->inv_prec = prec;
+    sv.inv_prec = prec;
     return FR_OK;
 }
 
-fr_status launch_block_apply(fr_ctx c, const double* r, double* z, hipStream_t s, const int* skip) {
-    const int nb = 4 * c->Np;
-    const int epb = 256 / nb;
-    const int threads = epb * nb;
-    const unsigned grid = (unsigned)((c->E + epb - 1) / epb);
-    const size_t lds = (size_t)threads * sizeof(double);
-    switch (c->inv_prec) {
-        case FR_FP64: hipLaunchKernelGGL(k_block_apply<double>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const double*)c->d_inv, r, z, skip); break;
-        case FR_FP32: hipLaunchKernelGGL(k_block_apply<float>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const float*)c->d_inv, r, z, skip); break;
-        case FR_BF16: hipLaunchKernelGGL(k_block_apply<uint16_t>, dim3(grid), dim3(threads), lds, s, c->E, c->Np, (const uint16_t*)c->d_inv, r, z, skip); break;
-        default: fr_set_error("preconditioner not factored"); return FR_EINVAL;
+int block_apply_width(int p) { return 256 / (4 * (p + 1) * (p + 1)); }
+
+fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s) {
+    for (const Group& gr : sv.groups) {
+        const int Np = (gr.p + 1) * (gr.p + 1), nb = 4 * Np;
+        const int epb = block_apply_width(gr.p);
+        const int threads = epb * nb;
+        GroupArgs ga = group_args(sv, gr, epb);
+        if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
+        if (ga.ntiles == 0) continue;
+        const size_t lds = (size_t)threads * sizeof(double);
+        switch (sv.inv_prec) {
+            case FR_FP64: hipLaunchKernelGGL(k_block_apply<double>, dim3(ga.ntiles), dim3(threads), lds, s, ga, Np, (const double*)sv.d_inv, r, z, flags, flag); break;
+            case FR_FP32: hipLaunchKernelGGL(k_block_apply<float>, dim3(ga.ntiles), dim3(threads), lds, s, ga, Np, (const float*)sv.d_inv, r, z, flags, flag); break;
+            case FR_BF16: hipLaunchKernelGGL(k_block_apply<uint16_t>, dim3(ga.ntiles), dim3(threads), lds, s, ga, Np, (const uint16_t*)sv.d_inv, r, z, flags, flag); break;
+            default: fr_set_error("preconditioner not factored"); return FR_EINVAL;
+        }
+        FR_HIP(hipGetLastError());
     }
-    FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
-fr_status la_krylov(fr_ctx c, size_t N, const double* V, int nv_upd, const double* d_coef, int nv_dot,
-                    const double* w_in, double* w_out, bool want_norm, double* d_out, hipStream_t s,
-                    const int* skip) {
+fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, const double* coef, int cstride,
+                    int nv_dot, const double* w_in, double* w_out, bool want_norm, bool mass_only, double* out,
+                    int ostride, const int* flags, int flag, hipStream_t s) {
     if (nv_upd > MAXV - 1 || nv_dot > MAXV - 1) { fr_set_error("too many Krylov vectors"); return FR_EINVAL; }
-    double* partial = c->d_scal + SC_PART;
-    const size_t ldv = c->N();
+    if (mass_only && nv_upd > 0) { fr_set_error("mass-row norm only on a plain norm pass"); return FR_EINVAL; }
+    const ChunkArgs ca = chunk_args(sv, flags, flag);
+    double* partial = sv.d_part;
+    const unsigned grid = chunk_grid(sv);
     const double* w = w_in;
     if (nv_upd > 0) {
         // the norm of the updated vector rides on the update pass when no dots follow
         const int nrm = (want_norm && nv_dot == 0) ? 1 : 0;
-        hipLaunchKernelGGL(k_update, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, N, V, ldv, nv_upd, d_coef, w_in, w_out,
-                           nrm, partial, skip);
+        hipLaunchKernelGGL(k_update, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef, cstride, w_in,
+                           w_out, nrm, partial);
         FR_HIP(hipGetLastError());
         w = w_out;
         if (nv_dot == 0) {
             if (nrm) {
-                hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, RED_BLOCKS, partial, d_out, skip);
+                hipLaunchKernelGGL(k_final, dim3(sv.n, 1), dim3(256), 0, s, ca, partial, out, ostride);
                 FR_HIP(hipGetLastError());
             }
             return FR_OK;
         }
     }
-    const int chunks = nv_dot > 0 ? (nv_dot + 7) / 8 : 1;
-    hipLaunchKernelGGL(k_dots8, dim3(RED_BLOCKS, chunks), dim3(RED_THREADS), 0, s, N, V, ldv, nv_dot, w,
-                       want_norm ? 1 : 0, partial, skip);
+    const int ychunks = nv_dot > 0 ? (nv_dot + 7) / 8 : 1;
+    hipLaunchKernelGGL(k_dots8, dim3(grid, ychunks), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_dot, w,
+                       want_norm ? 1 : 0, mass_only ? 1 : 0, partial);
     FR_HIP(hipGetLastError());
     const int nout = nv_dot + (want_norm ? 1 : 0);
     if (nout > 0) {
-        hipLaunchKernelGGL(k_final, dim3(nout), dim3(256), 0, s, RED_BLOCKS, partial, d_out, skip);
+        hipLaunchKernelGGL(k_final, dim3(sv.n, nout), dim3(256), 0, s, ca, partial, out, ostride);
         FR_HIP(hipGetLastError());
     }
     return FR_OK;
 }
 
-fr_status la_dots(fr_ctx c, size_t N, const double* V, int nv, const double* w, double* d_out, hipStream_t s) {
-    return la_krylov(c, N, V, 0, nullptr, nv, w, nullptr, false, d_out, s);
-}
-
-fr_status la_combine(size_t N, const double* V, int nv, const double* d_y, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_combine, dim3(grid_for(N, 256)), dim3(256), 0, s, N, out, V, N, nv, d_y);
+fr_status launch_cons(const Solver& sv, const double* q, double* Qc, const int* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_cons, dim3(chunk_grid(sv)), dim3(256), 0, s, chunk_args(sv, flags, GI_NDONE), q, Qc);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
-fr_status la_axpy(size_t N, double a, const double* x, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy, dim3(grid_for(N, 256)), dim3(256), 0, s, N, a, x, y);
+fr_status launch_bdf_rhs(const Solver& sv, const double* q, const double* Qn, const double* Qnm1, const double* R,
+                         double* b, const int* flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_bdf_rhs, dim3(chunk_grid(sv)), dim3(256), 0, s, chunk_args(sv, flags, GI_NDONE), sv.d_step, q,
+                       Qn, Qnm1, R, b);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
-fr_status la_scale_copy(size_t N, double a, const double* x, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(N, 256)), dim3(256), 0, s, N, a, x, y);
-    FR_HIP(hipGetLastError());
-    return FR_OK;
-}
-
-fr_status launch_cons(fr_ctx c, const double* q, double* Qc, hipStream_t s) {
-    const size_t EN = (size_t)c->E * c->Np;
-    hipLaunchKernelGGL(k_cons, dim3((unsigned)((EN + 255) / 256)), dim3(256), 0, s, EN, c->pc, q, Qc);
-    FR_HIP(hipGetLastError());
-    return FR_OK;
-}
-
-fr_status launch_bdf_rhs(fr_ctx c, const double* q, const double* Qn, const double* Qnm1, const double* R,
-                         double a0, double a1, double a2, double dt, double* b, hipStream_t s) {
-    const size_t EN = (size_t)c->E * c->Np;
-    hipLaunchKernelGGL(k_bdf_rhs, dim3((unsigned)((EN + 255) / 256)), dim3(256), 0, s, EN, c->pc, q, Qn, Qnm1, R, a0, a1,
-                       a2, 1.0 / dt, b);
+fr_status launch_cons_nm1(const Solver& sv, double* buf, hipStream_t s) {
+    hipLaunchKernelGGL(k_cons_nm1, dim3(chunk_grid(sv)), dim3(256), 0, s, chunk_args(sv, nullptr, 0), sv.d_step, buf);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

@@ -1,0 +1,382 @@
+// Solvers: the layout that lets many cases (meshes of different sizes, orders, flow
+// parameters, static or deforming) share every launch of the hot path, the BDF2 step
+// driver shared by a context and a batch, and the autotuner of the fused kernels'
+// launch shape.
+//
+// Layout.  Case c's state vector [4][E_c][Np_c] starts at off_c, a multiple of CHUNK
+// doubles, and is zero-padded to the next multiple; chunk k of the concatenated vector
+// belongs to exactly one case (chunk_case), so segmented reductions and per-case vector
+// operations walk chunks.  Cases are grouped by (order, viscous, moving); each group
+// is one launch of the fused kernel whose tiles (EPB elements of one case) are listed
+// by a prefix over the group's members for every tile width a kernel may use.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+
+#include "fr_internal.hpp"
+
+namespace {
+
+template <class T>
+fr_status upload(T** d, const std::vector<T>& h) {
+    FR_TRY(dalloc(d, h.size()));
+    FR_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FR_OK;
+}
+
+}  // namespace
+
+fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
+    sv.cs.assign(ctxs, ctxs + n);
+    sv.n = n;
+    FR_HIP(hipGetDevice(&sv.device));
+    sv.off.resize(n);
+    sv.len.resize(n);
+    sv.boff.resize(n);
+    size_t o = 0, bo = 0;
+    std::vector<CaseDev> cd(n);
+    for (int c = 0; c < n; ++c) {
+        const fr_ctx x = ctxs[c];
+        if (x->device != sv.device) { fr_set_error("every case must live on the current device"); return FR_EINVAL; }
+        const size_t N = x->N();
+        const size_t nb = 4 * (size_t)x->Np;
+        sv.off[c] = o;
+        sv.len[c] = ((N + CHUNK - 1) / CHUNK) * CHUNK;
+        sv.boff[c] = bo;
+        o += sv.len[c];
+        bo += (size_t)x->E * nb * nb;
+        cd[c].E = x->E;
+        cd[c].Np = x->Np;
+        cd[c].off = sv.off[c];
+        cd[c].boff = sv.boff[c];
+        cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr};
+        cd[c].pc = x->pc;
+    }
+    sv.Ntot = o;
+    sv.Btot = bo;
+    sv.nchunks = (int)(o / CHUNK);
+    if ((size_t)sv.nchunks * CHUNK != o || o / CHUNK > (size_t)1 << 30) { fr_set_error("solver too large"); return FR_EINVAL; }
+    std::vector<int> chunk_case(sv.nchunks), case_chunk(n + 1);
+    for (int c = 0; c < n; ++c) {
+        case_chunk[c] = (int)(sv.off[c] / CHUNK);
+        for (size_t k = sv.off[c] / CHUNK; k < (sv.off[c] + sv.len[c]) / CHUNK; ++k) chunk_case[k] = c;
+    }
+    case_chunk[n] = sv.nchunks;
+    FR_TRY(upload(&sv.d_cases, cd));
+    FR_TRY(upload(&sv.d_chunk_case, chunk_case));
+    FR_TRY(upload(&sv.d_case_chunk, case_chunk));
+    // launch groups
+    for (int c = 0; c < n; ++c) {
+        const fr_ctx x = ctxs[c];
+        Group* g = nullptr;
+        for (Group& h : sv.groups)
+            if (h.p == x->p && h.visc == (x->prm.viscous != 0) && h.mov == (x->prm.moving != 0)) g = &h;
+        if (!g) {
+            sv.groups.emplace_back();
+            g = &sv.groups.back();
+            g->p = x->p;
+            g->visc = x->prm.viscous != 0;
+            g->mov = x->prm.moving != 0;
+        }
+        g->ids.push_back(c);
+        g->elems.push_back(x->E);
+    }
+    for (Group& g : sv.groups) {
+        FR_TRY(upload(&g.d_ids, g.ids));
+        std::vector<int> widths = fused_tile_widths(g.p);
+        widths.push_back(1);
+        widths.push_back(block_apply_width(g.p));
+        for (int w : widths) {
+            if (g.tile_pfx(w)) continue;
+            std::vector<int> pfx(g.ids.size() + 1, 0);
+            for (size_t k = 0; k < g.ids.size(); ++k) pfx[k + 1] = pfx[k] + (int)((g.elems[k] + w - 1) / w);
+            int* d = nullptr;
+            FR_TRY(upload(&d, pfx));
+            g.pfx.emplace_back(w, d);
+        }
+    }
+    // per-case flags, step scalars, summary, reduction partials, pinned staging
+    FR_TRY(dalloc(&sv.d_gi, (size_t)n * GI_STRIDE));
+    FR_HIP(hipMemset(sv.d_gi, 0, (size_t)n * GI_STRIDE * sizeof(int)));
+    FR_TRY(dalloc(&sv.d_sum, (size_t)n * SUM_STRIDE));
+    FR_HIP(hipMemset(sv.d_sum, 0, (size_t)n * SUM_STRIDE * sizeof(double)));
+    FR_TRY(dalloc(&sv.d_step, (size_t)n));
+    FR_TRY(dalloc(&sv.d_part, (size_t)sv.nchunks * MAXV));
+    sv.h_pin_doubles = (size_t)n * (SUM_STRIDE + sizeof(CaseStep) / sizeof(double) + 2) + 64;
+    if (hipHostMalloc((void**)&sv.h_pin, sv.h_pin_doubles * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        sv.h_pin = nullptr;
+        fr_set_error("hipHostMalloc failed");
+        return FR_ENOMEM;
+    }
+    return FR_OK;
+}
+
+void solver_free(Solver& sv) {
+    gmres_release(sv);
+    for (Group& g : sv.groups) {
+        dfree(g.d_ids);
+        for (auto& x : g.pfx) dfree(x.second);
+    }
+    sv.groups.clear();
+    dfree(sv.d_cases); dfree(sv.d_chunk_case); dfree(sv.d_case_chunk);
+    dfree(sv.d_blk); dfree(sv.d_inv); dfree(sv.d_blk_keep);
+    dfree(sv.d_q); dfree(sv.d_w); dfree(sv.d_V); dfree(sv.d_gs); dfree(sv.d_gi); dfree(sv.d_part);
+    dfree(sv.d_step); dfree(sv.d_sum);
+    if (sv.h_pin) (void)hipHostFree(sv.h_pin);
+    if (sv.ws) (void)hipStreamDestroy(sv.ws);
+    if (sv.ev_in) (void)hipEventDestroy(sv.ev_in);
+    if (sv.ev_out) (void)hipEventDestroy(sv.ev_out);
+    sv = Solver();
+}
+
+fr_status solver_ensure_blocks(Solver& sv) {
+    FR_TRY(dalloc(&sv.d_blk, sv.Btot));
+    if (!sv.d_inv) FR_TRY(dalloc((double**)&sv.d_inv, sv.Btot));   // sized for FP64, reused by any precision
+    if (sv.keep_blocks) FR_TRY(dalloc(&sv.d_blk_keep, sv.Btot));
+    return FR_OK;
+}
+
+fr_status solver_ensure_step(Solver& sv, int m) {
+    FR_TRY(solver_ensure_blocks(sv));
+    if (sv.kry_m < m || !sv.d_V) {
+        gmres_release(sv);
+        dfree(sv.d_V); sv.d_V = nullptr;
+        dfree(sv.d_gs); sv.d_gs = nullptr;
+        FR_TRY(dalloc(&sv.d_V, (size_t)(m + 1) * sv.Ntot));
+        FR_HIP(hipMemset(sv.d_V, 0, (size_t)(m + 1) * sv.Ntot * sizeof(double)));
+        sv.gs_stride = (int)gmres_state_doubles(m);
+        FR_TRY(dalloc(&sv.d_gs, (size_t)sv.n * sv.gs_stride));
+        FR_HIP(hipMemset(sv.d_gs, 0, (size_t)sv.n * sv.gs_stride * sizeof(double)));
+        sv.kry_m = m;
+    }
+    if (!sv.d_w) {
+        // padding entries of every vector stay zero: kernels only ever write zeros there
+        FR_TRY(dalloc(&sv.d_w, (size_t)NWORK * sv.Ntot));
+        FR_HIP(hipMemset(sv.d_w, 0, (size_t)NWORK * sv.Ntot * sizeof(double)));
+    }
+    if (!sv.d_q) {
+        FR_TRY(dalloc(&sv.d_q, sv.Ntot));
+        FR_HIP(hipMemset(sv.d_q, 0, sv.Ntot * sizeof(double)));
+    }
+    if (!sv.ws) {
+        FR_HIP(hipStreamCreateWithFlags(&sv.ws, hipStreamNonBlocking));
+        FR_HIP(hipEventCreateWithFlags(&sv.ev_in, hipEventDisableTiming));
+        FR_HIP(hipEventCreateWithFlags(&sv.ev_out, hipEventDisableTiming));
+    }
+    return FR_OK;
+}
+
+// ----------------------------------------------------------------------------- step driver
+fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, const fr_step_opts* o,
+                      fr_step_stats* stats, hipStream_t caller) {
+    const int n = sv.n;
+    for (int c = 0; c < n; ++c) {
+        if (!sv.cs[c]->geometry_set) { fr_set_error("fr_set_geometry has not been called for every case"); return FR_EINVAL; }
+        if (!q[c]) { fr_set_error("null state pointer"); return FR_EINVAL; }
+        const fr_step_opts& x = o[c];
+        if (!(x.dt > 0.0) || x.krylov < 1 || x.krylov > MAXV - 4 || x.max_lin_it < 1 || x.max_newton < 0 ||
+            x.jac_lag < 1 || x.prec < FR_FP64 || x.prec > FR_BF16 || !(x.inv_dtau >= 0.0)) {
+            fr_set_error("invalid step options");
+            return FR_EINVAL;
+        }
+        if (x.krylov != o[0].krylov || x.max_lin_it != o[0].max_lin_it || x.max_newton != o[0].max_newton ||
+            x.jac_lag != o[0].jac_lag || x.prec != o[0].prec) {
+            fr_set_error("krylov, max_lin_it, max_newton, jac_lag and prec must agree across a batch");
+            return FR_EINVAL;
+        }
+    }
+    FR_TRY(solver_ensure_step(sv, o[0].krylov));
+    // the step runs on the solver stream, ordered after and before the caller's stream
+    FR_HIP(hipEventRecord(sv.ev_in, caller));
+    FR_HIP(hipStreamWaitEvent(sv.ws, sv.ev_in, 0));
+    hipStream_t s = sv.ws;
+    // per-case step scalars through the pinned staging area (the previous step has synchronised)
+    CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
+    for (int c = 0; c < n; ++c) {
+        const bool b2 = q_nm1 && q_nm1[c];
+        CaseStep& st = hst[c];
+        st.a0 = b2 ? 1.5 : 1.0;
+        st.a1 = b2 ? -2.0 : -1.0;
+        st.a2 = b2 ? 0.5 : 0.0;
+        st.inv_dt = 1.0 / o[c].dt;
+        st.ct = st.a0 / o[c].dt;
+        st.idt = o[c].inv_dtau;
+        st.tol_res = o[c].tol_res;
+        st.tol_pseudo = o[c].tol_pseudo;
+        st.tol_abs = o[c].tol_abs;
+        st.has_nm1 = b2 ? 1 : 0;
+        st.max_newton = o[c].max_newton;
+    }
+    FR_HIP(hipMemcpyAsync(sv.d_step, hst, (size_t)n * sizeof(CaseStep), hipMemcpyHostToDevice, s));
+    double* wq = sv.d_w + (size_t)WQNM1 * sv.Ntot;
+    for (int c = 0; c < n; ++c) {
+        const size_t bytes = sv.N(c) * sizeof(double);
+        FR_HIP(hipMemcpyAsync(sv.d_q + sv.off[c], q[c], bytes, hipMemcpyDeviceToDevice, s));
+        if (q_nm1 && q_nm1[c]) FR_HIP(hipMemcpyAsync(wq + sv.off[c], q_nm1[c], bytes, hipMemcpyDeviceToDevice, s));
+    }
+    const fr_status st = solver_newton(sv, &o[0], s);
+    if (st == FR_OK) {
+        for (int c = 0; c < n; ++c)
+            FR_HIP(hipMemcpyAsync(q[c], sv.d_q + sv.off[c], sv.N(c) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    FR_HIP(hipEventRecord(sv.ev_out, s));
+    FR_HIP(hipStreamWaitEvent(caller, sv.ev_out, 0));
+    if (st != FR_OK) return st;
+    // the summary was copied to h_pin by the Newton loop's last synchronisation
+    fr_status ret = FR_OK;
+    for (int c = 0; c < n; ++c) {
+        const double* x = sv.h_pin + (size_t)c * SUM_STRIDE;
+        if (stats) {
+            stats[c].newton_its = (int32_t)x[S_NEWTON];
+            stats[c].gmres_its = (int32_t)x[S_GMRES];
+            stats[c].converged = x[S_CONV] != 0.0;
+            stats[c].res0 = x[S_RES0];
+            stats[c].res_final = x[S_RES];
+        }
+        const int status = (int)x[S_STATUS];
+        char buf[160];
+        if (status == 1 && ret != FR_ENONFINITE) {
+            snprintf(buf, sizeof buf, "case %d: non-finite residual", c);
+            fr_set_error(buf);
+            ret = FR_ENONFINITE;
+        } else if ((status == 2 || status == 3) && ret == FR_OK) {
+            snprintf(buf, sizeof buf, "case %d: %s", c,
+                     status == 2 ? "Newton iteration limit reached" : "singular element block");
+            fr_set_error(buf);
+            ret = FR_ENOCONV;
+        }
+    }
+    return ret;
+}
+
+// ----------------------------------------------------------------------------- autotuner
+namespace {
+
+// free-stream state of every case (rho = T = 1, |v| = 1): inputs for timing
+__global__ void k_tune_state(const CaseDev* cases, const int* chunk_case, int nchunks, double* q, double* v) {
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int c = chunk_case[ch];
+        const CaseDev& cd = cases[c];
+        const size_t EN = (size_t)cd.E * cd.Np;
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x) {
+            const size_t r = t - cd.off;
+            const int var = (int)(r / EN);
+            double x = 0.0, d = 0.0;
+            if (var < 4) {
+                const double phase = 0.001 * (double)(r % EN);
+                x = var == 0 ? cd.pc.Rg : var == 1 ? 0.8 + 0.1 * sin(phase) : var == 2 ? 0.6 : 1.0 + 0.01 * cos(phase);
+                d = 1e-3 * cos(3.0 * phase + var);
+            }
+            q[t] = x;
+            v[t] = d;
+        }
+    }
+}
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string s = p.gcnArchName;
+    for (char& ch : s) if (ch == ' ') ch = '_';
+    return s;
+}
+
+std::string tune_key(const std::string& arch, const Group& g, int mode) {
+    long long E = 0;
+    for (long long e : g.elems) E += e;
+    int bucket = 0;
+    while ((1LL << (bucket + 1)) <= E) ++bucket;
+    std::ostringstream o;
+    o << arch << " p" << g.p << " v" << g.visc << " m" << g.mov << " mode" << mode << " e2^" << bucket;
+    return o.str();
+}
+
+}  // namespace
+
+fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
+    const std::string arch = arch_name(sv.device);
+    // cached choices
+    std::vector<std::pair<std::string, Tune>> cache;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.find('|');
+            if (bar == std::string::npos) continue;
+            std::istringstream v(line.substr(bar + 1));
+            Tune t;
+            if (v >> t.lanes >> t.grid) cache.emplace_back(line.substr(0, bar), t);
+        }
+    }
+    double *q = nullptr, *v = nullptr, *out = nullptr, *out2 = nullptr;
+    auto release = [&]() { dfree(q); dfree(v); dfree(out); dfree(out2); };
+    if (dalloc(&q, sv.Ntot) != FR_OK || dalloc(&v, sv.Ntot) != FR_OK || dalloc(&out, sv.Ntot) != FR_OK ||
+        dalloc(&out2, sv.Ntot) != FR_OK) {
+        release();
+        return FR_ENOMEM;
+    }
+    hipLaunchKernelGGL(k_tune_state, dim3((unsigned)std::min(sv.nchunks, 8192)), dim3(256), 0, s, sv.d_cases,
+                       sv.d_chunk_case, sv.nchunks, q, v);
+    hipEvent_t e0, e1;
+    FR_HIP(hipEventCreate(&e0));
+    FR_HIP(hipEventCreate(&e1));
+    fr_status ret = FR_OK;
+    std::string appended;
+    const int grids[] = {0, 512, 1024, 2048};
+    for (Group& g : sv.groups) {
+        for (int mode : {MODE_R, MODE_JVP, MODE_AOP}) {
+            const std::string key = tune_key(arch, g, mode);
+            bool found = false;
+            for (auto& kv : cache)
+                if (kv.first == key) { g.tune[mode] = kv.second; found = true; }
+            if (found) continue;
+            KArgs a{};
+            a.q = q; a.v = mode == MODE_R ? nullptr : v; a.out = out; a.out2 = nullptr;
+            a.c_time = 1.0; a.inv_dtau = 0.0;
+            Tune best;
+            float best_ms = 1e30f;
+            for (int lanes : {64, 128, 256}) {
+                if (lanes == 256 && mode != MODE_R) continue;
+                for (int grid : grids) {
+                    Tune t;
+                    t.lanes = lanes;
+                    t.grid = grid;
+                    if ((ret = launch_fused(sv, g, mode, a, t, s)) != FR_OK) break;   // warm-up
+                    FR_HIP(hipEventRecord(e0, s));
+                    const int reps = 5;
+                    for (int r = 0; r < reps && ret == FR_OK; ++r) ret = launch_fused(sv, g, mode, a, t, s);
+                    FR_HIP(hipEventRecord(e1, s));
+                    FR_HIP(hipEventSynchronize(e1));
+                    if (ret != FR_OK) break;
+                    float ms = 0.f;
+                    FR_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) { best_ms = ms; best = t; }
+                }
+                if (ret != FR_OK) break;
+            }
+            if (ret != FR_OK) break;
+            g.tune[mode] = best;
+            std::ostringstream o;
+            o << key << "|" << best.lanes << " " << best.grid << "\n";
+            appended += o.str();
+        }
+        if (ret != FR_OK) break;
+        // block columns use the dual-number shape of the Newton operator
+        g.tune[MODE_BLK] = g.tune[MODE_AOP];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    FR_HIP(hipStreamSynchronize(s));
+    release();
+    if (ret != FR_OK) return ret;
+    gmres_release(sv);   // captured cycles baked the previous shapes
+    if (cache_path && !appended.empty()) {
+        std::ofstream outf(cache_path, std::ios::app);
+        outf << appended;
+    }
+    return FR_OK;
+}

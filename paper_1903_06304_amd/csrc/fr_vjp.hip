@@ -546,7 +546,7 @@ fr_status vjp_p(fr_ctx c, const double* q, const double* w, double* out, hipStre
 }  // namespace
 
 fr_status launch_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
-    fr_status st = launch_traces(c, q, nullptr, c->d_trace, 0, s);
+    fr_status st = launch_traces(c, q, c->d_trace, s);
     if (st != FR_OK) return st;
     if (!c->d_vj) {
         const size_t sz = (size_t)c->E * 4 * 10 * c->n * sizeof(double);

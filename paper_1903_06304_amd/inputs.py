@@ -253,6 +253,18 @@ def _fourier_modes(kmax: int):
     return np.array(ks, dtype=float)
 
 
+def _mode_sum(x, y, x0, y0, Lx, Ly, ks, coef, kmax):
+    """sum_k Re(coef_k exp(i (2 pi kx (x - x0)/Lx + 2 pi ky (y - y0)/Ly))), evaluated with
+    the separable factors exp(i 2 pi kx x / Lx) and exp(i 2 pi ky y / Ly)."""
+    n = 2 * kmax + 1
+    C = np.zeros((n, n), dtype=complex)
+    for (kx, ky), c in zip(ks.astype(int), coef):
+        C[kx + kmax, ky + kmax] += c
+    ex = np.exp(1j * 2 * np.pi * np.outer(np.arange(-kmax, kmax + 1), (x - x0).ravel() / Lx))
+    ey = np.exp(1j * 2 * np.pi * np.outer(np.arange(-kmax, kmax + 1), (y - y0).ravel() / Ly))
+    return np.real(np.sum(ex * (C @ ey), axis=0)).reshape(x.shape)
+
+
 def random_scalar_field(mesh: Mesh, rng: np.random.Generator, kmax: int = 4, xy=None):
     """Unit-RMS smooth periodic random field sum_k a_k cos(k.x + phase_k), |k|_inf <= kmax."""
     if xy is None:
@@ -262,9 +274,7 @@ def random_scalar_field(mesh: Mesh, rng: np.random.Generator, kmax: int = 4, xy=
     ks = _fourier_modes(kmax)
     amp = rng.standard_normal(len(ks)) / np.maximum(1.0, np.hypot(ks[:, 0], ks[:, 1]))
     ph = rng.uniform(0, 2 * np.pi, len(ks))
-    f = np.zeros_like(x)
-    for (kx, ky), a, s in zip(ks, amp, ph):
-        f += a * np.cos(2 * np.pi * (kx * (x - x0) / (x1 - x0) + ky * (y - y0) / (y1 - y0)) + s)
+    f = _mode_sum(x, y, x0, y0, x1 - x0, y1 - y0, ks, amp * np.exp(1j * ph), kmax)
     return f / np.sqrt(np.mean(f * f))
 
 
@@ -282,13 +292,9 @@ def random_solenoidal_velocity(mesh: Mesh, rng: np.random.Generator, rms: float,
     ks = _fourier_modes(kmax)
     a = rng.standard_normal(len(ks))
     ph = rng.uniform(0, 2 * np.pi, len(ks))
-    u = np.zeros_like(x)
-    v = np.zeros_like(x)
-    for (kx, ky), ak, s in zip(ks, a, ph):
-        wx, wy = 2 * np.pi * kx / Lx, 2 * np.pi * ky / Ly
-        c = ak / (kx * kx + ky * ky) * np.cos(wx * (x - x0) + wy * (y - y0) + s)
-        u += c * wy
-        v -= c * wx
+    base = a / (ks[:, 0] ** 2 + ks[:, 1] ** 2) * np.exp(1j * ph)
+    u = _mode_sum(x, y, x0, y0, Lx, Ly, ks, base * (2 * np.pi * ks[:, 1] / Ly), kmax)
+    v = -_mode_sum(x, y, x0, y0, Lx, Ly, ks, base * (2 * np.pi * ks[:, 0] / Lx), kmax)
     scale = rms / np.sqrt(np.mean(u * u + v * v) / 2.0 + 1e-300)
     return u * scale, v * scale
 

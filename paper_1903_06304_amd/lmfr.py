@@ -23,7 +23,9 @@ PREC = {"fp64": FR_FP64, "fp32": FR_FP32, "bf16": FR_BF16}
 # every symbol declared in include/lmfr.h
 EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "fr_bdf_operator",
            "fr_block_jacobi_factor", "fr_block_jacobi_apply", "fr_get_blocks", "fr_bdf2_step",
-           "fr_set_option", "fr_last_error", "fr_destroy"]
+           "fr_set_option", "fr_autotune", "fr_batch_create", "fr_batch_destroy", "fr_batch_layout",
+           "fr_batch_residual", "fr_batch_jvp", "fr_batch_bdf2_step", "fr_batch_set_option",
+           "fr_batch_autotune", "fr_last_error", "fr_destroy"]
 
 
 class FRError(RuntimeError):
@@ -72,10 +74,19 @@ def load_library(path: str = LIB_PATH):
     L.fr_get_blocks.argtypes = [vp, dp, vp]
     L.fr_bdf2_step.argtypes = [vp, dp, dp, ctypes.POINTER(fr_step_opts), ctypes.POINTER(fr_step_stats), vp]
     L.fr_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+    L.fr_autotune.argtypes = [vp, ctypes.c_char_p, vp]
+    L.fr_batch_create.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+    L.fr_batch_destroy.argtypes = [vp]
+    L.fr_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.fr_batch_residual.argtypes = [vp, dp, dp, vp]
+    L.fr_batch_jvp.argtypes = [vp, dp, dp, dp, vp]
+    L.fr_batch_bdf2_step.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.fr_batch_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+    L.fr_batch_autotune.argtypes = [vp, ctypes.c_char_p, vp]
     L.fr_last_error.restype = ctypes.c_char_p
     L.fr_destroy.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("fr_last_error", "fr_destroy"):
+        if name not in ("fr_last_error", "fr_destroy", "fr_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -192,20 +203,105 @@ class Context:
         _check(load_library().fr_get_blocks(self.h, _ptr(out), _stream()))
         return out
 
+    def autotune(self, cache_path=None):
+        _check(load_library().fr_autotune(self.h, None if cache_path is None else str(cache_path).encode(),
+                                          _stream()))
+
     def bdf2_step(self, q, q_nm1, dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=100,
                   max_newton=100, jac_lag=2, inv_dtau=1e-20, tol_abs=0.0, prec="fp64", check=True):
         """One BDF2 step in place on q (a float64 device tensor); returns the stats dict."""
         q = self._state(q)
         qn1 = None if q_nm1 is None else self._state(q_nm1)
-        o = fr_step_opts(float(dt), float(inv_dtau), float(tol_pseudo), float(tol_res), float(tol_abs),
-                         int(krylov), int(max_lin_it), int(max_newton), int(jac_lag),
-                         PREC[prec] if isinstance(prec, str) else int(prec))
+        o = step_opts(dt, tol_pseudo, tol_res, krylov, max_lin_it, max_newton, jac_lag, inv_dtau, tol_abs, prec)
         st = fr_step_stats()
         rc = load_library().fr_bdf2_step(self.h, _ptr(q), _ptr(qn1), ctypes.byref(o), ctypes.byref(st), _stream())
         if check and rc not in (FR_OK, FR_ENOCONV):
             _check(rc)
         return dict(rc=rc, newton_its=st.newton_its, gmres_its=st.gmres_its, converged=st.converged,
                     res0=st.res0, res_final=st.res_final)
+
+
+def step_opts(dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=100, max_newton=100, jac_lag=2,
+              inv_dtau=1e-20, tol_abs=0.0, prec="fp64"):
+    return fr_step_opts(float(dt), float(inv_dtau), float(tol_pseudo), float(tol_res), float(tol_abs),
+                        int(krylov), int(max_lin_it), int(max_newton), int(jac_lag),
+                        PREC[prec] if isinstance(prec, str) else int(prec))
+
+
+class Batch:
+    """Many contexts advanced together (fr_batch_*): one launch per kind of case."""
+
+    def __init__(self, contexts):
+        L = load_library()
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = ctypes.c_void_p()
+        _check(L.fr_batch_create(arr, len(self.contexts), ctypes.byref(h)))
+        self.h = h
+        n_total = ctypes.c_int64()
+        offs = (ctypes.c_int64 * len(self.contexts))()
+        _check(L.fr_batch_layout(self.h, ctypes.byref(n_total), offs))
+        self.n_total = int(n_total.value)
+        self.offsets = [int(x) for x in offs]
+        self.device = self.contexts[0].device
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                load_library().fr_batch_destroy(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def pack(self, states):
+        """Concatenate per-case states into the batch layout (zero padding)."""
+        out = torch.zeros(self.n_total, dtype=torch.float64, device=self.device)
+        for c, (ctx, x) in enumerate(zip(self.contexts, states)):
+            n = 4 * ctx.E * ctx.Np
+            out[self.offsets[c]:self.offsets[c] + n] = ctx._state(x).reshape(-1)
+        return out
+
+    def unpack(self, flat):
+        return [flat[o:o + 4 * c.E * c.Np].view(c.shape) for c, o in zip(self.contexts, self.offsets)]
+
+    def residual(self, q_flat, out=None):
+        R = torch.zeros_like(q_flat) if out is None else out
+        _check(load_library().fr_batch_residual(self.h, _ptr(q_flat), _ptr(R), _stream()))
+        return R
+
+    def jvp(self, q_flat, v_flat):
+        Jv = torch.zeros_like(q_flat)
+        _check(load_library().fr_batch_jvp(self.h, _ptr(q_flat), _ptr(v_flat), _ptr(Jv), _stream()))
+        return Jv
+
+    def set_option(self, name: str, value: int):
+        _check(load_library().fr_batch_set_option(self.h, name.encode(), int(value)))
+
+    def autotune(self, cache_path=None):
+        _check(load_library().fr_batch_autotune(self.h, None if cache_path is None else str(cache_path).encode(),
+                                                _stream()))
+
+    def bdf2_step(self, qs, q_nm1s, opts, check=True):
+        """One step of every case in place on the tensors qs; opts: one fr_step_opts per case
+        (or one shared).  Returns (status, [stats dicts])."""
+        n = len(self.contexts)
+        if isinstance(opts, fr_step_opts):
+            opts = [opts] * n
+        qs = [c._state(q) for c, q in zip(self.contexts, qs)]
+        qarr = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        if q_nm1s is None:
+            parr = None
+        else:
+            pm = [None if x is None else c._state(x) for c, x in zip(self.contexts, q_nm1s)]
+            self._keep = pm
+            parr = (ctypes.c_void_p * n)(*[None if x is None else x.data_ptr() for x in pm])
+        oarr = (fr_step_opts * n)(*opts)
+        sarr = (fr_step_stats * n)()
+        rc = load_library().fr_batch_bdf2_step(self.h, qarr, parr, oarr, sarr, _stream())
+        if check and rc not in (FR_OK, FR_ENOCONV):
+            _check(rc)
+        return rc, [dict(newton_its=s.newton_its, gmres_its=s.gmres_its, converged=s.converged, res0=s.res0,
+                         res_final=s.res_final) for s in sarr]
 
 
 class FRResidual(torch.autograd.Function):
