@@ -141,11 +141,17 @@ fr_status fr_bdf2_step(fr_ctx ctx, double* q, const double* q_nm1, const fr_step
                        fr_step_stats* h_stats, void* stream);
 
 /* Options: "keep_blocks" (0/1: keep the FP64 blocks for fr_get_blocks), "graph" (0/1:
- * replay each GMRES restart cycle from a captured hipGraph, default 1). */
+ * replay each GMRES restart cycle from a captured hipGraph, default 1), "gram_schmidt"
+ * (1: classical Gram-Schmidt, one orthogonalisation pass per Arnoldi step, the default;
+ * 2: with one re-orthogonalisation pass), and a manual
+ * launch shape of the fused kernels (what fr_autotune chooses): "tile_lanes" (0 =
+ * default, 64, 128, 256; dual-number modes cap it at 128), "tile_grid" (0 = one
+ * workgroup per tile, else the persistent grid size), "tile_xcd" (1 = each XCD walks a
+ * contiguous eighth of the tiles, 0 = round robin). */
 fr_status fr_set_option(fr_ctx ctx, const char* name, int64_t value);
 
-/* Choose the launch shape (workgroup width: elements per workgroup, and persistent grid
- * size) of the residual, JVP and Newton-operator kernels by timing the candidates on the
+/* Choose the launch shape (workgroup width: elements per workgroup, persistent grid
+ * size, tile order across XCDs) of the residual, JVP and Newton-operator kernels by timing the candidates on the
  * device with a free-stream state; block-column assembly takes the Newton operator's
  * shape.  cache_path (may be NULL): text file of earlier choices keyed by GPU
  * architecture, order, viscous/moving flags, mode and element-count bucket; entries
@@ -187,7 +193,8 @@ fr_status fr_batch_jvp(fr_batch batch, const double* q, const double* v, double*
 fr_status fr_batch_bdf2_step(fr_batch batch, double* const* q, const double* const* q_nm1,
                              const fr_step_opts* opts, fr_step_stats* h_stats, void* stream);
 
-/* Options: "graph" (0/1) as for a context. */
+/* Options: "graph", "gram_schmidt" and the "tile_*" launch-shape options, as for a
+ * context. */
 fr_status fr_batch_set_option(fr_batch batch, const char* name, int64_t value);
 
 /* fr_autotune for every launch group of the batch. */

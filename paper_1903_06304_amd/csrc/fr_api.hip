@@ -218,12 +218,49 @@ extern "C" void fr_destroy(fr_ctx c) {
     delete c;
 }
 
+static bool is_tile_option(const char* name);
+static fr_status set_tile_option(Solver& sv, const char* name, int64_t value);
+
+static bool is_tile_option(const char* name) {
+    return !strcmp(name, "tile_lanes") || !strcmp(name, "tile_grid") || !strcmp(name, "tile_xcd");
+}
+
+// solver options shared by contexts and batches; returns FR_EINVAL with no message for
+// names it does not know
+static fr_status solver_option(Solver& sv, const char* name, int64_t value) {
+    if (!strcmp(name, "graph")) { sv.use_graph = value != 0; gmres_release(sv); return FR_OK; }
+    if (!strcmp(name, "gram_schmidt")) {
+        if (value != 1 && value != 2) return bad("gram_schmidt must be 1 or 2");
+        sv.gs_passes = (int)value;
+        gmres_release(sv);
+        return FR_OK;
+    }
+    if (is_tile_option(name)) return set_tile_option(sv, name, value);
+    fr_set_error(std::string("unknown option ") + name);
+    return FR_EINVAL;
+}
+
+// manual launch shape of every group and mode of a solver
+static fr_status set_tile_option(Solver& sv, const char* name, int64_t value) {
+    if (value < 0 || value > (1 << 24)) return bad("tile option out of range");
+    if (!strcmp(name, "tile_lanes") && value != 0 && value != 64 && value != 128 && value != 256)
+        return bad("tile_lanes must be 0, 64, 128 or 256");
+    for (Group& g : sv.groups)
+        for (int m = 0; m < 4; ++m) {
+            Tune& t = g.tune[m];
+            if (!strcmp(name, "tile_lanes")) t.lanes = (m != MODE_R && value == 256) ? 128 : (int)value;
+            else if (!strcmp(name, "tile_grid")) t.grid = (int)value;
+            else t.xcd = value != 0;
+        }
+    gmres_release(sv);
+    return FR_OK;
+}
+
 extern "C" fr_status fr_set_option(fr_ctx c, const char* name, int64_t value) {
     if (!c || !name) return bad("fr_set_option: null argument");
     Solver& sv = *c->self;
     if (!strcmp(name, "keep_blocks")) { sv.keep_blocks = value != 0; return FR_OK; }
-    if (!strcmp(name, "graph")) { sv.use_graph = value != 0; gmres_release(sv); return FR_OK; }
-    return bad("fr_set_option: unknown option");
+    return solver_option(sv, name, value);
 }
 
 extern "C" fr_status fr_set_geometry(fr_ctx c, const double* xg, const double* vg, void* stream) {
@@ -406,8 +443,7 @@ extern "C" fr_status fr_batch_bdf2_step(fr_batch b, double* const* q, const doub
 
 extern "C" fr_status fr_batch_set_option(fr_batch b, const char* name, int64_t value) {
     if (!b || !name) return bad("fr_batch_set_option: null argument");
-    if (!strcmp(name, "graph")) { b->sv.use_graph = value != 0; gmres_release(b->sv); return FR_OK; }
-    return bad("fr_batch_set_option: unknown option");
+    return solver_option(b->sv, name, value);
 }
 
 extern "C" fr_status fr_batch_autotune(fr_batch b, const char* cache_path, void* stream) {

@@ -138,13 +138,20 @@ __device__ __forceinline__ int find_member(const GroupArgs& ga, int t) {
     return lo;
 }
 
-// first tile of the range walked by this workgroup, and the end of that range
-__device__ __forceinline__ void xcd_range(int ntiles, int& t0, int& tend, int& stride) {
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
-    const int t8 = (ntiles + 7) >> 3;
-    t0 = xcd * t8 + slot;
-    tend = min((xcd + 1) * t8, ntiles);
-    stride = per;
+// first tile of the range walked by this workgroup, the end of that range and the
+// stride: XCD-contiguous ranges (workgroup b runs on XCD b % 8), or plain round robin
+__device__ __forceinline__ void tile_range(int ntiles, int xcd_order, int& t0, int& tend, int& stride) {
+    if (xcd_order) {
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, per = gridDim.x >> 3;
+        const int t8 = (ntiles + 7) >> 3;
+        t0 = xcd * t8 + slot;
+        tend = min((xcd + 1) * t8, ntiles);
+        stride = per;
+    } else {
+        t0 = blockIdx.x;
+        tend = ntiles;
+        stride = gridDim.x;
+    }
 }
 
 template <int P, bool VISC, bool MOV, int MODE, int K, int LANES>
@@ -172,7 +179,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     }
     const int i = lt % n, j = lt / n;
     int tile, tend, tstride;
-    xcd_range(ga.ntiles, tile, tend, tstride);
+    tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
     for (; tile < tend; tile += tstride) {
         // ---- the tile's case (uniform across the workgroup)
         const int lo = find_member(ga, tile);
@@ -443,7 +450,7 @@ inline unsigned grid_of(int ntiles, int grid) {
 }
 
 template <int P, bool VISC, bool MOV, int MODE, int LANES>
-fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, hipStream_t s) {
+fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int xcd, hipStream_t s) {
     using SH = Shape<P, LANES>;
     GroupArgs ga;
     ga.cases = sv.d_cases;
@@ -451,6 +458,7 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, hipSt
     ga.pfx = gr.tile_pfx(SH::EPB);
     ga.nmem = (int)gr.ids.size();
     ga.ntiles = gr.ntiles(SH::EPB);
+    ga.xcd = xcd;
     if (!ga.pfx) { fr_set_error("tile prefix missing for this workgroup shape"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
     const OpTab& op = sv.cs[gr.ids[0]]->op;
@@ -467,10 +475,10 @@ fr_status run_lanes(const Solver& sv, const Group& gr, const KArgs& a, const Tun
     constexpr bool dual = MODE != MODE_R;
     const int lanes = t.lanes > 0 ? t.lanes : (dual ? 64 : 128);
     switch (lanes) {
-        case 64: return run<P, VISC, MOV, MODE, 64>(sv, gr, a, t.grid, s);
-        case 128: return run<P, VISC, MOV, MODE, 128>(sv, gr, a, t.grid, s);
+        case 64: return run<P, VISC, MOV, MODE, 64>(sv, gr, a, t.grid, t.xcd, s);
+        case 128: return run<P, VISC, MOV, MODE, 128>(sv, gr, a, t.grid, t.xcd, s);
         case 256:
-            if constexpr (!dual) return run<P, VISC, MOV, MODE, 256>(sv, gr, a, t.grid, s);
+            if constexpr (!dual) return run<P, VISC, MOV, MODE, 256>(sv, gr, a, t.grid, t.xcd, s);
             break;
     }
     fr_set_error("unsupported workgroup width");

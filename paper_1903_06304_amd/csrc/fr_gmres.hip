@@ -4,7 +4,8 @@
 //
 // One restart cycle is a fixed sequence of launches over all cases:
 //   cycle init (per case: idle test, g = beta e1, V_0 = r / beta) |
-//   m x [ z = P^-1 V_j ; w = A z ; classical Gram-Schmidt twice (3 streaming passes) ;
+//   m x [ z = P^-1 V_j ; w = A z ; classical Gram-Schmidt (2 streaming passes over V, or
+//         4 when re-orthogonalised: option "gram_schmidt" = 2) ;
 //         Givens update of column j and of g, convergence test ; V_{j+1} = w / h_{j+1,j} ] |
 //   y = H^-1 g ; x += P^-1 (V y) ; r = b - A x ; beta = |r|
 // Per-case flags decide which cases a launch touches: a case whose Arnoldi process has
@@ -100,7 +101,7 @@ __global__ void k_cycle_init(Ctl k, int m) {
 }
 
 // column j of each case's Hessenberg matrix, Givens rotations, convergence flag
-__global__ void k_givens(Ctl k, int j, int m) {
+__global__ void k_givens(Ctl k, int j, int m, int passes) {
     const int c = case_index();
     if (c >= k.n) return;
     int* gi = k.gi + c * GI_STRIDE;
@@ -111,7 +112,7 @@ __global__ void k_givens(Ctl k, int j, int m) {
     double* cs = gs + L.CS;
     double* sn = gs + L.SN;
     double* g = gs + L.G;
-    for (int i = 0; i <= j; ++i) H[i * m + j] = gs[L.H1 + i] + gs[L.H2 + i];
+    for (int i = 0; i <= j; ++i) H[i * m + j] = passes == 2 ? gs[L.H1 + i] + gs[L.H2 + i] : gs[L.H1 + i];
     const double hn = sqrt(gs[L.NRM]);
     H[(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
@@ -270,10 +271,18 @@ fr_status enqueue_cycle(Solver& sv, int m, hipStream_t s) {
         double* vj = V + (size_t)j * N;
         FR_TRY(launch_block_apply(sv, vj, z, sv.d_gi, GI_DONE, s));
         FR_TRY(bdf_op(sv, q, z, w, GI_DONE, s));
+        // classical Gram-Schmidt: h = V^T w, w -= V h (and once more when re-orthogonalising)
         FR_TRY(la_krylov(sv, V, N, 0, nullptr, 0, j + 1, w, nullptr, false, false, gs + L.H1, gst, sv.d_gi, GI_DONE, s));
-        FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, j + 1, w, w, false, false, gs + L.H2, gst, sv.d_gi, GI_DONE, s));
-        FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H2, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi, GI_DONE, s));
-        hipLaunchKernelGGL(k_givens, dim3(cgrid(sv)), dim3(64), 0, s, k, j, m);
+        if (sv.gs_passes == 2) {
+            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, j + 1, w, w, false, false, gs + L.H2, gst, sv.d_gi,
+                             GI_DONE, s));
+            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H2, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi,
+                             GI_DONE, s));
+        } else {
+            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi,
+                             GI_DONE, s));
+        }
+        hipLaunchKernelGGL(k_givens, dim3(cgrid(sv)), dim3(64), 0, s, k, j, m, sv.gs_passes);
         FR_HIP(hipGetLastError());
         if (j + 1 < m) {
             hipLaunchKernelGGL(k_scale_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_DONE), w,
@@ -374,7 +383,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
     FR_HIP(hipGetLastError());
 
     const bool graph = sv.use_graph;
-    if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec)) {
+    if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec || sv.graph_passes != sv.gs_passes)) {
         gmres_release(sv);
         // capture one cycle (all buffers are solver-owned; tolerances, time coefficients and
         // caps are read on the device, so the graph depends on m and the block precision only)
@@ -391,6 +400,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
         sv.graph_exec = ex;
         sv.graph_m = m;
         sv.graph_prec = prec;
+        sv.graph_passes = sv.gs_passes;
     }
     double* hs = sv.h_pin;
     for (;;) {

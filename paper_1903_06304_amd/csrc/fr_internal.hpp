@@ -99,12 +99,14 @@ struct GroupArgs {
     const int* pfx;       // first tile of each member, [nmem + 1]
     int nmem;
     int ntiles;
+    int xcd;              // tile order (Tune::xcd)
 };
 
 // launch shape of the fused kernel: workgroup width (lanes) and persistent grid size
 struct Tune {
     int lanes = 0;        // 0: default of the variant
     int grid = 0;         // 0: one workgroup per tile
+    int xcd = 1;          // 1: each XCD walks a contiguous eighth of the tiles; 0: round robin
 };
 
 struct Group {
@@ -181,7 +183,8 @@ struct Solver {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     bool use_graph = true;
     void* graph_exec = nullptr;
-    int graph_m = 0, graph_prec = -1;
+    int graph_m = 0, graph_prec = -1, graph_passes = 0;
+    int gs_passes = 1;                     // classical Gram-Schmidt passes per Arnoldi step (1 or 2)
     size_t N(int c) const { return (size_t)4 * cs[c]->E * cs[c]->Np; }
 };
 

@@ -364,6 +364,7 @@ GroupArgs group_args(const Solver& sv, const Group& gr, int epb) {
     ga.pfx = gr.tile_pfx(epb);
     ga.nmem = (int)gr.ids.size();
     ga.ntiles = gr.ntiles(epb);
+    ga.xcd = 0;
     return ga;
 }
 

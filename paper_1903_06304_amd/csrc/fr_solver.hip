@@ -309,7 +309,7 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
             if (bar == std::string::npos) continue;
             std::istringstream v(line.substr(bar + 1));
             Tune t;
-            if (v >> t.lanes >> t.grid) cache.emplace_back(line.substr(0, bar), t);
+            if (v >> t.lanes >> t.grid >> t.xcd) cache.emplace_back(line.substr(0, bar), t);
         }
     }
     double *q = nullptr, *v = nullptr, *out = nullptr, *out2 = nullptr;
@@ -341,10 +341,11 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
             float best_ms = 1e30f;
             for (int lanes : {64, 128, 256}) {
                 if (lanes == 256 && mode != MODE_R) continue;
-                for (int grid : grids) {
+                for (int gx = 0; gx < 8; ++gx) {
                     Tune t;
                     t.lanes = lanes;
-                    t.grid = grid;
+                    t.grid = grids[gx % 4];
+                    t.xcd = gx / 4;
                     if ((ret = launch_fused(sv, g, mode, a, t, s)) != FR_OK) break;   // warm-up
                     FR_HIP(hipEventRecord(e0, s));
                     const int reps = 5;
@@ -361,7 +362,7 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
             if (ret != FR_OK) break;
             g.tune[mode] = best;
             std::ostringstream o;
-            o << key << "|" << best.lanes << " " << best.grid << "\n";
+            o << key << "|" << best.lanes << " " << best.grid << " " << best.xcd << "\n";
             appended += o.str();
         }
         if (ret != FR_OK) break;

@@ -180,9 +180,11 @@ def test_blocks_parity(nx, ny, p, kind):
         assert rel <= tol, (prec, rel)
 
 
-def test_bdf2_step_parity_c1():
+@pytest.mark.parametrize("gram_schmidt", [1, 2])
+def test_bdf2_step_parity_c1(gram_schmidt):
     c = I.config_c1(nx=4)
     o, g = _pair(c.prm, c.mesh)
+    g.set_option("gram_schmidt", gram_schmidt)
     kw = dict(tol_pseudo=1e-10, tol_res=1e-9, krylov=20, max_lin_it=200, max_newton=20)
     qo, sto = o.bdf2_step(c.q, c.q_nm1, c.dt, **kw)
     qg = _dev(c.q)
