@@ -154,6 +154,20 @@ __device__ __forceinline__ void tile_range(int ntiles, int xcd_order, int& t0, i
     }
 }
 
+// LDS padding (in scalars of type T) of the solution-point arrays: per field, per group
+// of four fields (one face of neighbour states) and per element.  Chosen with a model of
+// the kernel's main access patterns so that the lanes of a wave (several elements, the
+// four faces of each) spread over the 32 banks; W = doubles per scalar.
+template <int P, int W> struct LPad { static constexpr int F = 0, FACE = 2, E = 1; };
+template <> struct LPad<1, 1> { static constexpr int F = 1, FACE = 1, E = 0; };
+template <> struct LPad<1, 2> { static constexpr int F = 0, FACE = 1, E = 2; };
+template <> struct LPad<2, 1> { static constexpr int F = 1, FACE = 1, E = 0; };
+template <> struct LPad<2, 2> { static constexpr int F = 1, FACE = 3, E = 2; };
+template <> struct LPad<3, 1> { static constexpr int F = 0, FACE = 2, E = 1; };
+template <> struct LPad<3, 2> { static constexpr int F = 0, FACE = 2, E = 3; };
+template <> struct LPad<4, 1> { static constexpr int F = 1, FACE = 1, E = 4; };
+template <> struct LPad<4, 2> { static constexpr int F = 0, FACE = 1, E = 5; };
+
 template <int P, bool VISC, bool MOV, int MODE, int K, int LANES>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused(GroupArgs ga, KArgs a, OpTab op) {
@@ -162,12 +176,26 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     constexpr int EPB = Shape<P, LANES>::EPB;
     constexpr int NW = MOV ? 12 : 8;
     static_assert(NW <= 16, "flux fields alias the neighbour staging area");
-    __shared__ T s_q[EPB][4][Np];
-    __shared__ T s_n[EPB][16][Np];      // neighbour states [face*4 + var]; later f, g (, q^c)
-    __shared__ T s_g[EPB][VISC ? 6 : 1][Np];
-    __shared__ T s_F[EPB][NF][4];       // F^num, then F^num - F^loc
-    __shared__ T s_dq[EPB][NF][VISC ? 3 : 1];
-    __shared__ double s_S[EPB][NF][3];  // element-oriented S, S . v_g
+    using PD = LPad<P, Store<T>::W>;
+    constexpr int FS = Np + PD::F;               // field stride
+    constexpr int FACE = 4 * FS + PD::FACE;      // stride of a group of 4 fields
+    constexpr int ESN = 4 * FACE + PD::E;        // element stride of the neighbour / flux area
+    constexpr int ESQ = 4 * FS + PD::E;
+    constexpr int NG = VISC ? 6 : 1;
+    constexpr int ESG = NG * FS + PD::E;
+    constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1, ESS = 3 * NF + 1;
+    __shared__ T s_q[EPB * ESQ];       // own state [el][var][point]
+    __shared__ T s_n[EPB * ESN];       // neighbour states [el][face][var][point]; later f, g (, q^c)
+    __shared__ T s_g[EPB * ESG];       // own uncorrected gradient [el][6][point]
+    __shared__ T s_F[EPB * ESF];       // F^num, then F^num - F^loc  [el][var][flux point]
+    __shared__ T s_dq[EPB * ESD];      // q^com - q^- of (u, v, T)  [el][3][flux point]
+    __shared__ double s_S[EPB * ESS];  // element-oriented S, S . v_g  [el][3][flux point]
+    auto QI = [](int el, int v, int sp) { return el * ESQ + v * FS + sp; };
+    auto NI = [](int el, int fld, int sp) { return el * ESN + (fld >> 2) * FACE + (fld & 3) * FS + sp; };
+    auto GI = [](int el, int c, int sp) { return el * ESG + c * FS + sp; };
+    auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
+    auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
+    auto SI = [](int el, int c, int fp) { return el * ESS + c * NF + fp; };
     __shared__ double s_D[n * n];       // operator tables (lane-dependent indexing goes to LDS)
     __shared__ double s_lam[2][n], s_gam[2][n];
 
@@ -199,14 +227,14 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) s_q[el][vv][lt] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + lt);
+            for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + lt);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 const int nb = g.nbr[e * 4 + f] >> 3;
                 const unsigned nid = (unsigned)nb * Np + lt;
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv)
-                    s_n[el][f * 4 + vv][lt] = NbLoad<T>::load(a, q, v, vv * EN + nid, vv * Np + lt, nb == e);
+                    s_n[NI(el, f * 4 + vv, lt)] = NbLoad<T>::load(a, q, v, vv * EN + nid, vv * Np + lt, nb == e);
             }
         }
         __syncthreads();
@@ -220,11 +248,11 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                 T dxi = cst<T>(0.0), deta = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
-                    dxi = dxi + s_D[i * n + b] * s_q[el][c + 1][b + n * j];
-                    deta = deta + s_D[j * n + b] * s_q[el][c + 1][i + n * b];
+                    dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
+                    deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
                 }
-                s_g[el][2 * c][lt] = xix * dxi + etx * deta;
-                s_g[el][2 * c + 1][lt] = xiy * dxi + ety * deta;
+                s_g[GI(el, 2 * c, lt)] = xix * dxi + etx * deta;
+                s_g[GI(el, 2 * c + 1, lt)] = xiy * dxi + ety * deta;
             }
         }
         __syncthreads();
@@ -249,8 +277,8 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                     T am = cst<T>(0.0), ap = cst<T>(0.0);
 #pragma unroll
                     for (int b = 0; b < n; ++b) {
-                        am = am + lam[b] * s_q[el][vv][line_pt(n, f, k, b)];
-                        ap = ap + lamn[b] * s_n[el][f * 4 + vv][line_pt(n, nf, k2, b)];
+                        am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                        ap = ap + lamn[b] * s_n[NI(el, f * 4 + vv, line_pt(n, nf, k2, b))];
                     }
                     qm[vv] = am;
                     qp[vv] = ap;
@@ -263,7 +291,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                 for (int c = 0; c < 6; ++c) {
                     T am = cst<T>(0.0);
 #pragma unroll
-                    for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[el][c][line_pt(n, f, k, b)];
+                    for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
                     gm[c] = am;
                     gp[c] = cst<T>(0.0);
                 }
@@ -280,50 +308,50 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                         T dxi = cst<T>(0.0), deta = cst<T>(0.0);
 #pragma unroll
                         for (int m = 0; m < n; ++m) {
-                            dxi = dxi + s_D[is * n + m] * s_n[el][f * 4 + c + 1][m + n * js];
-                            deta = deta + s_D[js * n + m] * s_n[el][f * 4 + c + 1][is + n * m];
+                            dxi = dxi + s_D[is * n + m] * s_n[NI(el, f * 4 + c + 1, m + n * js)];
+                            deta = deta + s_D[js * n + m] * s_n[NI(el, f * 4 + c + 1, is + n * m)];
                         }
                         gp[2 * c] = gp[2 * c] + lamn[b] * (xix * dxi + etx * deta);
                         gp[2 * c + 1] = gp[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
                     }
                 }
                 // q^com velocity = average of the two traces = q^- + dq/2
-                const T qcu = am_avg<T>(s_q[el][1], lam, f, k, dq[1], n);
-                const T qcv = am_avg<T>(s_q[el][2], lam, f, k, dq[2], n);
+                const T qcu = am_avg<T>(&s_q[QI(el, 1, 0)], lam, f, k, dq[1], n);
+                const T qcv = am_avg<T>(&s_q[QI(el, 2, 0)], lam, f, k, dq[2], n);
                 T dqh[3];
                 fr_common_viscous<T>(pc, dq, qcu, qcv, gm, gp, nx, ny, g.fp[F_CC * FE + sid], fn, dqh);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) s_dq[el][lt][c] = dqh[c];
+                for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c];
             }
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) s_F[el][lt][vv] = sc * fn[vv];
-            s_S[el][lt][0] = sc * nx;                                  // element-oriented S
-            s_S[el][lt][1] = sc * ny;
-            s_S[el][lt][2] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;   // S . v_g
+            for (int vv = 0; vv < 4; ++vv) s_F[FI(el, vv, lt)] = sc * fn[vv];
+            s_S[SI(el, 0, lt)] = sc * nx;                                  // element-oriented S
+            s_S[SI(el, 1, lt)] = sc * ny;
+            s_S[SI(el, 2, lt)] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;   // S . v_g
         }
         __syncthreads();
 
         // ---- stage 4: corrected gradient, pointwise fluxes (into the staging area)
-        T (*s_w)[Np] = s_n[el];
+        auto WI = [&](int fld, int sp) { return NI(el, fld, sp); };   // fluxes alias the neighbour area
         T qs[4];
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
             const double ij = g.sp[G_IJ * EN + id];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[el][vv][lt];
+            for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[QI(el, vv, lt)];
             T gu[2], gv[2], gT[2];
             if (VISC) {
 #pragma unroll
-                for (int d = 0; d < 2; ++d) { gu[d] = s_g[el][d][lt]; gv[d] = s_g[el][2 + d][lt]; gT[d] = s_g[el][4 + d][lt]; }
+                for (int d = 0; d < 2; ++d) { gu[d] = s_g[GI(el, d, lt)]; gv[d] = s_g[GI(el, 2 + d, lt)]; gT[d] = s_g[GI(el, 4 + d, lt)]; }
                 const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
                 const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
                 T* gr[3] = {gu, gv, gT};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    T cx = (s_S[el][fp0][0] * gL_i) * s_dq[el][fp0][c] + (s_S[el][fp1][0] * gR_i) * s_dq[el][fp1][c]
-                         + (s_S[el][fp2][0] * gL_j) * s_dq[el][fp2][c] + (s_S[el][fp3][0] * gR_j) * s_dq[el][fp3][c];
-                    T cy = (s_S[el][fp0][1] * gL_i) * s_dq[el][fp0][c] + (s_S[el][fp1][1] * gR_i) * s_dq[el][fp1][c]
-                         + (s_S[el][fp2][1] * gL_j) * s_dq[el][fp2][c] + (s_S[el][fp3][1] * gR_j) * s_dq[el][fp3][c];
+                    T cx = (s_S[SI(el, 0, fp0)] * gL_i) * s_dq[DI(el, c, fp0)] + (s_S[SI(el, 0, fp1)] * gR_i) * s_dq[DI(el, c, fp1)]
+                         + (s_S[SI(el, 0, fp2)] * gL_j) * s_dq[DI(el, c, fp2)] + (s_S[SI(el, 0, fp3)] * gR_j) * s_dq[DI(el, c, fp3)];
+                    T cy = (s_S[SI(el, 1, fp0)] * gL_i) * s_dq[DI(el, c, fp0)] + (s_S[SI(el, 1, fp1)] * gR_i) * s_dq[DI(el, c, fp1)]
+                         + (s_S[SI(el, 1, fp2)] * gL_j) * s_dq[DI(el, c, fp2)] + (s_S[SI(el, 1, fp3)] * gR_j) * s_dq[DI(el, c, fp3)];
                     gr[c][0] = gr[c][0] + ij * cx;
                     gr[c][1] = gr[c][1] + ij * cy;
                 }
@@ -332,9 +360,9 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
             fr_point_flux<T, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                s_w[vv][lt] = fl[vv];
-                s_w[4 + vv][lt] = gl[vv];
-                if (MOV) s_w[8 + vv][lt] = qc[vv];
+                s_n[WI(vv, lt)] = fl[vv];
+                s_n[WI(4 + vv, lt)] = gl[vv];
+                if (MOV) s_n[WI(8 + vv, lt)] = qc[vv];
             }
         }
         __syncthreads();
@@ -343,18 +371,18 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         if (act && lt < NF) {
             const int f = lt / n, k = lt % n;
             const double* lam = s_lam[f & 1];
-            const double Sx = s_S[el][lt][0], Sy = s_S[el][lt][1], Svg = s_S[el][lt][2];
+            const double Sx = s_S[SI(el, 0, lt)], Sy = s_S[SI(el, 1, lt)], Svg = s_S[SI(el, 2, lt)];
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
                 T acc = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
                     const int sp = line_pt(n, f, k, b);
-                    T w = Sx * s_w[vv][sp] + Sy * s_w[4 + vv][sp];
-                    if (MOV) w = w - Svg * s_w[8 + vv][sp];
+                    T w = Sx * s_n[WI(vv, sp)] + Sy * s_n[WI(4 + vv, sp)];
+                    if (MOV) w = w - Svg * s_n[WI(8 + vv, sp)];
                     acc = acc + lam[b] * w;
                 }
-                s_F[el][lt][vv] = s_F[el][lt][vv] - acc;
+                s_F[FI(el, vv, lt)] = s_F[FI(el, vv, lt)] - acc;
             }
         }
         __syncthreads();
@@ -384,19 +412,19 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
                     const double Dx = s_D[i * n + b], De = s_D[j * n + b];
-                    dfx = dfx + Dx * s_w[vv][b + n * j];
-                    dgx = dgx + Dx * s_w[4 + vv][b + n * j];
-                    dfe = dfe + De * s_w[vv][i + n * b];
-                    dge = dge + De * s_w[4 + vv][i + n * b];
+                    dfx = dfx + Dx * s_n[WI(vv, b + n * j)];
+                    dgx = dgx + Dx * s_n[WI(4 + vv, b + n * j)];
+                    dfe = dfe + De * s_n[WI(vv, i + n * b)];
+                    dge = dge + De * s_n[WI(4 + vv, i + n * b)];
                     if (MOV) {
-                        dqx = dqx + Dx * s_w[8 + vv][b + n * j];
-                        dqe = dqe + De * s_w[8 + vv][i + n * b];
+                        dqx = dqx + Dx * s_n[WI(8 + vv, b + n * j)];
+                        dqe = dqe + De * s_n[WI(8 + vv, i + n * b)];
                     }
                 }
                 T vol = geo[G_XIX] * dfx + geo[G_ETX] * dfe + geo[G_XIY] * dgx + geo[G_ETY] * dge;
                 if (MOV) vol = vol - axi * dqx - aet * dqe;
-                T cor = s_gam[0][i] * s_F[el][0 * n + j][vv] + s_gam[1][i] * s_F[el][1 * n + j][vv]
-                      + s_gam[0][j] * s_F[el][2 * n + i][vv] + s_gam[1][j] * s_F[el][3 * n + i][vv];
+                T cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
+                      + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
                 const T R = -(vol + geo[G_IJ] * cor);
                 if constexpr (MODE == MODE_R) {
                     out[vv * EN + id] = val(R);

@@ -136,6 +136,75 @@ __global__ void __launch_bounds__(256) k_block_invert(GroupArgs ga, int nb, cons
     }
 }
 
+// Gauss-Jordan inversion with partial pivoting, one wave per element, the block held in
+// registers: lane r owns row r (NB <= 64).  Pivoting is implicit: the row chosen for
+// column k stays in its lane, which records k.  Step k broadcasts the pivot row with
+// readlane and eliminates column k from every other row (the in-place inverse trick:
+// column k is replaced by the corresponding column of the accumulated inverse).  With
+// piv[k] the lane chosen at step k and B the final array, the inverse is
+// A^-1[k'][piv[k]] = B[piv[k']][k] where k' is the step of the lane: lane L writes its
+// values a[k] to column piv[k], row step(L).  Same arithmetic per entry as the LDS
+// kernel; ties between equal pivot magnitudes go to the lowest lane.
+__device__ __forceinline__ double rdlane(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int NB, class Tout>
+__global__ void __launch_bounds__(256) k_block_invert_wave(GroupArgs ga, const double* __restrict__ blk,
+                                                           Tout* __restrict__ inv, int* __restrict__ gi,
+                                                           const int* __restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);   // element tile of this wave
+    if (t >= ga.ntiles) return;                                           // uniform per wave
+    const int lo = tile_member(ga, t);
+    const int cid = ga.ids[lo];
+    if (flags && flags[cid * GI_STRIDE + GI_NDONE]) return;
+    const CaseDev& cd = ga.cases[cid];
+    const int e = t - ga.pfx[lo];
+    const double* src = blk + cd.boff + (size_t)e * NB * NB;
+    const bool row = lane < NB;
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] = row ? src[(size_t)c * NB + lane] : 0.0;
+    bool used = !row;
+    int mystep = 0;
+    __shared__ int s_piv[4][NB];   // pivot lane of each step, per wave of the workgroup
+    int* piv = s_piv[threadIdx.x >> 6];
+#pragma clang loop unroll(full)
+    for (int k = 0; k < NB; ++k) {
+        // pivot: largest |a[k]| over the rows not used yet, lowest lane on ties
+        double m = used ? -1.0 : fabs(a[k]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        const unsigned long long cand = __ballot(!used && fabs(a[k]) == m);
+        const int p = __builtin_amdgcn_readfirstlane(cand ? (int)__ffsll((long long)cand) - 1 : 0);
+        const double pv = rdlane(a[k], p);
+        if (!(pv != 0.0)) {
+            if (lane == 0) gi[cid * GI_STRIDE + GI_STATUS] = 3;   // plain vector store
+            return;                                                // uniform per wave
+        }
+        if (lane == 0) piv[k] = p;
+        const bool isp = lane == p;
+        if (isp) { used = true; mystep = k; }
+        const double ip = 1.0 / pv;
+        const double f = a[k];
+#pragma clang loop unroll(full)
+        for (int c = 0; c < NB; ++c) {
+            const double pc = ((c == k) ? 1.0 : rdlane(a[c], p)) * ip;   // normalised pivot row
+            const double ac = (c == k) ? 0.0 : a[c];
+            a[c] = isp ? pc : ac - f * pc;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();   // the wave's own pivot list (LDS is in order within a wave)
+    if (!row) return;
+    Tout* dst = inv + cd.boff + (size_t)e * NB * NB;
+#pragma clang loop unroll(full)
+    for (int k = 0; k < NB; ++k) dst[(size_t)piv[k] * NB + mystep] = to_store<Tout>(a[k]);   // column-major
+}
+
 // z_e = Ainv_e r_e for the elements of one group; state layout [4][E][Np] per case,
 // block row/col index v*Np + s; one thread per block row, tile width 256 / nb
 template <class Tin>
@@ -385,10 +454,25 @@ fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, 
     return FR_OK;
 }
 
+template <int NB, class Tout>
+static fr_status invert_wave(Solver& sv, const Group& gr, const int* flags, hipStream_t s) {
+    GroupArgs ga = group_args(sv, gr, 1);
+    if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
+    if (ga.ntiles == 0) return FR_OK;
+    hipLaunchKernelGGL((k_block_invert_wave<NB, Tout>), dim3((ga.ntiles + 3) / 4), dim3(256), 0, s, ga, sv.d_blk,
+                       (Tout*)sv.d_inv, sv.d_gi, flags);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
 template <class Tout>
 static fr_status invert_as(Solver& sv, const int* flags, hipStream_t s) {
     for (const Group& gr : sv.groups) {
         const int nb = 4 * (gr.p + 1) * (gr.p + 1);
+        // blocks up to 64 rows: one wave per element, block in registers
+        if (gr.p == 1) { FR_TRY((invert_wave<16, Tout>(sv, gr, flags, s))); continue; }
+        if (gr.p == 2) { FR_TRY((invert_wave<36, Tout>(sv, gr, flags, s))); continue; }
+        if (gr.p == 3) { FR_TRY((invert_wave<64, Tout>(sv, gr, flags, s))); continue; }
         const size_t lds = ((size_t)nb * (nb + 1) + nb) * sizeof(double) + nb * sizeof(int);
         GroupArgs ga = group_args(sv, gr, 1);
         if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
