@@ -265,7 +265,7 @@ fr_status launch_bdf_rhs(const Solver& sv, const double* q, const double* Qn, co
 fr_status launch_cons(const Solver& sv, const double* q, double* Qc, const int* flags, hipStream_t s);
 // q^c in place for the cases that have a q^{n-1}
 fr_status launch_cons_nm1(const Solver& sv, double* buf, hipStream_t s);
-int block_apply_width(int p);
+std::vector<int> block_apply_widths(int p);
 
 // device GMRES (fr_gmres.hip)
 size_t gmres_state_doubles(int m);

@@ -206,32 +206,79 @@ __global__ void __launch_bounds__(256) k_block_invert_wave(GroupArgs ga, const d
 }
 
 // z_e = Ainv_e r_e for the elements of one group; state layout [4][E][Np] per case,
-// block row/col index v*Np + s; one thread per block row, tile width 256 / nb
-template <class Tin>
-__global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, int Np, const Tin* __restrict__ inv,
+// block row/col index v*Np + s.  Each thread owns RPT consecutive rows and reads them
+// from every column of the column-major inverse with one 8-byte load (1 double, 2
+// floats or 4 bfloat16), so every precision streams its blocks with full-width loads;
+// FP64 accumulation over the columns in ascending order.
+template <class Tin> struct Pack8;
+template <> struct Pack8<double> {
+    static constexpr int R = 1;
+    __device__ static void ld(const double* p, double* x) { x[0] = *p; }
+};
+template <> struct Pack8<float> {
+    static constexpr int R = 2;
+    __device__ static void ld(const float* p, double* x) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        x[0] = v.x; x[1] = v.y;
+    }
+};
+template <> struct Pack8<uint16_t> {
+    static constexpr int R = 4;
+    __device__ static void ld(const uint16_t* p, double* x) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        x[0] = (double)__uint_as_float(v.x << 16);
+        x[1] = (double)__uint_as_float(v.x & 0xffff0000u);
+        x[2] = (double)__uint_as_float(v.y << 16);
+        x[3] = (double)__uint_as_float(v.y & 0xffff0000u);
+    }
+};
+
+template <class Tin, int NB>
+struct ApplyShape {
+    static constexpr int RPT = Pack8<Tin>::R, TPE = NB / RPT, EPB = 256 / TPE, threads = EPB * TPE;
+    static_assert(NB % RPT == 0, "block size must be a multiple of the rows per thread");
+};
+
+template <class Tin, int NB>
+__global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __restrict__ inv,
                                                      const double* __restrict__ r, double* __restrict__ z,
                                                      const int* __restrict__ flags, int flag) {
-    extern __shared__ double rs[];
-    const int nb = 4 * Np;
-    const int epb = blockDim.x / nb;
+    using SH = ApplyShape<Tin, NB>;
+    constexpr int Np = NB / 4, RPT = SH::RPT, TPE = SH::TPE, EPB = SH::EPB;
+    __shared__ double rs[EPB][NB + 1];
     const int t = blockIdx.x;
     if (t >= ga.ntiles) return;
     const int lo = tile_member(ga, t);
     const int cid = ga.ids[lo];
     if (flags && flags[cid * GI_STRIDE + flag]) return;
     const CaseDev& cd = ga.cases[cid];
-    const int el = threadIdx.x / nb, row = threadIdx.x % nb;
-    const int e = (t - ga.pfx[lo]) * epb + el;
-    const bool act = (el < epb) && (e < cd.E);
+    const int el = threadIdx.x / TPE, r0 = (threadIdx.x % TPE) * RPT;
+    const int e = (t - ga.pfx[lo]) * EPB + el;
+    const bool act = (el < EPB) && (e < cd.E);
     const size_t EN = (size_t)cd.E * Np;
-    const size_t gid = cd.off + (row / Np) * EN + (size_t)e * Np + (row % Np);
-    if (act) rs[el * nb + row] = r[gid];
+    size_t gid[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int row = r0 + k;
+        gid[k] = cd.off + (row / Np) * EN + (size_t)e * Np + (row % Np);
+        if (act) rs[el][row] = r[gid[k]];
+    }
     __syncthreads();
     if (!act) return;
-    const Tin* A = inv + cd.boff + (size_t)e * nb * nb;
-    double acc = 0.0;
-    for (int c = 0; c < nb; ++c) acc += from_store(A[(size_t)c * nb + row]) * rs[el * nb + c];
-    z[gid] = acc;
+    const Tin* A = inv + cd.boff + (size_t)e * NB * NB + r0;
+    double acc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) acc[k] = 0.0;
+#pragma unroll 4
+    for (int c = 0; c < NB; ++c) {
+        double x[RPT];
+        Pack8<Tin>::ld(A + (size_t)c * NB, x);
+        const double rc = rs[el][c];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) acc[k] += x[k] * rc;
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) z[gid[k]] = acc[k];
 }
 
 // ------------------------------------------------------------------ segmented Krylov reductions
@@ -497,24 +544,46 @@ fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_
     return FR_OK;
 }
 
-int block_apply_width(int p) { return 256 / (4 * (p + 1) * (p + 1)); }
+// tile widths (elements per workgroup) of the block apply, per stored precision
+std::vector<int> block_apply_widths(int p) {
+    const int nb = 4 * (p + 1) * (p + 1);
+    return {256 / nb, 512 / nb, 1024 / nb};
+}
+
+template <class Tin, int NB>
+static fr_status apply_as(const Solver& sv, const Group& gr, const double* r, double* z, const int* flags, int flag,
+                          hipStream_t s) {
+    using SH = ApplyShape<Tin, NB>;
+    GroupArgs ga = group_args(sv, gr, SH::EPB);
+    if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
+    if (ga.ntiles == 0) return FR_OK;
+    hipLaunchKernelGGL((k_block_apply<Tin, NB>), dim3(ga.ntiles), dim3(SH::threads), 0, s, ga, (const Tin*)sv.d_inv, r,
+                       z, flags, flag);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+template <class Tin>
+static fr_status apply_p(const Solver& sv, const Group& gr, const double* r, double* z, const int* flags, int flag,
+                         hipStream_t s) {
+    switch (gr.p) {
+        case 1: return apply_as<Tin, 16>(sv, gr, r, z, flags, flag, s);
+        case 2: return apply_as<Tin, 36>(sv, gr, r, z, flags, flag, s);
+        case 3: return apply_as<Tin, 64>(sv, gr, r, z, flags, flag, s);
+        case 4: return apply_as<Tin, 100>(sv, gr, r, z, flags, flag, s);
+    }
+    fr_set_error("order outside 1..4");
+    return FR_EUNSUPPORTED;
+}
 
 fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s) {
     for (const Group& gr : sv.groups) {
-        const int Np = (gr.p + 1) * (gr.p + 1), nb = 4 * Np;
-        const int epb = block_apply_width(gr.p);
-        const int threads = epb * nb;
-        GroupArgs ga = group_args(sv, gr, epb);
-        if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
-        if (ga.ntiles == 0) continue;
-        const size_t lds = (size_t)threads * sizeof(double);
         switch (sv.inv_prec) {
-            case FR_FP64: hipLaunchKernelGGL(k_block_apply<double>, dim3(ga.ntiles), dim3(threads), lds, s, ga, Np, (const double*)sv.d_inv, r, z, flags, flag); break;
-            case FR_FP32: hipLaunchKernelGGL(k_block_apply<float>, dim3(ga.ntiles), dim3(threads), lds, s, ga, Np, (const float*)sv.d_inv, r, z, flags, flag); break;
-            case FR_BF16: hipLaunchKernelGGL(k_block_apply<uint16_t>, dim3(ga.ntiles), dim3(threads), lds, s, ga, Np, (const uint16_t*)sv.d_inv, r, z, flags, flag); break;
+            case FR_FP64: FR_TRY(apply_p<double>(sv, gr, r, z, flags, flag, s)); break;
+            case FR_FP32: FR_TRY(apply_p<float>(sv, gr, r, z, flags, flag, s)); break;
+            case FR_BF16: FR_TRY(apply_p<uint16_t>(sv, gr, r, z, flags, flag, s)); break;
             default: fr_set_error("preconditioner not factored"); return FR_EINVAL;
         }
-        FR_HIP(hipGetLastError());
     }
     return FR_OK;
 }

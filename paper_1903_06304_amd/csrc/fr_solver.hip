@@ -89,7 +89,7 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
         FR_TRY(upload(&g.d_ids, g.ids));
         std::vector<int> widths = fused_tile_widths(g.p);
         widths.push_back(1);
-        widths.push_back(block_apply_width(g.p));
+        for (int w : block_apply_widths(g.p)) widths.push_back(w);
         for (int w : widths) {
             if (g.tile_pfx(w)) continue;
             std::vector<int> pfx(g.ids.size() + 1, 0);
