@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblmfr.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["fr_fused_p3.hip", "fr_fused_p4.hip", "fr_fused_p2.hip", "fr_fused_p1.hip", "fr_api.hip",
+SOURCES = ["fr_invert.hip", "fr_fused_p3.hip", "fr_fused_p4.hip", "fr_fused_p2.hip", "fr_fused_p1.hip", "fr_api.hip",
            "fr_kernels.hip", "fr_vjp.hip", "fr_linalg.hip", "fr_gmres.hip", "fr_solver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -24,8 +24,18 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _deps_mtime() -> float:
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    hdrs.append(os.path.join(ROOT, "include", "lmfr.h"))
+    return max(os.path.getmtime(h) for h in hdrs)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(_deps_mtime(), os.path.getmtime(os.path.join(CSRC, src)))
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -33,11 +43,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their object file's
+    inputs) and link liblmfr.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda x: _compile(x, incremental), srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,5 +62,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

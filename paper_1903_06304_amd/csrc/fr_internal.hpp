@@ -252,6 +252,9 @@ fr_status solver_ensure_step(Solver& sv, int m);
 // preconditioner (fr_linalg.hip)
 fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s);
 fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s);
+// blocks of 100 rows (p = 4), two waves per element (fr_invert.hip)
+fr_status launch_block_invert_p4(Solver& sv, const Group& gr, const GroupArgs& ga, int prec, const int* flags,
+                                 hipStream_t s);
 fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s);
 // segmented reductions over the concatenated vectors: for every case c (not skipped),
 //   w_out = w_in - sum_{i<nv_upd} coef_c[i] V_i            (coef_c = coef + c * cstride)

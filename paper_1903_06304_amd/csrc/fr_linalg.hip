@@ -512,6 +512,11 @@ static fr_status invert_wave(Solver& sv, const Group& gr, const int* flags, hipS
     return FR_OK;
 }
 
+template <class Tout> constexpr int prec_of();
+template <> constexpr int prec_of<double>() { return FR_FP64; }
+template <> constexpr int prec_of<float>() { return FR_FP32; }
+template <> constexpr int prec_of<uint16_t>() { return FR_BF16; }
+
 template <class Tout>
 static fr_status invert_as(Solver& sv, const int* flags, hipStream_t s) {
     for (const Group& gr : sv.groups) {
@@ -520,6 +525,14 @@ static fr_status invert_as(Solver& sv, const int* flags, hipStream_t s) {
         if (gr.p == 1) { FR_TRY((invert_wave<16, Tout>(sv, gr, flags, s))); continue; }
         if (gr.p == 2) { FR_TRY((invert_wave<36, Tout>(sv, gr, flags, s))); continue; }
         if (gr.p == 3) { FR_TRY((invert_wave<64, Tout>(sv, gr, flags, s))); continue; }
+        if (gr.p == 4) {
+            // 100 rows: two waves per element (fr_invert.hip)
+            GroupArgs ga = group_args(sv, gr, 1);
+            if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
+            if (ga.ntiles == 0) continue;
+            FR_TRY(launch_block_invert_p4(sv, gr, ga, prec_of<Tout>(), flags, s));
+            continue;
+        }
         const size_t lds = ((size_t)nb * (nb + 1) + nb) * sizeof(double) + nb * sizeof(int);
         GroupArgs ga = group_args(sv, gr, 1);
         if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
