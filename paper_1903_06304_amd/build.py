@@ -24,16 +24,25 @@ FLAGS = [
 ]
 
 
-def _deps_mtime() -> float:
-    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
-    hdrs.append(os.path.join(ROOT, "include", "lmfr.h"))
-    return max(os.path.getmtime(h) for h in hdrs)
+def _deps(path: str, seen=None) -> set:
+    """The file and every quoted include it pulls in, recursively."""
+    seen = set() if seen is None else seen
+    path = os.path.normpath(path)
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("#include \""):
+            inc = line.split('"')[1]
+            _deps(os.path.join(os.path.dirname(path), inc), seen)
+    return seen
 
 
 def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     if incremental and os.path.exists(obj):
-        newest = max(_deps_mtime(), os.path.getmtime(os.path.join(CSRC, src)))
+        newest = max(os.path.getmtime(d) for d in _deps(os.path.join(CSRC, src)))
         if os.path.getmtime(obj) > newest:
             return obj
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]

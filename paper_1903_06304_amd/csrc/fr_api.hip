@@ -246,9 +246,10 @@ static fr_status set_tile_option(Solver& sv, const char* name, int64_t value) {
     if (!strcmp(name, "tile_lanes") && value != 0 && value != 64 && value != 128 && value != 256)
         return bad("tile_lanes must be 0, 64, 128 or 256");
     for (Group& g : sv.groups)
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < NMODES; ++m) {
             Tune& t = g.tune[m];
-            if (!strcmp(name, "tile_lanes")) t.lanes = (m != MODE_R && value == 256) ? 128 : (int)value;
+            const bool dual = m == MODE_JVP || m == MODE_AOP || m == MODE_BLK;
+            if (!strcmp(name, "tile_lanes")) t.lanes = (dual && value == 256) ? 128 : (int)value;
             else if (!strcmp(name, "tile_grid")) t.grid = (int)value;
             else t.xcd = value != 0;
         }
@@ -260,6 +261,15 @@ extern "C" fr_status fr_set_option(fr_ctx c, const char* name, int64_t value) {
     if (!c || !name) return bad("fr_set_option: null argument");
     Solver& sv = *c->self;
     if (!strcmp(name, "keep_blocks")) { sv.keep_blocks = value != 0; return FR_OK; }
+    if (!strcmp(name, "operator_packs")) {
+        if (value) {
+            FR_TRY(dalloc(&sv.d_fpack, sv.fpack_len));
+            FR_TRY(dalloc(&sv.d_spack, sv.spack_len));
+            FR_TRY(dalloc(&sv.d_rscratch, sv.Ntot));
+        }
+        sv.op_packs = value != 0;
+        return FR_OK;
+    }
     return solver_option(sv, name, value);
 }
 
@@ -299,9 +309,16 @@ extern "C" fr_status fr_bdf_operator(fr_ctx c, const double* q, const double* v,
                                      double* Av, void* stream) {
     FR_TRY(ready(c));
     if (!q || !v || !Av) return bad("fr_bdf_operator: null argument");
+    Solver& sv = *c->self;
     KArgs a = plain_args(q, v, Av, nullptr);
     a.c_time = c_time; a.inv_dtau = inv_dtau;
-    return solver_fused(*c->self, MODE_AOP, a, (hipStream_t)stream);
+    if (!sv.op_packs) return solver_fused(sv, MODE_AOP, a, (hipStream_t)stream);
+    // linearisation packs of q (R into the scratch vector), then the tangent-only operator
+    KArgs p = plain_args(q, nullptr, sv.d_rscratch, nullptr);
+    p.fpack = sv.d_fpack; p.spack = sv.d_spack;
+    FR_TRY(solver_fused(sv, MODE_PREP, p, (hipStream_t)stream));
+    a.fpack = sv.d_fpack; a.spack = sv.d_spack;
+    return solver_fused(sv, MODE_LIN, a, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_vjp(fr_ctx c, const double* q, const double* w, double* JTw, void* stream) {

@@ -45,6 +45,7 @@ __device__ __forceinline__ int line_pt(int n, int f, int k, int a) {
 
 template <int MODE, int K> struct ModeT { using T = Dual<K>; };
 template <int K> struct ModeT<MODE_R, K> { using T = double; };
+template <int K> struct ModeT<MODE_PREP, K> { using T = double; };
 
 // own state with the tangent the mode asks for: JVP/AOP carry v; block mode seeds the
 // unit column seed0 (+k)
@@ -110,13 +111,17 @@ template <class T> __device__ __forceinline__ T* rfl(T* p) {
     return reinterpret_cast<T*>(rfl((unsigned long long)reinterpret_cast<uintptr_t>(p)));
 }
 
-// the descriptor of a case, in scalar registers
+// the descriptor of a case, in scalar registers (every field is copied: a new field must
+// be added here, which the size check below enforces)
+static_assert(sizeof(CaseDev) == 8 + 4 * 8 + sizeof(Geo) + sizeof(PhysConst), "load_case copies every field");
 __device__ __forceinline__ CaseDev load_case(const CaseDev* p) {
     CaseDev c;
     c.E = rfl(p->E);
     c.Np = rfl(p->Np);
     c.off = rfl(p->off);
     c.boff = rfl(p->boff);
+    c.fpoff = rfl(p->fpoff);
+    c.spoff = rfl(p->spoff);
     c.g.sp = rfl(p->g.sp);
     c.g.fp = rfl(p->g.fp);
     c.g.nbr = rfl(p->g.nbr);
@@ -283,6 +288,12 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                     qm[vv] = am;
                     qp[vv] = ap;
                 }
+                if constexpr (MODE == MODE_PREP) {
+                    double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
+                    const size_t fs = (size_t)E * NF;
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) { fpk[vv * fs] = qm[vv]; fpk[(4 + vv) * fs] = qp[vv]; }
+                }
                 fr_common_inviscid<T>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
             }
             if (VISC) {
@@ -314,6 +325,12 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                         gp[2 * c] = gp[2 * c] + lamn[b] * (xix * dxi + etx * deta);
                         gp[2 * c + 1] = gp[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
                     }
+                }
+                if constexpr (MODE == MODE_PREP) {
+                    double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
+                    const size_t fs = (size_t)E * NF;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) { fpk[(8 + c) * fs] = gm[c]; fpk[(14 + c) * fs] = gp[c]; }
                 }
                 // q^com velocity = average of the two traces = q^- + dq/2
                 const T qcu = am_avg<T>(&s_q[QI(el, 1, 0)], lam, f, k, dq[1], n);
@@ -354,6 +371,19 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                          + (s_S[SI(el, 1, fp2)] * gL_j) * s_dq[DI(el, c, fp2)] + (s_S[SI(el, 1, fp3)] * gR_j) * s_dq[DI(el, c, fp3)];
                     gr[c][0] = gr[c][0] + ij * cx;
                     gr[c][1] = gr[c][1] + ij * cy;
+                }
+            }
+            if constexpr (MODE == MODE_PREP) {
+                double* spk = a.spack + cd.spoff + (size_t)e * Np + lt;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) spk[(size_t)vv * EN] = qs[vv];
+                if (VISC) {
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        spk[(size_t)(4 + d) * EN] = gu[d];
+                        spk[(size_t)(6 + d) * EN] = gv[d];
+                        spk[(size_t)(8 + d) * EN] = gT[d];
+                    }
                 }
             }
             T fl[4], gl[4], qc[4];
@@ -426,7 +456,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                 T cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
                       + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
                 const T R = -(vol + geo[G_IJ] * cor);
-                if constexpr (MODE == MODE_R) {
+                if constexpr (MODE == MODE_R || MODE == MODE_PREP) {
                     out[vv * EN + id] = val(R);
                 } else if constexpr (MODE == MODE_JVP) {
                     out[vv * EN + id] = R.d[0];
@@ -468,6 +498,273 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     }
 }
 
+// Newton operator Av = inv_dtau Gamma v + c_time M v - J v from the linearisation packs of
+// the state (MODE_LIN).  Every stage that is linear in the state (gradients, traces,
+// interpolation, divergence, lifting) acts on the tangent v alone, so LDS holds doubles;
+// the nonlinear point functions (common flux, point flux) run on dual numbers whose
+// values come from the packs.  The tangent arithmetic is the dual-number arithmetic of
+// the other modes term by term (same sums in the same order); the result matches MODE_AOP
+// to a few ulp, where the compiler contracts different products into fused multiply-adds.
+template <int P, bool VISC, bool MOV, int LANES>
+__global__ void __launch_bounds__((Shape<P, LANES>::threads))
+k_lin(GroupArgs ga, KArgs a, OpTab op) {
+    using D = Dual<1>;
+    constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
+    constexpr int EPB = Shape<P, LANES>::EPB;
+    using PD = LPad<P, 1>;
+    constexpr int FS = Np + PD::F, FACE = 4 * FS + PD::FACE, ESN = 4 * FACE + PD::E, ESQ = 4 * FS + PD::E;
+    constexpr int NG = VISC ? 6 : 1;
+    constexpr int ESG = NG * FS + PD::E;
+    constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1, ESS = 3 * NF + 1;
+    __shared__ double s_q[EPB * ESQ];       // own tangent [el][var][point]
+    __shared__ double s_n[EPB * ESN];       // neighbour tangents [el][face][var][point]; later f', g' (, q^c')
+    __shared__ double s_g[EPB * ESG];       // own uncorrected gradient tangent
+    __shared__ double s_F[EPB * ESF];       // F^num', then F^num' - F^loc'
+    __shared__ double s_dq[EPB * ESD];      // (q^com - q^-)' of (u, v, T)
+    __shared__ double s_S[EPB * ESS];       // element-oriented S, S . v_g
+    auto QI = [](int el, int v, int sp) { return el * ESQ + v * FS + sp; };
+    auto NI = [](int el, int fld, int sp) { return el * ESN + (fld >> 2) * FACE + (fld & 3) * FS + sp; };
+    auto GI = [](int el, int c, int sp) { return el * ESG + c * FS + sp; };
+    auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
+    auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
+    auto SI = [](int el, int c, int fp) { return el * ESS + c * NF + fp; };
+    __shared__ double s_D[n * n];
+    __shared__ double s_lam[2][n], s_gam[2][n];
+    auto mk = [](double v, double d) { D r; r.v = v; r.d[0] = d; return r; };
+
+    const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
+    if (threadIdx.x < n) {
+        s_lam[0][threadIdx.x] = op.lamL[threadIdx.x]; s_lam[1][threadIdx.x] = op.lamR[threadIdx.x];
+        s_gam[0][threadIdx.x] = op.gamL[threadIdx.x]; s_gam[1][threadIdx.x] = op.gamR[threadIdx.x];
+    }
+    const int i = lt % n, j = lt / n;
+    int tile, tend, tstride;
+    tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
+    for (; tile < tend; tile += tstride) {
+        const int lo = find_member(ga, tile);
+        const int cid = rfl(ga.ids[lo]);
+        if (a.flags && rfl(a.flags[cid * GI_STRIDE + a.flag])) continue;
+        const CaseDev cd = load_case(ga.cases + cid);
+        const PhysConst& pc = cd.pc;
+        const Geo g = cd.g;
+        const int E = cd.E;
+        const int e = (tile - rfl(ga.pfx[lo])) * EPB + el;
+        const bool act = e < E;
+        const unsigned EN = (unsigned)E * Np;
+        const double* v = a.v + cd.off;
+        const double* fpk = a.fpack + cd.fpoff;
+        const double* spk = a.spack + cd.spoff;
+        __syncthreads();
+        // ---- stage 1: own and neighbour tangents
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = v[vv * EN + id];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int nb = g.nbr[e * 4 + f] >> 3;
+                const unsigned nid = (unsigned)nb * Np + lt;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) s_n[NI(el, f * 4 + vv, lt)] = v[vv * EN + nid];
+            }
+        }
+        __syncthreads();
+        // ---- stage 2: uncorrected gradient tangent
+        if (VISC && act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            const double xix = g.sp[G_XIX * EN + id], xiy = g.sp[G_XIY * EN + id];
+            const double etx = g.sp[G_ETX * EN + id], ety = g.sp[G_ETY * EN + id];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double dxi = 0.0, deta = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
+                    deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
+                }
+                s_g[GI(el, 2 * c, lt)] = xix * dxi + etx * deta;
+                s_g[GI(el, 2 * c + 1, lt)] = xiy * dxi + ety * deta;
+            }
+        }
+        __syncthreads();
+        // ---- stage 3: trace tangents, common flux on dual numbers (values from the face pack)
+        if (act && lt < NF) {
+            const int f = lt / n, k = lt % n;
+            const int pk = g.nbr[e * 4 + f];
+            const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
+            const double* lam = s_lam[f & 1];
+            const double* lamn = s_lam[nf & 1];
+            const unsigned FE = (unsigned)E * NF;
+            const unsigned sid = (unsigned)e * NF + lt;
+            const double nx = g.fp[F_NX * FE + sid], ny = g.fp[F_NY * FE + sid];
+            const double sc = g.fp[F_SC * FE + sid];
+            const double ugf = MOV ? g.fp[F_UG * FE + sid] : 0.0;
+            const double vgf = MOV ? g.fp[F_VG * FE + sid] : 0.0;
+            D fn[4], dq[4], qm[4], qp[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                double am = 0.0, ap = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                    ap = ap + lamn[b] * s_n[NI(el, f * 4 + vv, line_pt(n, nf, k2, b))];
+                }
+                qm[vv] = mk(fpk[(size_t)vv * FE + sid], am);
+                qp[vv] = mk(fpk[(size_t)(4 + vv) * FE + sid], ap);
+            }
+            fr_common_inviscid<D>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
+            if (VISC) {
+                D gm[6], gp[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    double am = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                    gm[c] = mk(fpk[(size_t)(8 + c) * FE + sid], am);
+                }
+                double gpt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const int sp = line_pt(n, nf, k2, b);
+                    const int is = sp % n, js = sp / n;
+                    const unsigned gid = (unsigned)nb * Np + sp;
+                    const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
+                    const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double dxi = 0.0, deta = 0.0;
+#pragma unroll
+                        for (int m = 0; m < n; ++m) {
+                            dxi = dxi + s_D[is * n + m] * s_n[NI(el, f * 4 + c + 1, m + n * js)];
+                            deta = deta + s_D[js * n + m] * s_n[NI(el, f * 4 + c + 1, is + n * m)];
+                        }
+                        gpt[2 * c] = gpt[2 * c] + lamn[b] * (xix * dxi + etx * deta);
+                        gpt[2 * c + 1] = gpt[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) gp[c] = mk(fpk[(size_t)(14 + c) * FE + sid], gpt[c]);
+                // q^com velocity = q^- + dq/2 (the own trace as formed above)
+                const D qcu = qm[1] + 0.5 * dq[1];
+                const D qcv = qm[2] + 0.5 * dq[2];
+                D dqh[3];
+                fr_common_viscous<D>(pc, dq, qcu, qcv, gm, gp, nx, ny, g.fp[F_CC * FE + sid], fn, dqh);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c].d[0];
+            }
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) s_F[FI(el, vv, lt)] = (sc * fn[vv]).d[0];
+            s_S[SI(el, 0, lt)] = sc * nx;
+            s_S[SI(el, 1, lt)] = sc * ny;
+            s_S[SI(el, 2, lt)] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;
+        }
+        __syncthreads();
+        // ---- stage 4: corrected gradient tangent, point flux on dual numbers (values from the point pack)
+        auto WI = [&](int fld, int sp) { return NI(el, fld, sp); };
+        double qv[4];
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            const double ij = g.sp[G_IJ * EN + id];
+            D qs[4], gu[2], gv[2], gT[2];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                qv[vv] = spk[(size_t)vv * EN + id];
+                qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
+            }
+            if (VISC) {
+                double gt[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) gt[c] = s_g[GI(el, c, lt)];
+                const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
+                const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double cx = (s_S[SI(el, 0, fp0)] * gL_i) * s_dq[DI(el, c, fp0)] + (s_S[SI(el, 0, fp1)] * gR_i) * s_dq[DI(el, c, fp1)]
+                                    + (s_S[SI(el, 0, fp2)] * gL_j) * s_dq[DI(el, c, fp2)] + (s_S[SI(el, 0, fp3)] * gR_j) * s_dq[DI(el, c, fp3)];
+                    const double cy = (s_S[SI(el, 1, fp0)] * gL_i) * s_dq[DI(el, c, fp0)] + (s_S[SI(el, 1, fp1)] * gR_i) * s_dq[DI(el, c, fp1)]
+                                    + (s_S[SI(el, 1, fp2)] * gL_j) * s_dq[DI(el, c, fp2)] + (s_S[SI(el, 1, fp3)] * gR_j) * s_dq[DI(el, c, fp3)];
+                    gt[2 * c] = gt[2 * c] + ij * cx;
+                    gt[2 * c + 1] = gt[2 * c + 1] + ij * cy;
+                }
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    gu[d] = mk(spk[(size_t)(4 + d) * EN + id], gt[d]);
+                    gv[d] = mk(spk[(size_t)(6 + d) * EN + id], gt[2 + d]);
+                    gT[d] = mk(spk[(size_t)(8 + d) * EN + id], gt[4 + d]);
+                }
+            }
+            D fl[4], gl[4], qc[4];
+            fr_point_flux<D, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                s_n[WI(vv, lt)] = fl[vv].d[0];
+                s_n[WI(4 + vv, lt)] = gl[vv].d[0];
+                if (MOV) s_n[WI(8 + vv, lt)] = qc[vv].d[0];
+            }
+        }
+        __syncthreads();
+        // ---- stage 5: F^num' - F^loc'
+        if (act && lt < NF) {
+            const int f = lt / n, k = lt % n;
+            const double* lam = s_lam[f & 1];
+            const double Sx = s_S[SI(el, 0, lt)], Sy = s_S[SI(el, 1, lt)], Svg = s_S[SI(el, 2, lt)];
+#pragma unroll 1
+            for (int vv = 0; vv < 4; ++vv) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const int sp = line_pt(n, f, k, b);
+                    double w = Sx * s_n[WI(vv, sp)] + Sy * s_n[WI(4 + vv, sp)];
+                    if (MOV) w = w - Svg * s_n[WI(8 + vv, sp)];
+                    acc = acc + lam[b] * w;
+                }
+                s_F[FI(el, vv, lt)] = s_F[FI(el, vv, lt)] - acc;
+            }
+        }
+        __syncthreads();
+        // ---- stage 6: divergence, moving-mesh terms, lift of the tangents; time terms
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            double geo[NGSP] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int c = 0; c < (MOV ? NGSP : G_UG); ++c) geo[c] = g.sp[c * EN + id];
+            const double axi = MOV ? geo[G_UG] * geo[G_XIX] + geo[G_VG] * geo[G_XIY] : 0.0;
+            const double aet = MOV ? geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY] : 0.0;
+            double ct = a.c_time, idt = a.inv_dtau;
+            if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
+            double tt[4], x[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
+            fr_time_apply<double, double>(pc, qv, geo[G_UG], geo[G_VG], idt, ct, x, tt);
+            double* out = a.out + cd.off;
+#pragma unroll 1
+            for (int vv = 0; vv < 4; ++vv) {
+                double dfx = 0.0, dfe = 0.0, dgx = 0.0, dge = 0.0, dqx = 0.0, dqe = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const double Dx = s_D[i * n + b], De = s_D[j * n + b];
+                    dfx = dfx + Dx * s_n[WI(vv, b + n * j)];
+                    dgx = dgx + Dx * s_n[WI(4 + vv, b + n * j)];
+                    dfe = dfe + De * s_n[WI(vv, i + n * b)];
+                    dge = dge + De * s_n[WI(4 + vv, i + n * b)];
+                    if (MOV) {
+                        dqx = dqx + Dx * s_n[WI(8 + vv, b + n * j)];
+                        dqe = dqe + De * s_n[WI(8 + vv, i + n * b)];
+                    }
+                }
+                double vol = geo[G_XIX] * dfx + geo[G_ETX] * dfe + geo[G_XIY] * dgx + geo[G_ETY] * dge;
+                if (MOV) vol = vol - axi * dqx - aet * dqe;
+                const double cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
+                                 + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
+                const double Rd = -(vol + geo[G_IJ] * cor);
+                const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                out[vv * EN + id] = ttv - Rd;
+            }
+        }
+    }
+}
+
 // grid of a launch: one workgroup per tile by default, else the tuned persistent size;
 // always a multiple of 8 (the XCD count) so every XCD walks an equal tile range
 inline unsigned grid_of(int ntiles, int grid) {
@@ -490,8 +787,15 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
     if (!ga.pfx) { fr_set_error("tile prefix missing for this workgroup shape"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
     const OpTab& op = sv.cs[gr.ids[0]]->op;
-    hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s,
-                       ga, a, op);
+    if constexpr (MODE == MODE_LIN) {
+        if (!a.fpack || !a.spack || !a.v) { fr_set_error("linearised operator without packs"); return FR_EINVAL; }
+        hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s, ga,
+                           a, op);
+    } else {
+        if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
+        hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads),
+                           0, s, ga, a, op);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { fr_set_error(std::string("k_fused launch: ") + hipGetErrorString(e)); return FR_EHIP; }
     return FR_OK;
@@ -500,13 +804,13 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
 // workgroup widths built per mode: plain doubles 64/128/256 lanes, dual numbers 64/128
 template <int P, bool VISC, bool MOV, int MODE>
 fr_status run_lanes(const Solver& sv, const Group& gr, const KArgs& a, const Tune& t, hipStream_t s) {
-    constexpr bool dual = MODE != MODE_R;
+    constexpr bool dual = MODE == MODE_JVP || MODE == MODE_AOP || MODE == MODE_BLK;
     const int lanes = t.lanes > 0 ? t.lanes : (dual ? 64 : 128);
     switch (lanes) {
         case 64: return run<P, VISC, MOV, MODE, 64>(sv, gr, a, t.grid, t.xcd, s);
         case 128: return run<P, VISC, MOV, MODE, 128>(sv, gr, a, t.grid, t.xcd, s);
         case 256:
-            if constexpr (!dual) return run<P, VISC, MOV, MODE, 256>(sv, gr, a, t.grid, t.xcd, s);
+            if constexpr (MODE == MODE_R) return run<P, VISC, MOV, MODE, 256>(sv, gr, a, t.grid, t.xcd, s);
             break;
     }
     fr_set_error("unsupported workgroup width");
@@ -520,6 +824,8 @@ fr_status run_mode(const Solver& sv, const Group& gr, int mode, const KArgs& a, 
         case MODE_JVP: return run_lanes<P, VISC, MOV, MODE_JVP>(sv, gr, a, t, s);
         case MODE_AOP: return run_lanes<P, VISC, MOV, MODE_AOP>(sv, gr, a, t, s);
         case MODE_BLK: return run_lanes<P, VISC, MOV, MODE_BLK>(sv, gr, a, t, s);
+        case MODE_PREP: return run_lanes<P, VISC, MOV, MODE_PREP>(sv, gr, a, t, s);
+        case MODE_LIN: return run_lanes<P, VISC, MOV, MODE_LIN>(sv, gr, a, t, s);
     }
     fr_set_error("unknown residual mode");
     return FR_EINVAL;

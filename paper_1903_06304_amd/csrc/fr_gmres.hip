@@ -243,10 +243,12 @@ Vec vec(const Solver& sv, int flag) { return Vec{sv.d_chunk_case, sv.nchunks, sv
 
 double* wv(const Solver& sv, int i) { return sv.d_w + (size_t)i * sv.Ntot; }
 
+// Newton operator at the iterate whose linearisation packs the Newton loop has written
 fr_status bdf_op(const Solver& sv, const double* q, const double* v, double* Av, int flag, hipStream_t s) {
     KArgs a{};
     a.q = q; a.v = v; a.out = Av; a.cstep = sv.d_step; a.flags = sv.d_gi; a.flag = flag;
-    return solver_fused(sv, MODE_AOP, a, s);
+    a.fpack = sv.d_fpack; a.spack = sv.d_spack;
+    return solver_fused(sv, MODE_LIN, a, s);
 }
 
 // the launches of one cycle (enqueued eagerly or under capture)
@@ -432,9 +434,11 @@ fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
     FR_TRY(launch_cons_nm1(sv, wv(sv, WQNM1), s));
     double* hs = sv.h_pin;
     for (int it = 0;; ++it) {
+        // R at the iterate, and the linearisation packs the GMRES operator reads
         KArgs a{};
         a.q = sv.d_q; a.out = wv(sv, WR); a.flags = sv.d_gi; a.flag = GI_NDONE;
-        FR_TRY(solver_fused(sv, MODE_R, a, s));
+        a.fpack = sv.d_fpack; a.spack = sv.d_spack;
+        FR_TRY(solver_fused(sv, MODE_PREP, a, s));
         FR_TRY(launch_bdf_rhs(sv, sv.d_q, wv(sv, WQN), wv(sv, WQNM1), wv(sv, WR), wv(sv, WB), sv.d_gi, s));
         FR_TRY(la_krylov(sv, wv(sv, WB), sv.Ntot, 0, nullptr, 0, 0, wv(sv, WB), nullptr, true, true, sv.d_gs + L.NRM,
                          sv.gs_stride, sv.d_gi, GI_NDONE, s));

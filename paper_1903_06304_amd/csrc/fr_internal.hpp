@@ -38,7 +38,17 @@ struct Geo {
     const int32_t* nbr;   // [E][4]: nb*8 + nb_face*2 + flip
 };
 
-enum FrMode { MODE_R = 0, MODE_JVP = 1, MODE_AOP = 2, MODE_BLK = 3 };
+// R; exact JVP; Newton operator; one seeded block column; R plus the linearisation packs;
+// Newton operator from the packs (tangent-only staging)
+enum FrMode { MODE_R = 0, MODE_JVP = 1, MODE_AOP = 2, MODE_BLK = 3, MODE_PREP = 4, MODE_LIN = 5, NMODES = 6 };
+
+// Linearisation packs of a state (written by MODE_PREP, read by MODE_LIN): the values the
+// Newton operator's nonlinear point functions need, so that its staged data are tangents.
+//   face pack [NPF][E][4n]: own and neighbour traces q^-, q^+ (4 + 4), uncorrected
+//                           gradient traces g^-, g^+ (6 + 6, viscous only)
+//   point pack [NPS][E][Np]: q (4) and the corrected gradient (6, viscous only)
+constexpr int npf(bool visc) { return visc ? 20 : 8; }
+constexpr int nps(bool visc) { return visc ? 10 : 4; }
 
 // Device view of one case (one mesh) of a solver.  A solver concatenates the state
 // vectors [4][E][Np] of its cases, each starting at a multiple of CHUNK doubles, and
@@ -47,6 +57,8 @@ struct CaseDev {
     int E, Np;
     unsigned long long off;    // first entry of the case's state vector
     unsigned long long boff;   // first entry of the case's element blocks
+    unsigned long long fpoff;  // first entry of the case's face pack
+    unsigned long long spoff;  // first entry of the case's point pack
     Geo g;
     PhysConst pc;
 };
@@ -90,6 +102,8 @@ struct KArgs {
     int seed0;            // first seeded column (block mode)
     const int* flags;     // per-case flags (gi layout) or NULL
     int flag;             // which flag skips a case
+    double* fpack;        // linearisation packs (MODE_PREP writes, MODE_LIN reads)
+    double* spack;
 };
 
 // tiles of one launch group (cases of one order / viscous / moving combination)
@@ -115,7 +129,7 @@ struct Group {
     int* d_ids = nullptr;
     std::vector<std::pair<int, int*>> pfx;   // tile width (elements) -> device prefix
     std::vector<long long> elems;            // elements of each member
-    Tune tune[4];                            // per mode
+    Tune tune[NMODES];                       // per mode
     const int* tile_pfx(int epb) const {
         for (auto& x : pfx) if (x.first == epb) return x.second;
         return nullptr;
@@ -177,6 +191,11 @@ struct Solver {
     double* d_part = nullptr;              // reduction partials [nchunks][MAXV]
     CaseStep* d_step = nullptr;            // [n]
     double* d_sum = nullptr;               // per-case summary [n][SUM_STRIDE]
+    double* d_fpack = nullptr;             // linearisation packs of the Newton iterate
+    double* d_spack = nullptr;
+    size_t fpack_len = 0, spack_len = 0;
+    bool op_packs = false;                 // fr_bdf_operator through the packs (two passes)
+    double* d_rscratch = nullptr;          // R of that path
     double* h_pin = nullptr;               // pinned host staging
     size_t h_pin_doubles = 0;
     hipStream_t ws = nullptr;

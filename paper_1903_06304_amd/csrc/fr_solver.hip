@@ -37,7 +37,7 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
     sv.off.resize(n);
     sv.len.resize(n);
     sv.boff.resize(n);
-    size_t o = 0, bo = 0;
+    size_t o = 0, bo = 0, fo = 0, so = 0;
     std::vector<CaseDev> cd(n);
     for (int c = 0; c < n; ++c) {
         const fr_ctx x = ctxs[c];
@@ -53,11 +53,17 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
         cd[c].Np = x->Np;
         cd[c].off = sv.off[c];
         cd[c].boff = sv.boff[c];
+        cd[c].fpoff = fo;
+        cd[c].spoff = so;
+        fo += (size_t)npf(x->prm.viscous != 0) * x->E * 4 * x->n;
+        so += (size_t)nps(x->prm.viscous != 0) * x->E * x->Np;
         cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr};
         cd[c].pc = x->pc;
     }
     sv.Ntot = o;
     sv.Btot = bo;
+    sv.fpack_len = fo;
+    sv.spack_len = so;
     sv.nchunks = (int)(o / CHUNK);
     if ((size_t)sv.nchunks * CHUNK != o || o / CHUNK > (size_t)1 << 30) { fr_set_error("solver too large"); return FR_EINVAL; }
     std::vector<int> chunk_case(sv.nchunks), case_chunk(n + 1);
@@ -125,7 +131,7 @@ void solver_free(Solver& sv) {
     dfree(sv.d_cases); dfree(sv.d_chunk_case); dfree(sv.d_case_chunk);
     dfree(sv.d_blk); dfree(sv.d_inv); dfree(sv.d_blk_keep);
     dfree(sv.d_q); dfree(sv.d_w); dfree(sv.d_V); dfree(sv.d_gs); dfree(sv.d_gi); dfree(sv.d_part);
-    dfree(sv.d_step); dfree(sv.d_sum);
+    dfree(sv.d_step); dfree(sv.d_sum); dfree(sv.d_fpack); dfree(sv.d_spack); dfree(sv.d_rscratch);
     if (sv.h_pin) (void)hipHostFree(sv.h_pin);
     if (sv.ws) (void)hipStreamDestroy(sv.ws);
     if (sv.ev_in) (void)hipEventDestroy(sv.ev_in);
@@ -158,6 +164,8 @@ fr_status solver_ensure_step(Solver& sv, int m) {
         FR_TRY(dalloc(&sv.d_w, (size_t)NWORK * sv.Ntot));
         FR_HIP(hipMemset(sv.d_w, 0, (size_t)NWORK * sv.Ntot * sizeof(double)));
     }
+    FR_TRY(dalloc(&sv.d_fpack, sv.fpack_len));
+    FR_TRY(dalloc(&sv.d_spack, sv.spack_len));
     if (!sv.d_q) {
         FR_TRY(dalloc(&sv.d_q, sv.Ntot));
         FR_HIP(hipMemset(sv.d_q, 0, sv.Ntot * sizeof(double)));
@@ -312,10 +320,10 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
             if (v >> t.lanes >> t.grid >> t.xcd) cache.emplace_back(line.substr(0, bar), t);
         }
     }
-    double *q = nullptr, *v = nullptr, *out = nullptr, *out2 = nullptr;
-    auto release = [&]() { dfree(q); dfree(v); dfree(out); dfree(out2); };
+    double *q = nullptr, *v = nullptr, *out = nullptr, *out2 = nullptr, *pf = nullptr, *ps = nullptr;
+    auto release = [&]() { dfree(q); dfree(v); dfree(out); dfree(out2); dfree(pf); dfree(ps); };
     if (dalloc(&q, sv.Ntot) != FR_OK || dalloc(&v, sv.Ntot) != FR_OK || dalloc(&out, sv.Ntot) != FR_OK ||
-        dalloc(&out2, sv.Ntot) != FR_OK) {
+        dalloc(&out2, sv.Ntot) != FR_OK || dalloc(&pf, sv.fpack_len) != FR_OK || dalloc(&ps, sv.spack_len) != FR_OK) {
         release();
         return FR_ENOMEM;
     }
@@ -328,15 +336,22 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
     std::string appended;
     const int grids[] = {0, 512, 1024, 2048};
     for (Group& g : sv.groups) {
-        for (int mode : {MODE_R, MODE_JVP, MODE_AOP}) {
+        for (int mode : {MODE_R, MODE_JVP, MODE_AOP, MODE_PREP, MODE_LIN}) {
             const std::string key = tune_key(arch, g, mode);
             bool found = false;
             for (auto& kv : cache)
                 if (kv.first == key) { g.tune[mode] = kv.second; found = true; }
             if (found) continue;
             KArgs a{};
-            a.q = q; a.v = mode == MODE_R ? nullptr : v; a.out = out; a.out2 = nullptr;
+            a.q = q; a.v = (mode == MODE_R || mode == MODE_PREP) ? nullptr : v; a.out = out; a.out2 = nullptr;
             a.c_time = 1.0; a.inv_dtau = 0.0;
+            a.fpack = pf; a.spack = ps;
+            if (mode == MODE_LIN) {
+                // the linearisation packs of the tuning state
+                KArgs pa = a;
+                pa.v = nullptr;
+                if ((ret = launch_fused(sv, g, MODE_PREP, pa, g.tune[MODE_PREP], s)) != FR_OK) break;
+            }
             Tune best;
             float best_ms = 1e30f;
             for (int lanes : {64, 128, 256}) {
