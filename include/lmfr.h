@@ -145,7 +145,8 @@ fr_status fr_bdf2_step(fr_ctx ctx, double* q, const double* q_nm1, const fr_step
  * (1: classical Gram-Schmidt, one orthogonalisation pass per Arnoldi step, the default;
  * 2: with one re-orthogonalisation pass), "operator_packs" (0/1: fr_bdf_operator first
  * stores the values its nonlinear point functions need at q, then applies the operator
- * on tangents only -- the form the BDF2 step uses inside GMRES; same result), and a manual
+ * on tangents only -- the form the BDF2 step uses inside GMRES; fr_block_jacobi_factor
+ * assembles its block columns the same way; same results to rounding), and a manual
  * launch shape of the fused kernels (what fr_autotune chooses): "tile_lanes" (0 =
  * default, 64, 128, 256; dual-number modes cap it at 128), "tile_grid" (0 = one
  * workgroup per tile, else the persistent grid size), "tile_xcd" (1 = each XCD walks a

@@ -248,7 +248,7 @@ static fr_status set_tile_option(Solver& sv, const char* name, int64_t value) {
     for (Group& g : sv.groups)
         for (int m = 0; m < NMODES; ++m) {
             Tune& t = g.tune[m];
-            const bool dual = m == MODE_JVP || m == MODE_AOP || m == MODE_BLK;
+            const bool dual = m != MODE_R;   // only the residual is built with 256 lanes
             if (!strcmp(name, "tile_lanes")) t.lanes = (dual && value == 256) ? 128 : (int)value;
             else if (!strcmp(name, "tile_grid")) t.grid = (int)value;
             else t.xcd = value != 0;
@@ -337,6 +337,13 @@ extern "C" fr_status fr_block_jacobi_factor(fr_ctx c, const double* q, double c_
     FR_TRY(solver_ensure_blocks(sv));
     KArgs a{};
     a.c_time = c_time; a.inv_dtau = inv_dtau;
+    if (sv.op_packs) {
+        // linearisation packs of q, then tangent-only block columns
+        KArgs p = plain_args(q, nullptr, sv.d_rscratch, nullptr);
+        p.fpack = sv.d_fpack; p.spack = sv.d_spack;
+        FR_TRY(solver_fused(sv, MODE_PREP, p, s));
+        a.fpack = sv.d_fpack; a.spack = sv.d_spack;
+    }
     FR_TRY(launch_block_assembly(sv, q, a, s));
     if (sv.keep_blocks) FR_HIP(hipMemcpyAsync(sv.d_blk_keep, sv.d_blk, sv.Btot * sizeof(double), hipMemcpyDeviceToDevice, s));
     // a zero pivot marks the case status; reading it synchronises once per refresh

@@ -505,7 +505,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 // values come from the packs.  The tangent arithmetic is the dual-number arithmetic of
 // the other modes term by term (same sums in the same order); the result matches MODE_AOP
 // to a few ulp, where the compiler contracts different products into fused multiply-adds.
-template <int P, bool VISC, bool MOV, int LANES>
+template <int P, bool VISC, bool MOV, int LANES, bool BLK>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_lin(GroupArgs ga, KArgs a, OpTab op) {
     using D = Dual<1>;
@@ -552,21 +552,25 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         const int e = (tile - rfl(ga.pfx[lo])) * EPB + el;
         const bool act = e < E;
         const unsigned EN = (unsigned)E * Np;
-        const double* v = a.v + cd.off;
+        const double* v = BLK ? nullptr : a.v + cd.off;
         const double* fpk = a.fpack + cd.fpoff;
         const double* spk = a.spack + cd.spoff;
         __syncthreads();
-        // ---- stage 1: own and neighbour tangents
+        // ---- stage 1: own and neighbour tangents (block columns: the unit seed of column
+        // seed0 in the element itself, and in a neighbour only when it is the element)
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = v[vv * EN + id];
+            for (int vv = 0; vv < 4; ++vv)
+                s_q[QI(el, vv, lt)] = BLK ? ((vv * Np + lt == a.seed0) ? 1.0 : 0.0) : v[vv * EN + id];
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 const int nb = g.nbr[e * 4 + f] >> 3;
                 const unsigned nid = (unsigned)nb * Np + lt;
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv) s_n[NI(el, f * 4 + vv, lt)] = v[vv * EN + nid];
+                for (int vv = 0; vv < 4; ++vv)
+                    s_n[NI(el, f * 4 + vv, lt)] =
+                        BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : v[vv * EN + nid];
             }
         }
         __syncthreads();
@@ -737,7 +741,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
             fr_time_apply<double, double>(pc, qv, geo[G_UG], geo[G_VG], idt, ct, x, tt);
-            double* out = a.out + cd.off;
+            double* out = a.out + (BLK ? cd.boff + (size_t)e * (4 * Np) * (4 * Np) : cd.off);
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
                 double dfx = 0.0, dfe = 0.0, dgx = 0.0, dge = 0.0, dqx = 0.0, dqe = 0.0;
@@ -759,7 +763,13 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                                  + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
                 const double Rd = -(vol + geo[G_IJ] * cor);
                 const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
-                out[vv * EN + id] = ttv - Rd;
+                if (BLK) {
+                    // column seed0 of the element's block, column-major; the time terms are zero
+                    // away from the seeded point, where ttv - Rd is exactly -Rd
+                    out[(size_t)a.seed0 * (4 * Np) + vv * Np + lt] = ttv - Rd;
+                } else {
+                    out[vv * EN + id] = ttv - Rd;
+                }
             }
         }
     }
@@ -787,10 +797,11 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
     if (!ga.pfx) { fr_set_error("tile prefix missing for this workgroup shape"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
     const OpTab& op = sv.cs[gr.ids[0]]->op;
-    if constexpr (MODE == MODE_LIN) {
-        if (!a.fpack || !a.spack || !a.v) { fr_set_error("linearised operator without packs"); return FR_EINVAL; }
-        hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s, ga,
-                           a, op);
+    if constexpr (MODE == MODE_LIN || MODE == MODE_LINBLK) {
+        constexpr bool B = MODE == MODE_LINBLK;
+        if (!a.fpack || !a.spack || (!B && !a.v)) { fr_set_error("linearised operator without packs"); return FR_EINVAL; }
+        hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s,
+                           ga, a, op);
     } else {
         if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
         hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads),
@@ -826,6 +837,7 @@ fr_status run_mode(const Solver& sv, const Group& gr, int mode, const KArgs& a, 
         case MODE_BLK: return run_lanes<P, VISC, MOV, MODE_BLK>(sv, gr, a, t, s);
         case MODE_PREP: return run_lanes<P, VISC, MOV, MODE_PREP>(sv, gr, a, t, s);
         case MODE_LIN: return run_lanes<P, VISC, MOV, MODE_LIN>(sv, gr, a, t, s);
+        case MODE_LINBLK: return run_lanes<P, VISC, MOV, MODE_LINBLK>(sv, gr, a, t, s);
     }
     fr_set_error("unknown residual mode");
     return FR_EINVAL;

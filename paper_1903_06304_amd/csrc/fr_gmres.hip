@@ -454,6 +454,7 @@ fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
         if (it % o->jac_lag == 0) {
             KArgs b{};
             b.cstep = sv.d_step; b.flags = sv.d_gi; b.flag = GI_NDONE;
+            b.fpack = sv.d_fpack; b.spack = sv.d_spack;   // written by this iteration's residual pass
             FR_TRY(launch_block_assembly(sv, sv.d_q, b, s));
             if (sv.keep_blocks) {
                 FR_HIP(hipMemcpyAsync(sv.d_blk_keep, sv.d_blk, sv.Btot * sizeof(double), hipMemcpyDeviceToDevice, s));

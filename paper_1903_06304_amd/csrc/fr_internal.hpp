@@ -40,7 +40,8 @@ struct Geo {
 
 // R; exact JVP; Newton operator; one seeded block column; R plus the linearisation packs;
 // Newton operator from the packs (tangent-only staging)
-enum FrMode { MODE_R = 0, MODE_JVP = 1, MODE_AOP = 2, MODE_BLK = 3, MODE_PREP = 4, MODE_LIN = 5, NMODES = 6 };
+enum FrMode { MODE_R = 0, MODE_JVP = 1, MODE_AOP = 2, MODE_BLK = 3, MODE_PREP = 4, MODE_LIN = 5, MODE_LINBLK = 6,
+              NMODES = 7 };   // MODE_LINBLK: block columns from the packs
 
 // Linearisation packs of a state (written by MODE_PREP, read by MODE_LIN): the values the
 // Newton operator's nonlinear point functions need, so that its staged data are tangents.

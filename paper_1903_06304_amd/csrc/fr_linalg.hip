@@ -488,14 +488,16 @@ GroupArgs group_args(const Solver& sv, const Group& gr, int epb) {
 
 // ----------------------------------------------------------------------------- launchers
 fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s) {
-    // one seeded column of every element's block per launch and group
+    // one seeded column of every element's block per launch and group; with the
+    // linearisation packs of q in base (fpack/spack), tangents only
     KArgs a = base;
     a.q = q; a.v = nullptr; a.out = sv.d_blk; a.out2 = nullptr;
+    const int mode = (a.fpack && a.spack) ? MODE_LINBLK : MODE_BLK;
     for (const Group& gr : sv.groups) {
         const int nb = 4 * (gr.p + 1) * (gr.p + 1);
         for (int col = 0; col < nb; ++col) {
             a.seed0 = col;
-            FR_TRY(launch_fused(sv, gr, MODE_BLK, a, gr.tune[MODE_BLK], s));
+            FR_TRY(launch_fused(sv, gr, mode, a, gr.tune[mode], s));
         }
     }
     return FR_OK;

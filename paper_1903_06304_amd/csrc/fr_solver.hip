@@ -381,8 +381,9 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
             appended += o.str();
         }
         if (ret != FR_OK) break;
-        // block columns use the dual-number shape of the Newton operator
+        // block columns use the shapes of the matching Newton operators
         g.tune[MODE_BLK] = g.tune[MODE_AOP];
+        g.tune[MODE_LINBLK] = g.tune[MODE_LIN];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

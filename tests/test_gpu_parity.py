@@ -139,10 +139,13 @@ def test_bdf_operator_parity():
     assert np.all(err <= 1e-12), err
 
 
+@pytest.mark.parametrize("packs", [0, 1])
 @pytest.mark.parametrize("nx,ny,p,kind", [(3, 3, 2, "curved"), (1, 3, 1, "curved"), (2, 3, 2, "deforming"),
                                           (4, 3, 3, "curved"), (3, 2, 4, "curved")])
-def test_blocks_parity(nx, ny, p, kind):
-    print(f"[parity] blocks {nx}x{ny} p={p} {kind}", flush=True)
+def test_blocks_parity(nx, ny, p, kind, packs):
+    """Blocks from dual-number columns (packs = 0) and from tangent-only columns over the
+    linearisation packs (packs = 1, the BDF2 step's path)."""
+    print(f"[parity] blocks {nx}x{ny} p={p} {kind} packs={packs}", flush=True)
     if kind == "curved":
         mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
         prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
@@ -159,6 +162,7 @@ def test_blocks_parity(nx, ny, p, kind):
         t = 0.1
     o, g = _pair(prm, mesh, t)
     g.set_option("keep_blocks", 1)
+    g.set_option("operator_packs", packs)
     ct, idt = 150.0, 1e-3
     g.block_jacobi_factor(_dev(q), ct, idt, "fp64")
     B = g.get_blocks().cpu().numpy()
