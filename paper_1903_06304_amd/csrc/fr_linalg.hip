@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
     double acc[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) acc[k] = 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int c = 0; c < NB; ++c) {
         double x[RPT];
         Pack8<Tin>::ld(A + (size_t)c * NB, x);
@@ -298,14 +298,16 @@ __device__ __forceinline__ bool chunk_skipped(const ChunkArgs& ca, int c) {
     return ca.flags && ca.flags[c * GI_STRIDE + ca.flag];
 }
 
-// Dot products V_i . w for i in [8*blockIdx.y, 8*blockIdx.y + 8) ∩ [0, nv), plus |w|^2 in
+// Dot products V_i . w for i in [DB*blockIdx.y, DB*blockIdx.y + DB) ∩ [0, nv), plus |w|^2 in
 // slot nv when want_norm (y-block 0 only; mass_only: first E Np entries of the case).
+// DB = 16 vectors per pass keep w's re-reads to one per 16 basis vectors.
+constexpr int DB = 16;
 __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const double* __restrict__ V, size_t ldv, int nv,
                                                        const double* __restrict__ w, int want_norm, int mass_only,
                                                        double* __restrict__ partial) {
-    __shared__ double red[RED_THREADS / 64][9];
-    const int i0 = blockIdx.y * 8;
-    const int cnt = nv - i0 < 8 ? nv - i0 : 8;
+    __shared__ double red[RED_THREADS / 64][DB + 1];
+    const int i0 = blockIdx.y * DB;
+    const int cnt = nv - i0 < DB ? nv - i0 : DB;
     const bool nrm = want_norm && blockIdx.y == 0;
     const double* Vc = V + (size_t)i0 * ldv;
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
@@ -318,30 +320,32 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const doubl
             const size_t m = cd.off + (size_t)cd.E * cd.Np;
             lim = m < lim ? m : lim;
         }
-        double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double acc[DB];
+#pragma unroll
+        for (int i = 0; i < DB; ++i) acc[i] = 0.0;
         double nacc = 0.0;
         for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
             const double wt = w[t];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int i = 0; i < DB; ++i)
                 if (i < cnt) acc[i] += Vc[i * ldv + t] * wt;
             if (nrm && t < lim) nacc += wt * wt;
         }
         __syncthreads();   // red[] of the previous chunk consumed
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const bool live = (i < cnt) || (i == 8 && nrm);
+        for (int i = 0; i < DB + 1; ++i) {
+            const bool live = (i < cnt) || (i == DB && nrm);
             if (!live) continue;
-            double v = (i < 8) ? acc[i] : nacc;
+            double v = (i < DB) ? acc[i] : nacc;
             for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
             if (lane == 0) red[wid][i] = v;
         }
         __syncthreads();
         const int k = threadIdx.x;
-        if (k < cnt || (k == 8 && nrm)) {
+        if (k < cnt || (k == DB && nrm)) {
             double v = 0.0;
             for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q][k];
-            partial[(size_t)ch * MAXV + (k < 8 ? i0 + k : nv)] = v;
+            partial[(size_t)ch * MAXV + (k < DB ? i0 + k : nv)] = v;
         }
     }
 }
@@ -627,7 +631,7 @@ fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, c
             return FR_OK;
         }
     }
-    const int ychunks = nv_dot > 0 ? (nv_dot + 7) / 8 : 1;
+    const int ychunks = nv_dot > 0 ? (nv_dot + DB - 1) / DB : 1;
     hipLaunchKernelGGL(k_dots8, dim3(grid, ychunks), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_dot, w,
                        want_norm ? 1 : 0, mass_only ? 1 : 0, partial);
     FR_HIP(hipGetLastError());
