@@ -300,8 +300,8 @@ __device__ __forceinline__ bool chunk_skipped(const ChunkArgs& ca, int c) {
 
 // Dot products V_i . w for i in [DB*blockIdx.y, DB*blockIdx.y + DB) ∩ [0, nv), plus |w|^2 in
 // slot nv when want_norm (y-block 0 only; mass_only: first E Np entries of the case).
-// DB = 16 vectors per pass keep w's re-reads to one per 16 basis vectors.
-constexpr int DB = 16;
+// DB = 8 vectors per pass (16 measured slower: fewer workgroups, heavier reduction).
+constexpr int DB = 8;
 __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const double* __restrict__ V, size_t ldv, int nv,
                                                        const double* __restrict__ w, int want_norm, int mass_only,
                                                        double* __restrict__ partial) {
