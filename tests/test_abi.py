@@ -104,3 +104,35 @@ def test_binding_refuses_without_device():
     nbr, nbf, flip = c.connectivity()
     with pytest.raises(RuntimeError):
         lmfr.Context(c.prm, nbr, nbf, flip)
+
+
+def test_null_arguments_rejected_everywhere():
+    """Every entry point validates its handles and pointers before any device work."""
+    L = _lib()
+    vp = None
+    assert L.fr_set_geometry(vp, vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_bdf_operator(vp, vp, vp, 1.0, 0.0, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_block_jacobi_factor(vp, vp, 1.0, 0.0, 0, vp) == lmfr.FR_EINVAL
+    assert L.fr_get_blocks(vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_set_option(vp, b"graph", 1) == lmfr.FR_EINVAL
+    assert L.fr_autotune(vp, None, vp) == lmfr.FR_EINVAL
+    assert L.fr_batch_create(vp, 0, vp) == lmfr.FR_EINVAL
+    n = ctypes.c_int64()
+    assert L.fr_batch_layout(vp, ctypes.byref(n), vp) == lmfr.FR_EINVAL
+    assert L.fr_batch_residual(vp, vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_batch_jvp(vp, vp, vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_batch_bdf2_step(vp, vp, vp, vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_batch_set_option(vp, b"graph", 1) == lmfr.FR_EINVAL
+    assert L.fr_batch_autotune(vp, None, vp) == lmfr.FR_EINVAL
+    L.fr_batch_destroy(vp)
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.fr_batch_create(arr, 2, ctypes.byref(ctypes.c_void_p())) == lmfr.FR_EINVAL
+
+
+def test_create_rejects_sizes_beyond_32_bit_offsets():
+    # 4 E (p+1)^2 >= 2^31 would overflow the kernels' 32-bit state offsets
+    nbr, nbf, _ = _table()
+    prm = _params(order=4, E=(1 << 31) // 100 + 1)
+    st, h = _create(prm, nbr, nbf)
+    assert st == lmfr.FR_EINVAL and not h.value
+    assert b"2^31" in _lib().fr_last_error()

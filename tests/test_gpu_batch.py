@@ -222,3 +222,71 @@ def test_batch_residual_c5_full():
         err = row_errors(Rs[k].cpu().numpy(), Ro)
         print(f"  oracle {c.name}: err/S {err / S}", flush=True)
         assert np.all(err <= 1e-12 * S), (c.name, err / S)
+
+
+def _mixed_cases():
+    """Kinds the 48-case draw does not contain: order 1, Euler (inviscid groups), a one-element
+    wide periodic strip (an element is its own neighbour), an Euler moving mesh."""
+    out = []
+    c1 = I.config_c1(nx=5, p=1)
+    out.append(c1)
+    mesh = I.Mesh(1, 4, 2, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.1, reynolds=200.0, viscous=True, kappa=1.0)
+    q = I.taylor_green(mesh, prm); q[1] += 0.05; q[2] -= 0.03
+    out.append(I.Case("strip_1x4_p2", mesh, prm, q))
+    mesh = I.Mesh(5, 6, 2, (0.0, 10.0, 0.0, 10.0), I.map_vortex_motion(0.5, 1.0, 0.1, 0.1), moving=True)
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.1, moving=True, kappa=1.0)
+    out.append(I.Case("euler_moving_p2", mesh, prm, I.isentropic_vortex(mesh, prm, xy=mesh.solution_points(T_GEO))))
+    out += _c5(1.0 / 16.0, idx=[0, 1])
+    return out
+
+
+def test_batch_mixed_kinds_residual_and_step():
+    lmfr = _lmfr()
+    cases = _mixed_cases()
+    ctxs = [_context(c, _t(c)) for c in cases]
+    b = lmfr.Batch(ctxs)
+    Rs = b.unpack(b.residual(b.pack([_dev(c.q) for c in cases])))
+    for c, g, Rb in zip(cases, ctxs, Rs):
+        assert torch.equal(Rb, g.residual(_dev(c.q))), c.name
+        xg, vg = c.mesh.nodes(_t(c))
+        o = Oracle(c.prm, c.mesh, xg, vg)
+        S = flux_scale(o.geometry(), c.prm, c.q)
+        err = row_errors(Rb.cpu().numpy(), o.residual(c.q))
+        assert np.all(err <= 1e-12 * S), (c.name, err / S)
+    dts = [5e-3, 2e-3, 1e-2, 1e-3, 2e-3]
+    opts = _opts(dts, "fp32")
+    qb = [_dev(c.q) for c in cases]
+    rc, stats = b.bdf2_step(qb, None, opts)
+    torch.cuda.synchronize()
+    assert rc == lmfr.FR_OK, rc
+    for c, g, dt, xb, st in zip(cases, ctxs, dts, qb, stats):
+        xs = _dev(c.q)
+        ss = g.bdf2_step(xs, None, dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=12, max_lin_it=300, max_newton=20,
+                         jac_lag=2, prec="fp32")
+        torch.cuda.synchronize()
+        assert (st["newton_its"], st["gmres_its"], st["converged"]) == (ss["newton_its"], ss["gmres_its"], 1), c.name
+        assert torch.equal(xb, xs), c.name
+
+
+def test_step_status_non_finite_and_iteration_cap():
+    """A non-finite state is reported as FR_ENONFINITE for its case only; a Newton cap of
+    zero iterations reports FR_ENOCONV and leaves the state unchanged."""
+    lmfr = _lmfr()
+    cases = _c5(1.0 / 16.0, idx=[0, 2])
+    ctxs = [_context(c, _t(c)) for c in cases]
+    b = lmfr.Batch(ctxs)
+    bad = cases[0].q.copy()
+    bad[3, 0, 0] = np.nan
+    qs = [_dev(bad), _dev(cases[1].q)]
+    rc, stats = b.bdf2_step(qs, None, _opts([1e-3, 1e-3], "fp64"), check=False)
+    torch.cuda.synchronize()
+    assert rc == lmfr.FR_ENONFINITE
+    assert stats[0]["converged"] == 0 and stats[1]["converged"] == 1
+    g = ctxs[1]
+    q0 = _dev(cases[1].q)
+    q = q0.clone()
+    st = g.bdf2_step(q, None, 1e-3, max_newton=0, check=False)
+    torch.cuda.synchronize()
+    assert st["rc"] == lmfr.FR_ENOCONV and st["converged"] == 0
+    assert torch.equal(q, q0)
