@@ -96,6 +96,13 @@ fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h
  * computed once, from its owner side, and shared by both sides. */
 fr_status fr_set_geometry(fr_ctx ctx, const double* xg, const double* vg, void* stream);
 
+/* Number of elements the last fr_set_geometry found affine: every metric term constant
+ * over the element to 1e-10 of its scale.  Where the neighbour across a face is affine,
+ * the kernels form its gradient trace from its state traces (the chain rule applied to
+ * the traced reference derivatives, the same values to rounding) instead of tracing its
+ * pointwise gradient.  *n_affine is HOST; synchronises `stream`. */
+fr_status fr_affine_elements(fr_ctx ctx, int32_t* n_affine, void* stream);
+
 /* R(q): the FR/CPR residual of paper Eq. (cpr_ns) with the moving-mesh terms of
  * Eq. (unsteady_pre_mov_pdomain), preconditioned Rusanov common flux (Eq. Rosanov),
  * BR2 common gradient and Radau correction functions.  q, R: [4][E][Np]. */

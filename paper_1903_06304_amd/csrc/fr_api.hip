@@ -110,9 +110,9 @@ void build_tables(fr_ctx c) {
         for (int a = 0; a < n; ++a) c->op.D[i * n + a] = dL[a];
     }
     lag_eval(x, bw, -1.0, L, dL);
-    for (int a = 0; a < n; ++a) c->op.lamL[a] = L[a];
+    for (int a = 0; a < n; ++a) { c->op.lamL[a] = L[a]; c->op.dlamL[a] = dL[a]; }
     lag_eval(x, bw, 1.0, L, dL);
-    for (int a = 0; a < n; ++a) c->op.lamR[a] = L[a];
+    for (int a = 0; a < n; ++a) { c->op.lamR[a] = L[a]; c->op.dlamR[a] = dL[a]; }
     // Radau correction functions (g_L right Radau, g_R left Radau) have nodal slopes
     // -l_i(-1)/w_i and l_i(+1)/w_i on the Gauss-Legendre points
     for (int i = 0; i < n; ++i) {
@@ -192,6 +192,7 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
     if ((st = dalloc(&c->d_nbr, (size_t)E * 4)) != FR_OK ||
         (st = dalloc(&c->d_gsp, NGSP * EN)) != FR_OK ||
         (st = dalloc(&c->d_gfp, NGFP * FE)) != FR_OK ||
+        (st = dalloc(&c->d_aff, (size_t)E)) != FR_OK ||
         (st = dalloc(&c->d_trace, FE * 10)) != FR_OK ||
         (st = dalloc(&c->d_vj, FE * 10)) != FR_OK) {
         fr_destroy(c);
@@ -214,7 +215,7 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
 extern "C" void fr_destroy(fr_ctx c) {
     if (!c) return;
     if (c->self) { solver_free(*c->self); delete c->self; }
-    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_trace); dfree(c->d_vj);
+    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_aff); dfree(c->d_trace); dfree(c->d_vj);
     delete c;
 }
 
@@ -377,6 +378,19 @@ __global__ void k_transpose_blocks(size_t E, int nb, const double* __restrict__ 
     dst[e * nn + row * nb + col] = src[t];
 }
 }  // namespace
+
+extern "C" fr_status fr_affine_elements(fr_ctx c, int32_t* n_affine, void* stream) {
+    FR_TRY(ready(c));
+    if (!n_affine) return bad("fr_affine_elements: null argument");
+    std::vector<int32_t> h((size_t)c->E);
+    FR_HIP(hipMemcpyAsync(h.data(), c->d_aff, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          (hipStream_t)stream));
+    FR_HIP(hipStreamSynchronize((hipStream_t)stream));
+    int32_t n = 0;
+    for (int32_t a : h) n += a;
+    *n_affine = n;
+    return FR_OK;
+}
 
 extern "C" fr_status fr_get_blocks(fr_ctx c, double* blk, void* stream) {
     FR_TRY(ready(c));

@@ -111,25 +111,23 @@ template <class T> __device__ __forceinline__ T* rfl(T* p) {
     return reinterpret_cast<T*>(rfl((unsigned long long)reinterpret_cast<uintptr_t>(p)));
 }
 
-// the descriptor of a case, in scalar registers (every field is copied: a new field must
-// be added here, which the size check below enforces)
-static_assert(sizeof(CaseDev) == 8 + 4 * 8 + sizeof(Geo) + sizeof(PhysConst), "load_case copies every field");
+// Read-only tables of a launch (case descriptors, case ids, tile prefixes: written once when
+// the solver is set up) are read through the scalar cache: the address is uniform, and a
+// pointer into the constant address space lets the compiler use scalar loads.
+template <class T> __device__ __forceinline__ T sld(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
+// the descriptor of a case, in scalar registers (read as 8-byte words)
 __device__ __forceinline__ CaseDev load_case(const CaseDev* p) {
+    static_assert(sizeof(CaseDev) % 8 == 0 && alignof(CaseDev) == 8, "descriptor read as 8-byte words");
+    constexpr int W = sizeof(CaseDev) / 8;
+    const unsigned long long* w = reinterpret_cast<const unsigned long long*>(p);
+    unsigned long long buf[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) buf[i] = sld(w + i);
     CaseDev c;
-    c.E = rfl(p->E);
-    c.Np = rfl(p->Np);
-    c.off = rfl(p->off);
-    c.boff = rfl(p->boff);
-    c.fpoff = rfl(p->fpoff);
-    c.spoff = rfl(p->spoff);
-    c.g.sp = rfl(p->g.sp);
-    c.g.fp = rfl(p->g.fp);
-    c.g.nbr = rfl(p->g.nbr);
-    const PhysConst& s = p->pc;
-    PhysConst& d = c.pc;
-    d.gam = rfl(s.gam); d.Rg = rfl(s.Rg); d.Cp = rfl(s.Cp); d.inv_gm1 = rfl(s.inv_gm1); d.gRg = rfl(s.gRg);
-    d.inv_Cp = rfl(s.inv_Cp); d.inv_Rg = rfl(s.inv_Rg); d.mu_re = rfl(s.mu_re); d.kc_re = rfl(s.kc_re);
-    d.eps_min = rfl(s.eps_min); d.br2 = rfl(s.br2);
+    __builtin_memcpy(&c, buf, sizeof(CaseDev));
     return c;
 }
 
@@ -138,7 +136,7 @@ __device__ __forceinline__ int find_member(const GroupArgs& ga, int t) {
     int lo = 0, hi = ga.nmem - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (rfl(ga.pfx[mid]) <= t) lo = mid; else hi = mid - 1;
+        if (sld(ga.pfx + mid) <= t) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -173,6 +171,44 @@ template <> struct LPad<3, 2> { static constexpr int F = 0, FACE = 2, E = 3; };
 template <> struct LPad<4, 1> { static constexpr int F = 1, FACE = 1, E = 4; };
 template <> struct LPad<4, 2> { static constexpr int F = 0, FACE = 1, E = 5; };
 
+// Metric terms one lane uses: those of its solution point, of its flux point and of the
+// neighbour across that face (the neighbour's constant metrics, used when it is affine).
+// They are requested when a tile starts, next to the states, so that a tile waits on memory
+// twice (the connectivity, then all that depends on it) rather than once per stage.  Lanes
+// past Np (NF) read a valid point they do not use, which keeps the loads in one sequence.
+struct LaneGeo {
+    double xix, xiy, etx, ety, ij, ug, vg;   // solution point lt % Np
+    double nx, ny, sc, cc, fug, fvg;         // flux point lt % NF
+    double mxix, mxiy, metx, mety;           // neighbour across face (lt % NF) / n
+    int nb, nf, k2, aff;                     // that neighbour, its face, the point index there
+};
+
+template <int P, bool VISC, bool MOV>
+__device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt, const int (&pk4)[4], LaneGeo& lg) {
+    constexpr int n = P + 1, Np = n * n, NF = 4 * n;
+    const unsigned EN = (unsigned)E * Np, FE = (unsigned)E * NF;
+    const int ls = lt % Np, lf = lt % NF, f = lf / n, k = lf % n;
+    const unsigned id = (unsigned)e * Np + ls, sid = (unsigned)e * NF + lf;
+    lg.xix = g.sp[G_XIX * EN + id]; lg.xiy = g.sp[G_XIY * EN + id];
+    lg.etx = g.sp[G_ETX * EN + id]; lg.ety = g.sp[G_ETY * EN + id];
+    lg.ij = g.sp[G_IJ * EN + id];
+    lg.ug = MOV ? g.sp[G_UG * EN + id] : 0.0;
+    lg.vg = MOV ? g.sp[G_VG * EN + id] : 0.0;
+    lg.nx = g.fp[F_NX * FE + sid]; lg.ny = g.fp[F_NY * FE + sid]; lg.sc = g.fp[F_SC * FE + sid];
+    lg.cc = VISC ? g.fp[F_CC * FE + sid] : 0.0;
+    lg.fug = MOV ? g.fp[F_UG * FE + sid] : 0.0;
+    lg.fvg = MOV ? g.fp[F_VG * FE + sid] : 0.0;
+    const int pk = f == 0 ? pk4[0] : f == 1 ? pk4[1] : f == 2 ? pk4[2] : pk4[3];
+    lg.nb = pk >> 3; lg.nf = (pk >> 1) & 3; lg.k2 = (pk & 1) ? n - 1 - k : k;
+    lg.aff = 0; lg.mxix = lg.mxiy = lg.metx = lg.mety = 0.0;
+    if (VISC) {
+        const unsigned gid = (unsigned)lg.nb * Np;
+        lg.aff = g.aff[lg.nb];
+        lg.mxix = g.sp[G_XIX * EN + gid]; lg.mxiy = g.sp[G_XIY * EN + gid];
+        lg.metx = g.sp[G_ETX * EN + gid]; lg.mety = g.sp[G_ETY * EN + gid];
+    }
+}
+
 template <int P, bool VISC, bool MOV, int MODE, int K, int LANES>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused(GroupArgs ga, KArgs a, OpTab op) {
@@ -202,13 +238,14 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
     auto SI = [](int el, int c, int fp) { return el * ESS + c * NF + fp; };
     __shared__ double s_D[n * n];       // operator tables (lane-dependent indexing goes to LDS)
-    __shared__ double s_lam[2][n], s_gam[2][n];
+    __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
 
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
     if (threadIdx.x < n) {
         s_lam[0][threadIdx.x] = op.lamL[threadIdx.x]; s_lam[1][threadIdx.x] = op.lamR[threadIdx.x];
         s_gam[0][threadIdx.x] = op.gamL[threadIdx.x]; s_gam[1][threadIdx.x] = op.gamR[threadIdx.x];
+        s_dlam[0][threadIdx.x] = op.dlamL[threadIdx.x]; s_dlam[1][threadIdx.x] = op.dlamR[threadIdx.x];
     }
     const int i = lt % n, j = lt / n;
     int tile, tend, tstride;
@@ -216,38 +253,47 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     for (; tile < tend; tile += tstride) {
         // ---- the tile's case (uniform across the workgroup)
         const int lo = find_member(ga, tile);
-        const int cid = rfl(ga.ids[lo]);
+        const int cid = sld(ga.ids + lo);
         if (a.flags && rfl(a.flags[cid * GI_STRIDE + a.flag])) continue;
         const CaseDev cd = load_case(ga.cases + cid);
         const PhysConst& pc = cd.pc;
         const Geo g = cd.g;
         const int E = cd.E;
-        const int e = (tile - rfl(ga.pfx[lo])) * EPB + el;
+        const int e = (tile - sld(ga.pfx + lo)) * EPB + el;
         const bool act = e < E;
         const unsigned EN = (unsigned)E * Np;   // state arrays hold < 2^31 entries (checked at creation)
         const double* q = a.q + cd.off;
         const double* v = a.v ? a.v + cd.off : nullptr;
         __syncthreads();   // the previous tile's readers of s_n / s_F are done
-        // ---- stage 1: own state and neighbour states into LDS
-        if (act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
+        // ---- stage 1: own state and neighbour states into LDS; the lane's metric terms
+        LaneGeo lg;
+        if (act) {
+            int pk4[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + lt);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = g.nbr[e * 4 + ff];
+            const int ls = lt % Np;
+            const unsigned id = (unsigned)e * Np + ls;
+            T qo[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const int nb = g.nbr[e * 4 + f] >> 3;
-                const unsigned nid = (unsigned)nb * Np + lt;
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + ls);
+            lane_geo_load<P, VISC, MOV>(g, E, e, lt, pk4, lg);
+            if (lt < Np) {
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv)
-                    s_n[NI(el, f * 4 + vv, lt)] = NbLoad<T>::load(a, q, v, vv * EN + nid, vv * Np + lt, nb == e);
+                for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+#pragma unroll
+                for (int ff = 0; ff < 4; ++ff) {
+                    const int nb = pk4[ff] >> 3;
+                    const unsigned nid = (unsigned)nb * Np + lt;
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv)
+                        s_n[NI(el, ff * 4 + vv, lt)] = NbLoad<T>::load(a, q, v, vv * EN + nid, vv * Np + lt, nb == e);
+                }
             }
         }
         __syncthreads();
         // ---- stage 2: own uncorrected gradient (kept in LDS only)
         if (VISC && act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
-            const double xix = g.sp[G_XIX * EN + id], xiy = g.sp[G_XIY * EN + id];
-            const double etx = g.sp[G_ETX * EN + id], ety = g.sp[G_ETY * EN + id];
+            const double xix = lg.xix, xiy = lg.xiy, etx = lg.etx, ety = lg.ety;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 T dxi = cst<T>(0.0), deta = cst<T>(0.0);
@@ -261,41 +307,46 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
             }
         }
         __syncthreads();
-        // ---- stage 3: own and neighbour traces, common flux at the flux points
+        // ---- stage 3: own and neighbour traces, common flux at the flux points.  The
+        // neighbour's gradient trace on an affine neighbour follows from its traces: the
+        // face-normal derivative from its line of states with l'(+-1), the tangential one
+        // from the traces along the face; the trace samples wait in the (still unused) s_F.
+        const int f = (lt % NF) / n, k = lt % n;
+        const int nb = lg.nb, nf = lg.nf, k2 = lg.k2;
+        T qm[4], qp[4];
         if (act && lt < NF) {
-            const int f = lt / n, k = lt % n;
-            const int pk = g.nbr[e * 4 + f];
-            const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
             const double* lam = s_lam[f & 1];
             const double* lamn = s_lam[nf & 1];
-            const unsigned FE = (unsigned)E * NF;
-            const unsigned sid = (unsigned)e * NF + lt;
-            const double nx = g.fp[F_NX * FE + sid], ny = g.fp[F_NY * FE + sid];
-            const double sc = g.fp[F_SC * FE + sid];
-            const double ugf = MOV ? g.fp[F_UG * FE + sid] : 0.0;
-            const double vgf = MOV ? g.fp[F_VG * FE + sid] : 0.0;
-            T fn[4], dq[4];
-            {
-                T qm[4], qp[4];
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv) {
-                    T am = cst<T>(0.0), ap = cst<T>(0.0);
+            for (int vv = 0; vv < 4; ++vv) {
+                T am = cst<T>(0.0), ap = cst<T>(0.0);
 #pragma unroll
-                    for (int b = 0; b < n; ++b) {
-                        am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
-                        ap = ap + lamn[b] * s_n[NI(el, f * 4 + vv, line_pt(n, nf, k2, b))];
-                    }
-                    qm[vv] = am;
-                    qp[vv] = ap;
+                for (int b = 0; b < n; ++b) {
+                    am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                    ap = ap + lamn[b] * s_n[NI(el, f * 4 + vv, line_pt(n, nf, k2, b))];
                 }
-                if constexpr (MODE == MODE_PREP) {
-                    double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
-                    const size_t fs = (size_t)E * NF;
-#pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) { fpk[vv * fs] = qm[vv]; fpk[(4 + vv) * fs] = qp[vv]; }
-                }
-                fr_common_inviscid<T>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
+                qm[vv] = am;
+                qp[vv] = ap;
             }
+            if constexpr (MODE == MODE_PREP) {
+                double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
+                const size_t fs = (size_t)E * NF;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) { fpk[vv * fs] = qm[vv]; fpk[(4 + vv) * fs] = qp[vv]; }
+            }
+            if (VISC) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s_F[FI(el, c, f * n + k2)] = qp[c + 1];
+            }
+        }
+        if (VISC) __syncthreads();
+        T fsc[4];   // S F^num, kept in registers until stage 5 writes F^num - F^loc
+        if (act && lt < NF) {
+            const double* lam = s_lam[f & 1];
+            const double* lamn = s_lam[nf & 1];
+            const double nx = lg.nx, ny = lg.ny, sc = lg.sc, ugf = lg.fug, vgf = lg.fvg;
+            T fn[4], dq[4];
+            fr_common_inviscid<T>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
             if (VISC) {
                 T gm[6], gp[6];
 #pragma unroll
@@ -306,24 +357,43 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                     gm[c] = am;
                     gp[c] = cst<T>(0.0);
                 }
-                // neighbour's uncorrected gradient along the line through its face point, traced
-#pragma unroll
-                for (int b = 0; b < n; ++b) {
-                    const int sp = line_pt(n, nf, k2, b);
-                    const int is = sp % n, js = sp / n;
-                    const unsigned gid = (unsigned)nb * Np + sp;
-                    const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
-                    const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+                if (lg.aff) {
+                    // constant metrics: the trace of the chain-rule gradient is the chain rule
+                    // applied to the traced reference derivatives
+                    const double xix = lg.mxix, xiy = lg.mxiy, etx = lg.metx, ety = lg.mety;
+                    const double* dlamn = s_dlam[nf & 1];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        T dxi = cst<T>(0.0), deta = cst<T>(0.0);
+                        T dnor = cst<T>(0.0), dtan = cst<T>(0.0);
 #pragma unroll
                         for (int m = 0; m < n; ++m) {
-                            dxi = dxi + s_D[is * n + m] * s_n[NI(el, f * 4 + c + 1, m + n * js)];
-                            deta = deta + s_D[js * n + m] * s_n[NI(el, f * 4 + c + 1, is + n * m)];
+                            dnor = dnor + dlamn[m] * s_n[NI(el, f * 4 + c + 1, line_pt(n, nf, k2, m))];
+                            dtan = dtan + s_D[k2 * n + m] * s_F[FI(el, c, f * n + m)];
                         }
-                        gp[2 * c] = gp[2 * c] + lamn[b] * (xix * dxi + etx * deta);
-                        gp[2 * c + 1] = gp[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
+                        const T dxi = nf < 2 ? dnor : dtan, deta = nf < 2 ? dtan : dnor;
+                        gp[2 * c] = xix * dxi + etx * deta;
+                        gp[2 * c + 1] = xiy * dxi + ety * deta;
+                    }
+                } else {
+                    // neighbour's uncorrected gradient along the line through its face point, traced
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        const int sp = line_pt(n, nf, k2, b);
+                        const int is = sp % n, js = sp / n;
+                        const unsigned gid = (unsigned)nb * Np + sp;
+                        const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
+                        const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            T dxi = cst<T>(0.0), deta = cst<T>(0.0);
+#pragma unroll
+                            for (int m = 0; m < n; ++m) {
+                                dxi = dxi + s_D[is * n + m] * s_n[NI(el, f * 4 + c + 1, m + n * js)];
+                                deta = deta + s_D[js * n + m] * s_n[NI(el, f * 4 + c + 1, is + n * m)];
+                            }
+                            gp[2 * c] = gp[2 * c] + lamn[b] * (xix * dxi + etx * deta);
+                            gp[2 * c + 1] = gp[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
+                        }
                     }
                 }
                 if constexpr (MODE == MODE_PREP) {
@@ -336,12 +406,12 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                 const T qcu = am_avg<T>(&s_q[QI(el, 1, 0)], lam, f, k, dq[1], n);
                 const T qcv = am_avg<T>(&s_q[QI(el, 2, 0)], lam, f, k, dq[2], n);
                 T dqh[3];
-                fr_common_viscous<T>(pc, dq, qcu, qcv, gm, gp, nx, ny, g.fp[F_CC * FE + sid], fn, dqh);
+                fr_common_viscous<T>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c];
             }
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) s_F[FI(el, vv, lt)] = sc * fn[vv];
+            for (int vv = 0; vv < 4; ++vv) fsc[vv] = sc * fn[vv];
             s_S[SI(el, 0, lt)] = sc * nx;                                  // element-oriented S
             s_S[SI(el, 1, lt)] = sc * ny;
             s_S[SI(el, 2, lt)] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;   // S . v_g
@@ -352,8 +422,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         auto WI = [&](int fld, int sp) { return NI(el, fld, sp); };   // fluxes alias the neighbour area
         T qs[4];
         if (act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
-            const double ij = g.sp[G_IJ * EN + id];
+            const double ij = lg.ij;
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[QI(el, vv, lt)];
             T gu[2], gv[2], gT[2];
@@ -399,10 +468,9 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 
         // ---- stage 5: F^num - F^loc, F^loc = S.(Pi f, Pi g) - (S.v_g) Pi q^c
         if (act && lt < NF) {
-            const int f = lt / n, k = lt % n;
             const double* lam = s_lam[f & 1];
             const double Sx = s_S[SI(el, 0, lt)], Sy = s_S[SI(el, 1, lt)], Svg = s_S[SI(el, 2, lt)];
-#pragma unroll 1
+#pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
                 T acc = cst<T>(0.0);
 #pragma unroll
@@ -412,7 +480,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                     if (MOV) w = w - Svg * s_n[WI(8 + vv, sp)];
                     acc = acc + lam[b] * w;
                 }
-                s_F[FI(el, vv, lt)] = s_F[FI(el, vv, lt)] - acc;
+                s_F[FI(el, vv, lt)] = fsc[vv] - acc;
             }
         }
         __syncthreads();
@@ -420,9 +488,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         // ---- stage 6: divergence + moving-mesh terms + Radau lift, one variable at a time
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
-            double geo[NGSP] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-            for (int c = 0; c < (MOV ? NGSP : G_UG); ++c) geo[c] = g.sp[c * EN + id];
+            const double geo[NGSP] = {lg.xix, lg.xiy, lg.etx, lg.ety, lg.ij, lg.ug, lg.vg};
             const double axi = MOV ? geo[G_UG] * geo[G_XIX] + geo[G_VG] * geo[G_XIY] : 0.0;
             const double aet = MOV ? geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY] : 0.0;
             double ct = a.c_time, idt = a.inv_dtau;
@@ -529,7 +595,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
     auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
     auto SI = [](int el, int c, int fp) { return el * ESS + c * NF + fp; };
     __shared__ double s_D[n * n];
-    __shared__ double s_lam[2][n], s_gam[2][n];
+    __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
     auto mk = [](double v, double d) { D r; r.v = v; r.d[0] = d; return r; };
 
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
@@ -537,19 +603,20 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
     if (threadIdx.x < n) {
         s_lam[0][threadIdx.x] = op.lamL[threadIdx.x]; s_lam[1][threadIdx.x] = op.lamR[threadIdx.x];
         s_gam[0][threadIdx.x] = op.gamL[threadIdx.x]; s_gam[1][threadIdx.x] = op.gamR[threadIdx.x];
+        s_dlam[0][threadIdx.x] = op.dlamL[threadIdx.x]; s_dlam[1][threadIdx.x] = op.dlamR[threadIdx.x];
     }
     const int i = lt % n, j = lt / n;
     int tile, tend, tstride;
     tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
     for (; tile < tend; tile += tstride) {
         const int lo = find_member(ga, tile);
-        const int cid = rfl(ga.ids[lo]);
+        const int cid = sld(ga.ids + lo);
         if (a.flags && rfl(a.flags[cid * GI_STRIDE + a.flag])) continue;
         const CaseDev cd = load_case(ga.cases + cid);
         const PhysConst& pc = cd.pc;
         const Geo g = cd.g;
         const int E = cd.E;
-        const int e = (tile - rfl(ga.pfx[lo])) * EPB + el;
+        const int e = (tile - sld(ga.pfx + lo)) * EPB + el;
         const bool act = e < E;
         const unsigned EN = (unsigned)E * Np;
         const double* v = BLK ? nullptr : a.v + cd.off;
@@ -558,27 +625,35 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         __syncthreads();
         // ---- stage 1: own and neighbour tangents (block columns: the unit seed of column
         // seed0 in the element itself, and in a neighbour only when it is the element)
-        if (act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
+        LaneGeo lg;
+        if (act) {
+            int pk4[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv)
-                s_q[QI(el, vv, lt)] = BLK ? ((vv * Np + lt == a.seed0) ? 1.0 : 0.0) : v[vv * EN + id];
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = g.nbr[e * 4 + ff];
+            const int ls = lt % Np;
+            const unsigned id = (unsigned)e * Np + ls;
+            double qo[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const int nb = g.nbr[e * 4 + f] >> 3;
-                const unsigned nid = (unsigned)nb * Np + lt;
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : v[vv * EN + id];
+            lane_geo_load<P, VISC, MOV>(g, E, e, lt, pk4, lg);
+            if (lt < Np) {
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv)
-                    s_n[NI(el, f * 4 + vv, lt)] =
-                        BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : v[vv * EN + nid];
+                for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+#pragma unroll
+                for (int ff = 0; ff < 4; ++ff) {
+                    const int nb = pk4[ff] >> 3;
+                    const unsigned nid = (unsigned)nb * Np + lt;
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv)
+                        s_n[NI(el, ff * 4 + vv, lt)] =
+                            BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : v[vv * EN + nid];
+                }
             }
         }
         __syncthreads();
         // ---- stage 2: uncorrected gradient tangent
         if (VISC && act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
-            const double xix = g.sp[G_XIX * EN + id], xiy = g.sp[G_XIY * EN + id];
-            const double etx = g.sp[G_ETX * EN + id], ety = g.sp[G_ETY * EN + id];
+            const double xix = lg.xix, xiy = lg.xiy, etx = lg.etx, ety = lg.ety;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 double dxi = 0.0, deta = 0.0;
@@ -592,20 +667,14 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             }
         }
         __syncthreads();
-        // ---- stage 3: trace tangents, common flux on dual numbers (values from the face pack)
+        // ---- stage 3: trace tangents, common flux on dual numbers (values from the face pack);
+        // an affine neighbour's gradient trace from its traces, as in the residual kernel
+        const int f = (lt % NF) / n, k = lt % n;
+        const int nf = lg.nf, k2 = lg.k2;
+        double qmt[4], qpt[4];
         if (act && lt < NF) {
-            const int f = lt / n, k = lt % n;
-            const int pk = g.nbr[e * 4 + f];
-            const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
             const double* lam = s_lam[f & 1];
             const double* lamn = s_lam[nf & 1];
-            const unsigned FE = (unsigned)E * NF;
-            const unsigned sid = (unsigned)e * NF + lt;
-            const double nx = g.fp[F_NX * FE + sid], ny = g.fp[F_NY * FE + sid];
-            const double sc = g.fp[F_SC * FE + sid];
-            const double ugf = MOV ? g.fp[F_UG * FE + sid] : 0.0;
-            const double vgf = MOV ? g.fp[F_VG * FE + sid] : 0.0;
-            D fn[4], dq[4], qm[4], qp[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
                 double am = 0.0, ap = 0.0;
@@ -614,8 +683,27 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                     am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
                     ap = ap + lamn[b] * s_n[NI(el, f * 4 + vv, line_pt(n, nf, k2, b))];
                 }
-                qm[vv] = mk(fpk[(size_t)vv * FE + sid], am);
-                qp[vv] = mk(fpk[(size_t)(4 + vv) * FE + sid], ap);
+                qmt[vv] = am;
+                qpt[vv] = ap;
+            }
+            if (VISC) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s_F[FI(el, c, f * n + k2)] = qpt[c + 1];
+            }
+        }
+        if (VISC) __syncthreads();
+        double fsc[4];   // tangent of S F^num, kept in registers until stage 5
+        if (act && lt < NF) {
+            const double* lam = s_lam[f & 1];
+            const double* lamn = s_lam[nf & 1];
+            const unsigned FE = (unsigned)E * NF;
+            const unsigned sid = (unsigned)e * NF + lt;
+            const double nx = lg.nx, ny = lg.ny, sc = lg.sc, ugf = lg.fug, vgf = lg.fvg;
+            D fn[4], dq[4], qm[4], qp[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                qm[vv] = mk(fpk[(size_t)vv * FE + sid], qmt[vv]);
+                qp[vv] = mk(fpk[(size_t)(4 + vv) * FE + sid], qpt[vv]);
             }
             fr_common_inviscid<D>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
             if (VISC) {
@@ -628,23 +716,40 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                     gm[c] = mk(fpk[(size_t)(8 + c) * FE + sid], am);
                 }
                 double gpt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int b = 0; b < n; ++b) {
-                    const int sp = line_pt(n, nf, k2, b);
-                    const int is = sp % n, js = sp / n;
-                    const unsigned gid = (unsigned)nb * Np + sp;
-                    const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
-                    const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+                if (lg.aff) {
+                    const double xix = lg.mxix, xiy = lg.mxiy, etx = lg.metx, ety = lg.mety;
+                    const double* dlamn = s_dlam[nf & 1];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        double dxi = 0.0, deta = 0.0;
+                        double dnor = 0.0, dtan = 0.0;
 #pragma unroll
                         for (int m = 0; m < n; ++m) {
-                            dxi = dxi + s_D[is * n + m] * s_n[NI(el, f * 4 + c + 1, m + n * js)];
-                            deta = deta + s_D[js * n + m] * s_n[NI(el, f * 4 + c + 1, is + n * m)];
+                            dnor = dnor + dlamn[m] * s_n[NI(el, f * 4 + c + 1, line_pt(n, nf, k2, m))];
+                            dtan = dtan + s_D[k2 * n + m] * s_F[FI(el, c, f * n + m)];
                         }
-                        gpt[2 * c] = gpt[2 * c] + lamn[b] * (xix * dxi + etx * deta);
-                        gpt[2 * c + 1] = gpt[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
+                        const double dxi = nf < 2 ? dnor : dtan, deta = nf < 2 ? dtan : dnor;
+                        gpt[2 * c] = xix * dxi + etx * deta;
+                        gpt[2 * c + 1] = xiy * dxi + ety * deta;
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        const int sp = line_pt(n, nf, k2, b);
+                        const int is = sp % n, js = sp / n;
+                        const unsigned gid = (unsigned)lg.nb * Np + sp;
+                        const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
+                        const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double dxi = 0.0, deta = 0.0;
+#pragma unroll
+                            for (int m = 0; m < n; ++m) {
+                                dxi = dxi + s_D[is * n + m] * s_n[NI(el, f * 4 + c + 1, m + n * js)];
+                                deta = deta + s_D[js * n + m] * s_n[NI(el, f * 4 + c + 1, is + n * m)];
+                            }
+                            gpt[2 * c] = gpt[2 * c] + lamn[b] * (xix * dxi + etx * deta);
+                            gpt[2 * c + 1] = gpt[2 * c + 1] + lamn[b] * (xiy * dxi + ety * deta);
+                        }
                     }
                 }
 #pragma unroll
@@ -653,12 +758,12 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                 const D qcu = qm[1] + 0.5 * dq[1];
                 const D qcv = qm[2] + 0.5 * dq[2];
                 D dqh[3];
-                fr_common_viscous<D>(pc, dq, qcu, qcv, gm, gp, nx, ny, g.fp[F_CC * FE + sid], fn, dqh);
+                fr_common_viscous<D>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c].d[0];
             }
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) s_F[FI(el, vv, lt)] = (sc * fn[vv]).d[0];
+            for (int vv = 0; vv < 4; ++vv) fsc[vv] = (sc * fn[vv]).d[0];
             s_S[SI(el, 0, lt)] = sc * nx;
             s_S[SI(el, 1, lt)] = sc * ny;
             s_S[SI(el, 2, lt)] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;
@@ -669,7 +774,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         double qv[4];
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
-            const double ij = g.sp[G_IJ * EN + id];
+            const double ij = lg.ij;
             D qs[4], gu[2], gv[2], gT[2];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
@@ -710,10 +815,9 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         __syncthreads();
         // ---- stage 5: F^num' - F^loc'
         if (act && lt < NF) {
-            const int f = lt / n, k = lt % n;
             const double* lam = s_lam[f & 1];
             const double Sx = s_S[SI(el, 0, lt)], Sy = s_S[SI(el, 1, lt)], Svg = s_S[SI(el, 2, lt)];
-#pragma unroll 1
+#pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
                 double acc = 0.0;
 #pragma unroll
@@ -723,16 +827,14 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                     if (MOV) w = w - Svg * s_n[WI(8 + vv, sp)];
                     acc = acc + lam[b] * w;
                 }
-                s_F[FI(el, vv, lt)] = s_F[FI(el, vv, lt)] - acc;
+                s_F[FI(el, vv, lt)] = fsc[vv] - acc;
             }
         }
         __syncthreads();
         // ---- stage 6: divergence, moving-mesh terms, lift of the tangents; time terms
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
-            double geo[NGSP] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-            for (int c = 0; c < (MOV ? NGSP : G_UG); ++c) geo[c] = g.sp[c * EN + id];
+            const double geo[NGSP] = {lg.xix, lg.xiy, lg.etx, lg.ety, lg.ij, lg.ug, lg.vg};
             const double axi = MOV ? geo[G_UG] * geo[G_XIX] + geo[G_VG] * geo[G_XIY] : 0.0;
             const double aet = MOV ? geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY] : 0.0;
             double ct = a.c_time, idt = a.inv_dtau;

@@ -15,6 +15,7 @@ struct OpTab {
     double D[FR_MAXN * FR_MAXN];   // D[i*n+a] = l_a'(xi_i)
     double lamL[FR_MAXN], lamR[FR_MAXN];   // l_a(-1), l_a(+1)
     double gamL[FR_MAXN], gamR[FR_MAXN];   // Radau correction slopes at xi_i
+    double dlamL[FR_MAXN], dlamR[FR_MAXN]; // l_a'(-1), l_a'(+1): derivative traces
 };
 
 // Gauss-Lobatto geometry basis evaluated where the metrics are needed
@@ -36,6 +37,7 @@ struct Geo {
     const double* sp;     // [NGSP][E][Np]
     const double* fp;     // [NGFP][E][4n]
     const int32_t* nbr;   // [E][4]: nb*8 + nb_face*2 + flip
+    const int32_t* aff;   // [E]: 1 when the element's metrics are constant (affine map)
 };
 
 // R; exact JVP; Newton operator; one seeded block column; R plus the linearisation packs;
@@ -156,6 +158,7 @@ struct fr_ctx_s {
     int32_t* d_nbr = nullptr;       // packed [E][4]
     double* d_gsp = nullptr;        // [NGSP][E][Np]
     double* d_gfp = nullptr;        // [NGFP][E][4n]
+    int32_t* d_aff = nullptr;       // [E] affine-element flags
     double* d_trace = nullptr;      // neighbour traces (adjoint path)
     double* d_vj = nullptr;         // adjoint trace buffer
     Solver* self = nullptr;         // one-case solver of the context's own entry points

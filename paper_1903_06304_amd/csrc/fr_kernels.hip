@@ -92,6 +92,27 @@ __device__ void face_eval(int E, int n, const GeoTab& gt, const double* xg, cons
     J = xr * ys - xs * yr;
 }
 
+// 1 when every solution-point metric term of the element equals its first point's to 1e-10
+// of the metric's scale (an affine element): its gradient traces then follow from its
+// face traces.  The rounding of metrics computed from node coordinates grows with
+// |x| / h (about 1e-12 on a 256 x 256 mesh of [0, 2 pi]^2); a map curved by less than
+// 1e-10 of the element size is affine for every purpose of the discretisation.
+__global__ void k_affine(int E, int Np, const double* __restrict__ gsp, int32_t* __restrict__ aff) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const size_t EN = (size_t)E * Np;
+    const double* m = gsp + (size_t)e * Np;
+    double scale = 0.0;
+    for (int c = G_XIX; c <= G_ETY; ++c) scale = fmax(scale, fabs(m[c * EN]));
+    bool ok = true;
+    for (int c = G_XIX; c <= G_IJ; ++c) {
+        const double* mc = m + c * EN;
+        const double tol = 1e-10 * (c == G_IJ ? fabs(mc[0]) : scale);
+        for (int s = 1; s < Np; ++s) ok = ok && fabs(mc[s] - mc[0]) <= tol;
+    }
+    aff[e] = ok ? 1 : 0;
+}
+
 __global__ void k_geo_fp(int E, int n, GeoTab gt, double br2, const int32_t* __restrict__ nbr,
                          const double* __restrict__ xg, const double* __restrict__ vg, double* __restrict__ gfp) {
     const int NF = 4 * n;
@@ -195,7 +216,7 @@ k_traces(TrArgs a, OpTab op_in, Geo g) {
 template <int P, bool VISC>
 fr_status run_traces(fr_ctx c, const TrArgs& a, hipStream_t s) {
     using B = Blk<P, 1>;
-    Geo g{c->d_gsp, c->d_gfp, c->d_nbr};
+    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff};
     const int grid = (c->E + B::EPB - 1) / B::EPB;
     hipLaunchKernelGGL((k_traces<P, VISC>), dim3(grid), dim3(B::threads), 0, s, a, c->op, g);
     FR_HIP(hipGetLastError());
@@ -216,6 +237,9 @@ fr_status launch_geometry(fr_ctx c, const double* xg, const double* vg, hipStrea
     FR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_geo_fp, dim3((unsigned)((nfp + bs - 1) / bs)), dim3(bs), 0, s, c->E, c->n, c->gt, c->pc.br2,
                        c->d_nbr, xg, vg, c->d_gfp);
+    FR_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_affine, dim3((unsigned)((c->E + bs - 1) / bs)), dim3(bs), 0, s, c->E, c->Np, c->d_gsp,
+                       c->d_aff);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

@@ -57,7 +57,7 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
         cd[c].spoff = so;
         fo += (size_t)npf(x->prm.viscous != 0) * x->E * 4 * x->n;
         so += (size_t)nps(x->prm.viscous != 0) * x->E * x->Np;
-        cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr};
+        cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr, x->d_aff};
         cd[c].pc = x->pc;
     }
     sv.Ntot = o;

@@ -23,6 +23,7 @@ PREC = {"fp64": FR_FP64, "fp32": FR_FP32, "bf16": FR_BF16}
 # every symbol declared in include/lmfr.h
 EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "fr_bdf_operator",
            "fr_block_jacobi_factor", "fr_block_jacobi_apply", "fr_get_blocks", "fr_bdf2_step",
+           "fr_affine_elements",
            "fr_set_option", "fr_autotune", "fr_batch_create", "fr_batch_destroy", "fr_batch_layout",
            "fr_batch_residual", "fr_batch_jvp", "fr_batch_bdf2_step", "fr_batch_set_option",
            "fr_batch_autotune", "fr_last_error", "fr_destroy"]
@@ -72,6 +73,7 @@ def load_library(path: str = LIB_PATH):
     L.fr_block_jacobi_factor.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
     L.fr_block_jacobi_apply.argtypes = [vp, dp, dp, vp]
     L.fr_get_blocks.argtypes = [vp, dp, vp]
+    L.fr_affine_elements.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     L.fr_bdf2_step.argtypes = [vp, dp, dp, ctypes.POINTER(fr_step_opts), ctypes.POINTER(fr_step_stats), vp]
     L.fr_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
     L.fr_autotune.argtypes = [vp, ctypes.c_char_p, vp]
@@ -196,6 +198,12 @@ class Context:
         z = torch.empty_like(r)
         _check(load_library().fr_block_jacobi_apply(self.h, _ptr(r), _ptr(z), _stream()))
         return z
+
+    def affine_elements(self):
+        """Elements the last set_geometry found affine (constant metrics)."""
+        n = ctypes.c_int32()
+        _check(load_library().fr_affine_elements(self.h, ctypes.byref(n), _stream()))
+        return n.value
 
     def get_blocks(self):
         nb = 4 * self.Np

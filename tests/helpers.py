@@ -56,6 +56,16 @@ def normwise_rel(a, b):
     return np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300)
 
 
+def map_half_curved(amp):
+    """Identity for x in [0, pi], the curved map for x in [pi, 2 pi] (continuous at both ends):
+    on a mesh with an even number of columns half of the elements are affine."""
+    def f(xr, yr, t):
+        d = amp * np.minimum(np.sin(xr), 0.0) * np.sin(yr)
+        z = np.zeros_like(xr)
+        return xr + d, yr + d, z, z.copy()
+    return f
+
+
 def small_cases():
     """Small meshes of every kind, sized so several workgroups and a ragged tail occur."""
     out = []
@@ -94,6 +104,20 @@ def small_cases():
         q[2] += 0.3 * rng.standard_normal(q[2].shape)
         q[3] *= 1 + 0.03 * rng.standard_normal(q[3].shape)
         out.append((f"ns_random_p{p}", prm, mesh, q, 0.21 if mov else 0.0))
+    for p in (1, 2, 3, 4):
+        # affine elements (the kind of the 256x256 workload): an affine neighbour's gradient
+        # trace is formed from its traces; the half-curved mesh puts both forms side by side
+        half = p == 3
+        mapping = map_half_curved(0.1) if half else I.map_affine
+        mesh = I.Mesh(6, 5, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), mapping)
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.2, reynolds=50.0, viscous=True, kappa=1.0)
+        rng = np.random.default_rng(50 + p)
+        q = I.uniform_flow(mesh, prm)
+        q[0] *= 1 + 0.05 * rng.standard_normal(q[0].shape)
+        q[1] += 0.3 * rng.standard_normal(q[1].shape)
+        q[2] += 0.3 * rng.standard_normal(q[2].shape)
+        q[3] *= 1 + 0.03 * rng.standard_normal(q[3].shape)
+        out.append((f"ns_random_{'halfaffine' if half else 'affine'}_p{p}", prm, mesh, q, 0.0))
     mesh = I.Mesh(5, 6, 2, (0.0, 10.0, 0.0, 10.0), I.map_vortex_motion(0.5, 1.0, 0.1, 0.1), moving=True)
     prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.1, moving=True, kappa=0.0)
     out.append(("euler_moving_p2", prm, mesh, I.isentropic_vortex(mesh, prm, xy=mesh.solution_points(0.1)), 0.1))

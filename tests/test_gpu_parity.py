@@ -47,6 +47,14 @@ def test_residual_parity(case):
     name, prm, mesh, q, t = case
     print(f"[parity] residual {name} E={mesh.E}", flush=True)
     o, g = _pair(prm, mesh, t)
+    # which elements take the constant-metric form of the neighbour gradient trace
+    n_aff = g.affine_elements()
+    if "halfaffine" in name:
+        assert n_aff == mesh.E // 2, n_aff
+    elif "affine" in name:
+        assert n_aff == mesh.E, n_aff
+    elif "curved" in name:
+        assert n_aff == 0, n_aff
     R = g.residual(_dev(q)).cpu().numpy()
     Ro = o.residual(q)
     S = flux_scale(o.geometry(), prm, q)
@@ -68,6 +76,25 @@ def test_residual_parity_c2_full():
     err = row_errors(R, Ro)
     assert np.all(err <= 1e-12 * S), err / S
     print("  plain rel", normwise_rel(R, Ro), flush=True)
+
+
+def test_residual_and_jvp_parity_c4_full():
+    """The 256x256 affine p=3 workload at full size, every row."""
+    c = I.config_c4()
+    print(f"[parity] residual + jvp C4 full E={c.mesh.E}", flush=True)
+    o, g = _pair(c.prm, c.mesh)
+    assert g.affine_elements() == c.mesh.E
+    R = g.residual(_dev(c.q)).cpu().numpy()
+    Ro = o.residual(c.q)
+    S = flux_scale(o.geometry(), c.prm, c.q)
+    err = row_errors(R, Ro)
+    print("  err/S", err / S, " plain rel", normwise_rel(R, Ro), flush=True)
+    assert np.all(err <= 1e-12 * S), err / S
+    v = np.random.default_rng(8).standard_normal(c.q.shape)
+    Jv = g.jvp(_dev(c.q), _dev(v)).cpu().numpy()
+    errj = normwise_rel(Jv, o.jvp(c.q, v))
+    print("  jvp", errj, flush=True)
+    assert np.all(errj <= 1e-12), errj
 
 
 def test_residual_deterministic_and_free_stream():
