@@ -118,6 +118,13 @@ template <class T> __device__ __forceinline__ T sld(const T* p) {
     return *(const __attribute__((address_space(4))) T*)p;
 }
 
+// Loads through pointers read from a descriptor: the compiler cannot tell that they point
+// to global memory and would emit flat loads, which also count against the LDS wait
+// counter; a pointer into the global address space gives plain global loads.
+template <class T> __device__ __forceinline__ T gld(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // the descriptor of a case, in scalar registers (read as 8-byte words)
 __device__ __forceinline__ CaseDev load_case(const CaseDev* p) {
     static_assert(sizeof(CaseDev) % 8 == 0 && alignof(CaseDev) == 8, "descriptor read as 8-byte words");
@@ -189,23 +196,23 @@ __device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt
     const unsigned EN = (unsigned)E * Np, FE = (unsigned)E * NF;
     const int ls = lt % Np, lf = lt % NF, f = lf / n, k = lf % n;
     const unsigned id = (unsigned)e * Np + ls, sid = (unsigned)e * NF + lf;
-    lg.xix = g.sp[G_XIX * EN + id]; lg.xiy = g.sp[G_XIY * EN + id];
-    lg.etx = g.sp[G_ETX * EN + id]; lg.ety = g.sp[G_ETY * EN + id];
-    lg.ij = g.sp[G_IJ * EN + id];
-    lg.ug = MOV ? g.sp[G_UG * EN + id] : 0.0;
-    lg.vg = MOV ? g.sp[G_VG * EN + id] : 0.0;
-    lg.nx = g.fp[F_NX * FE + sid]; lg.ny = g.fp[F_NY * FE + sid]; lg.sc = g.fp[F_SC * FE + sid];
-    lg.cc = VISC ? g.fp[F_CC * FE + sid] : 0.0;
-    lg.fug = MOV ? g.fp[F_UG * FE + sid] : 0.0;
-    lg.fvg = MOV ? g.fp[F_VG * FE + sid] : 0.0;
+    lg.xix = gld(g.sp + G_XIX * EN + id); lg.xiy = gld(g.sp + G_XIY * EN + id);
+    lg.etx = gld(g.sp + G_ETX * EN + id); lg.ety = gld(g.sp + G_ETY * EN + id);
+    lg.ij = gld(g.sp + G_IJ * EN + id);
+    lg.ug = MOV ? gld(g.sp + G_UG * EN + id) : 0.0;
+    lg.vg = MOV ? gld(g.sp + G_VG * EN + id) : 0.0;
+    lg.nx = gld(g.fp + F_NX * FE + sid); lg.ny = gld(g.fp + F_NY * FE + sid); lg.sc = gld(g.fp + F_SC * FE + sid);
+    lg.cc = VISC ? gld(g.fp + F_CC * FE + sid) : 0.0;
+    lg.fug = MOV ? gld(g.fp + F_UG * FE + sid) : 0.0;
+    lg.fvg = MOV ? gld(g.fp + F_VG * FE + sid) : 0.0;
     const int pk = f == 0 ? pk4[0] : f == 1 ? pk4[1] : f == 2 ? pk4[2] : pk4[3];
     lg.nb = pk >> 3; lg.nf = (pk >> 1) & 3; lg.k2 = (pk & 1) ? n - 1 - k : k;
     lg.aff = 0; lg.mxix = lg.mxiy = lg.metx = lg.mety = 0.0;
     if (VISC) {
         const unsigned gid = (unsigned)lg.nb * Np;
-        lg.aff = g.aff[lg.nb];
-        lg.mxix = g.sp[G_XIX * EN + gid]; lg.mxiy = g.sp[G_XIY * EN + gid];
-        lg.metx = g.sp[G_ETX * EN + gid]; lg.mety = g.sp[G_ETY * EN + gid];
+        lg.aff = gld(g.aff + lg.nb);
+        lg.mxix = gld(g.sp + G_XIX * EN + gid); lg.mxiy = gld(g.sp + G_XIY * EN + gid);
+        lg.metx = gld(g.sp + G_ETX * EN + gid); lg.mety = gld(g.sp + G_ETY * EN + gid);
     }
 }
 
@@ -270,7 +277,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = g.nbr[e * 4 + ff];
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             T qo[4];
@@ -381,8 +388,8 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                         const int sp = line_pt(n, nf, k2, b);
                         const int is = sp % n, js = sp / n;
                         const unsigned gid = (unsigned)nb * Np + sp;
-                        const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
-                        const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+                        const double xix = gld(g.sp + G_XIX * EN + gid), xiy = gld(g.sp + G_XIY * EN + gid);
+                        const double etx = gld(g.sp + G_ETX * EN + gid), ety = gld(g.sp + G_ETY * EN + gid);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             T dxi = cst<T>(0.0), deta = cst<T>(0.0);
@@ -629,7 +636,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = g.nbr[e * 4 + ff];
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             double qo[4];
@@ -737,8 +744,8 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                         const int sp = line_pt(n, nf, k2, b);
                         const int is = sp % n, js = sp / n;
                         const unsigned gid = (unsigned)lg.nb * Np + sp;
-                        const double xix = g.sp[G_XIX * EN + gid], xiy = g.sp[G_XIY * EN + gid];
-                        const double etx = g.sp[G_ETX * EN + gid], ety = g.sp[G_ETY * EN + gid];
+                        const double xix = gld(g.sp + G_XIX * EN + gid), xiy = gld(g.sp + G_XIY * EN + gid);
+                        const double etx = gld(g.sp + G_ETX * EN + gid), ety = gld(g.sp + G_ETY * EN + gid);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             double dxi = 0.0, deta = 0.0;
