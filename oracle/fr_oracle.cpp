@@ -796,6 +796,88 @@ static int bdf2_step(const Ctx& c, double* q, const double* q_nm1, const StepOpt
     return st.converged ? 0 : -5;
 }
 
+// ---------------------------------------------------------------- steady pseudo-transient continuation
+struct SteadyOpts { double dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs; int krylov, max_lin_it, max_steps, jac_lag; };
+
+// Sec. 3.2 Eq. (steady_pre_discretized_1): (Gamma^m/dtau - dR/dq^m) dq^m = R^m, backward Euler
+// in pseudo time linearised about q^m, with dtau from Eq. (SER): the step size used at pseudo-step
+// m is that of step m-1 times (Res_{m-1}/Res_m)^r_ser, clipped to [dtau_min, dtau_max], and dtau0
+// at m = 0 (reading: the freshest residual ratio sets the next step); Res is the 2-norm of the
+// continuity (pressure) rows of R.  hist (may be null) receives (Res_m, dtau_m) per step taken.
+static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats& st, double* dtau_final,
+                        std::vector<double>* hist) {
+    const int Np = c.Np, E = c.E, nb = 4 * Np;
+    const size_t N = (size_t)4 * E * Np;
+    NSPhys ph{&c};
+    std::vector<double> R(N), dq(N);
+    std::vector<double> blk((size_t)E * nb * nb); std::vector<int> piv((size_t)E * nb);
+    st = StepStats{0, 0, 0, 0.0, 0.0};
+    double dtau = o.dtau0, res_prev = 0.0;
+    auto gamma_pt = [&](const double* qq, int e, int s, double G[4][4]) {
+        double qs[4]; for (int v = 0; v < 4; ++v) qs[v] = qq[((size_t)v * E + e) * Np + s];
+        const size_t id = (size_t)e * Np + s;
+        mat_Gamma(c, qs, c.ugs[id], c.vgs[id], G);
+    };
+    for (int m = 0; ; ++m) {
+        residual(c, ph, q, R.data());
+        double res = 0.0;
+        for (size_t i = 0; i < (size_t)E * Np; ++i) res += R[i] * R[i];
+        res = std::sqrt(res);
+        if (!std::isfinite(res)) return -4;
+        if (m == 0) st.res0 = res;
+        st.res_final = res;
+        if (res <= o.tol_abs || res <= o.tol_pseudo * st.res0) { st.converged = 1; break; }
+        if (m >= o.max_steps) break;
+        if (m > 0) dtau = std::max(o.dtau_min, std::min(o.dtau_max, dtau * std::pow(res_prev / res, o.r_ser)));
+        res_prev = res;
+        if (hist) { hist->push_back(res); hist->push_back(dtau); }
+        const double idt = 1.0 / dtau;
+        if (m % o.jac_lag == 0) {
+            Traces<cplx> trz;
+            std::vector<cplx> qz(q, q + N);
+            compute_traces(c, ph, qz.data(), trz);
+            for (int e = 0; e < E; ++e) {
+                double* B = blk.data() + (size_t)e * nb * nb;
+                element_block_cs(c, q, trz, e, B);
+                for (int r = 0; r < nb * nb; ++r) B[r] = -B[r];
+                for (int s = 0; s < Np; ++s) {
+                    double G[4][4]; gamma_pt(q, e, s, G);
+                    for (int r = 0; r < 4; ++r) for (int k = 0; k < 4; ++k) B[(size_t)(r * Np + s) * nb + k * Np + s] += idt * G[r][k];
+                }
+                if (lu_factor(nb, B, piv.data() + (size_t)e * nb) != 0) return -5;
+            }
+        }
+        std::vector<double> qcur(q, q + N);
+        auto Aop = [&](const double* v, double* out) {
+            jvp_cs(c, qcur.data(), v, out);
+            for (int e = 0; e < E; ++e)
+                for (int s = 0; s < Np; ++s) {
+                    double G[4][4]; gamma_pt(qcur.data(), e, s, G);
+                    for (int r = 0; r < 4; ++r) {
+                        double t = 0.0;
+                        for (int k = 0; k < 4; ++k) t += idt * G[r][k] * v[((size_t)k * E + e) * Np + s];
+                        const size_t id = ((size_t)r * E + e) * Np + s;
+                        out[id] = t - out[id];
+                    }
+                }
+        };
+        auto Pop = [&](const double* v, double* out) {
+            std::vector<double> tmp(nb);
+            for (int e = 0; e < E; ++e) {
+                for (int r = 0; r < 4; ++r) for (int s = 0; s < Np; ++s) tmp[r * Np + s] = v[((size_t)r * E + e) * Np + s];
+                lu_solve(nb, blk.data() + (size_t)e * nb * nb, piv.data() + (size_t)e * nb, tmp.data());
+                for (int r = 0; r < 4; ++r) for (int s = 0; s < Np; ++s) out[((size_t)r * E + e) * Np + s] = tmp[r * Np + s];
+            }
+        };
+        GmresOut go = gmres(N, Aop, Pop, R.data(), dq.data(), o.krylov, o.tol_res, o.max_lin_it);
+        st.gmres_its += go.its;
+        for (size_t i = 0; i < N; ++i) q[i] += dq[i];
+        st.newton_its++;
+    }
+    if (dtau_final) *dtau_final = dtau;
+    return st.converged ? 0 : -5;
+}
+
 }  // namespace ora
 
 // =====================================================================================
@@ -1015,6 +1097,25 @@ int ora_bdf2_step(void* h, double* q, const double* q_nm1, const double* dopt, c
     int rc = bdf2_step(c, q, q_nm1, o, st);
     istat[0] = st.newton_its; istat[1] = st.gmres_its; istat[2] = st.converged;
     dstat[0] = st.res0; dstat[1] = st.res_final;
+    return rc;
+}
+
+// Steady pseudo-transient continuation with SER; q updated in place.
+// dopt: dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs;
+// iopt: krylov, max_lin_it, max_steps, jac_lag
+// istat: steps, gmres_its, converged; dstat: res0, res_final, dtau of the last step taken;
+// hist (length 2 * (max_steps + 1), may be null): Res_m, dtau_m of every step taken
+int ora_steady_solve(void* h, double* q, const double* dopt, const int* iopt, int* istat, double* dstat,
+                     double* hist) {
+    Ctx& c = *(Ctx*)h;
+    SteadyOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], dopt[5], dopt[6], iopt[0], iopt[1], iopt[2], iopt[3]};
+    StepStats st;
+    double dtf = 0.0;
+    std::vector<double> hv;
+    int rc = steady_solve(c, q, o, st, &dtf, &hv);
+    istat[0] = st.newton_its; istat[1] = st.gmres_its; istat[2] = st.converged;
+    dstat[0] = st.res0; dstat[1] = st.res_final; dstat[2] = dtf;
+    if (hist) std::copy(hv.begin(), hv.end(), hist);
     return rc;
 }
 

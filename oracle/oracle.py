@@ -41,7 +41,7 @@ def lib():
         L.ora_create.restype = ctypes.c_void_p
         L.ora_destroy.argtypes = [ctypes.c_void_p]
         for name in ["ora_residual", "ora_jvp", "ora_dense_jacobian", "ora_vjp_dofs", "ora_blocks",
-                     "ora_point", "ora_common_flux", "ora_phys_flux", "ora_bdf2_step",
+                     "ora_point", "ora_common_flux", "ora_phys_flux", "ora_bdf2_step", "ora_steady_solve",
                      "ora_geometry", "ora_scalar_residual", "ora_residual_cplx", "ora_cons_cplx"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -228,4 +228,21 @@ class Oracle:
         rc = lib().ora_bdf2_step(self.h, _p(q), _p(qn1), _p(d), _p(i, _ip), _p(ist, _ip), _p(dst))
         stats = dict(rc=rc, newton_its=int(ist[0]), gmres_its=int(ist[1]), converged=int(ist[2]),
                      res0=float(dst[0]), res_final=float(dst[1]))
+        return q, stats
+
+    def steady_solve(self, q, dtau0=0.01, dtau_min=0.01, dtau_max=1e20, r_ser=2.0, tol_pseudo=1e-8,
+                     tol_res=1e-6, tol_abs=0.0, krylov=30, max_lin_it=200, max_steps=100, jac_lag=1):
+        """Steady pseudo-transient continuation with SER (Sec. 3.2): returns the final state and
+        stats, with hist = [(Res_m, dtau_m)] of every pseudo-step taken."""
+        q = np.array(self._state(q), copy=True)
+        d = np.array([dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs], dtype=np.float64)
+        i = np.array([krylov, max_lin_it, max_steps, jac_lag], dtype=np.int32)
+        ist = np.zeros(3, dtype=np.int32)
+        dst = np.zeros(3)
+        hist = np.zeros(2 * (max_steps + 1))
+        rc = lib().ora_steady_solve(self.h, _p(q), _p(d), _p(i, _ip), _p(ist, _ip), _p(dst), _p(hist))
+        n = int(ist[0])
+        stats = dict(rc=rc, steps=n, gmres_its=int(ist[1]), converged=int(ist[2]), res0=float(dst[0]),
+                     res_final=float(dst[1]), dtau_final=float(dst[2]),
+                     hist=[(float(hist[2 * k]), float(hist[2 * k + 1])) for k in range(n)])
         return q, stats

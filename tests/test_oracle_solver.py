@@ -6,6 +6,12 @@
   mesh stays unchanged (implicit GCL); the converged iterate satisfies the BDF2
   equation; temporal order 2 on the isentropic vortex (paper Sec. 4.3 reports
   the optimal BDF2 rate).
+* Steady pseudo-transient continuation (Sec. 3.2, Eqs. steady_pre_discretized_1 and SER):
+  one step equals the dense solve of (Gamma/dtau - dR/dq) dq = R built from the pinned dense
+  Jacobian and the pinned Gamma; for small dtau it is the explicit pseudo-time step
+  dtau Gamma^-1 R to first order; a perturbed uniform NS flow converges to a uniform state
+  (R = 0 there) in a number of steps that does not depend on the Mach number (the purpose
+  of the preconditioning, Sec. 2.2).
 """
 import numpy as np
 import pytest
@@ -106,3 +112,76 @@ def test_bdf2_temporal_order():
     errs = np.array(errs)
     rates = np.log2(errs[:-1] / errs[1:])
     assert np.all(rates > 1.6) and rates[-1] > 1.85 and np.all(rates < 2.3), (errs, rates)
+
+
+def _steady_case(mach=0.1, nx=3, p=1, amp=0.1, seed=0):
+    mesh = I.Mesh(nx, nx, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi))
+    prm = I.Params(order=p, n_elem=mesh.E, mach_ref=mach, reynolds=100.0, viscous=True, kappa=1.0)
+    q = I.uniform_flow(mesh, prm)
+    du, dv = I.random_solenoidal_velocity(mesh, np.random.default_rng(seed), rms=amp)
+    q[1] += du
+    q[2] += dv
+    return Oracle(prm, mesh), q
+
+
+def _gamma_blockdiag(o, q):
+    """Gamma at every solution point as a matrix on the [4][E][Np] layout (static mesh)."""
+    _, E, Np = q.shape
+    N = q.size
+    G = np.zeros((N, N))
+    for e in range(E):
+        for s in range(Np):
+            g = o.point(q[:, e, s])["Gamma"]
+            idx = [v * E * Np + e * Np + s for v in range(4)]
+            G[np.ix_(idx, idx)] = g
+    return G
+
+
+def _one_step(o, q, dtau):
+    q1, st = o.steady_solve(q, dtau0=dtau, dtau_min=dtau, dtau_max=dtau, tol_pseudo=1e-30, tol_res=1e-14,
+                            krylov=400, max_lin_it=400, max_steps=1)
+    assert st["steps"] == 1 and st["hist"][0][1] == dtau
+    return q1 - q
+
+
+def test_steady_step_is_the_linearised_backward_euler_solve():
+    o, q = _steady_case()
+    dtau = 0.05
+    dq = _one_step(o, q, dtau)
+    A = _gamma_blockdiag(o, q) / dtau - o.dense_jacobian(q)
+    ref = np.linalg.solve(A, o.residual(q).ravel())
+    err = np.linalg.norm(dq.ravel() - ref) / np.linalg.norm(ref)
+    assert err < 1e-10, err
+
+
+def test_steady_step_small_dtau_is_the_explicit_pseudo_time_step():
+    o, q = _steady_case()
+    Ginv_R = np.linalg.solve(_gamma_blockdiag(o, q), o.residual(q).ravel())
+    errs = []
+    for dtau in (2e-5, 1e-5):
+        dq = _one_step(o, q, dtau).ravel()
+        errs.append(np.linalg.norm(dq - dtau * Ginv_R) / np.linalg.norm(dtau * Ginv_R))
+    assert errs[0] < 1e-2
+    assert 1.8 < errs[0] / errs[1] < 2.2, errs   # first order in dtau
+
+
+@pytest.mark.parametrize("mach", [0.3, 0.1, 0.01])
+def test_steady_converges_to_uniform_flow_mach_independent(mach):
+    o, q = _steady_case(mach=mach, nx=4, p=2)
+    qs, st = o.steady_solve(q, tol_pseudo=1e-10, tol_res=1e-6, krylov=60, max_lin_it=600, max_steps=40)
+    assert st["converged"] == 1, st
+    # the converged state is a zero of R: a uniform flow on this periodic mesh
+    vel = np.sqrt(np.mean((qs[1] - qs[1].mean()) ** 2 + (qs[2] - qs[2].mean()) ** 2))
+    assert vel < 1e-9, vel
+    R = o.residual(qs)
+    assert np.linalg.norm(R[0]) <= 1e-10 * st["res0"]
+    # the number of pseudo-steps does not depend on the Mach number
+    assert 14 <= st["steps"] <= 20, st["steps"]
+    # SER: dtau grows as the residual falls (dtau_min = dtau0 = 0.01, r_ser = 2)
+    res = [h[0] for h in st["hist"]]
+    dts = [h[1] for h in st["hist"]]
+    assert dts[0] == 0.01
+    for m in range(1, len(dts)):
+        expect = max(0.01, min(1e20, dts[m - 1] * (res[m - 1] / res[m]) ** 2))
+        assert abs(dts[m] - expect) <= 1e-12 * expect
+    assert dts[-1] > 1e6
