@@ -703,8 +703,83 @@ static GmresOut gmres(size_t N, const std::function<void(const double*, double*)
     return out;
 }
 
+// ---------------------------------------------------------------- preconditioners
+// Element colouring for the Gauss-Seidel sweeps: elements in index order take the smallest
+// colour that no face neighbour already has.
+static std::vector<int> colour_elements(const Ctx& c, int& ncol) {
+    std::vector<int> col(c.E, -1);
+    ncol = 0;
+    for (int e = 0; e < c.E; ++e) {
+        bool used[5] = {false, false, false, false, false};
+        for (int f = 0; f < 4; ++f) {
+            const int nb = c.nbr[e * 4 + f];
+            if (nb != e && col[nb] >= 0) used[col[nb]] = true;
+        }
+        int k = 0;
+        while (used[k]) ++k;
+        col[e] = k;
+        ncol = std::max(ncol, k + 1);
+    }
+    return col;
+}
+
+// z = P^-1 r.  precond 0: element-block Jacobi, z_e = D_e^-1 r_e with D_e the diagonal
+// block of the Newton operator A (factored in blk/piv).  precond 1: symmetric block
+// Gauss-Seidel over the elements in colour order (reading: the element-block form of the
+// relaxation-type preconditioning the paper's solver setup names, ILU(0)),
+// P = (D + L) D^-1 (D + U), L / U the couplings of A to elements of lower / higher colour:
+//   forward  y_k = D_k^-1 (r_k - sum_{k' < k} A_{k k'} y_{k'})   for k = 0 .. K-1,
+//   backward z_k = y_k - D_k^-1 sum_{k' > k} A_{k k'} z_{k'}      for k = K-2 .. 0,
+// with the off-diagonal products taken as A applied to y (z) restricted to those colours.
+static void precond_apply(const Ctx& c, int precond, const std::vector<int>& col, int ncol,
+                          const std::vector<double>& blk, const std::vector<int>& piv,
+                          const std::function<void(const double*, double*)>& A, const double* r, double* z) {
+    const int Np = c.Np, E = c.E, nb = 4 * Np;
+    const size_t N = (size_t)4 * E * Np;
+    std::vector<double> tmp(nb);
+    // z_e = D_e^-1 (a_e - b_e) (b may be null), or z_e -= D_e^-1 a_e when sub
+    auto dsolve = [&](int e, const double* a, const double* b, bool sub) {
+        for (int v = 0; v < 4; ++v)
+            for (int s = 0; s < Np; ++s) {
+                const size_t id = ((size_t)v * E + e) * Np + s;
+                tmp[v * Np + s] = a[id] - (b ? b[id] : 0.0);
+            }
+        lu_solve(nb, blk.data() + (size_t)e * nb * nb, piv.data() + (size_t)e * nb, tmp.data());
+        for (int v = 0; v < 4; ++v)
+            for (int s = 0; s < Np; ++s) {
+                const size_t id = ((size_t)v * E + e) * Np + s;
+                z[id] = sub ? z[id] - tmp[v * Np + s] : tmp[v * Np + s];
+            }
+    };
+    if (precond == 0) {
+        for (int e = 0; e < E; ++e) dsolve(e, r, nullptr, false);
+        return;
+    }
+    std::fill(z, z + N, 0.0);
+    std::vector<double> u(N), t(N);
+    auto restrict_to = [&](int lo, int hi) {   // u = z on colours lo..hi, 0 elsewhere
+        for (int v = 0; v < 4; ++v)
+            for (int e = 0; e < E; ++e)
+                for (int s = 0; s < Np; ++s) {
+                    const size_t id = ((size_t)v * E + e) * Np + s;
+                    u[id] = (col[e] >= lo && col[e] <= hi) ? z[id] : 0.0;
+                }
+    };
+    for (int k = 0; k < ncol; ++k) {
+        if (k > 0) { restrict_to(0, k - 1); A(u.data(), t.data()); }
+        for (int e = 0; e < E; ++e)
+            if (col[e] == k) dsolve(e, r, k > 0 ? t.data() : nullptr, false);
+    }
+    for (int k = ncol - 2; k >= 0; --k) {
+        restrict_to(k + 1, ncol - 1);
+        A(u.data(), t.data());
+        for (int e = 0; e < E; ++e)
+            if (col[e] == k) dsolve(e, t.data(), nullptr, true);
+    }
+}
+
 // ---------------------------------------------------------------- BDF2 dual-time Newton step
-struct StepOpts { double dt, inv_dtau, tol_pseudo, tol_res, tol_abs; int krylov, max_lin_it, max_newton, jac_lag; };
+struct StepOpts { double dt, inv_dtau, tol_pseudo, tol_res, tol_abs; int krylov, max_lin_it, max_newton, jac_lag, precond; };
 struct StepStats { int newton_its, gmres_its, converged; double res0, res_final; };
 
 // Sec. 3.2 Eq. (unsteady_pre_discretized_3):
@@ -730,6 +805,8 @@ static int bdf2_step(const Ctx& c, double* q, const double* q_nm1, const StepOpt
     qc_field(q, Qn);
     if (q_nm1) qc_field(q_nm1, Qnm1); else Qnm1.assign(N, 0.0);
     std::vector<double> blk((size_t)E * nb * nb); std::vector<int> piv((size_t)E * nb);
+    int ncol = 0;
+    const std::vector<int> col = colour_elements(c, ncol);
     st = StepStats{0, 0, 0, 0.0, 0.0};
     // time-term matrices at the current iterate: Gamma/dtau + ct M per solution point
     auto time_mat = [&](const double* qq, int e, int s, double T4[4][4]) {
@@ -780,14 +857,7 @@ static int bdf2_step(const Ctx& c, double* q, const double* q_nm1, const StepOpt
                     }
                 }
         };
-        auto Pop = [&](const double* v, double* out) {
-            std::vector<double> tmp(nb);
-            for (int e = 0; e < E; ++e) {
-                for (int r = 0; r < 4; ++r) for (int s = 0; s < Np; ++s) tmp[r * Np + s] = v[((size_t)r * E + e) * Np + s];
-                lu_solve(nb, blk.data() + (size_t)e * nb * nb, piv.data() + (size_t)e * nb, tmp.data());
-                for (int r = 0; r < 4; ++r) for (int s = 0; s < Np; ++s) out[((size_t)r * E + e) * Np + s] = tmp[r * Np + s];
-            }
-        };
+        auto Pop = [&](const double* v, double* out) { precond_apply(c, o.precond, col, ncol, blk, piv, Aop, v, out); };
         GmresOut go = gmres(N, Aop, Pop, b.data(), dq.data(), o.krylov, o.tol_res, o.max_lin_it);
         st.gmres_its += go.its;
         for (size_t i = 0; i < N; ++i) q[i] += dq[i];
@@ -797,7 +867,7 @@ static int bdf2_step(const Ctx& c, double* q, const double* q_nm1, const StepOpt
 }
 
 // ---------------------------------------------------------------- steady pseudo-transient continuation
-struct SteadyOpts { double dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs; int krylov, max_lin_it, max_steps, jac_lag; };
+struct SteadyOpts { double dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs; int krylov, max_lin_it, max_steps, jac_lag, precond; };
 
 // Sec. 3.2 Eq. (steady_pre_discretized_1): (Gamma^m/dtau - dR/dq^m) dq^m = R^m, backward Euler
 // in pseudo time linearised about q^m, with dtau from Eq. (SER): the step size used at pseudo-step
@@ -811,6 +881,8 @@ static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats&
     NSPhys ph{&c};
     std::vector<double> R(N), dq(N);
     std::vector<double> blk((size_t)E * nb * nb); std::vector<int> piv((size_t)E * nb);
+    int ncol = 0;
+    const std::vector<int> col = colour_elements(c, ncol);
     st = StepStats{0, 0, 0, 0.0, 0.0};
     double dtau = o.dtau0, res_prev = 0.0;
     auto gamma_pt = [&](const double* qq, int e, int s, double G[4][4]) {
@@ -861,14 +933,7 @@ static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats&
                     }
                 }
         };
-        auto Pop = [&](const double* v, double* out) {
-            std::vector<double> tmp(nb);
-            for (int e = 0; e < E; ++e) {
-                for (int r = 0; r < 4; ++r) for (int s = 0; s < Np; ++s) tmp[r * Np + s] = v[((size_t)r * E + e) * Np + s];
-                lu_solve(nb, blk.data() + (size_t)e * nb * nb, piv.data() + (size_t)e * nb, tmp.data());
-                for (int r = 0; r < 4; ++r) for (int s = 0; s < Np; ++s) out[((size_t)r * E + e) * Np + s] = tmp[r * Np + s];
-            }
-        };
+        auto Pop = [&](const double* v, double* out) { precond_apply(c, o.precond, col, ncol, blk, piv, Aop, v, out); };
         GmresOut go = gmres(N, Aop, Pop, R.data(), dq.data(), o.krylov, o.tol_res, o.max_lin_it);
         st.gmres_its += go.its;
         for (size_t i = 0; i < N; ++i) q[i] += dq[i];
@@ -1087,12 +1152,12 @@ int ora_gmres_dense(int n, const double* A, const double* Pinv, const double* b,
 }
 
 // One BDF2 (or BDF1 when q_nm1 == NULL) dual-time Newton step; q updated in place.
-// dopt: dt, inv_dtau, tol_pseudo, tol_res, tol_abs; iopt: krylov, max_lin_it, max_newton, jac_lag
+// dopt: dt, inv_dtau, tol_pseudo, tol_res, tol_abs; iopt: krylov, max_lin_it, max_newton, jac_lag, precond
 // istat: newton_its, gmres_its, converged; dstat: res0, res_final
 int ora_bdf2_step(void* h, double* q, const double* q_nm1, const double* dopt, const int* iopt,
                   int* istat, double* dstat) {
     Ctx& c = *(Ctx*)h;
-    StepOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], iopt[0], iopt[1], iopt[2], iopt[3]};
+    StepOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], iopt[0], iopt[1], iopt[2], iopt[3], iopt[4]};
     StepStats st;
     int rc = bdf2_step(c, q, q_nm1, o, st);
     istat[0] = st.newton_its; istat[1] = st.gmres_its; istat[2] = st.converged;
@@ -1102,13 +1167,14 @@ int ora_bdf2_step(void* h, double* q, const double* q_nm1, const double* dopt, c
 
 // Steady pseudo-transient continuation with SER; q updated in place.
 // dopt: dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs;
-// iopt: krylov, max_lin_it, max_steps, jac_lag
+// iopt: krylov, max_lin_it, max_steps, jac_lag, precond
 // istat: steps, gmres_its, converged; dstat: res0, res_final, dtau of the last step taken;
 // hist (length 2 * (max_steps + 1), may be null): Res_m, dtau_m of every step taken
 int ora_steady_solve(void* h, double* q, const double* dopt, const int* iopt, int* istat, double* dstat,
                      double* hist) {
     Ctx& c = *(Ctx*)h;
-    SteadyOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], dopt[5], dopt[6], iopt[0], iopt[1], iopt[2], iopt[3]};
+    SteadyOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], dopt[5], dopt[6], iopt[0], iopt[1], iopt[2], iopt[3],
+                 iopt[4]};
     StepStats st;
     double dtf = 0.0;
     std::vector<double> hv;
@@ -1117,6 +1183,56 @@ int ora_steady_solve(void* h, double* q, const double* dopt, const int* iopt, in
     dstat[0] = st.res0; dstat[1] = st.res_final; dstat[2] = dtf;
     if (hist) std::copy(hv.begin(), hv.end(), hist);
     return rc;
+}
+
+// z = P^-1 r for the Newton operator A v = inv_dtau Gamma v + c_time M v - J v at q:
+// precond 0 block Jacobi, 1 symmetric block Gauss-Seidel in colour order.  colours (may be
+// null) receives the element colours.
+int ora_precond_apply(void* h, const double* q, double c_time, double inv_dtau, int precond, const double* r,
+                      double* z, int* colours) {
+    Ctx& c = *(Ctx*)h;
+    const int Np = c.Np, E = c.E, nb = 4 * Np;
+    const size_t N = (size_t)4 * E * Np;
+    NSPhys ph{&c};
+    auto time_mat = [&](int e, int s, double T4[4][4]) {
+        double qs[4]; for (int v = 0; v < 4; ++v) qs[v] = q[((size_t)v * E + e) * Np + s];
+        double M[4][4], G[4][4]; mat_M(c, qs, M);
+        const size_t id = (size_t)e * Np + s;
+        mat_Gamma(c, qs, c.ugs[id], c.vgs[id], G);
+        for (int a = 0; a < 4; ++a) for (int k = 0; k < 4; ++k) T4[a][k] = inv_dtau * G[a][k] + c_time * M[a][k];
+    };
+    std::vector<double> blk((size_t)E * nb * nb); std::vector<int> piv((size_t)E * nb);
+    Traces<cplx> trz;
+    std::vector<cplx> qz(q, q + N);
+    compute_traces(c, ph, qz.data(), trz);
+    for (int e = 0; e < E; ++e) {
+        double* B = blk.data() + (size_t)e * nb * nb;
+        element_block_cs(c, q, trz, e, B);
+        for (int a = 0; a < nb * nb; ++a) B[a] = -B[a];
+        for (int s = 0; s < Np; ++s) {
+            double T4[4][4]; time_mat(e, s, T4);
+            for (int a = 0; a < 4; ++a) for (int k = 0; k < 4; ++k) B[(size_t)(a * Np + s) * nb + k * Np + s] += T4[a][k];
+        }
+        if (lu_factor(nb, B, piv.data() + (size_t)e * nb) != 0) return -5;
+    }
+    auto Aop = [&](const double* v, double* out) {
+        jvp_cs(c, q, v, out);
+        for (int e = 0; e < E; ++e)
+            for (int s = 0; s < Np; ++s) {
+                double T4[4][4]; time_mat(e, s, T4);
+                for (int a = 0; a < 4; ++a) {
+                    double t = 0.0;
+                    for (int k = 0; k < 4; ++k) t += T4[a][k] * v[((size_t)k * E + e) * Np + s];
+                    const size_t id = ((size_t)a * E + e) * Np + s;
+                    out[id] = t - out[id];
+                }
+            }
+    };
+    int ncol = 0;
+    const std::vector<int> col = colour_elements(c, ncol);
+    if (colours) std::copy(col.begin(), col.end(), colours);
+    precond_apply(c, precond, col, ncol, blk, piv, Aop, r, z);
+    return 0;
 }
 
 }  // extern "C"

@@ -41,7 +41,7 @@ def lib():
         L.ora_create.restype = ctypes.c_void_p
         L.ora_destroy.argtypes = [ctypes.c_void_p]
         for name in ["ora_residual", "ora_jvp", "ora_dense_jacobian", "ora_vjp_dofs", "ora_blocks",
-                     "ora_point", "ora_common_flux", "ora_phys_flux", "ora_bdf2_step", "ora_steady_solve",
+                     "ora_point", "ora_common_flux", "ora_phys_flux", "ora_bdf2_step", "ora_steady_solve", "ora_precond_apply",
                      "ora_geometry", "ora_scalar_residual", "ora_residual_cplx", "ora_cons_cplx"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -218,11 +218,11 @@ class Oracle:
         return f, g
 
     def bdf2_step(self, q, q_nm1, dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=100,
-                  max_newton=100, jac_lag=2, inv_dtau=1e-20, tol_abs=0.0):
+                  max_newton=100, jac_lag=2, inv_dtau=1e-20, tol_abs=0.0, precond=0):
         q = np.array(self._state(q), copy=True)
         qn1 = None if q_nm1 is None else self._state(q_nm1)
         d = np.array([dt, inv_dtau, tol_pseudo, tol_res, tol_abs], dtype=np.float64)
-        i = np.array([krylov, max_lin_it, max_newton, jac_lag], dtype=np.int32)
+        i = np.array([krylov, max_lin_it, max_newton, jac_lag, precond], dtype=np.int32)
         ist = np.zeros(3, dtype=np.int32)
         dst = np.zeros(2)
         rc = lib().ora_bdf2_step(self.h, _p(q), _p(qn1), _p(d), _p(i, _ip), _p(ist, _ip), _p(dst))
@@ -231,12 +231,12 @@ class Oracle:
         return q, stats
 
     def steady_solve(self, q, dtau0=0.01, dtau_min=0.01, dtau_max=1e20, r_ser=2.0, tol_pseudo=1e-8,
-                     tol_res=1e-6, tol_abs=0.0, krylov=30, max_lin_it=200, max_steps=100, jac_lag=1):
+                     tol_res=1e-6, tol_abs=0.0, krylov=30, max_lin_it=200, max_steps=100, jac_lag=1, precond=0):
         """Steady pseudo-transient continuation with SER (Sec. 3.2): returns the final state and
         stats, with hist = [(Res_m, dtau_m)] of every pseudo-step taken."""
         q = np.array(self._state(q), copy=True)
         d = np.array([dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs], dtype=np.float64)
-        i = np.array([krylov, max_lin_it, max_steps, jac_lag], dtype=np.int32)
+        i = np.array([krylov, max_lin_it, max_steps, jac_lag, precond], dtype=np.int32)
         ist = np.zeros(3, dtype=np.int32)
         dst = np.zeros(3)
         hist = np.zeros(2 * (max_steps + 1))
@@ -246,3 +246,16 @@ class Oracle:
                      res_final=float(dst[1]), dtau_final=float(dst[2]),
                      hist=[(float(hist[2 * k]), float(hist[2 * k + 1])) for k in range(n)])
         return q, stats
+
+    def precond_apply(self, q, r, c_time, inv_dtau, precond=1):
+        """z = P^-1 r for the Newton operator at q (precond 0: block Jacobi, 1: symmetric block
+        Gauss-Seidel in colour order); returns (z, element colours)."""
+        q = self._state(q)
+        r = self._state(r)
+        z = np.zeros_like(q)
+        col = np.zeros(self.prm.n_elem, dtype=np.int32)
+        rc = lib().ora_precond_apply(self.h, _p(q), ctypes.c_double(c_time), ctypes.c_double(inv_dtau), int(precond),
+                                     _p(r), _p(z), _p(col, _ip))
+        if rc != 0:
+            raise RuntimeError(f"ora_precond_apply failed: {rc}")
+        return z, col
