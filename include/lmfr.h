@@ -69,7 +69,7 @@ typedef struct {
     double tol_pseudo;    /* stop when Res_m / Res_0 <= tol_pseudo (mass-row 2-norm) */
     double tol_res;       /* GMRES relative tolerance ||b - A x|| <= tol_res ||b|| */
     double tol_abs;       /* also stop when Res_m <= tol_abs (round-off floor) */
-    int32_t krylov;       /* restart length m */
+    int32_t krylov;       /* restart length m, 1..156 */
     int32_t max_lin_it;   /* GMRES iteration cap per Newton step */
     int32_t max_newton;   /* Newton (pseudo-time) iteration cap */
     int32_t jac_lag;      /* refresh the block-Jacobi blocks when m % jac_lag == 0 */
@@ -80,6 +80,29 @@ typedef struct {
     int32_t newton_its, gmres_its, converged;
     double res0, res_final;
 } fr_step_stats;
+
+/* Options of a steady solve by pseudo-transient continuation (paper Sec. 3.2,
+ * Eq. steady_pre_discretized_1, with the pseudo-time step of Eq. SER).  The paper's
+ * defaults: dtau0 = dtau_min = 0.01, dtau_max = 1e20, r_ser = 2. */
+typedef struct {
+    double dtau0;         /* pseudo-time step of the first iteration */
+    double dtau_min, dtau_max;   /* SER bounds of the pseudo-time step */
+    double r_ser;         /* SER exponent: dtau_m = dtau_{m-1} (Res_{m-1}/Res_m)^r_ser, clipped */
+    double tol_pseudo;    /* stop when Res_m / Res_0 <= tol_pseudo (continuity-row 2-norm of R) */
+    double tol_res;       /* GMRES relative tolerance of each linear solve */
+    double tol_abs;       /* also stop when Res_m <= tol_abs (round-off floor) */
+    int32_t krylov;       /* restart length m, 1..156 (paper: 150 for steady problems) */
+    int32_t max_lin_it;   /* GMRES iteration cap per pseudo-time step */
+    int32_t max_steps;    /* pseudo-time step cap */
+    int32_t jac_lag;      /* refresh the block-Jacobi blocks when m % jac_lag == 0 (paper: 1) */
+    int32_t prec;         /* fr_prec of the stored preconditioner blocks */
+} fr_steady_opts;
+
+typedef struct {
+    int32_t steps, gmres_its, converged;
+    double res0, res_final;
+    double dtau_final;    /* pseudo-time step of the last step taken */
+} fr_steady_stats;
 
 /* Create a context for one mesh.  h_nbr/h_nbr_face/h_flip are HOST arrays [n_elem][4]:
  * neighbour element, neighbour's local face and point-order reversal (NULL = none)
@@ -130,7 +153,10 @@ fr_status fr_bdf_operator(fr_ctx ctx, const double* q, const double* v, double c
 fr_status fr_block_jacobi_factor(fr_ctx ctx, const double* q, double c_time, double inv_dtau,
                                  int32_t prec, void* stream);
 
-/* z = P^-1 r with the last factored blocks; r, z [4][E][Np] (may not alias). */
+/* z = P^-1 r with the last factored blocks; r, z [4][E][Np] (may not alias).  With the
+ * option "preconditioner" = 1, P is the symmetric block Gauss-Seidel preconditioner of the
+ * operator the last fr_block_jacobi_factor linearised (its q, c_time and inv_dtau; a later
+ * fr_bdf_operator with "operator_packs" replaces that linearisation). */
 fr_status fr_block_jacobi_apply(fr_ctx ctx, const double* r, double* z, void* stream);
 
 /* Copy the assembled (unfactored) FP64 blocks of the last fr_block_jacobi_factor to
@@ -147,14 +173,31 @@ fr_status fr_get_blocks(fr_ctx ctx, double* blk, void* stream);
 fr_status fr_bdf2_step(fr_ctx ctx, double* q, const double* q_nm1, const fr_step_opts* opts,
                        fr_step_stats* h_stats, void* stream);
 
+/* Steady solve by pseudo-transient continuation (paper Sec. 3.2): from q (DEVICE
+ * [4][E][Np], updated in place), repeat (Gamma^m/dtau_m - dR/dq^m) dq = R^m, q += dq,
+ * with dtau_m from the SER rule (Eq. SER; dtau0 at m = 0, then the previous step times
+ * (Res_{m-1}/Res_m)^r_ser, clipped to [dtau_min, dtau_max]), until Res_m/Res_0 <=
+ * tol_pseudo or Res_m <= tol_abs.  Each linear system is solved by the same restarted
+ * right-preconditioned FP64 GMRES and element-block-Jacobi preconditioner as the BDF2
+ * step.  Synchronises once per GMRES restart cycle and pseudo-time step.  h_stats: HOST,
+ * may be NULL.  Returns FR_ENOCONV (state still updated) when max_steps is reached. */
+fr_status fr_steady_solve(fr_ctx ctx, double* q, const fr_steady_opts* opts, fr_steady_stats* h_stats,
+                          void* stream);
+
 /* Options: "keep_blocks" (0/1: keep the FP64 blocks for fr_get_blocks), "graph" (0/1:
  * replay each GMRES restart cycle from a captured hipGraph, default 1), "gram_schmidt"
  * (1: classical Gram-Schmidt, one orthogonalisation pass per Arnoldi step, the default;
  * 2: with one re-orthogonalisation pass), "operator_packs" (0/1: fr_bdf_operator first
  * stores the values its nonlinear point functions need at q, then applies the operator
  * on tangents only -- the form the BDF2 step uses inside GMRES; fr_block_jacobi_factor
- * assembles its block columns the same way; same results to rounding), and a manual
- * launch shape of the fused kernels (what fr_autotune chooses): "tile_lanes" (0 =
+ * assembles its block columns the same way; same results to rounding), "preconditioner"
+ * (0: element-block Jacobi, the default; 1: symmetric block Gauss-Seidel over the
+ * elements in colour order, P = (D + L) D^-1 (D + U) with D the element blocks and L / U
+ * the couplings of the Newton operator to elements of lower / higher colour -- colours
+ * from fr_create, the smallest colour no face neighbour has, in element order; each
+ * application costs 2 (K - 1) operator applications for K colours, 2 on even periodic
+ * meshes; used by fr_block_jacobi_apply and the GMRES of the BDF2 and steady solves),
+ * and a manual launch shape of the fused kernels (what fr_autotune chooses): "tile_lanes" (0 =
  * default, 64, 128, 256; dual-number modes cap it at 128), "tile_grid" (0 = one
  * workgroup per tile, else the persistent grid size), "tile_xcd" (1 = each XCD walks a
  * contiguous eighth of the tiles, 0 = round robin). */
@@ -203,8 +246,15 @@ fr_status fr_batch_jvp(fr_batch batch, const double* q, const double* v, double*
 fr_status fr_batch_bdf2_step(fr_batch batch, double* const* q, const double* const* q_nm1,
                              const fr_step_opts* opts, fr_step_stats* h_stats, void* stream);
 
-/* Options: "graph", "gram_schmidt" and the "tile_*" launch-shape options, as for a
- * context. */
+/* Steady solve of every case (paper Sec. 3.2, as fr_steady_solve): q[c] DEVICE
+ * [4][E_c][Np_c], updated in place; opts[c] per-case pseudo-time steps and tolerances;
+ * krylov, max_lin_it, max_steps, jac_lag and prec must agree across the batch.  Each case
+ * keeps its own SER step and convergence.  h_stats: HOST [n] or NULL. */
+fr_status fr_batch_steady_solve(fr_batch batch, double* const* q, const fr_steady_opts* opts,
+                                fr_steady_stats* h_stats, void* stream);
+
+/* Options: "graph", "gram_schmidt", "preconditioner" and the "tile_*" launch-shape
+ * options, as for a context. */
 fr_status fr_batch_set_option(fr_batch batch, const char* name, int64_t value);
 
 /* fr_autotune for every launch group of the batch. */

@@ -168,8 +168,24 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
             if (nb == e && nf == f) return bad("fr_create: a face cannot neighbour itself");
             packed[(size_t)e * 4 + f] = nb * 8 + nf * 2 + fl;
         }
+    // colours of the Gauss-Seidel sweeps: in element order, the smallest colour no face
+    // neighbour has yet (a checkerboard on even periodic meshes; at most 5 colours)
+    std::vector<int32_t> colour((size_t)E, -1);
+    int ncol = 0;
+    for (int e = 0; e < E; ++e) {
+        bool used[5] = {false, false, false, false, false};
+        for (int f = 0; f < 4; ++f) {
+            const int nb = h_nbr[e * 4 + f];
+            if (nb != e && colour[nb] >= 0) used[colour[nb]] = true;
+        }
+        int k = 0;
+        while (used[k]) ++k;
+        colour[e] = k;
+        ncol = k + 1 > ncol ? k + 1 : ncol;
+    }
     fr_ctx c = new fr_ctx_s();
     c->prm = *prm;
+    c->ncolors = ncol;
     c->p = prm->order; c->n = c->p + 1; c->Np = c->n * c->n;
     c->pg = prm->geom_order; c->m = c->pg + 1; c->E = E;
     const double g = prm->gamma, Ma = prm->mach_ref;
@@ -193,12 +209,14 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         (st = dalloc(&c->d_gsp, NGSP * EN)) != FR_OK ||
         (st = dalloc(&c->d_gfp, NGFP * FE)) != FR_OK ||
         (st = dalloc(&c->d_aff, (size_t)E)) != FR_OK ||
+        (st = dalloc(&c->d_color, (size_t)E)) != FR_OK ||
         (st = dalloc(&c->d_trace, FE * 10)) != FR_OK ||
         (st = dalloc(&c->d_vj, FE * 10)) != FR_OK) {
         fr_destroy(c);
         return st;
     }
-    if (hipMemcpy(c->d_nbr, packed.data(), packed.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(c->d_nbr, packed.data(), packed.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_color, colour.data(), colour.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
         fr_destroy(c);
         fr_set_error("copy of the neighbour table failed");
         return FR_EHIP;
@@ -215,7 +233,8 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
 extern "C" void fr_destroy(fr_ctx c) {
     if (!c) return;
     if (c->self) { solver_free(*c->self); delete c->self; }
-    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_aff); dfree(c->d_trace); dfree(c->d_vj);
+    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_aff); dfree(c->d_color); dfree(c->d_trace);
+    dfree(c->d_vj);
     delete c;
 }
 
@@ -233,6 +252,17 @@ static fr_status solver_option(Solver& sv, const char* name, int64_t value) {
     if (!strcmp(name, "gram_schmidt")) {
         if (value != 1 && value != 2) return bad("gram_schmidt must be 1 or 2");
         sv.gs_passes = (int)value;
+        gmres_release(sv);
+        return FR_OK;
+    }
+    if (!strcmp(name, "preconditioner")) {
+        if (value != 0 && value != 1) return bad("preconditioner must be 0 (block Jacobi) or 1 (block Gauss-Seidel)");
+        if (value == 1) {   // the sweeps apply the Newton operator through the linearisation packs
+            FR_TRY(dalloc(&sv.d_fpack, sv.fpack_len));
+            FR_TRY(dalloc(&sv.d_spack, sv.spack_len));
+            FR_TRY(dalloc(&sv.d_rscratch, sv.Ntot));
+        }
+        sv.precond = (int)value;
         gmres_release(sv);
         return FR_OK;
     }
@@ -338,7 +368,8 @@ extern "C" fr_status fr_block_jacobi_factor(fr_ctx c, const double* q, double c_
     FR_TRY(solver_ensure_blocks(sv));
     KArgs a{};
     a.c_time = c_time; a.inv_dtau = inv_dtau;
-    if (sv.op_packs) {
+    sv.f_ct = c_time; sv.f_idt = inv_dtau;
+    if (sv.op_packs || sv.precond == 1) {
         // linearisation packs of q, then tangent-only block columns
         KArgs p = plain_args(q, nullptr, sv.d_rscratch, nullptr);
         p.fpack = sv.d_fpack; p.spack = sv.d_spack;
@@ -365,7 +396,11 @@ extern "C" fr_status fr_block_jacobi_apply(fr_ctx c, const double* r, double* z,
     FR_TRY(ready(c));
     if (!r || !z) return bad("fr_block_jacobi_apply: null argument");
     if (r == z) return bad("fr_block_jacobi_apply: r and z may not alias");
-    return launch_block_apply(*c->self, r, z, nullptr, 0, (hipStream_t)stream);
+    Solver& sv = *c->self;
+    KArgs op{};   // the Newton operator of the last factor (its packs, time coefficients)
+    op.c_time = sv.f_ct; op.inv_dtau = sv.f_idt;
+    op.fpack = sv.d_fpack; op.spack = sv.d_spack;
+    return precond_apply(sv, r, z, op, nullptr, 0, (hipStream_t)stream);
 }
 
 // blocks as assembled (column-major per element) -> caller's array row-major
@@ -412,6 +447,14 @@ extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q_io, const double* q_nm1, c
     double* qs[1] = {q_io};
     const double* qm[1] = {q_nm1};
     return solver_step(*c->self, qs, qm, o, h_stats, (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_steady_solve(fr_ctx c, double* q_io, const fr_steady_opts* o, fr_steady_stats* h_stats,
+                                     void* stream) {
+    FR_TRY(ready(c));
+    if (!q_io || !o) return bad("fr_steady_solve: null argument");
+    double* qs[1] = {q_io};
+    return solver_steady(*c->self, qs, o, h_stats, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_autotune(fr_ctx c, const char* cache_path, void* stream) {
@@ -477,6 +520,13 @@ extern "C" fr_status fr_batch_bdf2_step(fr_batch b, double* const* q, const doub
     FR_TRY(batch_ready(b));
     if (!q || !opts) return bad("fr_batch_bdf2_step: null argument");
     return solver_step(b->sv, q, q_nm1, opts, h_stats, (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_batch_steady_solve(fr_batch b, double* const* q, const fr_steady_opts* opts,
+                                           fr_steady_stats* h_stats, void* stream) {
+    FR_TRY(batch_ready(b));
+    if (!q || !opts) return bad("fr_batch_steady_solve: null argument");
+    return solver_steady(b->sv, q, opts, h_stats, (hipStream_t)stream);
 }
 
 extern "C" fr_status fr_batch_set_option(fr_batch b, const char* name, int64_t value) {

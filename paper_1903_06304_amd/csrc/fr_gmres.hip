@@ -46,7 +46,7 @@ struct Ctl {
     double* gs;
     int gs_stride;
     int* gi;
-    const CaseStep* step;
+    CaseStep* step;   // written only by the Newton check (SER)
     double* sum;
     int n;
 };
@@ -209,7 +209,8 @@ __global__ void k_scale_case(Vec vc, const double* __restrict__ in, double* __re
     }
 }
 
-// out = sum_{i < cyc_c} y_c[i] V_i
+// out = sum_{i < cyc_c} y_c[i] V_i (launched with 256 threads: one per coefficient)
+static_assert(MAXV <= 256, "k_combine_case stages one coefficient per thread");
 __global__ void k_combine_case(Vec vc, const double* __restrict__ V, size_t ldv, const double* gs, int stride,
                                int yfield, double* __restrict__ out) {
     __shared__ double y[MAXV];
@@ -244,10 +245,16 @@ Vec vec(const Solver& sv, int flag) { return Vec{sv.d_chunk_case, sv.nchunks, sv
 double* wv(const Solver& sv, int i) { return sv.d_w + (size_t)i * sv.Ntot; }
 
 // Newton operator at the iterate whose linearisation packs the Newton loop has written
-fr_status bdf_op(const Solver& sv, const double* q, const double* v, double* Av, int flag, hipStream_t s) {
+KArgs bdf_args(const Solver& sv, const double* q) {
     KArgs a{};
-    a.q = q; a.v = v; a.out = Av; a.cstep = sv.d_step; a.flags = sv.d_gi; a.flag = flag;
+    a.q = q; a.cstep = sv.d_step; a.flags = sv.d_gi;
     a.fpack = sv.d_fpack; a.spack = sv.d_spack;
+    return a;
+}
+
+fr_status bdf_op(const Solver& sv, const double* q, const double* v, double* Av, int flag, hipStream_t s) {
+    KArgs a = bdf_args(sv, q);
+    a.v = v; a.out = Av; a.flag = flag;
     return solver_fused(sv, MODE_LIN, a, s);
 }
 
@@ -271,7 +278,7 @@ fr_status enqueue_cycle(Solver& sv, int m, hipStream_t s) {
     FR_HIP(hipGetLastError());
     for (int j = 0; j < m; ++j) {
         double* vj = V + (size_t)j * N;
-        FR_TRY(launch_block_apply(sv, vj, z, sv.d_gi, GI_DONE, s));
+        FR_TRY(precond_apply(sv, vj, z, bdf_args(sv, q), sv.d_gi, GI_DONE, s));
         FR_TRY(bdf_op(sv, q, z, w, GI_DONE, s));
         // classical Gram-Schmidt: h = V^T w, w -= V h (and once more when re-orthogonalising)
         FR_TRY(la_krylov(sv, V, N, 0, nullptr, 0, j + 1, w, nullptr, false, false, gs + L.H1, gst, sv.d_gi, GI_DONE, s));
@@ -296,7 +303,7 @@ fr_status enqueue_cycle(Solver& sv, int m, hipStream_t s) {
     FR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_combine_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_IDLE), V, N, gs, gst, L.Y, w);
     FR_HIP(hipGetLastError());
-    FR_TRY(launch_block_apply(sv, w, z, sv.d_gi, GI_IDLE, s));
+    FR_TRY(precond_apply(sv, w, z, bdf_args(sv, q), sv.d_gi, GI_IDLE, s));
     hipLaunchKernelGGL(k_add, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_IDLE), z, x);
     FR_HIP(hipGetLastError());
     FR_TRY(bdf_op(sv, q, x, w, GI_IDLE, s));
@@ -318,7 +325,9 @@ __global__ void k_step_init(Ctl k) {
     for (int f = 0; f < SUM_STRIDE; ++f) s[f] = 0.0;
 }
 
-// per case: Newton test on the mass-row norm of b (in the NRM slot)
+// per case: Newton test on the mass-row norm of b (in the NRM slot).  With SER (steady
+// solves, paper Eq. SER) the pseudo-time step of this iteration follows from the previous
+// one and the residual ratio Res_{m-1}/Res_m, clipped to [dtau_min, dtau_max].
 __global__ void k_newton_check(Ctl k, int m, int it) {
     const int c = case_index();
     if (c >= k.n) return;
@@ -330,10 +339,19 @@ __global__ void k_newton_check(Ctl k, int m, int it) {
     if (it == 0) s[S_RES0] = rr;
     s[S_RES] = rr;
     s[S_NEWTON] = it;
-    const CaseStep& st = k.step[c];
+    CaseStep& st = k.step[c];
     if (!isfinite(rr)) { gi[GI_STATUS] = 1; gi[GI_NDONE] = 1; return; }
     if (rr <= st.tol_abs || rr <= st.tol_pseudo * s[S_RES0]) { gi[GI_CONV] = 1; gi[GI_NDONE] = 1; return; }
-    if (it >= st.max_newton) { gi[GI_STATUS] = 2; gi[GI_NDONE] = 1; }
+    if (it >= st.max_newton) { gi[GI_STATUS] = 2; gi[GI_NDONE] = 1; return; }
+    if (st.ser) {
+        if (it > 0) {
+            const double d = st.dtau * pow(st.res_prev / rr, st.r_ser);
+            st.dtau = fmax(st.dtau_min, fmin(st.dtau_max, d));
+            st.idt = 1.0 / st.dtau;
+        }
+        st.res_prev = rr;
+        s[S_DTAU] = st.dtau;
+    }
 }
 
 // a singular block (status 3) takes its case out of the iteration; flags to the summary
@@ -384,11 +402,17 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_norm0, dim3(cgrid(sv)), dim3(64), 0, s, k, m);
     FR_HIP(hipGetLastError());
 
+    if (sv.precond == 1) {   // the sweeps' work vectors exist before any capture
+        FR_TRY(dalloc(&sv.d_gsu, sv.Ntot));
+        FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
+    }
     const bool graph = sv.use_graph;
-    if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec || sv.graph_passes != sv.gs_passes)) {
+    if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec || sv.graph_passes != sv.gs_passes ||
+                  sv.graph_precond != sv.precond)) {
         gmres_release(sv);
         // capture one cycle (all buffers are solver-owned; tolerances, time coefficients and
-        // caps are read on the device, so the graph depends on m and the block precision only)
+        // caps are read on the device, so the graph depends on m, the block precision, the
+        // Gram-Schmidt passes and the preconditioner only)
         hipGraph_t gr;
         FR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         fr_status cst = enqueue_cycle(sv, m, s);
@@ -403,6 +427,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
         sv.graph_m = m;
         sv.graph_prec = prec;
         sv.graph_passes = sv.gs_passes;
+        sv.graph_precond = sv.precond;
     }
     double* hs = sv.h_pin;
     for (;;) {

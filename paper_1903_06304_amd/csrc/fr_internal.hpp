@@ -38,6 +38,7 @@ struct Geo {
     const double* fp;     // [NGFP][E][4n]
     const int32_t* nbr;   // [E][4]: nb*8 + nb_face*2 + flip
     const int32_t* aff;   // [E]: 1 when the element's metrics are constant (affine map)
+    const int32_t* color; // [E]: element colour of the Gauss-Seidel sweeps (no face neighbour shares it)
 };
 
 // R; exact JVP; Newton operator; one seeded block column; R plus the linearisation packs;
@@ -66,18 +67,21 @@ struct CaseDev {
     PhysConst pc;
 };
 
-// Per-case scalars of one dual-time step (written by the host before the step).
+// Per-case scalars of one dual-time step or steady solve (written by the host before it;
+// with SER the Newton check updates dtau, idt and res_prev on the device).
 struct CaseStep {
     double ct, idt;             // c_time (a0/dt) and inv_dtau of the Newton operator
     double inv_dt, a0, a1, a2;  // BDF coefficients: a0 q^c(q) + a1 Q^n + a2 Q^{n-1}
     double tol_res, tol_pseudo, tol_abs;
-    int has_nm1, max_newton;
+    double dtau, dtau_min, dtau_max, r_ser, res_prev;   // SER pseudo-time step control
+    int has_nm1, max_newton, ser;
 };
 
 // per-case summary published to the host: sum[case * SUM_STRIDE + field]
 enum { S_BN = 0, S_BETA, S_TOTAL, S_MORE,      // GMRES: |b|, |r|, iterations, wants another cycle
        S_RES0, S_RES, S_NEWTON, S_GMRES,       // Newton: Res_0, Res_m, iterations, GMRES iterations
-       S_NDONE, S_CONV, S_STATUS, SUM_STRIDE = 16 };
+       S_NDONE, S_CONV, S_STATUS, S_DTAU,      // flags, status, last pseudo-time step (SER)
+       SUM_STRIDE = 16 };
 
 // work vectors of a step inside Solver::d_w
 enum { WB = 0, WR, WQN, WQNM1, WRES, WW, WZ, WDQ, NWORK };
@@ -159,6 +163,8 @@ struct fr_ctx_s {
     double* d_gsp = nullptr;        // [NGSP][E][Np]
     double* d_gfp = nullptr;        // [NGFP][E][4n]
     int32_t* d_aff = nullptr;       // [E] affine-element flags
+    int32_t* d_color = nullptr;     // [E] element colours
+    int ncolors = 0;
     double* d_trace = nullptr;      // neighbour traces (adjoint path)
     double* d_vj = nullptr;         // adjoint trace buffer
     Solver* self = nullptr;         // one-case solver of the context's own entry points
@@ -184,6 +190,11 @@ struct Solver {
     int inv_prec = -1;
     bool keep_blocks = false;
     double* d_blk_keep = nullptr;
+    int precond = 0;                       // 0: element-block Jacobi, 1: symmetric block Gauss-Seidel
+    int ncolors = 1;                       // colours of the sweeps (max over the cases)
+    double* d_gsu = nullptr;               // Gauss-Seidel work vectors [Ntot] x 2
+    double* d_gst = nullptr;
+    double f_ct = 0.0, f_idt = 0.0;        // time coefficients of the last context-level factor
     // step workspace
     int kry_m = 0;
     double* d_q = nullptr;                 // Newton iterate
@@ -206,7 +217,7 @@ struct Solver {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     bool use_graph = true;
     void* graph_exec = nullptr;
-    int graph_m = 0, graph_prec = -1, graph_passes = 0;
+    int graph_m = 0, graph_prec = -1, graph_passes = 0, graph_precond = -1;
     int gs_passes = 1;                     // classical Gram-Schmidt passes per Arnoldi step (1 or 2)
     size_t N(int c) const { return (size_t)4 * cs[c]->E * cs[c]->Np; }
 };
@@ -216,7 +227,7 @@ struct fr_batch_s {
 };
 
 constexpr int CHUNK = 4096;   // alignment of case vectors; unit of the segmented reductions
-constexpr int MAXV = 64;      // max vectors in one multi-dot
+constexpr int MAXV = 160;     // max vectors in one multi-dot: Krylov dimension up to MAXV - 4
 
 // error handling
 void fr_set_error(const std::string& s);
@@ -279,6 +290,17 @@ fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_
 fr_status launch_block_invert_p4(Solver& sv, const Group& gr, const GroupArgs& ga, int prec, const int* flags,
                                  hipStream_t s);
 fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s);
+// restricted to the elements of one colour (color >= 0; -1: all):
+//   sub = false: z_e = D_e^-1 (r_e - b_e) (b may be null);  sub = true: z_e -= D_e^-1 r_e
+fr_status launch_block_apply_ex(const Solver& sv, const double* r, const double* b, double* z, int color, bool sub,
+                                const int* flags, int flag, hipStream_t s);
+// u = z on the elements whose colour lies in [lo, hi], 0 elsewhere
+fr_status launch_color_mask(const Solver& sv, const double* z, double* u, int lo, int hi, const int* flags, int flag,
+                            hipStream_t s);
+// z = P^-1 r with the solver's preconditioner; the Gauss-Seidel sweeps apply the Newton
+// operator described by op (its v and out are set here)
+fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op, const int* flags, int flag,
+                        hipStream_t s);
 // segmented reductions over the concatenated vectors: for every case c (not skipped),
 //   w_out = w_in - sum_{i<nv_upd} coef_c[i] V_i            (coef_c = coef + c * cstride)
 //   out_c[i] = V_i . w_out (i < nv_dot), out_c[nv_dot] = |w_out|^2 (want_norm)
@@ -301,6 +323,8 @@ void gmres_release(Solver& sv);
 // summary in h_pin
 fr_status solver_newton(Solver& sv, const fr_step_opts* opts, hipStream_t s);
 // one dual-time step of every case (copies in and out of the caller's arrays)
+fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* opts, fr_steady_stats* stats,
+                        hipStream_t s);
 fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, const fr_step_opts* opts,
                       fr_step_stats* stats, hipStream_t caller);
 fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s);

@@ -216,7 +216,7 @@ k_traces(TrArgs a, OpTab op_in, Geo g) {
 template <int P, bool VISC>
 fr_status run_traces(fr_ctx c, const TrArgs& a, hipStream_t s) {
     using B = Blk<P, 1>;
-    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff};
+    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff, c->d_color};
     const int grid = (c->E + B::EPB - 1) / B::EPB;
     hipLaunchKernelGGL((k_traces<P, VISC>), dim3(grid), dim3(B::threads), 0, s, a, c->op, g);
     FR_HIP(hipGetLastError());

@@ -15,6 +15,7 @@
 namespace {
 
 constexpr int RED_THREADS = 256;
+static_assert(MAXV <= RED_THREADS, "the coefficient staging takes one thread per Krylov vector");
 constexpr int MAX_GRID = 8192;    // workgroups of the chunk-walking kernels
 
 // case of tile t of a group (binary search over the group's tile prefix); uniform
@@ -239,9 +240,13 @@ struct ApplyShape {
     static_assert(NB % RPT == 0, "block size must be a multiple of the rows per thread");
 };
 
+// z_e = D_e^-1 r_e for every element, or, for the Gauss-Seidel sweeps, for the elements of
+// one colour only (color >= 0): z_e = D_e^-1 (r_e - b_e) (b may be null), or z_e -= D_e^-1 r_e
+// (sub).  Elements of other colours read no block.
 template <class Tin, int NB>
 __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __restrict__ inv,
-                                                     const double* __restrict__ r, double* __restrict__ z,
+                                                     const double* __restrict__ r, const double* __restrict__ b,
+                                                     double* __restrict__ z, int color, int sub,
                                                      const int* __restrict__ flags, int flag) {
     using SH = ApplyShape<Tin, NB>;
     constexpr int Np = NB / 4, RPT = SH::RPT, TPE = SH::TPE, EPB = SH::EPB;
@@ -254,14 +259,14 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
     const CaseDev& cd = ga.cases[cid];
     const int el = threadIdx.x / TPE, r0 = (threadIdx.x % TPE) * RPT;
     const int e = (t - ga.pfx[lo]) * EPB + el;
-    const bool act = (el < EPB) && (e < cd.E);
+    const bool act = (el < EPB) && (e < cd.E) && (color < 0 || cd.g.color[e] == color);
     const size_t EN = (size_t)cd.E * Np;
     size_t gid[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int row = r0 + k;
         gid[k] = cd.off + (row / Np) * EN + (size_t)e * Np + (row % Np);
-        if (act) rs[el][row] = r[gid[k]];
+        if (act) rs[el][row] = b ? r[gid[k]] - b[gid[k]] : r[gid[k]];
     }
     __syncthreads();
     if (!act) return;
@@ -277,8 +282,13 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
 #pragma unroll
         for (int k = 0; k < RPT; ++k) acc[k] += x[k] * rc;
     }
+    if (sub) {
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) z[gid[k]] = acc[k];
+        for (int k = 0; k < RPT; ++k) z[gid[k]] -= acc[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) z[gid[k]] = acc[k];
+    }
 }
 
 // ------------------------------------------------------------------ segmented Krylov reductions
@@ -569,40 +579,103 @@ std::vector<int> block_apply_widths(int p) {
     return {256 / nb, 512 / nb, 1024 / nb};
 }
 
+struct ApplyArgs {
+    const double* r;
+    const double* b;
+    double* z;
+    int color;
+    int sub;
+    const int* flags;
+    int flag;
+};
+
 template <class Tin, int NB>
-static fr_status apply_as(const Solver& sv, const Group& gr, const double* r, double* z, const int* flags, int flag,
-                          hipStream_t s) {
+static fr_status apply_as(const Solver& sv, const Group& gr, const ApplyArgs& x, hipStream_t s) {
     using SH = ApplyShape<Tin, NB>;
     GroupArgs ga = group_args(sv, gr, SH::EPB);
     if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
-    hipLaunchKernelGGL((k_block_apply<Tin, NB>), dim3(ga.ntiles), dim3(SH::threads), 0, s, ga, (const Tin*)sv.d_inv, r,
-                       z, flags, flag);
+    hipLaunchKernelGGL((k_block_apply<Tin, NB>), dim3(ga.ntiles), dim3(SH::threads), 0, s, ga, (const Tin*)sv.d_inv,
+                       x.r, x.b, x.z, x.color, x.sub, x.flags, x.flag);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
 template <class Tin>
-static fr_status apply_p(const Solver& sv, const Group& gr, const double* r, double* z, const int* flags, int flag,
-                         hipStream_t s) {
+static fr_status apply_p(const Solver& sv, const Group& gr, const ApplyArgs& x, hipStream_t s) {
     switch (gr.p) {
-        case 1: return apply_as<Tin, 16>(sv, gr, r, z, flags, flag, s);
-        case 2: return apply_as<Tin, 36>(sv, gr, r, z, flags, flag, s);
-        case 3: return apply_as<Tin, 64>(sv, gr, r, z, flags, flag, s);
-        case 4: return apply_as<Tin, 100>(sv, gr, r, z, flags, flag, s);
+        case 1: return apply_as<Tin, 16>(sv, gr, x, s);
+        case 2: return apply_as<Tin, 36>(sv, gr, x, s);
+        case 3: return apply_as<Tin, 64>(sv, gr, x, s);
+        case 4: return apply_as<Tin, 100>(sv, gr, x, s);
     }
     fr_set_error("order outside 1..4");
     return FR_EUNSUPPORTED;
 }
 
-fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s) {
+fr_status launch_block_apply_ex(const Solver& sv, const double* r, const double* b, double* z, int color, bool sub,
+                                const int* flags, int flag, hipStream_t s) {
+    const ApplyArgs x{r, b, z, color, sub ? 1 : 0, flags, flag};
     for (const Group& gr : sv.groups) {
         switch (sv.inv_prec) {
-            case FR_FP64: FR_TRY(apply_p<double>(sv, gr, r, z, flags, flag, s)); break;
-            case FR_FP32: FR_TRY(apply_p<float>(sv, gr, r, z, flags, flag, s)); break;
-            case FR_BF16: FR_TRY(apply_p<uint16_t>(sv, gr, r, z, flags, flag, s)); break;
+            case FR_FP64: FR_TRY(apply_p<double>(sv, gr, x, s)); break;
+            case FR_FP32: FR_TRY(apply_p<float>(sv, gr, x, s)); break;
+            case FR_BF16: FR_TRY(apply_p<uint16_t>(sv, gr, x, s)); break;
             default: fr_set_error("preconditioner not factored"); return FR_EINVAL;
         }
+    }
+    return FR_OK;
+}
+
+fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s) {
+    return launch_block_apply_ex(sv, r, nullptr, z, -1, false, flags, flag, s);
+}
+
+// u = z on the elements whose colour lies in [lo, hi], 0 elsewhere
+__global__ void k_color_mask(ChunkArgs ca, const double* __restrict__ z, double* __restrict__ u, int lo, int hi) {
+    FR_POINT_LOOP(ca, {
+        const int col = cd.g.color[t / cd.Np];
+        const bool keep = col >= lo && col <= hi;
+        for (int v = 0; v < 4; ++v) u[base + v * EN] = keep ? z[base + v * EN] : 0.0;
+    })
+}
+
+fr_status launch_color_mask(const Solver& sv, const double* z, double* u, int lo, int hi, const int* flags, int flag,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_color_mask, dim3(chunk_grid(sv)), dim3(256), 0, s, chunk_args(sv, flags, flag), z, u, lo, hi);
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+// Symmetric block Gauss-Seidel over the elements in colour order, P = (D + L) D^-1 (D + U)
+// with L / U the couplings of the Newton operator A to elements of lower / higher colour
+// (elements of one colour never share a face, so A restricted to a colour is D):
+//   forward   z_k = D_k^-1 (r_k - [A z_{<k}]_k),   k = 0 .. K-1
+//   backward  z_k -= D_k^-1 [A z_{>k}]_k,          k = K-2 .. 0
+// where z_{<k} (z_{>k}) is z on the colours below (above) k and zero elsewhere.  Costs
+// 2 (K - 1) operator applications and about 1.5 block-apply passes per application.
+fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op, const int* flags, int flag,
+                        hipStream_t s) {
+    if (sv.precond == 0) return launch_block_apply(sv, r, z, flags, flag, s);
+    FR_TRY(dalloc(&sv.d_gsu, sv.Ntot));
+    FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
+    const int K = sv.ncolors;
+    KArgs a = op;
+    a.v = sv.d_gsu;
+    a.out = sv.d_gst;
+    a.flags = flags;
+    a.flag = flag;
+    for (int k = 0; k < K; ++k) {
+        if (k > 0) {
+            FR_TRY(launch_color_mask(sv, z, sv.d_gsu, 0, k - 1, flags, flag, s));
+            FR_TRY(solver_fused(sv, MODE_LIN, a, s));
+        }
+        FR_TRY(launch_block_apply_ex(sv, r, k > 0 ? sv.d_gst : nullptr, z, k, false, flags, flag, s));
+    }
+    for (int k = K - 2; k >= 0; --k) {
+        FR_TRY(launch_color_mask(sv, z, sv.d_gsu, k + 1, K - 1, flags, flag, s));
+        FR_TRY(solver_fused(sv, MODE_LIN, a, s));
+        FR_TRY(launch_block_apply_ex(sv, sv.d_gst, nullptr, z, k, true, flags, flag, s));
     }
     return FR_OK;
 }

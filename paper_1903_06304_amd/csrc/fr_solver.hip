@@ -57,8 +57,9 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
         cd[c].spoff = so;
         fo += (size_t)npf(x->prm.viscous != 0) * x->E * 4 * x->n;
         so += (size_t)nps(x->prm.viscous != 0) * x->E * x->Np;
-        cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr, x->d_aff};
+        cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr, x->d_aff, x->d_color};
         cd[c].pc = x->pc;
+        sv.ncolors = x->ncolors > sv.ncolors ? x->ncolors : sv.ncolors;
     }
     sv.Ntot = o;
     sv.Btot = bo;
@@ -132,6 +133,7 @@ void solver_free(Solver& sv) {
     dfree(sv.d_blk); dfree(sv.d_inv); dfree(sv.d_blk_keep);
     dfree(sv.d_q); dfree(sv.d_w); dfree(sv.d_V); dfree(sv.d_gs); dfree(sv.d_gi); dfree(sv.d_part);
     dfree(sv.d_step); dfree(sv.d_sum); dfree(sv.d_fpack); dfree(sv.d_spack); dfree(sv.d_rscratch);
+    dfree(sv.d_gsu); dfree(sv.d_gst);
     if (sv.h_pin) (void)hipHostFree(sv.h_pin);
     if (sv.ws) (void)hipStreamDestroy(sv.ws);
     if (sv.ev_in) (void)hipEventDestroy(sv.ev_in);
@@ -179,46 +181,18 @@ fr_status solver_ensure_step(Solver& sv, int m) {
 }
 
 // ----------------------------------------------------------------------------- step driver
-fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, const fr_step_opts* o,
-                      fr_step_stats* stats, hipStream_t caller) {
+namespace {
+
+// Runs the device Newton loop over every case with the per-case scalars already in the
+// pinned staging area: states in, iteration, states out, all on the solver stream ordered
+// after and before the caller's stream.  The per-case summary is left in h_pin.
+fr_status run_newton(Solver& sv, double* const* q, const double* const* q_nm1, const fr_step_opts& common,
+                     hipStream_t caller) {
     const int n = sv.n;
-    for (int c = 0; c < n; ++c) {
-        if (!sv.cs[c]->geometry_set) { fr_set_error("fr_set_geometry has not been called for every case"); return FR_EINVAL; }
-        if (!q[c]) { fr_set_error("null state pointer"); return FR_EINVAL; }
-        const fr_step_opts& x = o[c];
-        if (!(x.dt > 0.0) || x.krylov < 1 || x.krylov > MAXV - 4 || x.max_lin_it < 1 || x.max_newton < 0 ||
-            x.jac_lag < 1 || x.prec < FR_FP64 || x.prec > FR_BF16 || !(x.inv_dtau >= 0.0)) {
-            fr_set_error("invalid step options");
-            return FR_EINVAL;
-        }
-        if (x.krylov != o[0].krylov || x.max_lin_it != o[0].max_lin_it || x.max_newton != o[0].max_newton ||
-            x.jac_lag != o[0].jac_lag || x.prec != o[0].prec) {
-            fr_set_error("krylov, max_lin_it, max_newton, jac_lag and prec must agree across a batch");
-            return FR_EINVAL;
-        }
-    }
-    FR_TRY(solver_ensure_step(sv, o[0].krylov));
-    // the step runs on the solver stream, ordered after and before the caller's stream
     FR_HIP(hipEventRecord(sv.ev_in, caller));
     FR_HIP(hipStreamWaitEvent(sv.ws, sv.ev_in, 0));
     hipStream_t s = sv.ws;
-    // per-case step scalars through the pinned staging area (the previous step has synchronised)
-    CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
-    for (int c = 0; c < n; ++c) {
-        const bool b2 = q_nm1 && q_nm1[c];
-        CaseStep& st = hst[c];
-        st.a0 = b2 ? 1.5 : 1.0;
-        st.a1 = b2 ? -2.0 : -1.0;
-        st.a2 = b2 ? 0.5 : 0.0;
-        st.inv_dt = 1.0 / o[c].dt;
-        st.ct = st.a0 / o[c].dt;
-        st.idt = o[c].inv_dtau;
-        st.tol_res = o[c].tol_res;
-        st.tol_pseudo = o[c].tol_pseudo;
-        st.tol_abs = o[c].tol_abs;
-        st.has_nm1 = b2 ? 1 : 0;
-        st.max_newton = o[c].max_newton;
-    }
+    const CaseStep* hst = reinterpret_cast<const CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
     FR_HIP(hipMemcpyAsync(sv.d_step, hst, (size_t)n * sizeof(CaseStep), hipMemcpyHostToDevice, s));
     double* wq = sv.d_w + (size_t)WQNM1 * sv.Ntot;
     for (int c = 0; c < n; ++c) {
@@ -226,26 +200,22 @@ fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, 
         FR_HIP(hipMemcpyAsync(sv.d_q + sv.off[c], q[c], bytes, hipMemcpyDeviceToDevice, s));
         if (q_nm1 && q_nm1[c]) FR_HIP(hipMemcpyAsync(wq + sv.off[c], q_nm1[c], bytes, hipMemcpyDeviceToDevice, s));
     }
-    const fr_status st = solver_newton(sv, &o[0], s);
+    const fr_status st = solver_newton(sv, &common, s);
     if (st == FR_OK) {
         for (int c = 0; c < n; ++c)
             FR_HIP(hipMemcpyAsync(q[c], sv.d_q + sv.off[c], sv.N(c) * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     FR_HIP(hipEventRecord(sv.ev_out, s));
     FR_HIP(hipStreamWaitEvent(caller, sv.ev_out, 0));
-    if (st != FR_OK) return st;
-    // the summary was copied to h_pin by the Newton loop's last synchronisation
+    return st;
+}
+
+// status of the cases from the summary: the first non-finite case, else the first that
+// hit the iteration cap or a singular block
+fr_status case_status(const Solver& sv) {
     fr_status ret = FR_OK;
-    for (int c = 0; c < n; ++c) {
-        const double* x = sv.h_pin + (size_t)c * SUM_STRIDE;
-        if (stats) {
-            stats[c].newton_its = (int32_t)x[S_NEWTON];
-            stats[c].gmres_its = (int32_t)x[S_GMRES];
-            stats[c].converged = x[S_CONV] != 0.0;
-            stats[c].res0 = x[S_RES0];
-            stats[c].res_final = x[S_RES];
-        }
-        const int status = (int)x[S_STATUS];
+    for (int c = 0; c < sv.n; ++c) {
+        const int status = (int)sv.h_pin[(size_t)c * SUM_STRIDE + S_STATUS];
         char buf[160];
         if (status == 1 && ret != FR_ENONFINITE) {
             snprintf(buf, sizeof buf, "case %d: non-finite residual", c);
@@ -259,6 +229,122 @@ fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, 
         }
     }
     return ret;
+}
+
+fr_status check_cases(const Solver& sv, double* const* q) {
+    for (int c = 0; c < sv.n; ++c) {
+        if (!sv.cs[c]->geometry_set) { fr_set_error("fr_set_geometry has not been called for every case"); return FR_EINVAL; }
+        if (!q[c]) { fr_set_error("null state pointer"); return FR_EINVAL; }
+    }
+    return FR_OK;
+}
+
+}  // namespace
+
+fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, const fr_step_opts* o,
+                      fr_step_stats* stats, hipStream_t caller) {
+    const int n = sv.n;
+    FR_TRY(check_cases(sv, q));
+    for (int c = 0; c < n; ++c) {
+        const fr_step_opts& x = o[c];
+        if (!(x.dt > 0.0) || x.krylov < 1 || x.krylov > MAXV - 4 || x.max_lin_it < 1 || x.max_newton < 0 ||
+            x.jac_lag < 1 || x.prec < FR_FP64 || x.prec > FR_BF16 || !(x.inv_dtau >= 0.0)) {
+            fr_set_error("invalid step options");
+            return FR_EINVAL;
+        }
+        if (x.krylov != o[0].krylov || x.max_lin_it != o[0].max_lin_it || x.max_newton != o[0].max_newton ||
+            x.jac_lag != o[0].jac_lag || x.prec != o[0].prec) {
+            fr_set_error("krylov, max_lin_it, max_newton, jac_lag and prec must agree across a batch");
+            return FR_EINVAL;
+        }
+    }
+    FR_TRY(solver_ensure_step(sv, o[0].krylov));
+    // per-case step scalars through the pinned staging area (the previous step has synchronised)
+    CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
+    for (int c = 0; c < n; ++c) {
+        const bool b2 = q_nm1 && q_nm1[c];
+        CaseStep st{};
+        st.a0 = b2 ? 1.5 : 1.0;
+        st.a1 = b2 ? -2.0 : -1.0;
+        st.a2 = b2 ? 0.5 : 0.0;
+        st.inv_dt = 1.0 / o[c].dt;
+        st.ct = st.a0 / o[c].dt;
+        st.idt = o[c].inv_dtau;
+        st.tol_res = o[c].tol_res;
+        st.tol_pseudo = o[c].tol_pseudo;
+        st.tol_abs = o[c].tol_abs;
+        st.has_nm1 = b2 ? 1 : 0;
+        st.max_newton = o[c].max_newton;
+        st.ser = 0;
+        hst[c] = st;
+    }
+    FR_TRY(run_newton(sv, q, q_nm1, o[0], caller));
+    for (int c = 0; c < n && stats; ++c) {
+        const double* x = sv.h_pin + (size_t)c * SUM_STRIDE;
+        stats[c].newton_its = (int32_t)x[S_NEWTON];
+        stats[c].gmres_its = (int32_t)x[S_GMRES];
+        stats[c].converged = x[S_CONV] != 0.0;
+        stats[c].res0 = x[S_RES0];
+        stats[c].res_final = x[S_RES];
+    }
+    return case_status(sv);
+}
+
+// Steady pseudo-transient continuation (paper Sec. 3.2, Eq. steady_pre_discretized_1):
+// the Newton loop with no physical-time terms (c_time = 0, right-hand side R) and the
+// pseudo-time step under SER control, Eq. (SER), updated per case on the device.
+fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, fr_steady_stats* stats,
+                        hipStream_t caller) {
+    const int n = sv.n;
+    FR_TRY(check_cases(sv, q));
+    for (int c = 0; c < n; ++c) {
+        const fr_steady_opts& x = o[c];
+        if (!(x.dtau0 > 0.0) || !(x.dtau_min > 0.0) || !(x.dtau_max >= x.dtau_min) || !(x.r_ser >= 0.0) ||
+            !(x.tol_pseudo >= 0.0) || !(x.tol_res >= 0.0) || !(x.tol_abs >= 0.0) || x.krylov < 1 ||
+            x.krylov > MAXV - 4 || x.max_lin_it < 1 || x.max_steps < 0 || x.jac_lag < 1 || x.prec < FR_FP64 ||
+            x.prec > FR_BF16) {
+            fr_set_error("invalid steady options");
+            return FR_EINVAL;
+        }
+        if (x.krylov != o[0].krylov || x.max_lin_it != o[0].max_lin_it || x.max_steps != o[0].max_steps ||
+            x.jac_lag != o[0].jac_lag || x.prec != o[0].prec) {
+            fr_set_error("krylov, max_lin_it, max_steps, jac_lag and prec must agree across a batch");
+            return FR_EINVAL;
+        }
+    }
+    FR_TRY(solver_ensure_step(sv, o[0].krylov));
+    CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
+    for (int c = 0; c < n; ++c) {
+        CaseStep st{};   // no physical-time terms: c_time = inv_dt = a0 = a1 = a2 = 0
+        st.dtau = o[c].dtau0;
+        st.idt = 1.0 / o[c].dtau0;
+        st.dtau_min = o[c].dtau_min;
+        st.dtau_max = o[c].dtau_max;
+        st.r_ser = o[c].r_ser;
+        st.tol_res = o[c].tol_res;
+        st.tol_pseudo = o[c].tol_pseudo;
+        st.tol_abs = o[c].tol_abs;
+        st.max_newton = o[c].max_steps;
+        st.ser = 1;
+        hst[c] = st;
+    }
+    fr_step_opts common{};
+    common.krylov = o[0].krylov;
+    common.max_lin_it = o[0].max_lin_it;
+    common.max_newton = o[0].max_steps;
+    common.jac_lag = o[0].jac_lag;
+    common.prec = o[0].prec;
+    FR_TRY(run_newton(sv, q, nullptr, common, caller));
+    for (int c = 0; c < n && stats; ++c) {
+        const double* x = sv.h_pin + (size_t)c * SUM_STRIDE;
+        stats[c].steps = (int32_t)x[S_NEWTON];
+        stats[c].gmres_its = (int32_t)x[S_GMRES];
+        stats[c].converged = x[S_CONV] != 0.0;
+        stats[c].res0 = x[S_RES0];
+        stats[c].res_final = x[S_RES];
+        stats[c].dtau_final = x[S_DTAU] > 0.0 ? x[S_DTAU] : o[c].dtau0;
+    }
+    return case_status(sv);
 }
 
 // ----------------------------------------------------------------------------- autotuner

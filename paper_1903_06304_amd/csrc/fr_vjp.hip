@@ -526,7 +526,7 @@ k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, 
 
 template <int P, bool VISC, bool MOV>
 fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
-    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff};
+    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff, c->d_color};
     const int grid = (c->E + Sz<P>::EPB - 1) / Sz<P>::EPB;
     hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w, c->d_trace,
                        out, c->d_vj, c->op, c->pc, g);

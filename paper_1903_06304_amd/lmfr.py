@@ -23,7 +23,7 @@ PREC = {"fp64": FR_FP64, "fp32": FR_FP32, "bf16": FR_BF16}
 # every symbol declared in include/lmfr.h
 EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "fr_bdf_operator",
            "fr_block_jacobi_factor", "fr_block_jacobi_apply", "fr_get_blocks", "fr_bdf2_step",
-           "fr_affine_elements",
+           "fr_affine_elements", "fr_steady_solve", "fr_batch_steady_solve",
            "fr_set_option", "fr_autotune", "fr_batch_create", "fr_batch_destroy", "fr_batch_layout",
            "fr_batch_residual", "fr_batch_jvp", "fr_batch_bdf2_step", "fr_batch_set_option",
            "fr_batch_autotune", "fr_last_error", "fr_destroy"]
@@ -55,6 +55,18 @@ class fr_step_stats(ctypes.Structure):
                 ("res0", ctypes.c_double), ("res_final", ctypes.c_double)]
 
 
+class fr_steady_opts(ctypes.Structure):
+    _fields_ = [("dtau0", ctypes.c_double), ("dtau_min", ctypes.c_double), ("dtau_max", ctypes.c_double),
+                ("r_ser", ctypes.c_double), ("tol_pseudo", ctypes.c_double), ("tol_res", ctypes.c_double),
+                ("tol_abs", ctypes.c_double), ("krylov", ctypes.c_int32), ("max_lin_it", ctypes.c_int32),
+                ("max_steps", ctypes.c_int32), ("jac_lag", ctypes.c_int32), ("prec", ctypes.c_int32)]
+
+
+class fr_steady_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("gmres_its", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double), ("dtau_final", ctypes.c_double)]
+
+
 def load_library(path: str = LIB_PATH):
     """Load liblmfr.so (raises if it has not been built)."""
     global _lib
@@ -74,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     L.fr_block_jacobi_apply.argtypes = [vp, dp, dp, vp]
     L.fr_get_blocks.argtypes = [vp, dp, vp]
     L.fr_affine_elements.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    L.fr_steady_solve.argtypes = [vp, dp, ctypes.POINTER(fr_steady_opts), ctypes.POINTER(fr_steady_stats), vp]
+    L.fr_batch_steady_solve.argtypes = [vp, vp, vp, vp, vp]
     L.fr_bdf2_step.argtypes = [vp, dp, dp, ctypes.POINTER(fr_step_opts), ctypes.POINTER(fr_step_stats), vp]
     L.fr_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
     L.fr_autotune.argtypes = [vp, ctypes.c_char_p, vp]
@@ -228,6 +242,29 @@ class Context:
         return dict(rc=rc, newton_its=st.newton_its, gmres_its=st.gmres_its, converged=st.converged,
                     res0=st.res0, res_final=st.res_final)
 
+    def steady_solve(self, q, check=True, **kw):
+        """Steady pseudo-transient solve in place on q; keywords as steady_opts.  Returns stats."""
+        q = self._state(q)
+        o = steady_opts(**kw)
+        st = fr_steady_stats()
+        rc = load_library().fr_steady_solve(self.h, _ptr(q), ctypes.byref(o), ctypes.byref(st), _stream())
+        if check and rc not in (FR_OK, FR_ENOCONV):
+            _check(rc)
+        return dict(rc=rc, **_steady_dict(st))
+
+
+def steady_opts(dtau0=0.01, dtau_min=0.01, dtau_max=1e20, r_ser=2.0, tol_pseudo=1e-8, tol_res=1e-6, tol_abs=0.0,
+                krylov=30, max_lin_it=200, max_steps=100, jac_lag=1, prec="fp64"):
+    """Options of a steady pseudo-transient solve (paper defaults for the SER controls)."""
+    return fr_steady_opts(float(dtau0), float(dtau_min), float(dtau_max), float(r_ser), float(tol_pseudo),
+                          float(tol_res), float(tol_abs), int(krylov), int(max_lin_it), int(max_steps), int(jac_lag),
+                          PREC[prec] if isinstance(prec, str) else int(prec))
+
+
+def _steady_dict(s):
+    return dict(steps=s.steps, gmres_its=s.gmres_its, converged=s.converged, res0=s.res0, res_final=s.res_final,
+                dtau_final=s.dtau_final)
+
 
 def step_opts(dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=100, max_newton=100, jac_lag=2,
               inv_dtau=1e-20, tol_abs=0.0, prec="fp64"):
@@ -310,6 +347,21 @@ class Batch:
             _check(rc)
         return rc, [dict(newton_its=s.newton_its, gmres_its=s.gmres_its, converged=s.converged, res0=s.res0,
                          res_final=s.res_final) for s in sarr]
+
+    def steady_solve(self, qs, opts, check=True):
+        """Steady solve of every case in place on the tensors qs; opts: one fr_steady_opts per
+        case (or one shared).  Returns (status, [stats dicts])."""
+        n = len(self.contexts)
+        if isinstance(opts, fr_steady_opts):
+            opts = [opts] * n
+        qs = [c._state(q) for c, q in zip(self.contexts, qs)]
+        qarr = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        oarr = (fr_steady_opts * n)(*opts)
+        sarr = (fr_steady_stats * n)()
+        rc = load_library().fr_batch_steady_solve(self.h, qarr, oarr, sarr, _stream())
+        if check and rc not in (FR_OK, FR_ENOCONV):
+            _check(rc)
+        return rc, [_steady_dict(s) for s in sarr]
 
 
 class FRResidual(torch.autograd.Function):

@@ -115,6 +115,8 @@ def test_null_arguments_rejected_everywhere():
     assert L.fr_block_jacobi_factor(vp, vp, 1.0, 0.0, 0, vp) == lmfr.FR_EINVAL
     assert L.fr_get_blocks(vp, vp, vp) == lmfr.FR_EINVAL
     assert L.fr_affine_elements(vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_steady_solve(vp, vp, vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_batch_steady_solve(vp, vp, vp, vp, vp) == lmfr.FR_EINVAL
     assert L.fr_set_option(vp, b"graph", 1) == lmfr.FR_EINVAL
     assert L.fr_autotune(vp, None, vp) == lmfr.FR_EINVAL
     assert L.fr_batch_create(vp, 0, vp) == lmfr.FR_EINVAL

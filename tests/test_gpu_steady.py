@@ -1,0 +1,134 @@
+"""Steady pseudo-transient continuation on the GPU path (paper Sec. 3.2, Eqs.
+steady_pre_discretized_1 and SER) against the oracle's.
+
+Case: a perturbed uniform NS flow on a periodic affine mesh, whose steady state (R = 0)
+is a uniform flow.  Checked: the first pseudo-steps (states, residuals, SER step sizes)
+against the oracle; convergence to a uniform state in a number of steps that does not
+depend on the Mach number; a batch of cases against the same cases solved one by one
+(bitwise: the batch runs the same kernels with per-case reductions); option checks.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.oracle import Oracle  # noqa: E402
+from paper_1903_06304_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(nx, p, mach, amp=0.1, seed=0, re=100.0):
+    """Uniform flow plus a solenoidal velocity perturbation (rms amp) and a pressure
+    perturbation of the size of the dynamic pressure (0.01 gamma Ma^2 p)."""
+    mesh = I.Mesh(nx, nx, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi))
+    prm = I.Params(order=p, n_elem=mesh.E, mach_ref=mach, reynolds=re, viscous=True, kappa=1.0)
+    q = I.uniform_flow(mesh, prm)
+    rng = np.random.default_rng(seed)
+    du, dv = I.random_solenoidal_velocity(mesh, rng, rms=amp)
+    q[1] += du
+    q[2] += dv
+    q[0] *= 1 + 0.01 * prm.gamma * mach ** 2 * I.random_scalar_field(mesh, rng)
+    return mesh, prm, q
+
+
+def _noise_floor(g, q):
+    """10x the continuity-row residual change under a one-ulp perturbation of the state."""
+    gen = torch.Generator(device=q.device).manual_seed(3)
+    r = torch.rand(q.shape, generator=gen, device=q.device, dtype=torch.float64) * 2.0 - 1.0
+    d = g.residual(q * (1.0 + 2.0 ** -52 * r)) - g.residual(q)
+    return 10.0 * float(torch.linalg.vector_norm(d[0]))
+
+
+def _ctx(mesh, prm):
+    from paper_1903_06304_amd import lmfr
+    nbr, nbf, flip = mesh.connectivity()
+    g = lmfr.Context(prm, nbr, nbf, flip)
+    g.set_geometry(*mesh.nodes(0.0))
+    return g
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def test_steady_first_steps_match_oracle():
+    mesh, prm, q = _case(4, 2, 0.1)
+    kw = dict(tol_pseudo=1e-30, tol_res=1e-12, krylov=60, max_lin_it=2000, max_steps=6)
+    g = _ctx(mesh, prm)
+    qg = _dev(q)
+    st = g.steady_solve(qg, **kw)
+    torch.cuda.synchronize()
+    qo, sto = Oracle(prm, mesh).steady_solve(q, **kw)
+    print(f"[steady] GPU {st}\n[steady] oracle { {k: v for k, v in sto.items() if k != 'hist'} }", flush=True)
+    assert st["steps"] == sto["steps"] == 6
+    assert abs(st["res_final"] - sto["res_final"]) <= 1e-8 * sto["res0"]
+    assert abs(st["dtau_final"] - sto["dtau_final"]) <= 1e-8 * sto["dtau_final"]
+    # per variable: GPU - oracle against the change the six steps made
+    diff = np.max(np.abs(qg.cpu().numpy() - qo), axis=(1, 2))
+    chg = np.max(np.abs(qo - q), axis=(1, 2))
+    print("[steady] |GPU - oracle| / change per variable", diff / chg, flush=True)
+    assert np.all(diff <= 1e-8 * chg + 1e-13 * np.max(np.abs(qo), axis=(1, 2))), diff / chg
+
+
+def test_steady_converges_to_uniform_flow_mach_independent():
+    """Same SER schedule, dtau0 = 1, Krylov dimension 150 (the paper's for steady problems):
+    the pseudo-step count does not change from Ma = 0.3 to Ma = 0.01."""
+    steps = []
+    for mach in (0.3, 0.1, 0.01):
+        mesh, prm, q = _case(8, 3, mach)
+        g = _ctx(mesh, prm)
+        qg = _dev(q)
+        floor = _noise_floor(g, qg)
+        st = g.steady_solve(qg, dtau0=1.0, dtau_min=1.0, tol_pseudo=1e-10, tol_abs=floor, tol_res=1e-6,
+                            krylov=150, max_lin_it=1500, max_steps=30)
+        torch.cuda.synchronize()
+        print(f"[steady] Ma={mach}: {st} floor/res0 {floor / st['res0']:.1e}", flush=True)
+        assert st["converged"] == 1, st
+        qs = qg.cpu().numpy()
+        vel = np.sqrt(np.mean((qs[1] - qs[1].mean()) ** 2 + (qs[2] - qs[2].mean()) ** 2))
+        assert vel < 1e-8, vel
+        R = g.residual(qg).cpu().numpy()
+        assert np.linalg.norm(R[0]) <= max(1e-10 * st["res0"], floor)
+        assert st["dtau_final"] > 1e6
+        steps.append(st["steps"])
+    assert max(steps) - min(steps) <= 1 and max(steps) <= 8, steps
+
+
+def test_steady_batch_matches_single_cases():
+    from paper_1903_06304_amd import lmfr
+    specs = [(8, 2, 0.1, 0), (6, 3, 0.02, 1), (5, 4, 0.2, 2)]
+    cases = [_case(nx, p, m, seed=s) for nx, p, m, s in specs]
+    d0s = (1.0, 0.5, 2.0)   # per-case SER controls
+    opts = [lmfr.steady_opts(tol_pseudo=1e-8, tol_res=1e-6, krylov=60, max_lin_it=2000, max_steps=12, dtau0=d,
+                             dtau_min=d) for d in d0s]
+    singles = []
+    for (mesh, prm, q), d in zip(cases, d0s):
+        g = _ctx(mesh, prm)
+        qg = _dev(q)
+        st = g.steady_solve(qg, dtau0=d, dtau_min=d, tol_pseudo=1e-8, tol_res=1e-6, krylov=60, max_lin_it=2000,
+                            max_steps=12)
+        singles.append((qg, st))
+    ctxs = [_ctx(mesh, prm) for mesh, prm, _ in cases]
+    b = lmfr.Batch(ctxs)
+    qs = [_dev(q) for _, _, q in cases]
+    rc, sts = b.steady_solve(qs, opts)
+    torch.cuda.synchronize()
+    assert rc in (lmfr.FR_OK, lmfr.FR_ENOCONV)
+    assert sts[0]["converged"] == 1
+    for (qg, st), qb, sb in zip(singles, qs, sts):
+        print(f"[steady] single {st} batch {sb}", flush=True)
+        for key in ("converged", "steps", "gmres_its", "res_final", "dtau_final"):
+            assert st[key] == sb[key], key
+        assert torch.equal(qg, qb)
+
+
+def test_steady_options_rejected():
+    from paper_1903_06304_amd import lmfr
+    mesh, prm, q = _case(3, 1, 0.1)
+    g = _ctx(mesh, prm)
+    qg = _dev(q)
+    for bad in (dict(dtau0=0.0), dict(dtau_min=0.0), dict(dtau_min=1.0, dtau_max=0.5), dict(r_ser=-1.0),
+                dict(krylov=0), dict(krylov=157), dict(max_steps=-1), dict(jac_lag=0), dict(prec=7)):
+        with pytest.raises(lmfr.FRError):
+            g.steady_solve(qg, **bad)
