@@ -9,6 +9,7 @@ One timed step = one pass of the hot path over that input:
     Infinity Cache, so inputs and outputs stream from HBM), NJ JVPs and NV VJPs,
   * one BDF2 dual-time step (Newton to Res_m/Res_0 <= 1e-8, GMRES(30), tol_res 1e-6)
     with FP64 element blocks ("plain"), and the same step with FP32 and BF16 blocks,
+    and with the symmetric block Gauss-Seidel preconditioner (FP64 and BF16 blocks),
   * the batched workload: 48 uneven cases (16^2..192^2 quads, p = 2..4, Ma 0.01..0.3,
     Re 100..5000, half deforming) -- one batched residual per step and one batched
     BDF2 step per block precision, launch shapes from the autotuner.
@@ -41,6 +42,8 @@ def parse():
     ap.add_argument("--dt", type=float, default=1e-3, help="physical time step of the BDF2 step")
     ap.add_argument("--max-lin-it", type=int, default=200)
     ap.add_argument("--precs", default="fp64,fp32,bf16")
+    ap.add_argument("--gs-precs", default="fp64,bf16",
+                    help="block precisions of the BDF2 step with the block Gauss-Seidel preconditioner")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-bdf2", action="store_true")
@@ -143,6 +146,7 @@ def main():
         print(f"[bench] BDF1 start step {st0}", file=sys.stderr, flush=True)
 
     precs = args.precs.split(",")
+    gprecs = [x for x in args.gs_precs.split(",") if x]
     bprecs = args.batch_precs.split(",")
     bt = None
     if not args.no_batch:
@@ -176,6 +180,16 @@ def main():
                 b.record(stream)
                 ev["bdf2_" + pr] = (a, b)
                 stats[pr] = (st, qw)
+            ctx.set_option("preconditioner", 1)
+            for pr in gprecs:
+                qw = q_n.clone()
+                a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                st = ctx.bdf2_step(qw, q_nm1, args.dt, prec=pr, **bdf_kw)
+                b.record(stream)
+                ev["gs_" + pr] = (a, b)
+                stats["gs_" + pr] = (st, qw)
+            ctx.set_option("preconditioner", 0)
         if bt is not None:
             a = torch.cuda.Event(enable_timing=True); b_ = torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -259,6 +273,15 @@ def main():
             d = (records[-1][1][pr][1] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
             bd[pr]["max_rel_diff_vs_fp64"] = float(d.max())
             bd[pr]["speedup_vs_fp64"] = bd["fp64"]["ms"] / bd[pr]["ms"]
+        # the same step with the symmetric block Gauss-Seidel preconditioner
+        for pr in gprecs:
+            st, qw = records[-1][1]["gs_" + pr]
+            d = (qw - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
+            bd["gauss_seidel_" + pr] = {"ms": mean_ms("gs_" + pr), "newton_its": st["newton_its"],
+                                        "gmres_its": st["gmres_its"], "converged": st["converged"],
+                                        "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
+                                        "max_rel_diff_vs_fp64": float(d.max()),
+                                        "speedup_vs_fp64": bd["fp64"]["ms"] / mean_ms("gs_" + pr)}
         out["bdf2_step"] = bd
     if bt is not None:
         bres_ms = mean_ms("bres") / args.nrb
