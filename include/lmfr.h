@@ -116,7 +116,8 @@ fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h
  * xg, vg are DEVICE arrays [2][n_elem][(geom_order+1)^2]; vg NULL for static meshes
  * (required when the context was created with moving = 1).  Computes and keeps the
  * metric terms at solution and flux points; the face vector of each interface is
- * computed once, from its owner side, and shared by both sides. */
+ * computed once, from its owner side, and shared by both sides.  Also flags the affine
+ * elements (constant metrics); reading the flags back synchronises `stream`. */
 fr_status fr_set_geometry(fr_ctx ctx, const double* xg, const double* vg, void* stream);
 
 /* Number of elements the last fr_set_geometry found affine: every metric term constant

@@ -308,6 +308,13 @@ extern "C" fr_status fr_set_geometry(fr_ctx c, const double* xg, const double* v
     if (!c || !xg) return bad("fr_set_geometry: null argument");
     if (c->prm.moving && !vg) return bad("fr_set_geometry: moving mesh needs grid velocities");
     FR_TRY(launch_geometry(c, xg, c->prm.moving ? vg : nullptr, (hipStream_t)stream));
+    // whether every element is affine decides the residual kernel variant: read the flags back
+    std::vector<int32_t> h((size_t)c->E);
+    FR_HIP(hipMemcpyAsync(h.data(), c->d_aff, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    FR_HIP(hipStreamSynchronize((hipStream_t)stream));
+    bool all = true;
+    for (int32_t x : h) all = all && x != 0;
+    c->all_affine = all;
     c->geometry_set = true;
     return FR_OK;
 }

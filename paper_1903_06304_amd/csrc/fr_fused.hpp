@@ -571,6 +571,265 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     }
 }
 
+// The residual (and in MODE_PREP the linearisation packs) of static groups whose elements
+// are all affine.  Same stages as k_fused, with what constant metrics allow:
+//  * neighbour states are not staged in LDS: each face lane reads the neighbour's line
+//    through its face point and forms the neighbour trace q+ and, for the gradient trace,
+//    the face-normal derivative sum_b l_b'(+-1) q_b in registers; the tangential derivative
+//    is the 1-D derivative of the neighbour traces along the face, exchanged through the
+//    (not yet used) F^num area; the neighbour's gradient trace is then the chain rule with
+//    its constant metrics;
+//  * point fluxes are kept in contravariant form, F~ = xi_x f + xi_y g, G~ = eta_x f + eta_y g,
+//    so the divergence is dF~/dxi + dG~/deta and S.(Pi f, Pi g) on a xi (eta) face is |J| Pi F~
+//    (|J| Pi G~): half the LDS reads of the last two stages.
+// Equal to k_fused's values up to rounding.
+template <int P, bool VISC, int MODE, int LANES>
+__global__ void __launch_bounds__((Shape<P, LANES>::threads))
+k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
+    static_assert(MODE == MODE_R || MODE == MODE_PREP, "plain-value modes only");
+    constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
+    constexpr int EPB = Shape<P, LANES>::EPB;
+    using PD = LPad<P, 1>;
+    constexpr int FS = Np + PD::F;
+    constexpr int ESQ = 4 * FS + PD::E;
+    constexpr int ESW = 8 * FS + PD::E;      // F~ of the 4 equations, then G~
+    constexpr int NG = VISC ? 6 : 1;
+    constexpr int ESG = NG * FS + PD::E;
+    constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1;
+    __shared__ double s_q[EPB * ESQ];       // own state [el][var][point]
+    __shared__ double s_w[EPB * ESW];       // F~, G~ [el][8][point]
+    __shared__ double s_g[EPB * ESG];       // own uncorrected gradient [el][6][point]
+    __shared__ double s_F[EPB * ESF];       // neighbour traces of (u, v, T) by neighbour point; then F^num - F^loc
+    __shared__ double s_dq[EPB * ESD];      // q^com - q^- of (u, v, T)
+    auto QI = [](int el, int v, int sp) { return el * ESQ + v * FS + sp; };
+    auto WI = [](int el, int fld, int sp) { return el * ESW + fld * FS + sp; };
+    auto GI = [](int el, int c, int sp) { return el * ESG + c * FS + sp; };
+    auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
+    auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
+    __shared__ double s_D[n * n];
+    __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
+
+    const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
+    if (threadIdx.x < n) {
+        s_lam[0][threadIdx.x] = op.lamL[threadIdx.x]; s_lam[1][threadIdx.x] = op.lamR[threadIdx.x];
+        s_gam[0][threadIdx.x] = op.gamL[threadIdx.x]; s_gam[1][threadIdx.x] = op.gamR[threadIdx.x];
+        s_dlam[0][threadIdx.x] = op.dlamL[threadIdx.x]; s_dlam[1][threadIdx.x] = op.dlamR[threadIdx.x];
+    }
+    const int i = lt % n, j = lt / n;
+    const int f = (lt % NF) / n, k = lt % n;
+    int tile, tend, tstride;
+    tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
+    for (; tile < tend; tile += tstride) {
+        const int lo = find_member(ga, tile);
+        const int cid = sld(ga.ids + lo);
+        if (a.flags && rfl(a.flags[cid * GI_STRIDE + a.flag])) continue;
+        const CaseDev cd = load_case(ga.cases + cid);
+        const PhysConst& pc = cd.pc;
+        const Geo g = cd.g;
+        const int E = cd.E;
+        const int e = (tile - sld(ga.pfx + lo)) * EPB + el;
+        const bool act = e < E;
+        const unsigned EN = (unsigned)E * Np;
+        const double* q = a.q + cd.off;
+        __syncthreads();   // the previous tile's readers of LDS are done
+        // ---- stage 1: own state into LDS; the lane's metric terms; the neighbour's line
+        // through this face point: trace and face-normal derivative
+        LaneGeo lg;
+        double qp[4], dnor[3];
+        if (act) {
+            int pk4[4];
+#pragma unroll
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            const unsigned id = (unsigned)e * Np + lt % Np;
+            double qo[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = q[vv * EN + id];
+            lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
+            if (lt < NF) {
+                const unsigned nbase = (unsigned)lg.nb * Np;
+                double ln[4][n];
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const unsigned sp = nbase + line_pt(n, lg.nf, lg.k2, b);
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) ln[vv][b] = q[vv * EN + sp];
+                }
+                const double* lamn = s_lam[lg.nf & 1];
+                const double* dlamn = s_dlam[lg.nf & 1];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) acc = acc + lamn[b] * ln[vv][b];
+                    qp[vv] = acc;
+                }
+                if (VISC) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < n; ++b) acc = acc + dlamn[b] * ln[c + 1][b];
+                        dnor[c] = acc;
+                        s_F[FI(el, c, f * n + lg.k2)] = qp[c + 1];
+                    }
+                }
+            }
+            if (lt < Np) {
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+            }
+        }
+        __syncthreads();
+        // ---- stage 2: own uncorrected gradient
+        if (VISC && act && lt < Np) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double dxi = 0.0, deta = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
+                    deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
+                }
+                s_g[GI(el, 2 * c, lt)] = lg.xix * dxi + lg.etx * deta;
+                s_g[GI(el, 2 * c + 1, lt)] = lg.xiy * dxi + lg.ety * deta;
+            }
+        }
+        __syncthreads();
+        // ---- stage 3: own traces, common flux at the flux points
+        double fsc[4];
+        if (act && lt < NF) {
+            const double* lam = s_lam[f & 1];
+            const double nx = lg.nx, ny = lg.ny, sc = lg.sc;
+            double qm[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                qm[vv] = acc;
+            }
+            if constexpr (MODE == MODE_PREP) {
+                double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
+                const size_t fs = (size_t)E * NF;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) { fpk[vv * fs] = qm[vv]; fpk[(4 + vv) * fs] = qp[vv]; }
+            }
+            double fn[4], dq[4];
+            fr_common_inviscid<double>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
+            if (VISC) {
+                double gm[6], gp[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                    gm[c] = acc;
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double dtan = 0.0;
+#pragma unroll
+                    for (int m = 0; m < n; ++m) dtan = dtan + s_D[lg.k2 * n + m] * s_F[FI(el, c, f * n + m)];
+                    const double dxi = lg.nf < 2 ? dnor[c] : dtan, deta = lg.nf < 2 ? dtan : dnor[c];
+                    gp[2 * c] = lg.mxix * dxi + lg.metx * deta;
+                    gp[2 * c + 1] = lg.mxiy * dxi + lg.mety * deta;
+                }
+                if constexpr (MODE == MODE_PREP) {
+                    double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
+                    const size_t fs = (size_t)E * NF;
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) { fpk[(8 + c) * fs] = gm[c]; fpk[(14 + c) * fs] = gp[c]; }
+                }
+                const double qcu = qm[1] + 0.5 * dq[1];
+                const double qcv = qm[2] + 0.5 * dq[2];
+                double dqh[3];
+                fr_common_viscous<double>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c];
+            }
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) fsc[vv] = sc * fn[vv];
+        }
+        __syncthreads();
+        // ---- stage 4: corrected gradient, point fluxes in contravariant form
+        if (act && lt < Np) {
+            double qs[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[QI(el, vv, lt)];
+            double gu[2], gv[2], gT[2];
+            if (VISC) {
+#pragma unroll
+                for (int d = 0; d < 2; ++d) { gu[d] = s_g[GI(el, d, lt)]; gv[d] = s_g[GI(el, 2 + d, lt)]; gT[d] = s_g[GI(el, 4 + d, lt)]; }
+                // lift of q^com - q^- through the Radau slopes; on an affine element the face
+                // vectors are |J| grad(xi) (faces 0, 1) and |J| grad(eta) (faces 2, 3), and |J| / |J| = 1
+                const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
+                const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
+                double* gr[3] = {gu, gv, gT};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double lx = gL_i * s_dq[DI(el, c, fp0)] + gR_i * s_dq[DI(el, c, fp1)];
+                    const double le = gL_j * s_dq[DI(el, c, fp2)] + gR_j * s_dq[DI(el, c, fp3)];
+                    gr[c][0] = gr[c][0] + (lg.xix * lx + lg.etx * le);
+                    gr[c][1] = gr[c][1] + (lg.xiy * lx + lg.ety * le);
+                }
+            }
+            if constexpr (MODE == MODE_PREP) {
+                double* spk = a.spack + cd.spoff + (size_t)e * Np + lt;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) spk[(size_t)vv * EN] = qs[vv];
+                if (VISC) {
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        spk[(size_t)(4 + d) * EN] = gu[d];
+                        spk[(size_t)(6 + d) * EN] = gv[d];
+                        spk[(size_t)(8 + d) * EN] = gT[d];
+                    }
+                }
+            }
+            double fl[4], gl[4], qc[4];
+            fr_point_flux<double, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                s_w[WI(el, vv, lt)] = lg.xix * fl[vv] + lg.xiy * gl[vv];
+                s_w[WI(el, 4 + vv, lt)] = lg.etx * fl[vv] + lg.ety * gl[vv];
+            }
+        }
+        __syncthreads();
+        // ---- stage 5: F^num - F^loc, F^loc = |J| Pi F~ (xi faces) or |J| Pi G~ (eta faces)
+        if (act && lt < NF) {
+            const double* lam = s_lam[f & 1];
+            const double jac = 1.0 / lg.ij;
+            const int base = f < 2 ? 0 : 4;
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
+                s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
+            }
+        }
+        __syncthreads();
+        // ---- stage 6: divergence dF~/dxi + dG~/deta, Radau lift
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            double* out = a.out + cd.off;
+#pragma unroll 1
+            for (int vv = 0; vv < 4; ++vv) {
+                double dF = 0.0, dG = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    dF = dF + s_D[i * n + b] * s_w[WI(el, vv, b + n * j)];
+                    dG = dG + s_D[j * n + b] * s_w[WI(el, 4 + vv, i + n * b)];
+                }
+                const double cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
+                                 + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
+                out[vv * EN + id] = -(dF + dG + lg.ij * cor);
+            }
+        }
+    }
+}
+
 // Newton operator Av = inv_dtau Gamma v + c_time M v - J v from the linearisation packs of
 // the state (MODE_LIN).  Every stage that is linear in the state (gradients, traces,
 // interpolation, divergence, lifting) acts on the tangent v alone, so LDS holds doubles;
@@ -884,6 +1143,14 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
     }
 }
 
+// every element of every member case is affine (the geometry pass's flags, read back by
+// fr_set_geometry)
+inline bool group_affine(const Solver& sv, const Group& gr) {
+    for (int id : gr.ids)
+        if (!sv.cs[id]->all_affine) return false;
+    return true;
+}
+
 // grid of a launch: one workgroup per tile by default, else the tuned persistent size;
 // always a multiple of 8 (the XCD count) so every XCD walks an equal tile range
 inline unsigned grid_of(int ntiles, int grid) {
@@ -913,8 +1180,18 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
                            ga, a, op);
     } else {
         if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
-        hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads),
-                           0, s, ga, a, op);
+        bool aff = false;
+        if constexpr (!MOV && (MODE == MODE_R || MODE == MODE_PREP)) aff = group_affine(sv, gr);
+        if constexpr (!MOV && (MODE == MODE_R || MODE == MODE_PREP)) {
+            if (aff) {
+                hipLaunchKernelGGL((k_fused_aff<P, VISC, MODE, LANES>), dim3(grid_of(ga.ntiles, grid)),
+                                   dim3(SH::threads), 0, s, ga, a, op);
+            }
+        }
+        if (!aff) {
+            hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)),
+                               dim3(SH::threads), 0, s, ga, a, op);
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { fr_set_error(std::string("k_fused launch: ") + hipGetErrorString(e)); return FR_EHIP; }

@@ -165,6 +165,7 @@ struct fr_ctx_s {
     int32_t* d_aff = nullptr;       // [E] affine-element flags
     int32_t* d_color = nullptr;     // [E] element colours
     int ncolors = 0;
+    bool all_affine = false;        // every element affine at the current geometry
     double* d_trace = nullptr;      // neighbour traces (adjoint path)
     double* d_vj = nullptr;         // adjoint trace buffer
     Solver* self = nullptr;         // one-case solver of the context's own entry points
