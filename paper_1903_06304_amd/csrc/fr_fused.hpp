@@ -407,7 +407,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                     double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
                     const size_t fs = (size_t)E * NF;
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) { fpk[(8 + c) * fs] = gm[c]; fpk[(14 + c) * fs] = gp[c]; }
+                    for (int c = 0; c < 6; ++c) fpk[(8 + c) * fs] = gm[c] + gp[c];   // the common flux needs the sum only
                 }
                 // q^com velocity = average of the two traces = q^- + dq/2
                 const T qcu = am_avg<T>(&s_q[QI(el, 1, 0)], lam, f, k, dq[1], n);
@@ -739,7 +739,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                     double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
                     const size_t fs = (size_t)E * NF;
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) { fpk[(8 + c) * fs] = gm[c]; fpk[(14 + c) * fs] = gp[c]; }
+                    for (int c = 0; c < 6; ++c) fpk[(8 + c) * fs] = gm[c] + gp[c];   // the common flux needs the sum only
                 }
                 const double qcu = qm[1] + 0.5 * dq[1];
                 const double qcv = qm[2] + 0.5 * dq[2];
@@ -1019,7 +1019,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < 6; ++c) gp[c] = mk(fpk[(size_t)(14 + c) * FE + sid], gpt[c]);
+                for (int c = 0; c < 6; ++c) gp[c] = mk(0.0, gpt[c]);   // the pack holds g^- + g^+ in gm
                 // q^com velocity = q^- + dq/2 (the own trace as formed above)
                 const D qcu = qm[1] + 0.5 * dq[1];
                 const D qcv = qm[2] + 0.5 * dq[2];
@@ -1143,6 +1143,258 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
     }
 }
 
+// The Newton operator from the linearisation packs (as k_lin) for static groups whose elements
+// are all affine, with the changes of k_fused_aff: neighbour tangent lines read into
+// registers, the neighbour gradient trace from its traces, contravariant flux tangents, face
+// vectors from the constant metrics.  BLK: one seeded block column per launch.
+template <int P, bool VISC, int LANES, bool BLK>
+__global__ void __launch_bounds__((Shape<P, LANES>::threads))
+k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
+    using D = Dual<1>;
+    constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
+    constexpr int EPB = Shape<P, LANES>::EPB;
+    using PD = LPad<P, 1>;
+    constexpr int FS = Np + PD::F;
+    constexpr int ESQ = 4 * FS + PD::E;
+    constexpr int ESW = 8 * FS + PD::E;
+    constexpr int NG = VISC ? 6 : 1;
+    constexpr int ESG = NG * FS + PD::E;
+    constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1;
+    __shared__ double s_q[EPB * ESQ];       // own tangent [el][var][point]
+    __shared__ double s_w[EPB * ESW];       // F~', G~' [el][8][point]
+    __shared__ double s_g[EPB * ESG];       // own uncorrected gradient tangent
+    __shared__ double s_F[EPB * ESF];       // neighbour trace tangents of (u, v, T); then F^num' - F^loc'
+    __shared__ double s_dq[EPB * ESD];      // (q^com - q^-)' of (u, v, T)
+    auto QI = [](int el, int v, int sp) { return el * ESQ + v * FS + sp; };
+    auto WI = [](int el, int fld, int sp) { return el * ESW + fld * FS + sp; };
+    auto GI = [](int el, int c, int sp) { return el * ESG + c * FS + sp; };
+    auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
+    auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
+    __shared__ double s_D[n * n];
+    __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
+    auto mk = [](double v, double d) { D r; r.v = v; r.d[0] = d; return r; };
+
+    const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
+    if (threadIdx.x < n) {
+        s_lam[0][threadIdx.x] = op.lamL[threadIdx.x]; s_lam[1][threadIdx.x] = op.lamR[threadIdx.x];
+        s_gam[0][threadIdx.x] = op.gamL[threadIdx.x]; s_gam[1][threadIdx.x] = op.gamR[threadIdx.x];
+        s_dlam[0][threadIdx.x] = op.dlamL[threadIdx.x]; s_dlam[1][threadIdx.x] = op.dlamR[threadIdx.x];
+    }
+    const int i = lt % n, j = lt / n;
+    const int f = (lt % NF) / n, k = lt % n;
+    int tile, tend, tstride;
+    tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
+    for (; tile < tend; tile += tstride) {
+        const int lo = find_member(ga, tile);
+        const int cid = sld(ga.ids + lo);
+        if (a.flags && rfl(a.flags[cid * GI_STRIDE + a.flag])) continue;
+        const CaseDev cd = load_case(ga.cases + cid);
+        const PhysConst& pc = cd.pc;
+        const Geo g = cd.g;
+        const int E = cd.E;
+        const int e = (tile - sld(ga.pfx + lo)) * EPB + el;
+        const bool act = e < E;
+        const unsigned EN = (unsigned)E * Np;
+        const double* v = BLK ? nullptr : a.v + cd.off;
+        const double* fpk = a.fpack + cd.fpoff;
+        const double* spk = a.spack + cd.spoff;
+        __syncthreads();
+        // ---- stage 1: own tangent; the neighbour's tangent line through this face point
+        LaneGeo lg;
+        double qpt[4], dnort[3];
+        if (act) {
+            int pk4[4];
+#pragma unroll
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            const int ls = lt % Np;
+            const unsigned id = (unsigned)e * Np + ls;
+            double qo[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : v[vv * EN + id];
+            lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
+            if (lt < NF) {
+                const unsigned nbase = (unsigned)lg.nb * Np;
+                double ln[4][n];
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    const int sp = line_pt(n, lg.nf, lg.k2, b);
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv)
+                        ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == a.seed0) ? 1.0 : 0.0) : v[vv * EN + nbase + sp];
+                }
+                const double* lamn = s_lam[lg.nf & 1];
+                const double* dlamn = s_dlam[lg.nf & 1];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) acc = acc + lamn[b] * ln[vv][b];
+                    qpt[vv] = acc;
+                }
+                if (VISC) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < n; ++b) acc = acc + dlamn[b] * ln[c + 1][b];
+                        dnort[c] = acc;
+                        s_F[FI(el, c, f * n + lg.k2)] = qpt[c + 1];
+                    }
+                }
+            }
+            if (lt < Np) {
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+            }
+        }
+        __syncthreads();
+        // ---- stage 2: uncorrected gradient tangent
+        if (VISC && act && lt < Np) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double dxi = 0.0, deta = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
+                    deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
+                }
+                s_g[GI(el, 2 * c, lt)] = lg.xix * dxi + lg.etx * deta;
+                s_g[GI(el, 2 * c + 1, lt)] = lg.xiy * dxi + lg.ety * deta;
+            }
+        }
+        __syncthreads();
+        // ---- stage 3: common flux on dual numbers (values from the face pack)
+        double fsc[4];
+        if (act && lt < NF) {
+            const double* lam = s_lam[f & 1];
+            const unsigned FE = (unsigned)E * NF;
+            const unsigned sid = (unsigned)e * NF + lt;
+            const double nx = lg.nx, ny = lg.ny, sc = lg.sc;
+            D fn[4], dq[4], qm[4], qp[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                qm[vv] = mk(fpk[(size_t)vv * FE + sid], acc);
+                qp[vv] = mk(fpk[(size_t)(4 + vv) * FE + sid], qpt[vv]);
+            }
+            fr_common_inviscid<D>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
+            if (VISC) {
+                D gm[6], gp[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                    gm[c] = mk(fpk[(size_t)(8 + c) * FE + sid], acc);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double dtan = 0.0;
+#pragma unroll
+                    for (int m = 0; m < n; ++m) dtan = dtan + s_D[lg.k2 * n + m] * s_F[FI(el, c, f * n + m)];
+                    const double dxi = lg.nf < 2 ? dnort[c] : dtan, deta = lg.nf < 2 ? dtan : dnort[c];
+                    gp[2 * c] = mk(0.0, lg.mxix * dxi + lg.metx * deta);   // the pack holds g^- + g^+ in gm
+                    gp[2 * c + 1] = mk(0.0, lg.mxiy * dxi + lg.mety * deta);
+                }
+                const D qcu = qm[1] + 0.5 * dq[1];
+                const D qcv = qm[2] + 0.5 * dq[2];
+                D dqh[3];
+                fr_common_viscous<D>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c].d[0];
+            }
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) fsc[vv] = (sc * fn[vv]).d[0];
+        }
+        __syncthreads();
+        // ---- stage 4: corrected gradient tangent, point flux on dual numbers, contravariant tangents
+        double qv[4];
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            D qs[4], gu[2], gv[2], gT[2];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                qv[vv] = spk[(size_t)vv * EN + id];
+                qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
+            }
+            if (VISC) {
+                double gt[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) gt[c] = s_g[GI(el, c, lt)];
+                const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
+                const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double lx = gL_i * s_dq[DI(el, c, fp0)] + gR_i * s_dq[DI(el, c, fp1)];
+                    const double le = gL_j * s_dq[DI(el, c, fp2)] + gR_j * s_dq[DI(el, c, fp3)];
+                    gt[2 * c] = gt[2 * c] + (lg.xix * lx + lg.etx * le);
+                    gt[2 * c + 1] = gt[2 * c + 1] + (lg.xiy * lx + lg.ety * le);
+                }
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    gu[d] = mk(spk[(size_t)(4 + d) * EN + id], gt[d]);
+                    gv[d] = mk(spk[(size_t)(6 + d) * EN + id], gt[2 + d]);
+                    gT[d] = mk(spk[(size_t)(8 + d) * EN + id], gt[4 + d]);
+                }
+            }
+            D fl[4], gl[4], qc[4];
+            fr_point_flux<D, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                s_w[WI(el, vv, lt)] = lg.xix * fl[vv].d[0] + lg.xiy * gl[vv].d[0];
+                s_w[WI(el, 4 + vv, lt)] = lg.etx * fl[vv].d[0] + lg.ety * gl[vv].d[0];
+            }
+        }
+        __syncthreads();
+        // ---- stage 5: F^num' - F^loc'
+        if (act && lt < NF) {
+            const double* lam = s_lam[f & 1];
+            const double jac = 1.0 / lg.ij;
+            const int base = f < 2 ? 0 : 4;
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                double acc = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
+                s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
+            }
+        }
+        __syncthreads();
+        // ---- stage 6: divergence and lift of the tangents; time terms
+        if (act && lt < Np) {
+            const unsigned id = (unsigned)e * Np + lt;
+            double ct = a.c_time, idt = a.inv_dtau;
+            if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
+            double tt[4], x[4];
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
+            fr_time_apply<double, double>(pc, qv, 0.0, 0.0, idt, ct, x, tt);
+            double* out = a.out + (BLK ? cd.boff + (size_t)e * (4 * Np) * (4 * Np) : cd.off);
+#pragma unroll 1
+            for (int vv = 0; vv < 4; ++vv) {
+                double dF = 0.0, dG = 0.0;
+#pragma unroll
+                for (int b = 0; b < n; ++b) {
+                    dF = dF + s_D[i * n + b] * s_w[WI(el, vv, b + n * j)];
+                    dG = dG + s_D[j * n + b] * s_w[WI(el, 4 + vv, i + n * b)];
+                }
+                const double cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
+                                 + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
+                const double Rd = -(dF + dG + lg.ij * cor);
+                const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                if (BLK) {
+                    out[(size_t)a.seed0 * (4 * Np) + vv * Np + lt] = ttv - Rd;
+                } else {
+                    out[vv * EN + id] = ttv - Rd;
+                }
+            }
+        }
+    }
+}
+
 // every element of every member case is affine (the geometry pass's flags, read back by
 // fr_set_geometry)
 inline bool group_affine(const Solver& sv, const Group& gr) {
@@ -1176,8 +1428,16 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
     if constexpr (MODE == MODE_LIN || MODE == MODE_LINBLK) {
         constexpr bool B = MODE == MODE_LINBLK;
         if (!a.fpack || !a.spack || (!B && !a.v)) { fr_set_error("linearised operator without packs"); return FR_EINVAL; }
-        hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s,
-                           ga, a, op);
+        bool aff = false;
+        if constexpr (!MOV) {
+            aff = group_affine(sv, gr);
+            if (aff)
+                hipLaunchKernelGGL((k_lin_aff<P, VISC, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads),
+                                   0, s, ga, a, op);
+        }
+        if (!aff)
+            hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0,
+                               s, ga, a, op);
     } else {
         if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
         bool aff = false;

@@ -407,8 +407,15 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
         FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
     }
     const bool graph = sv.use_graph;
+    // the operator kernel of a group depends on whether its elements are all affine
+    std::vector<char> aff(sv.groups.size());
+    for (size_t g = 0; g < sv.groups.size(); ++g) {
+        bool all = true;
+        for (int id : sv.groups[g].ids) all = all && sv.cs[id]->all_affine;
+        aff[g] = all ? 1 : 0;
+    }
     if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec || sv.graph_passes != sv.gs_passes ||
-                  sv.graph_precond != sv.precond)) {
+                  sv.graph_precond != sv.precond || sv.graph_aff != aff)) {
         gmres_release(sv);
         // capture one cycle (all buffers are solver-owned; tolerances, time coefficients and
         // caps are read on the device, so the graph depends on m, the block precision, the
@@ -428,6 +435,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
         sv.graph_prec = prec;
         sv.graph_passes = sv.gs_passes;
         sv.graph_precond = sv.precond;
+        sv.graph_aff = aff;
     }
     double* hs = sv.h_pin;
     for (;;) {

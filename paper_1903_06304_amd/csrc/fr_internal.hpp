@@ -48,10 +48,11 @@ enum FrMode { MODE_R = 0, MODE_JVP = 1, MODE_AOP = 2, MODE_BLK = 3, MODE_PREP = 
 
 // Linearisation packs of a state (written by MODE_PREP, read by MODE_LIN): the values the
 // Newton operator's nonlinear point functions need, so that its staged data are tangents.
-//   face pack [NPF][E][4n]: own and neighbour traces q^-, q^+ (4 + 4), uncorrected
-//                           gradient traces g^-, g^+ (6 + 6, viscous only)
+//   face pack [NPF][E][4n]: own and neighbour traces q^-, q^+ (4 + 4) and the sum of the
+//                           uncorrected gradient traces g^- + g^+ (6, viscous only: the BR2
+//                           common gradient depends on the two only through their sum)
 //   point pack [NPS][E][Np]: q (4) and the corrected gradient (6, viscous only)
-constexpr int npf(bool visc) { return visc ? 20 : 8; }
+constexpr int npf(bool visc) { return visc ? 14 : 8; }
 constexpr int nps(bool visc) { return visc ? 10 : 4; }
 
 // Device view of one case (one mesh) of a solver.  A solver concatenates the state
@@ -219,6 +220,7 @@ struct Solver {
     bool use_graph = true;
     void* graph_exec = nullptr;
     int graph_m = 0, graph_prec = -1, graph_passes = 0, graph_precond = -1;
+    std::vector<char> graph_aff;           // per group: all members affine when the cycle was captured
     int gs_passes = 1;                     // classical Gram-Schmidt passes per Arnoldi step (1 or 2)
     size_t N(int c) const { return (size_t)4 * cs[c]->E * cs[c]->Np; }
 };
