@@ -620,6 +620,9 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
     const int f = (lt % NF) / n, k = lt % n;
     int tile, tend, tstride;
     tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
+    // connectivity of the next tile of this workgroup, requested one tile ahead (persistent grids)
+    int pkn[4] = {0, 0, 0, 0};
+    int pkn_tile = -1;
     for (; tile < tend; tile += tstride) {
         const int lo = find_member(ga, tile);
         const int cid = sld(ga.ids + lo);
@@ -637,10 +640,11 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         // through this face point: trace and face-normal derivative
         LaneGeo lg;
         double qp[4], dnor[3];
+        const bool pre = pkn_tile == tile;
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : gld(g.nbr + e * 4 + ff);
             const unsigned id = (unsigned)e * Np + lt % Np;
             double qo[4];
 #pragma unroll
@@ -678,6 +682,16 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             if (lt < Np) {
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+            }
+        }
+        {
+            const int tn = tile + tstride;
+            const int pfx_hi = lo + 1 < ga.nmem ? sld(ga.pfx + lo + 1) : ga.ntiles;
+            pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
+            const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
+            if (pkn_tile >= 0 && en < E) {
+#pragma unroll
+                for (int ff = 0; ff < 4; ++ff) pkn[ff] = gld(g.nbr + en * 4 + ff);
             }
         }
         __syncthreads();
@@ -1185,6 +1199,8 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
     const int f = (lt % NF) / n, k = lt % n;
     int tile, tend, tstride;
     tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
+    int pkn[4] = {0, 0, 0, 0};   // connectivity of the next tile, requested one tile ahead
+    int pkn_tile = -1;
     for (; tile < tend; tile += tstride) {
         const int lo = find_member(ga, tile);
         const int cid = sld(ga.ids + lo);
@@ -1203,10 +1219,11 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
         // ---- stage 1: own tangent; the neighbour's tangent line through this face point
         LaneGeo lg;
         double qpt[4], dnort[3];
+        const bool pre = pkn_tile == tile;
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : gld(g.nbr + e * 4 + ff);
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             double qo[4];
@@ -1246,6 +1263,16 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             if (lt < Np) {
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+            }
+        }
+        {
+            const int tn = tile + tstride;
+            const int pfx_hi = lo + 1 < ga.nmem ? sld(ga.pfx + lo + 1) : ga.ntiles;
+            pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
+            const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
+            if (pkn_tile >= 0 && en < E) {
+#pragma unroll
+                for (int ff = 0; ff < 4; ++ff) pkn[ff] = gld(g.nbr + en * 4 + ff);
             }
         }
         __syncthreads();
