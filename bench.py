@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--order", type=int, default=3)
     ap.add_argument("--nr", type=int, default=40, help="residual evaluations per step")
     ap.add_argument("--nj", type=int, default=10, help="JVP evaluations per step")
+    ap.add_argument("--nv", type=int, default=10, help="VJP evaluations per step")
     ap.add_argument("--dt", type=float, default=1e-3, help="physical time step of the BDF2 step")
     ap.add_argument("--max-lin-it", type=int, default=200)
     ap.add_argument("--precs", default="fp64,fp32,bf16")
@@ -132,7 +133,6 @@ def main():
     qs = [q0 * (1.0 + 1e-3 * torch.tensor(rng.standard_normal(q0.shape), device=dev)) for _ in range(nsets)]
     Rs = [torch.empty_like(q0) for _ in range(nsets)]
     vdir = torch.tensor(rng.standard_normal(q0.shape), device=dev)
-    Jv = torch.empty_like(q0)
     stream = torch.cuda.current_stream()
 
     # BDF2 start: one BDF1 step gives (q^n, q^{n-1}); every timed step restarts from it
@@ -167,9 +167,15 @@ def main():
         t2 = torch.cuda.Event(enable_timing=True); t3 = torch.cuda.Event(enable_timing=True)
         t2.record(stream)
         for k in range(args.nj):
-            Jv.copy_(ctx.jvp(qs[k % nsets], vdir))
+            ctx.jvp(qs[k % nsets], vdir, out=Rs[k % nsets])
         t3.record(stream)
         ev["jvp"] = (t2, t3)
+        t4 = torch.cuda.Event(enable_timing=True); t5 = torch.cuda.Event(enable_timing=True)
+        t4.record(stream)
+        for k in range(args.nv):
+            ctx.vjp(qs[k % nsets], vdir, out=Rs[k % nsets])
+        t5.record(stream)
+        ev["vjp"] = (t4, t5)
         stats = {}
         if not args.no_bdf2:
             for pr in precs:
@@ -235,6 +241,8 @@ def main():
 
     res_ms = mean_ms("res") / args.nr          # per residual evaluation
     jvp_ms = mean_ms("jvp") / args.nj
+    vjp_ms = mean_ms("vjp") / max(args.nv, 1)
+    alg_j = algorithmic_bytes_jvp(E, args.order)
     value = dof / (res_ms * 1e-3)
     alg_b = algorithmic_bytes_residual(E, args.order)
     achieved = alg_b / (res_ms * 1e-3) / 1e9
@@ -258,6 +266,10 @@ def main():
         "autotune_s": t_tune,
         "jvp_ms": jvp_ms,
         "jvp_dof_per_s": dof / (jvp_ms * 1e-3),
+        "jvp_hbm_frac": alg_j / (jvp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "vjp_ms": vjp_ms,
+        "vjp_dof_per_s": dof / (vjp_ms * 1e-3),
+        "vjp_hbm_frac": alg_j / (vjp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "fused::k_fused<p, viscous, static, R> (fr_residual)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.order, args.nx), "algorithmic_bytes": alg_b},

@@ -181,16 +181,16 @@ class Context:
         _check(load_library().fr_residual(self.h, _ptr(q), _ptr(R), _stream()))
         return R
 
-    def jvp(self, q, v, want_residual=False):
+    def jvp(self, q, v, want_residual=False, out=None):
         q, v = self._state(q), self._state(v)
-        Jv = torch.empty_like(q)
+        Jv = torch.empty_like(q) if out is None else out
         R = torch.empty_like(q) if want_residual else None
         _check(load_library().fr_jvp(self.h, _ptr(q), _ptr(v), _ptr(Jv), _ptr(R), _stream()))
         return (Jv, R) if want_residual else Jv
 
-    def vjp(self, q, w):
+    def vjp(self, q, w, out=None):
         q, w = self._state(q), self._state(w)
-        out = torch.empty_like(q)
+        out = torch.empty_like(q) if out is None else out
         _check(load_library().fr_vjp(self.h, _ptr(q), _ptr(w), _ptr(out), _stream()))
         return out
 
