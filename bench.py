@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-bdf2", action="store_true")
+    ap.add_argument("--no-steady", action="store_true", help="skip the steady pseudo-transient solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20, help="oracle residual evaluations timed")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-case batched workload")
@@ -319,9 +320,46 @@ def main():
                 bd["bdf2_" + pr]["max_rel_diff_vs_fp64"] = d
                 bd["bdf2_" + pr]["speedup_vs_fp64"] = bd["bdf2_fp64"]["ms"] / bd["bdf2_" + pr]["ms"]
         out["batch"] = bd
+    if not args.no_steady:
+        out["steady"] = steady_solve(torch, lmfr, I, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def steady_solve(torch, lmfr, I, dev):
+    """Steady pseudo-transient solve with SER (once, outside the timed steps): NS p=3 16x16 on
+    [0, 2 pi]^2, Ma = 0.1, Re = 100, uniform flow plus a solenoidal velocity perturbation
+    (rms 0.1) and a pressure perturbation, to the uniform steady state; dtau0 = dtau_min = 1,
+    dtau_max = 1e20, r_ser = 2, GMRES(150) with the block Gauss-Seidel preconditioner."""
+    import numpy as np
+    mesh = I.Mesh(16, 16, 3, (0.0, 2 * np.pi, 0.0, 2 * np.pi))
+    prm = I.Params(order=3, n_elem=mesh.E, mach_ref=0.1, reynolds=100.0, viscous=True, kappa=1.0)
+    q = I.uniform_flow(mesh, prm)
+    rng = np.random.default_rng(0)
+    du, dv = I.random_solenoidal_velocity(mesh, rng, rms=0.1)
+    q[1] += du
+    q[2] += dv
+    q[0] *= 1 + 0.01 * prm.gamma * prm.mach_ref ** 2 * I.random_scalar_field(mesh, rng)
+    nbr, nbf, flip = mesh.connectivity()
+    g = lmfr.Context(prm, nbr, nbf, flip)
+    g.set_geometry(*mesh.nodes(0.0))
+    g.set_option("preconditioner", 1)
+    q0 = torch.tensor(q, device=dev)
+    floor = 10.0 * residual_noise(g, q0, torch)
+    kw = dict(dtau0=1.0, dtau_min=1.0, tol_pseudo=1e-10, tol_abs=floor, tol_res=1e-6, krylov=150, max_lin_it=1500,
+              max_steps=25, check=False)
+    g.steady_solve(q0.clone(), **kw)   # warm-up (allocations, graph capture)
+    qg = q0.clone()
+    a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    st = g.steady_solve(qg, **kw)
+    b.record()
+    torch.cuda.synchronize()
+    return {"workload": "NS p=3 16x16 periodic, Ma=0.1, Re=100, perturbed uniform flow to its steady state",
+            "ms": a.elapsed_time(b), "steps": st["steps"], "gmres_its": st["gmres_its"],
+            "converged": st["converged"], "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
+            "dtau_final": st["dtau_final"], "preconditioner": "block Gauss-Seidel", "krylov": 150}
 
 
 def setup_batch(args, torch, lmfr, I, dev):
