@@ -586,21 +586,22 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 template <int P, bool VISC, int MODE, int LANES>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
-    static_assert(MODE == MODE_R || MODE == MODE_PREP, "plain-value modes only");
+    static_assert(MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP, "residual, packs or JVP");
+    using T = typename ModeT<MODE, 1>::T;
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
     constexpr int EPB = Shape<P, LANES>::EPB;
-    using PD = LPad<P, 1>;
+    using PD = LPad<P, Store<T>::W>;
     constexpr int FS = Np + PD::F;
     constexpr int ESQ = 4 * FS + PD::E;
     constexpr int ESW = 8 * FS + PD::E;      // F~ of the 4 equations, then G~
     constexpr int NG = VISC ? 6 : 1;
     constexpr int ESG = NG * FS + PD::E;
     constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1;
-    __shared__ double s_q[EPB * ESQ];       // own state [el][var][point]
-    __shared__ double s_w[EPB * ESW];       // F~, G~ [el][8][point]
-    __shared__ double s_g[EPB * ESG];       // own uncorrected gradient [el][6][point]
-    __shared__ double s_F[EPB * ESF];       // neighbour traces of (u, v, T) by neighbour point; then F^num - F^loc
-    __shared__ double s_dq[EPB * ESD];      // q^com - q^- of (u, v, T)
+    __shared__ T s_q[EPB * ESQ];       // own state [el][var][point]
+    __shared__ T s_w[EPB * ESW];       // F~, G~ [el][8][point]
+    __shared__ T s_g[EPB * ESG];       // own uncorrected gradient [el][6][point]
+    __shared__ T s_F[EPB * ESF];       // neighbour traces of (u, v, T) by neighbour point; then F^num - F^loc
+    __shared__ T s_dq[EPB * ESD];      // q^com - q^- of (u, v, T)
     auto QI = [](int el, int v, int sp) { return el * ESQ + v * FS + sp; };
     auto WI = [](int el, int fld, int sp) { return el * ESW + fld * FS + sp; };
     auto GI = [](int el, int c, int sp) { return el * ESG + c * FS + sp; };
@@ -635,35 +636,38 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         const bool act = e < E;
         const unsigned EN = (unsigned)E * Np;
         const double* q = a.q + cd.off;
+        const double* v = a.v ? a.v + cd.off : nullptr;
         __syncthreads();   // the previous tile's readers of LDS are done
         // ---- stage 1: own state into LDS; the lane's metric terms; the neighbour's line
         // through this face point: trace and face-normal derivative
         LaneGeo lg;
-        double qp[4], dnor[3];
+        T qp[4], dnor[3];
         const bool pre = pkn_tile == tile;
         if (act) {
             int pk4[4];
 #pragma unroll
             for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : gld(g.nbr + e * 4 + ff);
-            const unsigned id = (unsigned)e * Np + lt % Np;
-            double qo[4];
+            const int ls = lt % Np;
+            const unsigned id = (unsigned)e * Np + ls;
+            T qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = q[vv * EN + id];
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + ls);
             lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
             if (lt < NF) {
                 const unsigned nbase = (unsigned)lg.nb * Np;
-                double ln[4][n];
+                T ln[4][n];
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
-                    const unsigned sp = nbase + line_pt(n, lg.nf, lg.k2, b);
+                    const int sp = line_pt(n, lg.nf, lg.k2, b);
 #pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) ln[vv][b] = q[vv * EN + sp];
+                    for (int vv = 0; vv < 4; ++vv)
+                        ln[vv][b] = NbLoad<T>::load(a, q, v, vv * EN + nbase + sp, vv * Np + sp, lg.nb == e);
                 }
                 const double* lamn = s_lam[lg.nf & 1];
                 const double* dlamn = s_dlam[lg.nf & 1];
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) {
-                    double acc = 0.0;
+                    T acc = cst<T>(0.0);
 #pragma unroll
                     for (int b = 0; b < n; ++b) acc = acc + lamn[b] * ln[vv][b];
                     qp[vv] = acc;
@@ -671,7 +675,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                 if (VISC) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        double acc = 0.0;
+                        T acc = cst<T>(0.0);
 #pragma unroll
                         for (int b = 0; b < n; ++b) acc = acc + dlamn[b] * ln[c + 1][b];
                         dnor[c] = acc;
@@ -699,7 +703,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         if (VISC && act && lt < Np) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double dxi = 0.0, deta = 0.0;
+                T dxi = cst<T>(0.0), deta = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
                     dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
@@ -711,14 +715,14 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         }
         __syncthreads();
         // ---- stage 3: own traces, common flux at the flux points
-        double fsc[4];
+        T fsc[4];
         if (act && lt < NF) {
             const double* lam = s_lam[f & 1];
             const double nx = lg.nx, ny = lg.ny, sc = lg.sc;
-            double qm[4];
+            T qm[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                double acc = 0.0;
+                T acc = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
                 qm[vv] = acc;
@@ -729,23 +733,23 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) { fpk[vv * fs] = qm[vv]; fpk[(4 + vv) * fs] = qp[vv]; }
             }
-            double fn[4], dq[4];
-            fr_common_inviscid<double>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
+            T fn[4], dq[4];
+            fr_common_inviscid<T>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
             if (VISC) {
-                double gm[6], gp[6];
+                T gm[6], gp[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
-                    double acc = 0.0;
+                    T acc = cst<T>(0.0);
 #pragma unroll
                     for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
                     gm[c] = acc;
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    double dtan = 0.0;
+                    T dtan = cst<T>(0.0);
 #pragma unroll
                     for (int m = 0; m < n; ++m) dtan = dtan + s_D[lg.k2 * n + m] * s_F[FI(el, c, f * n + m)];
-                    const double dxi = lg.nf < 2 ? dnor[c] : dtan, deta = lg.nf < 2 ? dtan : dnor[c];
+                    const T dxi = lg.nf < 2 ? dnor[c] : dtan, deta = lg.nf < 2 ? dtan : dnor[c];
                     gp[2 * c] = lg.mxix * dxi + lg.metx * deta;
                     gp[2 * c + 1] = lg.mxiy * dxi + lg.mety * deta;
                 }
@@ -755,10 +759,10 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
                     for (int c = 0; c < 6; ++c) fpk[(8 + c) * fs] = gm[c] + gp[c];   // the common flux needs the sum only
                 }
-                const double qcu = qm[1] + 0.5 * dq[1];
-                const double qcv = qm[2] + 0.5 * dq[2];
-                double dqh[3];
-                fr_common_viscous<double>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
+                const T qcu = qm[1] + 0.5 * dq[1];
+                const T qcv = qm[2] + 0.5 * dq[2];
+                T dqh[3];
+                fr_common_viscous<T>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c];
             }
@@ -768,10 +772,10 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         __syncthreads();
         // ---- stage 4: corrected gradient, point fluxes in contravariant form
         if (act && lt < Np) {
-            double qs[4];
+            T qs[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[QI(el, vv, lt)];
-            double gu[2], gv[2], gT[2];
+            T gu[2], gv[2], gT[2];
             if (VISC) {
 #pragma unroll
                 for (int d = 0; d < 2; ++d) { gu[d] = s_g[GI(el, d, lt)]; gv[d] = s_g[GI(el, 2 + d, lt)]; gT[d] = s_g[GI(el, 4 + d, lt)]; }
@@ -779,11 +783,11 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                 // vectors are |J| grad(xi) (faces 0, 1) and |J| grad(eta) (faces 2, 3), and |J| / |J| = 1
                 const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
                 const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
-                double* gr[3] = {gu, gv, gT};
+                T* gr[3] = {gu, gv, gT};
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double lx = gL_i * s_dq[DI(el, c, fp0)] + gR_i * s_dq[DI(el, c, fp1)];
-                    const double le = gL_j * s_dq[DI(el, c, fp2)] + gR_j * s_dq[DI(el, c, fp3)];
+                    const T lx = gL_i * s_dq[DI(el, c, fp0)] + gR_i * s_dq[DI(el, c, fp1)];
+                    const T le = gL_j * s_dq[DI(el, c, fp2)] + gR_j * s_dq[DI(el, c, fp3)];
                     gr[c][0] = gr[c][0] + (lg.xix * lx + lg.etx * le);
                     gr[c][1] = gr[c][1] + (lg.xiy * lx + lg.ety * le);
                 }
@@ -801,8 +805,8 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                     }
                 }
             }
-            double fl[4], gl[4], qc[4];
-            fr_point_flux<double, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
+            T fl[4], gl[4], qc[4];
+            fr_point_flux<T, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
                 s_w[WI(el, vv, lt)] = lg.xix * fl[vv] + lg.xiy * gl[vv];
@@ -817,7 +821,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             const int base = f < 2 ? 0 : 4;
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                double acc = 0.0;
+                T acc = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
                 s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
@@ -830,15 +834,21 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             double* out = a.out + cd.off;
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
-                double dF = 0.0, dG = 0.0;
+                T dF = cst<T>(0.0), dG = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
                     dF = dF + s_D[i * n + b] * s_w[WI(el, vv, b + n * j)];
                     dG = dG + s_D[j * n + b] * s_w[WI(el, 4 + vv, i + n * b)];
                 }
-                const double cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
-                                 + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
-                out[vv * EN + id] = -(dF + dG + lg.ij * cor);
+                const T cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
+                            + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
+                const T R = -(dF + dG + lg.ij * cor);
+                if constexpr (MODE == MODE_JVP) {
+                    out[vv * EN + id] = R.d[0];
+                    if (a.out2) a.out2[cd.off + vv * EN + id] = R.v;
+                } else {
+                    out[vv * EN + id] = R;
+                }
             }
         }
     }
@@ -1468,8 +1478,9 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
     } else {
         if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
         bool aff = false;
-        if constexpr (!MOV && (MODE == MODE_R || MODE == MODE_PREP)) aff = group_affine(sv, gr);
-        if constexpr (!MOV && (MODE == MODE_R || MODE == MODE_PREP)) {
+        constexpr bool has_aff = !MOV && (MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP);
+        if constexpr (has_aff) aff = group_affine(sv, gr);
+        if constexpr (has_aff) {
             if (aff) {
                 hipLaunchKernelGGL((k_fused_aff<P, VISC, MODE, LANES>), dim3(grid_of(ga.ntiles, grid)),
                                    dim3(SH::threads), 0, s, ga, a, op);
