@@ -586,7 +586,8 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 template <int P, bool VISC, int MODE, int LANES>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
-    static_assert(MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP, "residual, packs or JVP");
+    static_assert(MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP || MODE == MODE_AOP,
+                  "residual, packs, JVP or Newton operator");
     using T = typename ModeT<MODE, 1>::T;
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
     constexpr int EPB = Shape<P, LANES>::EPB;
@@ -832,6 +833,15 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         if (act && lt < Np) {
             const unsigned id = (unsigned)e * Np + lt;
             double* out = a.out + cd.off;
+            double tt[4] = {0.0, 0.0, 0.0, 0.0};   // time terms of the Newton operator
+            if constexpr (MODE == MODE_AOP) {
+                double ct = a.c_time, idt = a.inv_dtau;
+                if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
+                double qv[4], x[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) { const T w = s_q[QI(el, vv, lt)]; qv[vv] = w.v; x[vv] = w.d[0]; }
+                fr_time_apply<double, double>(pc, qv, 0.0, 0.0, idt, ct, x, tt);
+            }
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
                 T dF = cst<T>(0.0), dG = cst<T>(0.0);
@@ -846,6 +856,9 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                 if constexpr (MODE == MODE_JVP) {
                     out[vv * EN + id] = R.d[0];
                     if (a.out2) a.out2[cd.off + vv * EN + id] = R.v;
+                } else if constexpr (MODE == MODE_AOP) {
+                    const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                    out[vv * EN + id] = ttv - R.d[0];
                 } else {
                     out[vv * EN + id] = R;
                 }
@@ -1478,7 +1491,7 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
     } else {
         if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
         bool aff = false;
-        constexpr bool has_aff = !MOV && (MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP);
+        constexpr bool has_aff = !MOV && (MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP || MODE == MODE_AOP);
         if constexpr (has_aff) aff = group_affine(sv, gr);
         if constexpr (has_aff) {
             if (aff) {
