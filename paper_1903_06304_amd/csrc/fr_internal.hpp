@@ -133,6 +133,7 @@ struct Tune {
 
 struct Group {
     int p, visc, mov;
+    bool aff0 = false;                       // all members affine when the solver was made
     std::vector<int> ids;
     int* d_ids = nullptr;
     std::vector<std::pair<int, int*>> pfx;   // tile width (elements) -> device prefix

@@ -76,18 +76,23 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
     FR_TRY(upload(&sv.d_cases, cd));
     FR_TRY(upload(&sv.d_chunk_case, chunk_case));
     FR_TRY(upload(&sv.d_case_chunk, case_chunk));
-    // launch groups
+    // launch groups: cases of one order, viscous and moving kind, and (as the geometry stands
+    // when the solver is made) affine or not, so that a case runs the same kernel variant alone
+    // and in a batch; whether a group is affine is checked again at every launch
     for (int c = 0; c < n; ++c) {
         const fr_ctx x = ctxs[c];
         Group* g = nullptr;
         for (Group& h : sv.groups)
-            if (h.p == x->p && h.visc == (x->prm.viscous != 0) && h.mov == (x->prm.moving != 0)) g = &h;
+            if (h.p == x->p && h.visc == (x->prm.viscous != 0) && h.mov == (x->prm.moving != 0) &&
+                h.aff0 == x->all_affine)
+                g = &h;
         if (!g) {
             sv.groups.emplace_back();
             g = &sv.groups.back();
             g->p = x->p;
             g->visc = x->prm.viscous != 0;
             g->mov = x->prm.moving != 0;
+            g->aff0 = x->all_affine;
         }
         g->ids.push_back(c);
         g->elems.push_back(x->E);

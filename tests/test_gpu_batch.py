@@ -269,6 +269,32 @@ def test_batch_mixed_kinds_residual_and_step():
         assert torch.equal(xb, xs), c.name
 
 
+def test_batch_affine_and_curved_cases_of_one_kind():
+    """A static affine and a static curved case of the same order: the batch gives each the
+    kernel variant it runs alone (affine / general), so results equal the single contexts'
+    bit for bit; the affine case also takes the affine kernels inside the batch's GMRES."""
+    lmfr = _lmfr()
+    cases = [I.config_c4(nx=6, p=3), I.config_c2(nx=5, p=3), I.config_c4(nx=3, p=3)]
+    ctxs = [_context(c, 0.0) for c in cases]
+    assert [g.affine_elements() for g in ctxs] == [36, 0, 9]
+    b = lmfr.Batch(ctxs)
+    Rs = b.unpack(b.residual(b.pack([_dev(c.q) for c in cases])))
+    for c, g, Rb in zip(cases, ctxs, Rs):
+        assert torch.equal(Rb, g.residual(_dev(c.q))), c.name
+    dts = [5e-3, 2e-3, 1e-2]
+    qb = [_dev(c.q) for c in cases]
+    rc, stats = b.bdf2_step(qb, None, _opts(dts, "fp64"))
+    torch.cuda.synchronize()
+    assert rc == lmfr.FR_OK, rc
+    for c, g, dt, xb, st in zip(cases, ctxs, dts, qb, stats):
+        xs = _dev(c.q)
+        ss = g.bdf2_step(xs, None, dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=12, max_lin_it=300, max_newton=20,
+                         jac_lag=2, prec="fp64")
+        torch.cuda.synchronize()
+        assert (st["newton_its"], st["gmres_its"]) == (ss["newton_its"], ss["gmres_its"]), c.name
+        assert torch.equal(xb, xs), c.name
+
+
 def test_step_status_non_finite_and_iteration_cap():
     """A non-finite state is reported as FR_ENONFINITE for its case only; a Newton cap of
     zero iterations reports FR_ENOCONV and leaves the state unchanged."""
