@@ -153,7 +153,10 @@ struct Ctx {
     int p, n, Np, pg, ng, E, viscous, moving;
     double gam, Ma, Re, Pr, mu, kappa, Ma_inf, Rg, Cp, kc;
     Ops op;
+    // nbr[e*4+f] >= 0: neighbour element; < 0: boundary face of kind -nbr (1 far field,
+    // 2 slip wall, 3 adiabatic no-slip wall)
     std::vector<int> nbr, nbr_face; std::vector<signed char> flip;
+    double qinf[4] = {0.0, 0.0, 0.0, 0.0};   // far-field primitive state (p, u, v, T)
     // geometry at solution points, [E][Np]
     std::vector<double> xs, ys, jac, xix, xiy, etx, ety, ugs, vgs;
     // per element side [E][4][n]: element-oriented face vector S = |J| grad(xi) (faces 0,1)
@@ -226,7 +229,7 @@ static void build_geometry(Ctx& c) {
     for (int e = 0; e < E; ++e)
         for (int f = 0; f < 4; ++f) {
             int e2 = c.nbr[e * 4 + f], f2 = c.nbr_face[e * 4 + f], fl = c.flip[e * 4 + f];
-            bool own = (e * 4 + f) <= (e2 * 4 + f2);
+            bool own = e2 < 0 || (e * 4 + f) <= (e2 * 4 + f2);
             for (int k = 0; k < n; ++k) {
                 size_t id = ((size_t)e * 4 + f) * n + k;
                 if (own) { c.Sx[id] = sx[id]; c.Sy[id] = sy[id]; c.ugf[id] = ug[id]; c.vgf[id] = vg[id]; continue; }
@@ -374,6 +377,55 @@ struct NSPhys {
         T gv[4] = {T(0.0), ir * txy, ir * tyy, ir * (u * txy + v * tyy + C.kc * gy[3])};
         for (int r = 0; r < 4; ++r) fn[r] -= fv[r] * nx + gv[r] * ny;
     }
+    // Sec. "Boundary Conditions": the state on the far side of a boundary face, which then
+    // enters the same common flux as an interior neighbour's trace (the approximate Riemann
+    // solver enforces the condition).  n: unit outward normal, (ug, vg): face velocity.
+    //  1 far field: the free stream q^inf, uniform (zero gradient);
+    //  2 slip wall: the mirror image of the own side across the wall, with the velocity
+    //    taken relative to the moving wall (reading: a symmetry plane, so that viscous
+    //    terms see the mirrored gradients too);
+    //  3 adiabatic no-slip wall: velocity 2 v_wall - v (the average is the wall velocity),
+    //    same p and T, same velocity gradient, temperature gradient mirrored (the average
+    //    has no normal component: no heat flux through the wall).
+    template <class T> void exterior(int kind, const T* qL, const T* gxL, const T* gyL, double nx, double ny,
+                                     double ug, double vg, T* qR, T* gxR, T* gyR) const {
+        const Ctx& C = *c;
+        if (kind == 1) {
+            for (int r = 0; r < 4; ++r) { qR[r] = C.qinf[r]; gxR[r] = 0.0; gyR[r] = 0.0; }
+            return;
+        }
+        // reflection across the wall line: Rm = I - 2 n n^T
+        const double Rm[2][2] = {{1.0 - 2.0 * nx * nx, -2.0 * nx * ny}, {-2.0 * ny * nx, 1.0 - 2.0 * ny * ny}};
+        const double w[2] = {ug, vg};
+        auto mirror_vec = [&](const T* a, T* b) {   // b = Rm a
+            for (int r = 0; r < 2; ++r) b[r] = Rm[r][0] * a[0] + Rm[r][1] * a[1];
+        };
+        qR[0] = qL[0]; qR[3] = qL[3];
+        T gp[2] = {gxL[0], gyL[0]}, gT[2] = {gxL[3], gyL[3]}, mp[2], mT[2];
+        mirror_vec(gT, mT);
+        gxR[3] = mT[0]; gyR[3] = mT[1];
+        if (kind == 2) {
+            T rel[2] = {qL[1] - w[0], qL[2] - w[1]}, mr[2];
+            mirror_vec(rel, mr);
+            qR[1] = w[0] + mr[0]; qR[2] = w[1] + mr[1];
+            mirror_vec(gp, mp);
+            gxR[0] = mp[0]; gyR[0] = mp[1];
+            // velocity gradient G[a][b] = d u_a / d x_b of the mirror image: Rm G Rm
+            T G[2][2] = {{gxL[1], gyL[1]}, {gxL[2], gyL[2]}}, H[2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    T acc = 0.0;
+                    for (int k = 0; k < 2; ++k)
+                        for (int l = 0; l < 2; ++l) acc += Rm[a][k] * G[k][l] * Rm[l][b];
+                    H[a][b] = acc;
+                }
+            gxR[1] = H[0][0]; gyR[1] = H[0][1]; gxR[2] = H[1][0]; gyR[2] = H[1][1];
+        } else {
+            qR[1] = 2.0 * w[0] - qL[1]; qR[2] = 2.0 * w[1] - qL[2];
+            gxR[0] = gxL[0]; gyR[0] = gyL[0];
+            gxR[1] = gxL[1]; gyR[1] = gyL[1]; gxR[2] = gxL[2]; gyR[2] = gyL[2];
+        }
+    }
 };
 
 // Scalar advection-diffusion physics (1 variable): f = a_x u - nu u_x, g = a_y u - nu u_y,
@@ -397,6 +449,11 @@ struct ScalarPhys {
         T gx = 0.5 * ((gxL[0] + cL * (qcom[0] - qL[0]) * nx) + (gxR[0] - cR * (qcom[0] - qR[0]) * nx));
         T gy = 0.5 * ((gyL[0] + cL * (qcom[0] - qL[0]) * ny) + (gyR[0] - cR * (qcom[0] - qR[0]) * ny));
         fn[0] -= nu * (gx * nx + gy * ny);
+    }
+    // the scalar path checks the interior machinery only: a boundary face sees its own trace
+    template <class T> void exterior(int, const T* qL, const T* gxL, const T* gyL, double, double, double, double,
+                                     T* qR, T* gxR, T* gyR) const {
+        qR[0] = qL[0]; gxR[0] = gxL[0]; gyR[0] = gyL[0];
     }
 };
 
@@ -459,7 +516,7 @@ static void element_residual(const Ctx& c, const Phys& ph, int e, const T* q, Tr
         int e2 = c.nbr[e * 4 + f], f2 = c.nbr_face[e * 4 + f], fl = c.flip[e * 4 + f];
         for (int k = 0; k < n; ++k) {
             int k2 = fl ? n - 1 - k : k;
-            size_t sid = ((size_t)e * 4 + f) * n + k, sid2 = ((size_t)e2 * 4 + f2) * n + k2;
+            size_t sid = ((size_t)e * 4 + f) * n + k, sid2 = e2 >= 0 ? ((size_t)e2 * 4 + f2) * n + k2 : sid;
             double Sox = face_sign(f) * c.Sx[sid], Soy = face_sign(f) * c.Sy[sid];
             double Smag = std::sqrt(Sox * Sox + Soy * Soy);
             double nx = Sox / Smag, ny = Soy / Smag;
@@ -468,12 +525,22 @@ static void element_residual(const Ctx& c, const Phys& ph, int e, const T* q, Tr
                 qL[v] = tq[((size_t)f * NV + v) * n + k];
                 gxL[v] = tgx[((size_t)f * NV + v) * n + k];
                 gyL[v] = tgy[((size_t)f * NV + v) * n + k];
-                qR[v] = tr.pq(e2)[((size_t)f2 * NV + v) * n + k2];
-                gxR[v] = tr.pgx(e2)[((size_t)f2 * NV + v) * n + k2];
-                gyR[v] = tr.pgy(e2)[((size_t)f2 * NV + v) * n + k2];
+            }
+            double JfR;
+            if (e2 >= 0) {
+                for (int v = 0; v < NV; ++v) {
+                    qR[v] = tr.pq(e2)[((size_t)f2 * NV + v) * n + k2];
+                    gxR[v] = tr.pgx(e2)[((size_t)f2 * NV + v) * n + k2];
+                    gyR[v] = tr.pgy(e2)[((size_t)f2 * NV + v) * n + k2];
+                }
+                JfR = c.Jf[sid2];
+            } else {
+                // boundary face; reading: the BR2 lifting of the far side uses the own |J|
+                ph.exterior(-e2, qL, gxL, gyL, nx, ny, c.ugf[sid], c.vgf[sid], qR, gxR, gyR);
+                JfR = c.Jf[sid];
             }
             T fn[4], qcom[4];
-            ph.common(qL, qR, gxL, gyL, gxR, gyR, nx, ny, Smag, c.Jf[sid], c.Jf[sid2],
+            ph.common(qL, qR, gxL, gyL, gxR, gyR, nx, ny, Smag, c.Jf[sid], JfR,
                       c.ugf[sid], c.vgf[sid], fn, qcom);
             // Eq. (norm_f_2): F^num = |J||grad xi| f_n^com sign(n . grad xi); n is this side's
             // outward normal, so the sign is face_sign(f).
@@ -713,7 +780,7 @@ static std::vector<int> colour_elements(const Ctx& c, int& ncol) {
         bool used[5] = {false, false, false, false, false};
         for (int f = 0; f < 4; ++f) {
             const int nb = c.nbr[e * 4 + f];
-            if (nb != e && col[nb] >= 0) used[col[nb]] = true;
+            if (nb >= 0 && nb != e && col[nb] >= 0) used[col[nb]] = true;
         }
         int k = 0;
         while (used[k]) ++k;
@@ -991,6 +1058,12 @@ void* ora_create(const double* dprm, const int* iprm, const int* nbr, const int*
 
 void ora_destroy(void* h) { delete (Ctx*)h; }
 
+// far-field primitive state (p, u, v, T) of the boundary faces of kind 1
+void ora_set_farfield(void* h, const double* qinf) {
+    Ctx& c = *(Ctx*)h;
+    for (int r = 0; r < 4; ++r) c.qinf[r] = qinf[r];
+}
+
 // geometry at solution points: out[9][E][Np] = x, y, |J|, xi_x, xi_y, eta_x, eta_y, u_g, v_g
 // faces: fout[5][E][4][n] = Sx, Sy, Jf, u_g, v_g
 int ora_geometry(void* h, double* out, double* fout) {
@@ -1058,7 +1131,7 @@ int ora_vjp_dofs(void* h, const double* q, const double* w, const long long* dof
         std::vector<int> els{e};
         for (int f = 0; f < 4; ++f) {
             int e2 = c.nbr[e * 4 + f];
-            if (std::find(els.begin(), els.end(), e2) == els.end()) els.push_back(e2);
+            if (e2 >= 0 && std::find(els.begin(), els.end(), e2) == els.end()) els.push_back(e2);
         }
         double acc = 0.0;
         for (int e2 : els) {

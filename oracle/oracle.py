@@ -128,6 +128,11 @@ class Oracle:
         assert q.size == self.N, (q.shape, self.N)
         return q
 
+    def set_farfield(self, qinf):
+        """Free-stream primitive state (p, u, v, T) seen through the far-field boundary faces."""
+        a = np.ascontiguousarray(qinf, dtype=np.float64).reshape(4)
+        lib().ora_set_farfield(self.h, _p(a))
+
     def geometry(self):
         out = np.zeros((9, self.E, self.Np))
         fout = np.zeros((5, self.E, 4, self.n))

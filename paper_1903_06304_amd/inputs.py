@@ -1,12 +1,16 @@
-"""Seeded synthetic inputs: periodic quadrilateral meshes, their geometry nodes and
-grid velocities, and initial primitive fields (p, u, v, T).
+"""Seeded synthetic inputs: logically structured quadrilateral meshes (periodic, or with
+boundary faces), their geometry nodes and grid velocities, and initial primitive fields
+(p, u, v, T).
 
 This module is shared by the CPU oracle tests, the GPU tests and the benchmark.
 It holds no arithmetic of the discretisation itself: it only places mesh nodes,
 evaluates analytic maps and analytic initial fields, and draws random numbers.
 
 Conventions (also those of the C ABI):
-  * element e = ix + nx*iy on an nx-by-ny logically structured periodic mesh;
+  * element e = ix + nx*iy on an nx-by-ny logically structured mesh, periodic in a
+    direction unless that direction's two sides carry boundary codes;
+  * a boundary face has a negative neighbour entry: BC_FARFIELD (-1), BC_SLIP_WALL
+    (-2), BC_NOSLIP_WALL (-3) (adiabatic); its nbr_face entry is -1;
   * local faces 0: xi=-1, 1: xi=+1, 2: eta=-1, 3: eta=+1; face point k runs
     along the face (eta index on faces 0/1, xi index on faces 2/3);
   * geometry nodes: Gauss-Lobatto tensor grid of degree pg, node (a, b) at index
@@ -24,6 +28,10 @@ import numpy as np
 
 GAMMA = 1.4
 PRANDTL = 0.72
+
+BC_FARFIELD = -1
+BC_SLIP_WALL = -2
+BC_NOSLIP_WALL = -3
 
 
 def gl_points(n: int) -> np.ndarray:
@@ -74,6 +82,19 @@ def map_deforming(amp: float = 0.05, scale: float = 1.0) -> MapFn:
     return f
 
 
+def map_annulus(r0: float = 0.5, r1: float = 50.0) -> MapFn:
+    """O-grid around a cylinder of radius r0 out to radius r1, for a reference domain
+    [0, 1]^2: the angle runs clockwise with xr (periodic in xr, positive Jacobian), the
+    radius grows geometrically with yr (eta = -1 sides of the first row on the cylinder,
+    eta = +1 sides of the last row on the outer circle)."""
+    def f(xr, yr, t):
+        th = -2.0 * np.pi * xr
+        r = r0 * (r1 / r0) ** yr
+        z = np.zeros_like(xr)
+        return r * np.cos(th), r * np.sin(th), z, z.copy()
+    return f
+
+
 def map_vortex_motion(a: float = 1.0, fn: float = 1.0, fx: float = 0.1, fy: float = 0.1) -> MapFn:
     """Prescribed sinusoidal grid motion of the isentropic-vortex case (paper Sec. 4.3)."""
     def f(xr, yr, t):
@@ -93,11 +114,20 @@ class Mesh:
     mapping: MapFn = map_affine
     moving: bool = False
     pg: Optional[int] = None
+    # boundary codes of the sides (xi = -1, xi = +1, eta = -1, eta = +1) of the logical
+    # rectangle; 0 on both sides of a direction makes it periodic
+    bc: tuple = (0, 0, 0, 0)
 
     def __post_init__(self):
         if self.pg is None:
             self.pg = self.p
         self.pg = max(1, self.pg)
+        b = tuple(int(x) for x in self.bc)
+        if len(b) != 4 or any(x not in (0, BC_FARFIELD, BC_SLIP_WALL, BC_NOSLIP_WALL) for x in b):
+            raise ValueError(f"boundary codes must be 0 or -1..-3: {self.bc}")
+        if (b[0] == 0) != (b[1] == 0) or (b[2] == 0) != (b[3] == 0):
+            raise ValueError("a direction is either periodic on both sides or bounded on both")
+        self.bc = b
 
     @property
     def n(self):
@@ -116,7 +146,8 @@ class Mesh:
         return (self.pg + 1) ** 2
 
     def connectivity(self):
-        """Periodic face table: (nbr[E,4] int32, nbr_face[E,4] int32, flip[E,4] int8)."""
+        """Face table (nbr[E,4] int32, nbr_face[E,4] int32, flip[E,4] int8); boundary faces
+        carry their (negative) code in nbr and -1 in nbr_face."""
         nx, ny = self.nx, self.ny
         e = np.arange(nx * ny)
         ix, iy = e % nx, e // nx
@@ -127,6 +158,11 @@ class Mesh:
             ix + nx * ((iy + 1) % ny),
         ], axis=1).astype(np.int32)
         nbr_face = np.tile(np.array([1, 0, 3, 2], np.int32), (nx * ny, 1))
+        edge = [ix == 0, ix == nx - 1, iy == 0, iy == ny - 1]
+        for f in range(4):
+            if self.bc[f]:
+                nbr[edge[f], f] = self.bc[f]
+                nbr_face[edge[f], f] = -1
         flip = np.zeros((nx * ny, 4), np.int8)
         return nbr, nbr_face, flip
 
