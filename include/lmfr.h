@@ -50,6 +50,19 @@ typedef enum {
 
 typedef enum { FR_FP64 = 0, FR_FP32 = 1, FR_BF16 = 2 } fr_prec;
 
+/* Boundary faces (paper Sec. "Boundary Conditions"): a negative h_nbr entry in
+ * fr_create marks a face on the domain boundary and names its condition.  The state
+ * beyond the face, formed from the own trace, enters the same common flux (preconditioned
+ * Rusanov + BR2) as an interior neighbour's trace:
+ *   FR_BC_FARFIELD      the free stream q^inf of fr_set_farfield, uniform (zero gradient);
+ *   FR_BC_SLIP_WALL     the mirror image across the wall, velocity relative to the face's
+ *                       grid velocity (a symmetry plane: gradients mirrored too);
+ *   FR_BC_NOSLIP_WALL   adiabatic no-slip wall moving with the grid: velocity
+ *                       2 v_g - v, same p and T, same velocity gradient, temperature
+ *                       gradient mirrored (no heat flux through the wall).
+ * The BR2 lifting beyond a boundary face uses the own |J|. */
+typedef enum { FR_BC_FARFIELD = -1, FR_BC_SLIP_WALL = -2, FR_BC_NOSLIP_WALL = -3 } fr_bc;
+
 /* Physical and discretisation parameters (paper Sec. 2.1 non-dimensionalisation:
  * R = 1/(gamma mach_ref^2), Cp = 1/((gamma-1) mach_ref^2), k = mu Cp / prandtl;
  * Sec. 2.2 Eq. (eps_nonmove)/(eps_move): eps = min(1, max(kappa mach_inf, Ma))). */
@@ -106,10 +119,20 @@ typedef struct {
 
 /* Create a context for one mesh.  h_nbr/h_nbr_face/h_flip are HOST arrays [n_elem][4]:
  * neighbour element, neighbour's local face and point-order reversal (NULL = none)
- * across each face (periodic meshes only: every face has a neighbour).
- * Returns FR_EUNSUPPORTED for order or geom_order outside 1..4. */
+ * across each face.  An interior face must be listed from both sides; a boundary face
+ * has an fr_bc code in h_nbr (its h_nbr_face and h_flip entries are ignored).  A mesh
+ * with far-field faces needs fr_set_farfield before any evaluation.
+ * Returns FR_EUNSUPPORTED for order or geom_order outside 1..4, FR_EINVAL for a
+ * table that is out of range or not symmetric. */
 fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h_nbr_face,
                     const int8_t* h_flip, fr_ctx* out);
+
+/* Free-stream primitive state (p, u, v, T) beyond the far-field faces (paper Sec.
+ * "Boundary Conditions": q^{p,b} = q^{p,inf}).  h_qinf: HOST array [4].  Synchronous
+ * (a blocking copy): call it while no work of this context is in flight.  Every solver
+ * that holds the context (its own, batches) sees the new state.  FR_EINVAL for a
+ * non-finite entry or p, T <= 0. */
+fr_status fr_set_farfield(fr_ctx ctx, const double* h_qinf);
 
 /* Geometry of the mesh at the time level where the residual is evaluated (paper
  * Sec. 2.3, metrics of the map x(xi, eta, t) and grid velocity v_g = dx/dt):
@@ -121,7 +144,7 @@ fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h
 fr_status fr_set_geometry(fr_ctx ctx, const double* xg, const double* vg, void* stream);
 
 /* Number of elements the last fr_set_geometry found affine: every metric term constant
- * over the element to 1e-10 of its scale.  Where the neighbour across a face is affine,
+ * over the element to 1e-10 of its scale, and no boundary face.  Where the neighbour across a face is affine,
  * the kernels form its gradient trace from its state traces (the chain rule applied to
  * the traced reference derivatives, the same values to rounding) instead of tracing its
  * pointwise gradient.  *n_affine is HOST; synchronises `stream`. */

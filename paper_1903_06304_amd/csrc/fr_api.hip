@@ -157,10 +157,25 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         return bad("fr_create: invalid physical parameters");
     if (prm->viscous && !(prm->reynolds > 0.0)) return bad("fr_create: reynolds must be positive");
     const int E = prm->n_elem;
-    std::vector<int32_t> packed((size_t)E * 4);
+    std::vector<int32_t> packed((size_t)E * 4), bcode((size_t)E, 0);
+    bool any_bc = false, any_far = false;
     for (int e = 0; e < E; ++e)
         for (int f = 0; f < 4; ++f) {
-            const int nb = h_nbr[e * 4 + f], nf = h_nbr_face[e * 4 + f];
+            const int nb = h_nbr[e * 4 + f];
+            if (nb < 0) {
+                // boundary face: its kind in the element's code, the element itself as the
+                // (unused) neighbour so that every gather stays in bounds
+                if (nb < FR_BC_NOSLIP_WALL) return bad("fr_create: unknown boundary code");
+                const int kind = -nb;
+                static_assert(-FR_BC_FARFIELD == BC_FARFIELD && -FR_BC_SLIP_WALL == BC_SLIP &&
+                              -FR_BC_NOSLIP_WALL == BC_WALL, "boundary codes");
+                bcode[e] |= kind << (2 * f);
+                any_bc = true;
+                any_far = any_far || kind == BC_FARFIELD;
+                packed[(size_t)e * 4 + f] = e * 8 + f * 2;
+                continue;
+            }
+            const int nf = h_nbr_face[e * 4 + f];
             const int fl = h_flip ? (h_flip[e * 4 + f] != 0) : 0;
             if (nb < 0 || nb >= E || nf < 0 || nf > 3) return bad("fr_create: neighbour table out of range");
             if (h_nbr[nb * 4 + nf] != e || h_nbr_face[nb * 4 + nf] != f)
@@ -176,7 +191,7 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         bool used[5] = {false, false, false, false, false};
         for (int f = 0; f < 4; ++f) {
             const int nb = h_nbr[e * 4 + f];
-            if (nb != e && colour[nb] >= 0) used[colour[nb]] = true;
+            if (nb >= 0 && nb != e && colour[nb] >= 0) used[colour[nb]] = true;
         }
         int k = 0;
         while (used[k]) ++k;
@@ -211,9 +226,17 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         (st = dalloc(&c->d_aff, (size_t)E)) != FR_OK ||
         (st = dalloc(&c->d_color, (size_t)E)) != FR_OK ||
         (st = dalloc(&c->d_trace, FE * 10)) != FR_OK ||
-        (st = dalloc(&c->d_vj, FE * 10)) != FR_OK) {
+        (st = dalloc(&c->d_vj, FE * 10)) != FR_OK ||
+        (st = dalloc(&c->d_qinf, (size_t)4)) != FR_OK ||
+        (any_bc && (st = dalloc(&c->d_bc, (size_t)E)) != FR_OK)) {
         fr_destroy(c);
         return st;
+    }
+    c->has_farfield = any_far;
+    if (any_bc && hipMemcpy(c->d_bc, bcode.data(), bcode.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        fr_destroy(c);
+        fr_set_error("copy of the boundary codes failed");
+        return FR_EHIP;
     }
     if (hipMemcpy(c->d_nbr, packed.data(), packed.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_color, colour.data(), colour.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
@@ -234,7 +257,7 @@ extern "C" void fr_destroy(fr_ctx c) {
     if (!c) return;
     if (c->self) { solver_free(*c->self); delete c->self; }
     dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_aff); dfree(c->d_color); dfree(c->d_trace);
-    dfree(c->d_vj);
+    dfree(c->d_vj); dfree(c->d_bc); dfree(c->d_qinf);
     delete c;
 }
 
@@ -319,9 +342,19 @@ extern "C" fr_status fr_set_geometry(fr_ctx c, const double* xg, const double* v
     return FR_OK;
 }
 
+extern "C" fr_status fr_set_farfield(fr_ctx c, const double* h_qinf) {
+    if (!c || !h_qinf) return bad("fr_set_farfield: null argument");
+    for (int r = 0; r < 4; ++r)
+        if (!std::isfinite(h_qinf[r])) return bad("fr_set_farfield: non-finite state");
+    if (!(h_qinf[0] > 0.0) || !(h_qinf[3] > 0.0)) return bad("fr_set_farfield: p and T must be positive");
+    FR_HIP(hipMemcpy(c->d_qinf, h_qinf, 4 * sizeof(double), hipMemcpyHostToDevice));
+    c->farfield_set = true;
+    return FR_OK;
+}
+
 static fr_status ready(fr_ctx c) {
     if (!c) return bad("null context");
-    if (!c->geometry_set) return bad("fr_set_geometry has not been called");
+    if (const char* m = ctx_not_ready(c)) return bad(m);
     return FR_OK;
 }
 
@@ -506,7 +539,7 @@ extern "C" fr_status fr_batch_layout(fr_batch b, int64_t* n_total, int64_t* offs
 static fr_status batch_ready(fr_batch b) {
     if (!b) return bad("null batch");
     for (fr_ctx c : b->sv.cs)
-        if (!c->geometry_set) return bad("fr_set_geometry has not been called for every case");
+        if (const char* m = ctx_not_ready(c)) return bad(m);
     return FR_OK;
 }
 

@@ -216,7 +216,7 @@ __device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt
     }
 }
 
-template <int P, bool VISC, bool MOV, int MODE, int K, int LANES>
+template <int P, bool VISC, bool MOV, int MODE, int K, int LANES, bool BC>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused(GroupArgs ga, KArgs a, OpTab op) {
     using T = typename ModeT<MODE, K>::T;
@@ -274,10 +274,12 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         __syncthreads();   // the previous tile's readers of s_n / s_F are done
         // ---- stage 1: own state and neighbour states into LDS; the lane's metric terms
         LaneGeo lg;
+        int bck = 0;   // boundary kind of the lane's face (0: interior)
         if (act) {
             int pk4[4];
 #pragma unroll
             for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            if (BC && g.bc) bck = (gld(g.bc + e) >> (2 * ((lt % NF) / n))) & 3;
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             T qo[4];
@@ -335,6 +337,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                 qm[vv] = am;
                 qp[vv] = ap;
             }
+            if (BC && bck) fr_bc_state<T>(bck, g.qinf, qm, lg.nx, lg.ny, lg.fug, lg.fvg, qp);
             if constexpr (MODE == MODE_PREP) {
                 double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
                 const size_t fs = (size_t)E * NF;
@@ -403,6 +406,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                         }
                     }
                 }
+                if (BC && bck) fr_bc_grad<T>(bck, gm, nx, ny, gp);
                 if constexpr (MODE == MODE_PREP) {
                     double* fpk = a.fpack + cd.fpoff + (size_t)e * NF + lt;
                     const size_t fs = (size_t)E * NF;
@@ -874,7 +878,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
 // values come from the packs.  The tangent arithmetic is the dual-number arithmetic of
 // the other modes term by term (same sums in the same order); the result matches MODE_AOP
 // to a few ulp, where the compiler contracts different products into fused multiply-adds.
-template <int P, bool VISC, bool MOV, int LANES, bool BLK>
+template <int P, bool VISC, bool MOV, int LANES, bool BLK, bool BC>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_lin(GroupArgs ga, KArgs a, OpTab op) {
     using D = Dual<1>;
@@ -929,10 +933,12 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         // ---- stage 1: own and neighbour tangents (block columns: the unit seed of column
         // seed0 in the element itself, and in a neighbour only when it is the element)
         LaneGeo lg;
+        int bck = 0;   // boundary kind of the lane's face (0: interior)
         if (act) {
             int pk4[4];
 #pragma unroll
             for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            if (BC && g.bc) bck = (gld(g.bc + e) >> (2 * ((lt % NF) / n))) & 3;
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             double qo[4];
@@ -989,6 +995,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                 qmt[vv] = am;
                 qpt[vv] = ap;
             }
+            if (BC && bck) fr_bc_state_lin<double>(bck, qmt, lg.nx, lg.ny, qpt);
             if (VISC) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) s_F[FI(el, c, f * n + k2)] = qpt[c + 1];
@@ -1011,12 +1018,14 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             fr_common_inviscid<D>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
             if (VISC) {
                 D gm[6], gp[6];
+                double gmt[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     double am = 0.0;
 #pragma unroll
                     for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
                     gm[c] = mk(fpk[(size_t)(8 + c) * FE + sid], am);
+                    gmt[c] = am;
                 }
                 double gpt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 if (lg.aff) {
@@ -1055,6 +1064,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                         }
                     }
                 }
+                if (BC && bck) fr_bc_grad<double>(bck, gmt, nx, ny, gpt);
 #pragma unroll
                 for (int c = 0; c < 6; ++c) gp[c] = mk(0.0, gpt[c]);   // the pack holds g^- + g^+ in gm
                 // q^com velocity = q^- + dq/2 (the own trace as formed above)
@@ -1485,9 +1495,16 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
                 hipLaunchKernelGGL((k_lin_aff<P, VISC, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads),
                                    0, s, ga, a, op);
         }
-        if (!aff)
-            hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0,
-                               s, ga, a, op);
+        if (!aff) {
+            if (gr.bnd) {
+                if constexpr (LANES <= 128)
+                    hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, true>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
+            } else {
+                hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, false>), dim3(grid_of(ga.ntiles, grid)),
+                                   dim3(SH::threads), 0, s, ga, a, op);
+            }
+        }
     } else {
         if (MODE == MODE_PREP && (!a.fpack || !a.spack)) { fr_set_error("packs missing"); return FR_EINVAL; }
         bool aff = false;
@@ -1500,8 +1517,14 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
             }
         }
         if (!aff) {
-            hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES>), dim3(grid_of(ga.ntiles, grid)),
-                               dim3(SH::threads), 0, s, ga, a, op);
+            if (gr.bnd) {
+                if constexpr (LANES <= 128)
+                    hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, true>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
+            } else {
+                hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, false>), dim3(grid_of(ga.ntiles, grid)),
+                                   dim3(SH::threads), 0, s, ga, a, op);
+            }
         }
     }
     hipError_t e = hipGetLastError();
@@ -1513,7 +1536,8 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
 template <int P, bool VISC, bool MOV, int MODE>
 fr_status run_lanes(const Solver& sv, const Group& gr, const KArgs& a, const Tune& t, hipStream_t s) {
     constexpr bool dual = MODE == MODE_JVP || MODE == MODE_AOP || MODE == MODE_BLK;
-    const int lanes = t.lanes > 0 ? t.lanes : (dual ? 64 : 128);
+    int lanes = t.lanes > 0 ? t.lanes : (dual ? 64 : 128);
+    if (gr.bnd && lanes > 128) lanes = 128;   // the boundary-face variants are built for 64 and 128 lanes
     switch (lanes) {
         case 64: return run<P, VISC, MOV, MODE, 64>(sv, gr, a, t.grid, t.xcd, s);
         case 128: return run<P, VISC, MOV, MODE, 128>(sv, gr, a, t.grid, t.xcd, s);

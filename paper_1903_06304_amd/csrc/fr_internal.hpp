@@ -39,7 +39,14 @@ struct Geo {
     const int32_t* nbr;   // [E][4]: nb*8 + nb_face*2 + flip
     const int32_t* aff;   // [E]: 1 when the element's metrics are constant (affine map)
     const int32_t* color; // [E]: element colour of the Gauss-Seidel sweeps (no face neighbour shares it)
+    const int32_t* bc;    // [E]: boundary kind of face f in bits 2f..2f+1 (BC_*), 0 interior;
+                          // null when the mesh has no boundary face.  A boundary face's
+                          // entry in nbr names the element itself, same face, no reversal.
+    const double* qinf;   // [4]: far-field primitive state
 };
+
+// boundary kinds of the per-element face codes (the ABI codes are -1, -2, -3)
+enum { BC_NONE = 0, BC_FARFIELD = 1, BC_SLIP = 2, BC_WALL = 3 };
 
 // R; exact JVP; Newton operator; one seeded block column; R plus the linearisation packs;
 // Newton operator from the packs (tangent-only staging)
@@ -134,6 +141,7 @@ struct Tune {
 struct Group {
     int p, visc, mov;
     bool aff0 = false;                       // all members affine when the solver was made
+    bool bnd = false;                        // the members' meshes have boundary faces
     std::vector<int> ids;
     int* d_ids = nullptr;
     std::vector<std::pair<int, int*>> pfx;   // tile width (elements) -> device prefix
@@ -166,13 +174,24 @@ struct fr_ctx_s {
     double* d_gfp = nullptr;        // [NGFP][E][4n]
     int32_t* d_aff = nullptr;       // [E] affine-element flags
     int32_t* d_color = nullptr;     // [E] element colours
+    int32_t* d_bc = nullptr;        // [E] boundary face codes (null: no boundary face)
+    double* d_qinf = nullptr;       // [4] far-field state
+    bool has_farfield = false, farfield_set = false;
     int ncolors = 0;
     bool all_affine = false;        // every element affine at the current geometry
     double* d_trace = nullptr;      // neighbour traces (adjoint path)
     double* d_vj = nullptr;         // adjoint trace buffer
     Solver* self = nullptr;         // one-case solver of the context's own entry points
     size_t N() const { return (size_t)4 * E * Np; }
+    Geo geo() const { return Geo{d_gsp, d_gfp, d_nbr, d_aff, d_color, d_bc, d_qinf}; }
 };
+
+// why a context cannot be evaluated yet, or null
+inline const char* ctx_not_ready(const fr_ctx_s* c) {
+    if (!c->geometry_set) return "fr_set_geometry has not been called";
+    if (c->has_farfield && !c->farfield_set) return "the mesh has far-field faces: fr_set_farfield has not been called";
+    return nullptr;
+}
 
 // A solver: one or more cases advanced together (fr_batch, or the one-case solver of a
 // context).  Owns the concatenated work vectors, blocks and device GMRES state.

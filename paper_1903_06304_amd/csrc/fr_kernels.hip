@@ -96,10 +96,14 @@ __device__ void face_eval(int E, int n, const GeoTab& gt, const double* xg, cons
 // of the metric's scale (an affine element): its gradient traces then follow from its
 // face traces.  The rounding of metrics computed from node coordinates grows with
 // |x| / h (about 1e-12 on a 256 x 256 mesh of [0, 2 pi]^2); a map curved by less than
-// 1e-10 of the element size is affine for every purpose of the discretisation.
-__global__ void k_affine(int E, int Np, const double* __restrict__ gsp, int32_t* __restrict__ aff) {
+// 1e-10 of the element size is affine for every purpose of the discretisation.  An
+// element with a boundary face is not flagged: the kernels of affine elements assume
+// that every face has a neighbour element.
+__global__ void k_affine(int E, int Np, const double* __restrict__ gsp, const int32_t* __restrict__ bc,
+                         int32_t* __restrict__ aff) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
+    if (bc && bc[e] != 0) { aff[e] = 0; return; }
     const size_t EN = (size_t)E * Np;
     const double* m = gsp + (size_t)e * Np;
     double scale = 0.0;
@@ -216,7 +220,7 @@ k_traces(TrArgs a, OpTab op_in, Geo g) {
 template <int P, bool VISC>
 fr_status run_traces(fr_ctx c, const TrArgs& a, hipStream_t s) {
     using B = Blk<P, 1>;
-    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff, c->d_color};
+    const Geo g = c->geo();
     const int grid = (c->E + B::EPB - 1) / B::EPB;
     hipLaunchKernelGGL((k_traces<P, VISC>), dim3(grid), dim3(B::threads), 0, s, a, c->op, g);
     FR_HIP(hipGetLastError());
@@ -239,7 +243,7 @@ fr_status launch_geometry(fr_ctx c, const double* xg, const double* vg, hipStrea
                        c->d_nbr, xg, vg, c->d_gfp);
     FR_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_affine, dim3((unsigned)((c->E + bs - 1) / bs)), dim3(bs), 0, s, c->E, c->Np, c->d_gsp,
-                       c->d_aff);
+                       c->d_bc, c->d_aff);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

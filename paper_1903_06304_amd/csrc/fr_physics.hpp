@@ -14,6 +14,8 @@
 //    beta U_r^2 = eps^2 for an ideal gas), moving-face normal flux of Sec. 3.1
 //  - BR2 common gradient (Sec. 3.1) with the face-local Radau lifting evaluated at
 //    the face: r = ((p+1)^2/2)(|S|/|J|_f)(q^com - q) n_out on each side.
+//  - boundary faces (Sec. "Boundary Conditions"): the state and uncorrected gradient
+//    beyond the face, formed from the own trace and fed to the same common flux.
 #pragma once
 #include "fr_scalar.hpp"
 
@@ -179,4 +181,62 @@ FR_DEV void fr_common_viscous(const PhysConst& c, const T* dq, const T& qcu, con
     dqh[0] = 0.5 * dq[1];
     dqh[1] = 0.5 * dq[2];
     dqh[2] = 0.5 * dq[3];
+}
+
+// ---- boundary faces.  Kinds: 1 far field, 2 slip wall, 3 adiabatic no-slip wall.
+// n: unit outward normal of the own side; (wx, wy): grid velocity at the face point.
+//  far field:  q^+ = q^inf (uniform: zero gradient);
+//  slip wall:  mirror image across the wall, velocity relative to the wall:
+//              v^+ = v - 2 ((v - w).n) n, p and T unchanged, gradients mirrored;
+//  no-slip:    v^+ = 2 w - v, p and T unchanged, velocity gradient unchanged,
+//              temperature gradient mirrored (its average has no normal part).
+// The mirror of a gradient g is g - 2 (g.n) n; that of the velocity gradient
+// G (G[a][b] = d u_a / d x_b) is Rm G Rm with Rm = I - 2 n n^T.
+template <class T>
+FR_DEV void fr_bc_state(int kind, const double* qinf, const T* qm, double nx, double ny, double wx, double wy,
+                        T* qp) {
+    const bool far = kind == 1, slip = kind == 2;
+    const T urn = (qm[1] - wx) * nx + (qm[2] - wy) * ny;
+    const T s1 = qm[1] - (2.0 * nx) * urn, s2 = qm[2] - (2.0 * ny) * urn;   // slip
+    const T w1 = 2.0 * wx - qm[1], w2 = 2.0 * wy - qm[2];                   // no-slip
+    qp[0] = far ? cst<T>(qinf[0]) : qm[0];
+    qp[1] = far ? cst<T>(qinf[1]) : slip ? s1 : w1;
+    qp[2] = far ? cst<T>(qinf[2]) : slip ? s2 : w2;
+    qp[3] = far ? cst<T>(qinf[3]) : qm[3];
+}
+
+// The same map on a tangent (its linear part; the wall velocity and q^inf drop out).
+// It is symmetric, so it also maps an adjoint of q^+ to the adjoint of q^-.
+template <class T>
+FR_DEV void fr_bc_state_lin(int kind, const T* dm, double nx, double ny, T* dp) {
+    const T un = dm[1] * nx + dm[2] * ny;
+    const bool far = kind == 1;
+    const T zero = cst<T>(0.0);
+    dp[0] = far ? zero : dm[0];
+    dp[3] = far ? zero : dm[3];
+    dp[1] = far ? zero : kind == 2 ? dm[1] - (2.0 * nx) * un : -dm[1];
+    dp[2] = far ? zero : kind == 2 ? dm[2] - (2.0 * ny) * un : -dm[2];
+}
+
+// Uncorrected gradient beyond the face from the own trace gm = (ux, uy, vx, vy, Tx, Ty).
+// Linear and symmetric (self-adjoint): it also maps tangents and adjoints.
+template <class T>
+FR_DEV void fr_bc_grad(int kind, const T* gm, double nx, double ny, T* gp) {
+    const bool far = kind == 1, slip = kind == 2;
+    const T zero = cst<T>(0.0);
+    const T tn = gm[4] * nx + gm[5] * ny;
+    gp[4] = far ? zero : gm[4] - (2.0 * nx) * tn;
+    gp[5] = far ? zero : gm[5] - (2.0 * ny) * tn;
+    // slip: Rm G Rm = G - 2 n (n^T G) - 2 (G n) n^T + 4 (n^T G n) n n^T
+    const T a0 = nx * gm[0] + ny * gm[2], a1 = nx * gm[1] + ny * gm[3];   // n^T G
+    const T b0 = gm[0] * nx + gm[1] * ny, b1 = gm[2] * nx + gm[3] * ny;   // G n
+    const T s4 = 4.0 * (a0 * nx + a1 * ny);
+    const T m0 = gm[0] - (2.0 * nx) * a0 - (2.0 * nx) * b0 + (nx * nx) * s4;
+    const T m1 = gm[1] - (2.0 * nx) * a1 - (2.0 * ny) * b0 + (nx * ny) * s4;
+    const T m2 = gm[2] - (2.0 * ny) * a0 - (2.0 * nx) * b1 + (ny * nx) * s4;
+    const T m3 = gm[3] - (2.0 * ny) * a1 - (2.0 * ny) * b1 + (ny * ny) * s4;
+    gp[0] = far ? zero : slip ? m0 : gm[0];
+    gp[1] = far ? zero : slip ? m1 : gm[1];
+    gp[2] = far ? zero : slip ? m2 : gm[2];
+    gp[3] = far ? zero : slip ? m3 : gm[3];
 }

@@ -57,7 +57,7 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
         cd[c].spoff = so;
         fo += (size_t)npf(x->prm.viscous != 0) * x->E * 4 * x->n;
         so += (size_t)nps(x->prm.viscous != 0) * x->E * x->Np;
-        cd[c].g = Geo{x->d_gsp, x->d_gfp, x->d_nbr, x->d_aff, x->d_color};
+        cd[c].g = x->geo();
         cd[c].pc = x->pc;
         sv.ncolors = x->ncolors > sv.ncolors ? x->ncolors : sv.ncolors;
     }
@@ -76,15 +76,16 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
     FR_TRY(upload(&sv.d_cases, cd));
     FR_TRY(upload(&sv.d_chunk_case, chunk_case));
     FR_TRY(upload(&sv.d_case_chunk, case_chunk));
-    // launch groups: cases of one order, viscous and moving kind, and (as the geometry stands
-    // when the solver is made) affine or not, so that a case runs the same kernel variant alone
-    // and in a batch; whether a group is affine is checked again at every launch
+    // launch groups: cases of one order, viscous and moving kind, with or without boundary
+    // faces, and (as the geometry stands when the solver is made) affine or not, so that a
+    // case runs the same kernel variant alone and in a batch; whether a group is affine is
+    // checked again at every launch
     for (int c = 0; c < n; ++c) {
         const fr_ctx x = ctxs[c];
         Group* g = nullptr;
         for (Group& h : sv.groups)
             if (h.p == x->p && h.visc == (x->prm.viscous != 0) && h.mov == (x->prm.moving != 0) &&
-                h.aff0 == x->all_affine)
+                h.aff0 == x->all_affine && h.bnd == (x->d_bc != nullptr))
                 g = &h;
         if (!g) {
             sv.groups.emplace_back();
@@ -93,6 +94,7 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
             g->visc = x->prm.viscous != 0;
             g->mov = x->prm.moving != 0;
             g->aff0 = x->all_affine;
+            g->bnd = x->d_bc != nullptr;
         }
         g->ids.push_back(c);
         g->elems.push_back(x->E);
@@ -238,7 +240,7 @@ fr_status case_status(const Solver& sv) {
 
 fr_status check_cases(const Solver& sv, double* const* q) {
     for (int c = 0; c < sv.n; ++c) {
-        if (!sv.cs[c]->geometry_set) { fr_set_error("fr_set_geometry has not been called for every case"); return FR_EINVAL; }
+        if (const char* m = ctx_not_ready(sv.cs[c])) { fr_set_error(m); return FR_EINVAL; }
         if (!q[c]) { fr_set_error("null state pointer"); return FR_EINVAL; }
     }
     return FR_OK;

@@ -231,7 +231,7 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
 }
 
 // ---------------------------------------------------------------- kernel 2: element reverse sweep
-template <int P, bool VISC, bool MOV>
+template <int P, bool VISC, bool MOV, bool BC>
 __global__ void __launch_bounds__((Sz<P>::threads))
 k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, const double* __restrict__ tr,
            double* __restrict__ out, double* __restrict__ aside, OpTab op_in, PhysConst pc, Geo g) {
@@ -252,15 +252,19 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     const size_t EN = (size_t)E * Np, FE = (size_t)E * NF;
     const int i = lt % n, j = lt / n;
     double qs[4] = {0, 0, 0, 0}, G[6] = {0, 0, 0, 0, 0, 0}, geo[NGSP];
+    #pragma unroll
     for (int c = 0; c < NGSP; ++c) geo[c] = 0.0;
     // ---- forward: load, uncorrected gradient
     if (isS) {
         const size_t id = (size_t)e * Np + lt;
+        #pragma unroll
         for (int v = 0; v < 4; ++v) { qs[v] = q[v * EN + id]; s_q[el][v][lt] = qs[v]; }
+        #pragma unroll
         for (int c = 0; c < NGSP; ++c) geo[c] = g.sp[c * EN + id];
     }
     __syncthreads();
     if (VISC && isS) {
+        #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double dxi = 0, deta = 0;
             for (int b = 0; b < n; ++b) {
@@ -277,15 +281,17 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     // ---- forward: traces and the common solution (dqh) at flux points
     double qm[4], qp[4], gm[6], gp[6];
     double nx = 0, ny = 0, cc = 0, ugf = 0, vgf = 0, sc = 0;
-    int f = 0, k = 0;
+    int f = 0, k = 0, bck = 0;
     if (isF) {
         f = lt / n; k = lt % n;
         const double* lam = (f == 0 || f == 2) ? op.lamL : op.lamR;
+#pragma unroll
         for (int v = 0; v < 4; ++v) {
             double sacc = 0;
             for (int a = 0; a < n; ++a) sacc += lam[a] * s_q[el][v][line_pt(n, f, k, a)];
             qm[v] = sacc;
         }
+#pragma unroll
         for (int c = 0; c < 6; ++c) {
             double sacc = 0;
             if (VISC)
@@ -295,13 +301,21 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         const int pk = g.nbr[e * 4 + f];
         const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
         const double* src = tr + ((size_t)(nb * 4 + nf) * NTV) * n;
+#pragma unroll
         for (int v = 0; v < 4; ++v) qp[v] = src[(size_t)v * n + k2];
+#pragma unroll
         for (int c = 0; c < 6; ++c) gp[c] = VISC ? src[(size_t)(4 + c) * n + k2] : 0.0;
         const size_t sid = (size_t)e * NF + lt;
         nx = g.fp[F_NX * FE + sid]; ny = g.fp[F_NY * FE + sid];
         sc = g.fp[F_SC * FE + sid]; cc = g.fp[F_CC * FE + sid];
         ugf = MOV ? g.fp[F_UG * FE + sid] : 0.0;
         vgf = MOV ? g.fp[F_VG * FE + sid] : 0.0;
+        // a boundary face: the state beyond it comes from the own trace
+        bck = BC ? (g.bc[e] >> (2 * f)) & 3 : 0;
+        if (BC && bck) {
+            fr_bc_state<double>(bck, g.qinf, qm, nx, ny, ugf, vgf, qp);
+            if (VISC) fr_bc_grad<double>(bck, gm, nx, ny, gp);
+        }
         s_S[el][lt][0] = sc * nx; s_S[el][lt][1] = sc * ny;
         s_S[el][lt][2] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;
         s_S[el][lt][3] = sc;
@@ -314,6 +328,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     if (isS) {
         const double gLi = op.gamL[i], gRi = op.gamR[i], gLj = op.gamL[j], gRj = op.gamR[j];
         if (VISC) {
+            #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double cx = s_S[el][fp0][0] * gLi * s_f[el][fp0][c] + s_S[el][fp1][0] * gRi * s_f[el][fp1][c]
                                 + s_S[el][fp2][0] * gLj * s_f[el][fp2][c] + s_S[el][fp3][0] * gRj * s_f[el][fp3][c];
@@ -324,6 +339,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
             }
         }
         const size_t id = (size_t)e * Np + lt;
+        #pragma unroll
         for (int v = 0; v < 4; ++v) rho_w[v] = -w[v * EN + id];
     }
     __syncthreads();   // gradient fields in s_a are dead from here
@@ -331,6 +347,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     if (isS) {
         const double axi = MOV ? geo[G_UG] * geo[G_XIX] + geo[G_VG] * geo[G_XIY] : 0.0;
         const double aet = MOV ? geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY] : 0.0;
+        #pragma unroll
         for (int v = 0; v < 4; ++v) {
             s_a[el][0 + v][lt] = rho_w[v] * geo[G_XIX];
             s_a[el][4 + v][lt] = rho_w[v] * geo[G_ETX];
@@ -346,6 +363,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     // flux points: adjoint of F^num - F^loc from the lift
     double aDF[4] = {0, 0, 0, 0};
     if (isF) {
+        #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double sacc = 0;
             for (int b = 0; b < n; ++b) {
@@ -359,6 +377,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     // solution points: adjoints of f, g (and q^c) from the divergence terms
     double af[4] = {0, 0, 0, 0}, ag[4] = {0, 0, 0, 0}, aqc[4] = {0, 0, 0, 0};
     if (isS) {
+        #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double s1 = 0, s2 = 0, s3 = 0;
             for (int b = 0; b < n; ++b) {
@@ -373,15 +392,18 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     __syncthreads();
     if (MOV && isS) {
         const double aet = geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY];
+        #pragma unroll
         for (int v = 0; v < 4; ++v) s_a[el][20 + v][lt] = rho_w[v] * aet;
     }
     if (isF) {
         // store -aDF (adjoint of F^loc) for the solution-point gather
+        #pragma unroll
         for (int v = 0; v < 4; ++v) s_f[el][lt][3 + v] = -aDF[v];   // slots 3..6
     }
     __syncthreads();
     if (isS) {
         if (MOV) {
+            #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 double s3 = 0;
                 for (int b = 0; b < n; ++b) s3 += op.D[b * n + j] * s_a[el][20 + v][i + n * b];
@@ -391,9 +413,11 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         // F^loc(fp) = sum_b lam_b [Sx f + Sy g - Svg q^c](line b): gather over the 4 lines through s
         const int fps[4] = {fp0, fp1, fp2, fp3};
         const double lams[4] = {op.lamL[i], op.lamR[i], op.lamL[j], op.lamR[j]};
+        #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int fp = fps[t];
             const double l = lams[t];
+            #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const double aF = s_f[el][fp][3 + v];
                 af[v] += l * s_S[el][fp][0] * aF;
@@ -408,6 +432,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     if (isS) {
         point_flux_rev<VISC>(pc, qs, G, af, ag, aqc, aq, aG);
         if (VISC)
+            #pragma unroll
             for (int c = 0; c < 6; ++c) s_a[el][c][lt] = geo[G_IJ] * aG[c];
     }
     __syncthreads();
@@ -419,17 +444,34 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
             for (int b = 0; b < n; ++b) {
                 const int s = line_pt(n, f, k, b);
                 const double gm_ = (f == 0 || f == 2) ? op.gamL[b] : op.gamR[b];
+                #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     adqh[c] += gm_ * (Sx * s_a[el][2 * c][s] + Sy * s_a[el][2 * c + 1][s]);
             }
         }
         double afn[4];
+        #pragma unroll
         for (int v = 0; v < 4; ++v) afn[v] = sc * aDF[v];
         double aqm[4], aqp[4], agm[6], agp[6];
         common_flux_rev<VISC>(pc, qm, qp, gm, gp, nx, ny, cc, ugf, vgf, afn, adqh, aqm, aqp, agm, agp);
+        if (BC && bck) {
+            // q^+ and g^+ depend on the own traces through symmetric linear maps: their
+            // adjoints go back to the own side, and nothing to a neighbour
+            double t[6];
+            fr_bc_state_lin<double>(bck, aqp, nx, ny, t);
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) { aqm[v] += t[v]; aqp[v] = 0.0; }
+            if (VISC) {
+                fr_bc_grad<double>(bck, agp, nx, ny, t);
+                #pragma unroll
+                for (int c = 0; c < 6; ++c) { agm[c] += t[c]; agp[c] = 0.0; }
+            }
+        }
         double* dst = aside + ((size_t)(e * 4 + f) * NTV) * n;
+        #pragma unroll
         for (int v = 0; v < 4; ++v) dst[(size_t)v * n + k] = aqp[v];
         if (VISC) for (int c = 0; c < 6; ++c) dst[(size_t)(4 + c) * n + k] = agp[c];
+        #pragma unroll
         for (int v = 0; v < 4; ++v) s_f[el][lt][v] = aqm[v];
         if (VISC) for (int c = 0; c < 6; ++c) s_f[el][lt][4 + c] = agm[c];
     }
@@ -438,11 +480,14 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     if (isS) {
         const int fps[4] = {fp0, fp1, fp2, fp3};
         const double lams[4] = {op.lamL[i], op.lamR[i], op.lamL[j], op.lamR[j]};
+        #pragma unroll
         for (int t = 0; t < 4; ++t) {
+            #pragma unroll
             for (int v = 0; v < 4; ++v) aq[v] += lams[t] * s_f[el][fps[t]][v];
             if (VISC) for (int c = 0; c < 6; ++c) aG[c] += lams[t] * s_f[el][fps[t]][4 + c];
         }
         if (VISC) {
+            #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 s_a[el][c][lt] = geo[G_XIX] * aG[2 * c] + geo[G_XIY] * aG[2 * c + 1];       // a d_xi
                 s_a[el][3 + c][lt] = geo[G_ETX] * aG[2 * c] + geo[G_ETY] * aG[2 * c + 1];   // a d_eta
@@ -452,6 +497,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     __syncthreads();
     if (isS) {
         if (VISC) {
+            #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 double sacc = 0;
                 for (int b = 0; b < n; ++b)
@@ -460,6 +506,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
             }
         }
         const size_t id = (size_t)e * Np + lt;
+        #pragma unroll
         for (int v = 0; v < 4; ++v) out[v * EN + id] = aq[v];
     }
 }
@@ -526,10 +573,14 @@ k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, 
 
 template <int P, bool VISC, bool MOV>
 fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
-    Geo g{c->d_gsp, c->d_gfp, c->d_nbr, c->d_aff, c->d_color};
+    const Geo g = c->geo();
     const int grid = (c->E + Sz<P>::EPB - 1) / Sz<P>::EPB;
-    hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w, c->d_trace,
-                       out, c->d_vj, c->op, c->pc, g);
+    if (g.bc)
+        hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV, true>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w,
+                           c->d_trace, out, c->d_vj, c->op, c->pc, g);
+    else
+        hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV, false>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w,
+                           c->d_trace, out, c->d_vj, c->op, c->pc, g);
     FR_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_vjp_gather<P, VISC>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, c->d_vj, out, c->op, g);
     FR_HIP(hipGetLastError());

@@ -18,12 +18,14 @@ _lib = None
 
 FR_OK, FR_EINVAL, FR_EHIP, FR_ENOMEM, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FR_FP64, FR_FP32, FR_BF16 = 0, 1, 2
+# boundary codes of the neighbour table (negative entries)
+FR_BC_FARFIELD, FR_BC_SLIP_WALL, FR_BC_NOSLIP_WALL = -1, -2, -3
 PREC = {"fp64": FR_FP64, "fp32": FR_FP32, "bf16": FR_BF16}
 
 # every symbol declared in include/lmfr.h
 EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "fr_bdf_operator",
            "fr_block_jacobi_factor", "fr_block_jacobi_apply", "fr_get_blocks", "fr_bdf2_step",
-           "fr_affine_elements", "fr_steady_solve", "fr_batch_steady_solve",
+           "fr_affine_elements", "fr_steady_solve", "fr_batch_steady_solve", "fr_set_farfield",
            "fr_set_option", "fr_autotune", "fr_batch_create", "fr_batch_destroy", "fr_batch_layout",
            "fr_batch_residual", "fr_batch_jvp", "fr_batch_bdf2_step", "fr_batch_set_option",
            "fr_batch_autotune", "fr_last_error", "fr_destroy"]
@@ -86,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.fr_block_jacobi_apply.argtypes = [vp, dp, dp, vp]
     L.fr_get_blocks.argtypes = [vp, dp, vp]
     L.fr_affine_elements.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    L.fr_set_farfield.argtypes = [vp, dp]
     L.fr_steady_solve.argtypes = [vp, dp, ctypes.POINTER(fr_steady_opts), ctypes.POINTER(fr_steady_stats), vp]
     L.fr_batch_steady_solve.argtypes = [vp, vp, vp, vp, vp]
     L.fr_bdf2_step.argtypes = [vp, dp, dp, ctypes.POINTER(fr_step_opts), ctypes.POINTER(fr_step_stats), vp]
@@ -212,6 +215,11 @@ class Context:
         z = torch.empty_like(r)
         _check(load_library().fr_block_jacobi_apply(self.h, _ptr(r), _ptr(z), _stream()))
         return z
+
+    def set_farfield(self, qinf):
+        """Free-stream primitive state (p, u, v, T) beyond the far-field boundary faces."""
+        a = np.ascontiguousarray(qinf, dtype=np.float64).reshape(4)
+        _check(load_library().fr_set_farfield(self.h, a.ctypes.data_as(ctypes.c_void_p)))
 
     def affine_elements(self):
         """Elements the last set_geometry found affine (constant metrics)."""

@@ -79,6 +79,9 @@ def test_create_rejects_bad_tables_and_parameters():
     prm = _params(); prm.mach_ref = -1.0
     st, _ = _create(prm, nbr, nbf)
     assert st == lmfr.FR_EINVAL
+    unknown = nbr.copy(); unknown[0, 0] = -4     # boundary codes are -1..-3
+    st, _ = _create(_params(), unknown, nbf)
+    assert st == lmfr.FR_EINVAL and b"boundary" in _lib().fr_last_error()
     prm = _params(); prm.n_elem = 0
     st, _ = _create(prm, nbr, nbf)
     assert st == lmfr.FR_EINVAL
@@ -115,6 +118,7 @@ def test_null_arguments_rejected_everywhere():
     assert L.fr_block_jacobi_factor(vp, vp, 1.0, 0.0, 0, vp) == lmfr.FR_EINVAL
     assert L.fr_get_blocks(vp, vp, vp) == lmfr.FR_EINVAL
     assert L.fr_affine_elements(vp, vp, vp) == lmfr.FR_EINVAL
+    assert L.fr_set_farfield(vp, vp) == lmfr.FR_EINVAL
     assert L.fr_steady_solve(vp, vp, vp, vp, vp) == lmfr.FR_EINVAL
     assert L.fr_batch_steady_solve(vp, vp, vp, vp, vp) == lmfr.FR_EINVAL
     assert L.fr_set_option(vp, b"graph", 1) == lmfr.FR_EINVAL
