@@ -49,6 +49,10 @@ def parse():
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-bdf2", action="store_true")
     ap.add_argument("--no-steady", action="store_true", help="skip the steady pseudo-transient solve")
+    ap.add_argument("--no-boundary", action="store_true", help="skip the cylinder O-grid (boundary faces) figures")
+    ap.add_argument("--bnx", type=int, default=256, help="cylinder O-grid: elements around and across")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: reuse (and extend) launch shapes chosen by an earlier run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20, help="oracle residual evaluations timed")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-case batched workload")
@@ -124,7 +128,7 @@ def main():
     ctx = lmfr.Context(prm, nbr, nbf, flip)
     ctx.set_geometry(xg, vg)
     t_tune = time.perf_counter()
-    ctx.autotune(None)          # launch shapes of the fused kernels for this mesh
+    ctx.autotune(args.tune_cache)   # launch shapes of the fused kernels for this mesh
     t_tune = time.perf_counter() - t_tune
     q0 = torch.tensor(case.q, device=dev)
     # rotating input/output sets: > 512 MB in total so the residual streams from HBM
@@ -322,6 +326,8 @@ def main():
         out["batch"] = bd
     if not args.no_steady:
         out["steady"] = steady_solve(torch, lmfr, I, dev)
+    if not args.no_boundary:
+        out["boundary"] = boundary_case(args, torch, lmfr, I, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -362,6 +368,57 @@ def steady_solve(torch, lmfr, I, dev):
             "dtau_final": st["dtau_final"], "preconditioner": "block Gauss-Seidel", "krylov": 150}
 
 
+def boundary_case(args, torch, lmfr, I, dev):
+    """Meshes with boundary faces (once, outside the timed steps): a P4 curved O-grid around a
+    cylinder of radius 0.5 with the far field at radius 50, bnx x bnx elements (65,536 by
+    default, the C4 count), NS p=4, Re = 40, Ma = 0.05; adiabatic no-slip wall on the cylinder,
+    free stream (u, v) = (1, 0) at the far field; potential flow past the cylinder as the state.
+    Residual, JVP and VJP rates over rotating buffers (> 512 MB)."""
+    import numpy as np
+    nx = args.bnx
+    mesh = I.Mesh(nx, nx, 4, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 50.0),
+                  bc=(0, 0, I.BC_NOSLIP_WALL, I.BC_FARFIELD))
+    prm = I.Params(order=4, n_elem=mesh.E, mach_ref=0.05, reynolds=40.0, viscous=True, kappa=1.0)
+    x, y = mesh.solution_points()
+    r4 = (x * x + y * y) ** 2
+    q = I.uniform_flow(mesh, prm, u=1.0, v=0.0)
+    q[1] = 1.0 - 0.25 * (x * x - y * y) / r4
+    q[2] = -0.5 * x * y / r4
+    nbr, nbf, flip = mesh.connectivity()
+    g = lmfr.Context(prm, nbr, nbf, flip)
+    g.set_geometry(*mesh.nodes(0.0))
+    g.set_farfield([prm.gas_constant, 1.0, 0.0, 1.0])
+    g.autotune(args.tune_cache)
+    q0 = torch.tensor(q, device=dev)
+    nsets = max(2, int(np.ceil(512e6 / (2 * q0.numel() * 8))))
+    rng = np.random.default_rng(12)
+    qs = [q0 * (1.0 + 1e-3 * torch.tensor(rng.standard_normal(q0.shape), device=dev)) for _ in range(nsets)]
+    Rs = [torch.empty_like(q0) for _ in range(nsets)]
+    v = torch.tensor(rng.standard_normal(q0.shape), device=dev)
+
+    def timed(fn, n):
+        for k in range(2):
+            fn(k)
+        a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(n):
+            fn(k)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    res_ms = timed(lambda k: g.residual(qs[k % nsets], out=Rs[k % nsets]), 20)
+    jvp_ms = timed(lambda k: g.jvp(qs[k % nsets], v, out=Rs[k % nsets]), 10)
+    vjp_ms = timed(lambda k: g.vjp(qs[k % nsets], v, out=Rs[k % nsets]), 10)
+    dof = 4 * mesh.E * mesh.Np
+    alg = algorithmic_bytes_residual(mesh.E, 4)
+    alg_j = algorithmic_bytes_jvp(mesh.E, 4)
+    return {"workload": f"NS p=4 cylinder O-grid {nx}x{nx} (P4 curved), Re=40, Ma=0.05, no-slip wall + far field",
+            "dof": dof, "elements": mesh.E, "residual_ms": res_ms, "residual_dof_per_s": dof / (res_ms * 1e-3),
+            "residual_hbm_frac": alg / (res_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "jvp_ms": jvp_ms,
+            "jvp_hbm_frac": alg_j / (jvp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "vjp_ms": vjp_ms}
+
+
 def setup_batch(args, torch, lmfr, I, dev):
     """The 48-case batched workload: contexts, batch, packed state, per-case time steps."""
     import numpy as np
@@ -376,7 +433,7 @@ def setup_batch(args, torch, lmfr, I, dev):
         ctxs.append(g)
     b = lmfr.Batch(ctxs)
     t0 = time.perf_counter()
-    b.autotune(None)
+    b.autotune(args.tune_cache)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
     qs = [torch.tensor(c.q, device=dev) for c in cases]
