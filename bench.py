@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--order", type=int, default=3)
-    ap.add_argument("--nr", type=int, default=40, help="residual evaluations per step")
+    ap.add_argument("--nr", type=int, default=1000,
+                    help="residual evaluations per step (about 50 ms: long enough for the clocks to settle)")
     ap.add_argument("--nj", type=int, default=10, help="JVP evaluations per step")
     ap.add_argument("--nv", type=int, default=10, help="VJP evaluations per step")
     ap.add_argument("--dt", type=float, default=1e-3, help="physical time step of the BDF2 step")

@@ -443,9 +443,10 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
     FR_HIP(hipEventCreate(&e1));
     fr_status ret = FR_OK;
     std::string appended;
-    // persistent grids up to 4096 workgroups: the lighter variants run 3 waves per SIMD
-    const int grids[] = {0, 512, 1024, 2048, 4096};
-    constexpr int NGRID = 5;
+    // persistent grids up to 6144 workgroups: the lighter variants run 3 waves per SIMD, and
+    // 768 / 1536 / 3072 workgroups of 256 / 128 / 64 lanes are one resident round at that rate
+    const int grids[] = {0, 512, 1024, 1536, 2048, 3072, 4096, 6144};
+    constexpr int NGRID = 8;
     for (Group& g : sv.groups) {
         for (int mode : {MODE_R, MODE_JVP, MODE_AOP, MODE_PREP, MODE_LIN}) {
             const std::string key = tune_key(arch, sv, g, mode);
@@ -465,6 +466,9 @@ fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
             }
             Tune best;
             float best_ms = 1e30f;
+            // two sweeps, each candidate keeping its faster time: the GPU raises its clocks over
+            // the first tens of milliseconds of work, which would favour the later candidates
+            for (int pass = 0; pass < 2 && ret == FR_OK; ++pass)
             for (int lanes : {64, 128, 256}) {
                 if (lanes == 256 && mode != MODE_R) continue;
                 for (int gx = 0; gx < 2 * NGRID; ++gx) {
