@@ -220,3 +220,35 @@ def test_batch_of_boundary_and_periodic_cases_matches_singles():
     torch.cuda.synchronize()
     for k, (a, r) in enumerate(zip(singles, Rb)):
         assert torch.equal(a, r), k
+
+
+def test_cylinder_full_size_parity():
+    """The benchmark's boundary workload at full size (256 x 256 P4 O-grid, 65,536 elements,
+    potential flow past the cylinder), in the launch shape the autotuner picks: residual and
+    JVP, every row."""
+    from paper_1903_06304_amd import lmfr
+    mesh = I.Mesh(256, 256, 4, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 50.0), bc=(0, 0, WALL, FAR))
+    prm = I.Params(order=4, n_elem=mesh.E, mach_ref=0.05, reynolds=40.0, viscous=True, kappa=1.0)
+    print(f"[boundary] full-size cylinder E={mesh.E}", flush=True)
+    x, y = mesh.solution_points()
+    r4 = (x * x + y * y) ** 2
+    q = I.uniform_flow(mesh, prm, u=1.0, v=0.0)
+    q[1] = 1.0 - 0.25 * (x * x - y * y) / r4
+    q[2] = -0.5 * x * y / r4
+    qinf = [prm.gas_constant, 1.0, 0.0, 1.0]
+    o = Oracle(prm, mesh)
+    o.set_farfield(qinf)
+    g = lmfr.Context(prm, *mesh.connectivity())
+    g.set_geometry(*mesh.nodes(0.0))
+    g.set_farfield(qinf)
+    g.autotune(None)
+    R = g.residual(_dev(q)).cpu().numpy()
+    Ro = o.residual(q)
+    S = flux_scale(o.geometry(), prm, q)
+    err = row_errors(R, Ro)
+    print("  err/S", err / S, flush=True)
+    assert np.all(err <= 1e-12 * S), err / S
+    v = np.random.default_rng(8).standard_normal(q.shape)
+    errj = normwise_rel(g.jvp(_dev(q), _dev(v)).cpu().numpy(), o.jvp(q, v))
+    print("  jvp", errj, flush=True)
+    assert np.all(errj <= 1e-12), errj
