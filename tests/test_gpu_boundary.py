@@ -252,3 +252,50 @@ def test_cylinder_full_size_parity():
     errj = normwise_rel(g.jvp(_dev(q), _dev(v)).cpu().numpy(), o.jvp(q, v))
     print("  jvp", errj, flush=True)
     assert np.all(errj <= 1e-12), errj
+
+
+def _wall_forces_and_entropy(o, mesh, prm, q):
+    """C_d, C_l from the pressure on the wall faces (eta = -1 sides of the first row of the
+    O-grid; inviscid: pressure only), and the entropy error E_s over the domain (the paper's
+    definitions in Sec. 4, with rho_inf = U_inf = D = 1)."""
+    g = o.geometry()
+    n = mesh.n
+    x, w = np.polynomial.legendre.leggauss(n)
+    V = np.polynomial.legendre.legvander(x, n - 1)
+    lam_m = np.polynomial.legendre.legvander(np.array([-1.0]), n - 1)[0] @ np.linalg.inv(V)
+    F = np.zeros(2)
+    for e in range(mesh.nx):
+        pw = lam_m @ q[0, e].reshape(n, n)          # p at the eta = -1 face points
+        # |J| grad(eta) points into the fluid: the force on the body is -int p n_body dS
+        F -= np.array([np.sum(w * pw * g["Sx"][e, 2]), np.sum(w * pw * g["Sy"][e, 2])])
+    rho = q[0] / (prm.gas_constant * q[3])
+    s = q[0] / rho ** prm.gamma
+    s_inf = prm.gas_constant
+    W = np.outer(w, w).reshape(-1)[None, :] * g["jac"]
+    return F[0] / 0.5, F[1] / 0.5, np.sqrt(np.sum(W * (s - s_inf) ** 2) / np.sum(W * s_inf ** 2))
+
+
+def test_inviscid_cylinder_steady():
+    """The paper's inviscid cylinder setting (Sec. 4, Ma_inf = 1e-3, kappa = 1, slip wall, far
+    field beyond 100 diameters, 20 x 24 elements, 3rd order, P4 geometry, SER from dtau = 0.01,
+    GMRES(150), tol_res 1e-6) on a synthetic O-grid: the steady solve converges to 1e-9, the
+    flow stays symmetric (C_l ~ 0), and drag and entropy error are the discretisation's (the
+    exact inviscid values are 0)."""
+    from paper_1903_06304_amd import lmfr
+    mesh = I.Mesh(24, 20, 2, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 100.0), pg=4, bc=(0, 0, SLIP, FAR))
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=1e-3, viscous=False, kappa=1.0, geom_order=4)
+    qinf = [prm.gas_constant, 1.0, 0.0, 1.0]
+    g = lmfr.Context(prm, *mesh.connectivity())
+    g.set_geometry(*mesh.nodes(0.0))
+    g.set_farfield(qinf)
+    g.set_option("preconditioner", 1)
+    q = _dev(I.uniform_flow(mesh, prm, u=1.0, v=0.0))
+    st = g.steady_solve(q, dtau0=0.01, dtau_min=0.01, dtau_max=1e20, tol_pseudo=1e-9, tol_res=1e-6, krylov=150,
+                        max_lin_it=1500, max_steps=40)
+    torch.cuda.synchronize()
+    o = Oracle(prm, mesh)
+    o.set_farfield(qinf)
+    cd, cl, es = _wall_forces_and_entropy(o, mesh, prm, q.cpu().numpy())
+    print(f"[boundary] inviscid cylinder {st} Cd={cd:.3e} Cl={cl:.3e} Es={es:.3e}", flush=True)
+    assert st["converged"] == 1 and st["steps"] <= 30
+    assert abs(cd) < 5e-3 and abs(cl) < 1e-5 and es < 1e-10
