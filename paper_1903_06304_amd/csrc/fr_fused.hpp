@@ -598,18 +598,17 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
     using PD = LPad<P, Store<T>::W>;
     constexpr int FS = Np + PD::F;
     constexpr int ESQ = 4 * FS + PD::E;
-    constexpr int ESW = 8 * FS + PD::E;      // F~ of the 4 equations, then G~
-    constexpr int NG = VISC ? 6 : 1;
-    constexpr int ESG = NG * FS + PD::E;
+    constexpr int ESW = 8 * FS + PD::E;      // own gradient (6 fields); later F~ of the 4 equations, then G~
     constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1;
     __shared__ T s_q[EPB * ESQ];       // own state [el][var][point]
-    __shared__ T s_w[EPB * ESW];       // F~, G~ [el][8][point]
-    __shared__ T s_g[EPB * ESG];       // own uncorrected gradient [el][6][point]
+    __shared__ T s_w[EPB * ESW];       // own uncorrected gradient [el][6][point]; then F~, G~ [el][8][point]
     __shared__ T s_F[EPB * ESF];       // neighbour traces of (u, v, T) by neighbour point; then F^num - F^loc
     __shared__ T s_dq[EPB * ESD];      // q^com - q^- of (u, v, T)
     auto QI = [](int el, int v, int sp) { return el * ESQ + v * FS + sp; };
     auto WI = [](int el, int fld, int sp) { return el * ESW + fld * FS + sp; };
-    auto GI = [](int el, int c, int sp) { return el * ESG + c * FS + sp; };
+    // the gradient shares the flux area: in stage 4 a lane reads its own point's gradient
+    // before it writes its own point's fluxes, and no lane reads another point's gradient there
+    auto GI = [](int el, int c, int sp) { return el * ESW + c * FS + sp; };
     auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
     auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
     __shared__ double s_D[n * n];
@@ -714,8 +713,8 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                     dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
                     deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
                 }
-                s_g[GI(el, 2 * c, lt)] = lg.xix * dxi + lg.etx * deta;
-                s_g[GI(el, 2 * c + 1, lt)] = lg.xiy * dxi + lg.ety * deta;
+                s_w[GI(el, 2 * c, lt)] = lg.xix * dxi + lg.etx * deta;
+                s_w[GI(el, 2 * c + 1, lt)] = lg.xiy * dxi + lg.ety * deta;
             }
         }
         __syncthreads();
@@ -746,7 +745,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                 for (int c = 0; c < 6; ++c) {
                     T acc = cst<T>(0.0);
 #pragma unroll
-                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[GI(el, c, line_pt(n, f, k, b))];
                     gm[c] = acc;
                 }
 #pragma unroll
@@ -783,7 +782,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             T gu[2], gv[2], gT[2];
             if (VISC) {
 #pragma unroll
-                for (int d = 0; d < 2; ++d) { gu[d] = s_g[GI(el, d, lt)]; gv[d] = s_g[GI(el, 2 + d, lt)]; gT[d] = s_g[GI(el, 4 + d, lt)]; }
+                for (int d = 0; d < 2; ++d) { gu[d] = s_w[GI(el, d, lt)]; gv[d] = s_w[GI(el, 2 + d, lt)]; gT[d] = s_w[GI(el, 4 + d, lt)]; }
                 // lift of q^com - q^- through the Radau slopes; on an affine element the face
                 // vectors are |J| grad(xi) (faces 0, 1) and |J| grad(eta) (faces 2, 3), and |J| / |J| = 1
                 const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
