@@ -238,7 +238,8 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT, EPB = Sz<P>::EPB;
     constexpr int NTV = VISC ? 10 : 4;
     __shared__ double s_q[EPB][4][Np];
-    __shared__ double s_a[EPB][24][Np];      // scratch fields at solution points
+    constexpr int NA = MOV ? 24 : 20;       // moving meshes add the 4 grid-velocity products
+    __shared__ double s_a[EPB][NA][Np];      // scratch fields at solution points
     __shared__ double s_f[EPB][NF][10];      // per flux point scratch
     __shared__ double s_S[EPB][NF][4];       // Sx, Sy, S.vg, scale sg|S|
     __shared__ OpTab sop;                    // operator tables (lane-dependent indexing in LDS)
