@@ -11,8 +11,8 @@ One timed step = one pass of the hot path over that input:
     with FP64 element blocks ("plain"), and the same step with FP32 and BF16 blocks,
     and with the symmetric block Gauss-Seidel preconditioner (FP64 and BF16 blocks),
   * the batched workload: 48 uneven cases (16^2..192^2 quads, p = 2..4, Ma 0.01..0.3,
-    Re 100..5000, half deforming) -- one batched residual per step and one batched
-    BDF2 step per block precision, launch shapes from the autotuner.
+    Re 100..5000, half deforming) -- batched residuals and one batched BDF2 step per
+    block precision, also with block Gauss-Seidel; launch shapes from the autotuner.
 `value` = DOF-residual evaluations per second of the residual (the metric's first
 half); the BDF2 step times (second half) are reported beside it.
 """
@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=20, help="oracle residual evaluations timed")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-case batched workload")
     ap.add_argument("--batch-precs", default="fp64,bf16")
+    ap.add_argument("--batch-gs-precs", default="fp64,bf16",
+                    help="block precisions of the batched step with the block Gauss-Seidel preconditioner")
     ap.add_argument("--batch-cfl", type=float, default=2.0, help="acoustic CFL of each batched case's dt")
     ap.add_argument("--nrb", type=int, default=10, help="batched residual evaluations per step")
     return ap.parse_args()
@@ -154,6 +156,7 @@ def main():
     precs = args.precs.split(",")
     gprecs = [x for x in args.gs_precs.split(",") if x]
     bprecs = args.batch_precs.split(",")
+    bgprecs = [x for x in args.batch_gs_precs.split(",") if x]
     bt = None
     if not args.no_batch:
         bt = setup_batch(args, torch, lmfr, I, dev)
@@ -219,6 +222,18 @@ def main():
                 b_.record(stream)
                 ev["bbdf_" + pr] = (a, b_)
                 stats["batch_" + pr] = (rc, sts, qw)
+            bt["batch"].set_option("preconditioner", 1)
+            for pr in bgprecs:
+                qw = [q.clone() for q in bt["qs"]]
+                opts = [lmfr.step_opts(dt, krylov=30, max_lin_it=args.max_lin_it, max_newton=20, jac_lag=2,
+                                       tol_abs=ta, prec=pr) for dt, ta in zip(bt["dts"], bt["tol_abs"])]
+                a = torch.cuda.Event(enable_timing=True); b_ = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                rc, sts = bt["batch"].bdf2_step(qw, None, opts)
+                b_.record(stream)
+                ev["bgs_" + pr] = (a, b_)
+                stats["batch_gs_" + pr] = (rc, sts, qw)
+            bt["batch"].set_option("preconditioner", 0)
         if record is not None:
             record.append((ev, stats))
 
@@ -316,14 +331,21 @@ def main():
                                 "newton_its_max": max(x["newton_its"] for x in sts),
                                 "gmres_its_max": max(x["gmres_its"] for x in sts),
                                 "gmres_its_total": sum(x["gmres_its"] for x in sts)}
+        for pr in bgprecs:
+            rc, sts, qw = records[-1][1]["batch_gs_" + pr]
+            bd["gauss_seidel_" + pr] = {"ms": mean_ms("bgs_" + pr), "rc": rc,
+                                        "converged": sum(x["converged"] for x in sts),
+                                        "gmres_its_max": max(x["gmres_its"] for x in sts),
+                                        "gmres_its_total": sum(x["gmres_its"] for x in sts)}
         if "fp64" in bprecs:
             ref = records[-1][1]["batch_fp64"][2]
-            for pr in [x for x in bprecs if x != "fp64"]:
-                qw = records[-1][1]["batch_" + pr][2]
+            for key in [f"bdf2_{x}" for x in bprecs if x != "fp64"] + [f"gauss_seidel_{x}" for x in bgprecs]:
+                skey = "batch_" + key[5:] if key.startswith("bdf2_") else "batch_gs_" + key[len("gauss_seidel_"):]
+                qw = records[-1][1][skey][2]
                 d = max(float(((a - r).abs().amax(dim=(1, 2)) / r.abs().amax(dim=(1, 2))).max())
                         for a, r in zip(qw, ref))
-                bd["bdf2_" + pr]["max_rel_diff_vs_fp64"] = d
-                bd["bdf2_" + pr]["speedup_vs_fp64"] = bd["bdf2_fp64"]["ms"] / bd["bdf2_" + pr]["ms"]
+                bd[key]["max_rel_diff_vs_fp64"] = d
+                bd[key]["speedup_vs_fp64"] = bd["bdf2_fp64"]["ms"] / bd[key]["ms"]
         out["batch"] = bd
     if not args.no_steady:
         out["steady"] = steady_solve(torch, lmfr, I, dev)
