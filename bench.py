@@ -291,7 +291,7 @@ def main():
         "vjp_ms": vjp_ms,
         "vjp_dof_per_s": dof / (vjp_ms * 1e-3),
         "vjp_hbm_frac": alg_j / (vjp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": "fused::k_fused<p, viscous, static, R> (fr_residual)",
+        "roofline": {"bound": "hbm", "kernel": "fused::k_fused_aff<p, viscous, R> (fr_residual, the all-affine static variant)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.order, args.nx), "algorithmic_bytes": alg_b},
     }
