@@ -109,12 +109,18 @@ typedef struct {
     int32_t max_steps;    /* pseudo-time step cap */
     int32_t jac_lag;      /* refresh the block-Jacobi blocks when m % jac_lag == 0 (paper: 1) */
     int32_t prec;         /* fr_prec of the stored preconditioner blocks */
+    double reject_growth; /* step rejection, not part of the paper's method (0 = off, the paper's
+                             SER): a step after which Res is not finite or exceeds reject_growth
+                             times the Res before it is undone and retried from the same state
+                             with dtau / 10 (no SER update, no clipping, for that retry); undone
+                             steps count towards max_steps */
 } fr_steady_opts;
 
 typedef struct {
     int32_t steps, gmres_its, converged;
     double res0, res_final;
     double dtau_final;    /* pseudo-time step of the last step taken */
+    int32_t rejected;     /* steps undone by step rejection */
 } fr_steady_stats;
 
 /* Create a context for one mesh.  h_nbr/h_nbr_face/h_flip are HOST arrays [n_elem][4]:

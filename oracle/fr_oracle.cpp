@@ -934,15 +934,22 @@ static int bdf2_step(const Ctx& c, double* q, const double* q_nm1, const StepOpt
 }
 
 // ---------------------------------------------------------------- steady pseudo-transient continuation
-struct SteadyOpts { double dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs; int krylov, max_lin_it, max_steps, jac_lag, precond; };
+struct SteadyOpts { double dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs, reject_growth; int krylov, max_lin_it, max_steps, jac_lag, precond; };
 
 // Sec. 3.2 Eq. (steady_pre_discretized_1): (Gamma^m/dtau - dR/dq^m) dq^m = R^m, backward Euler
 // in pseudo time linearised about q^m, with dtau from Eq. (SER): the step size used at pseudo-step
 // m is that of step m-1 times (Res_{m-1}/Res_m)^r_ser, clipped to [dtau_min, dtau_max], and dtau0
 // at m = 0 (reading: the freshest residual ratio sets the next step); Res is the 2-norm of the
 // continuity (pressure) rows of R.  hist (may be null) receives (Res_m, dtau_m) per step taken.
+//
+// Step rejection (not in the paper, which leaves globalisation of SER to other work; off when
+// reject_growth = 0): when the residual after a step is not finite or exceeds reject_growth times
+// the one before it, the step is undone (q -= dq) and retried from the same state with a ten
+// times smaller dtau (the SER update and its clipping are skipped for that retry, since the
+// residual ratio is 1).  A rejected step is recorded in hist as (Res, -dtau of the retry) and
+// counts towards max_steps.
 static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats& st, double* dtau_final,
-                        std::vector<double>* hist) {
+                        std::vector<double>* hist, int* rejected = nullptr) {
     const int Np = c.Np, E = c.E, nb = 4 * Np;
     const size_t N = (size_t)4 * E * Np;
     NSPhys ph{&c};
@@ -952,6 +959,8 @@ static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats&
     const std::vector<int> col = colour_elements(c, ncol);
     st = StepStats{0, 0, 0, 0.0, 0.0};
     double dtau = o.dtau0, res_prev = 0.0;
+    bool retry = false;
+    int nrej = 0;
     auto gamma_pt = [&](const double* qq, int e, int s, double G[4][4]) {
         double qs[4]; for (int v = 0; v < 4; ++v) qs[v] = qq[((size_t)v * E + e) * Np + s];
         const size_t id = (size_t)e * Np + s;
@@ -962,12 +971,22 @@ static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats&
         double res = 0.0;
         for (size_t i = 0; i < (size_t)E * Np; ++i) res += R[i] * R[i];
         res = std::sqrt(res);
+        if (o.reject_growth > 0.0 && m > 0 && !retry && !(res <= o.reject_growth * res_prev)) {
+            for (size_t i = 0; i < N; ++i) q[i] -= dq[i];
+            dtau *= 0.1;
+            retry = true;
+            ++nrej;
+            if (hist) { hist->push_back(res); hist->push_back(-dtau); }
+            if (m >= o.max_steps) break;
+            continue;
+        }
         if (!std::isfinite(res)) return -4;
         if (m == 0) st.res0 = res;
         st.res_final = res;
         if (res <= o.tol_abs || res <= o.tol_pseudo * st.res0) { st.converged = 1; break; }
         if (m >= o.max_steps) break;
-        if (m > 0) dtau = std::max(o.dtau_min, std::min(o.dtau_max, dtau * std::pow(res_prev / res, o.r_ser)));
+        if (m > 0 && !retry) dtau = std::max(o.dtau_min, std::min(o.dtau_max, dtau * std::pow(res_prev / res, o.r_ser)));
+        retry = false;
         res_prev = res;
         if (hist) { hist->push_back(res); hist->push_back(dtau); }
         const double idt = 1.0 / dtau;
@@ -1007,6 +1026,7 @@ static int steady_solve(const Ctx& c, double* q, const SteadyOpts& o, StepStats&
         st.newton_its++;
     }
     if (dtau_final) *dtau_final = dtau;
+    if (rejected) *rejected = nrej;
     return st.converged ? 0 : -5;
 }
 
@@ -1239,20 +1259,22 @@ int ora_bdf2_step(void* h, double* q, const double* q_nm1, const double* dopt, c
 }
 
 // Steady pseudo-transient continuation with SER; q updated in place.
-// dopt: dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs;
+// dopt: dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs, reject_growth;
 // iopt: krylov, max_lin_it, max_steps, jac_lag, precond
-// istat: steps, gmres_its, converged; dstat: res0, res_final, dtau of the last step taken;
-// hist (length 2 * (max_steps + 1), may be null): Res_m, dtau_m of every step taken
+// istat: steps (accepted and rejected), gmres_its, converged, rejected steps;
+// dstat: res0, res_final, dtau of the last step taken;
+// hist (length 2 * (max_steps + 1), may be null): Res_m, dtau_m of every step (rejected: -dtau)
 int ora_steady_solve(void* h, double* q, const double* dopt, const int* iopt, int* istat, double* dstat,
                      double* hist) {
     Ctx& c = *(Ctx*)h;
-    SteadyOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], dopt[5], dopt[6], iopt[0], iopt[1], iopt[2], iopt[3],
-                 iopt[4]};
+    SteadyOpts o{dopt[0], dopt[1], dopt[2], dopt[3], dopt[4], dopt[5], dopt[6], dopt[7], iopt[0], iopt[1], iopt[2],
+                 iopt[3], iopt[4]};
     StepStats st;
     double dtf = 0.0;
     std::vector<double> hv;
-    int rc = steady_solve(c, q, o, st, &dtf, &hv);
-    istat[0] = st.newton_its; istat[1] = st.gmres_its; istat[2] = st.converged;
+    int nrej = 0;
+    int rc = steady_solve(c, q, o, st, &dtf, &hv, &nrej);
+    istat[0] = st.newton_its + nrej; istat[1] = st.gmres_its; istat[2] = st.converged; istat[3] = nrej;
     dstat[0] = st.res0; dstat[1] = st.res_final; dstat[2] = dtf;
     if (hist) std::copy(hv.begin(), hv.end(), hist);
     return rc;

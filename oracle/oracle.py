@@ -236,18 +236,19 @@ class Oracle:
         return q, stats
 
     def steady_solve(self, q, dtau0=0.01, dtau_min=0.01, dtau_max=1e20, r_ser=2.0, tol_pseudo=1e-8,
-                     tol_res=1e-6, tol_abs=0.0, krylov=30, max_lin_it=200, max_steps=100, jac_lag=1, precond=0):
+                     tol_res=1e-6, tol_abs=0.0, krylov=30, max_lin_it=200, max_steps=100, jac_lag=1, precond=0,
+                     reject_growth=0.0):
         """Steady pseudo-transient continuation with SER (Sec. 3.2): returns the final state and
         stats, with hist = [(Res_m, dtau_m)] of every pseudo-step taken."""
         q = np.array(self._state(q), copy=True)
-        d = np.array([dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs], dtype=np.float64)
+        d = np.array([dtau0, dtau_min, dtau_max, r_ser, tol_pseudo, tol_res, tol_abs, reject_growth], dtype=np.float64)
         i = np.array([krylov, max_lin_it, max_steps, jac_lag, precond], dtype=np.int32)
-        ist = np.zeros(3, dtype=np.int32)
+        ist = np.zeros(4, dtype=np.int32)
         dst = np.zeros(3)
         hist = np.zeros(2 * (max_steps + 1))
         rc = lib().ora_steady_solve(self.h, _p(q), _p(d), _p(i, _ip), _p(ist, _ip), _p(dst), _p(hist))
         n = int(ist[0])
-        stats = dict(rc=rc, steps=n, gmres_its=int(ist[1]), converged=int(ist[2]), res0=float(dst[0]),
+        stats = dict(rc=rc, steps=n, gmres_its=int(ist[1]), converged=int(ist[2]), rejected=int(ist[3]), res0=float(dst[0]),
                      res_final=float(dst[1]), dtau_final=float(dst[2]),
                      hist=[(float(hist[2 * k]), float(hist[2 * k + 1])) for k in range(n)])
         return q, stats

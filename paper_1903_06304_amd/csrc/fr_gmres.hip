@@ -340,18 +340,49 @@ __global__ void k_newton_check(Ctl k, int m, int it) {
     s[S_RES] = rr;
     s[S_NEWTON] = it;
     CaseStep& st = k.step[c];
+    if (st.ser && st.reject_growth > 0.0 && it > 0 && !st.retry && !(rr <= st.reject_growth * st.res_prev)) {
+        // step rejection (not in the paper; off unless requested): the step just taken is undone
+        // by k_reject_restore and retried from the same state with a ten times smaller dtau;
+        // the case sits out the rest of this iteration and recomputes its residual in the next
+        st.dtau *= 0.1;
+        st.idt = 1.0 / st.dtau;
+        st.retry = 1;
+        s[S_DTAU] = st.dtau;
+        s[S_REJ] += 1.0;
+        gi[GI_REJECT] = 1;
+        gi[GI_NDONE] = 1;
+        return;
+    }
     if (!isfinite(rr)) { gi[GI_STATUS] = 1; gi[GI_NDONE] = 1; return; }
     if (rr <= st.tol_abs || rr <= st.tol_pseudo * s[S_RES0]) { gi[GI_CONV] = 1; gi[GI_NDONE] = 1; return; }
     if (it >= st.max_newton) { gi[GI_STATUS] = 2; gi[GI_NDONE] = 1; return; }
     if (st.ser) {
-        if (it > 0) {
+        if (it > 0 && !st.retry) {
             const double d = st.dtau * pow(st.res_prev / rr, st.r_ser);
             st.dtau = fmax(st.dtau_min, fmin(st.dtau_max, d));
             st.idt = 1.0 / st.dtau;
         }
+        st.retry = 0;
         st.res_prev = rr;
         s[S_DTAU] = st.dtau;
     }
+}
+
+// q -= dq for the cases whose step k_newton_check undid
+__global__ void k_reject_restore(Vec vc, const double* __restrict__ dq, double* __restrict__ q) {
+    for (int ch = blockIdx.x; ch < vc.nchunks; ch += gridDim.x) {
+        const int c = vc.chunk_case[ch];
+        if (!vc.gi[c * GI_STRIDE + GI_REJECT]) continue;
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x) q[t] -= dq[t];
+    }
+}
+
+// a case whose step was undone takes part again, from its restored state
+__global__ void k_retry(Ctl k) {
+    const int c = case_index();
+    if (c >= k.n) return;
+    int* gi = k.gi + c * GI_STRIDE;
+    if (gi[GI_REJECT]) { gi[GI_REJECT] = 0; gi[GI_NDONE] = 0; }
 }
 
 // a singular block (status 3) takes its case out of the iteration; flags to the summary
@@ -367,7 +398,7 @@ __global__ void k_publish(Ctl k) {
     if (c >= k.n) return;
     const int* gi = k.gi + c * GI_STRIDE;
     double* s = k.sum + (size_t)c * SUM_STRIDE;
-    s[S_NDONE] = gi[GI_NDONE];
+    s[S_NDONE] = gi[GI_NDONE] && !gi[GI_REJECT];
     s[S_CONV] = gi[GI_CONV];
     s[S_STATUS] = gi[GI_STATUS];
 }
@@ -467,6 +498,10 @@ fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
     FR_TRY(launch_cons_nm1(sv, wv(sv, WQNM1), s));
     double* hs = sv.h_pin;
     for (int it = 0;; ++it) {
+        if (sv.reject_on) {
+            hipLaunchKernelGGL(k_retry, dim3(cgrid(sv)), dim3(64), 0, s, k);
+            FR_HIP(hipGetLastError());
+        }
         // R at the iterate, and the linearisation packs the GMRES operator reads
         KArgs a{};
         a.q = sv.d_q; a.out = wv(sv, WR); a.flags = sv.d_gi; a.flag = GI_NDONE;
@@ -477,6 +512,11 @@ fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
                          sv.gs_stride, sv.d_gi, GI_NDONE, s));
         hipLaunchKernelGGL(k_newton_check, dim3(cgrid(sv)), dim3(64), 0, s, k, o->krylov, it);
         FR_HIP(hipGetLastError());
+        if (sv.reject_on) {
+            hipLaunchKernelGGL(k_reject_restore, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_NDONE), wv(sv, WDQ),
+                               sv.d_q);
+            FR_HIP(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_publish, dim3(cgrid(sv)), dim3(64), 0, s, k);
         FR_HIP(hipGetLastError());
         FR_HIP(hipMemcpyAsync(hs, sv.d_sum, (size_t)sv.n * SUM_STRIDE * sizeof(double), hipMemcpyDeviceToHost, s));

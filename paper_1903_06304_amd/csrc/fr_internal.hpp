@@ -82,13 +82,16 @@ struct CaseStep {
     double inv_dt, a0, a1, a2;  // BDF coefficients: a0 q^c(q) + a1 Q^n + a2 Q^{n-1}
     double tol_res, tol_pseudo, tol_abs;
     double dtau, dtau_min, dtau_max, r_ser, res_prev;   // SER pseudo-time step control
+    double reject_growth;       // step rejection: undo a step whose residual grows beyond this factor (0: off)
     int has_nm1, max_newton, ser;
+    int retry;                  // the previous step was undone: keep dtau for the retry
 };
 
 // per-case summary published to the host: sum[case * SUM_STRIDE + field]
 enum { S_BN = 0, S_BETA, S_TOTAL, S_MORE,      // GMRES: |b|, |r|, iterations, wants another cycle
        S_RES0, S_RES, S_NEWTON, S_GMRES,       // Newton: Res_0, Res_m, iterations, GMRES iterations
        S_NDONE, S_CONV, S_STATUS, S_DTAU,      // flags, status, last pseudo-time step (SER)
+       S_REJ,                                  // pseudo-time steps undone (step rejection)
        SUM_STRIDE = 16 };
 
 // work vectors of a step inside Solver::d_w
@@ -103,6 +106,7 @@ enum { GI_DONE = 0,   // Arnoldi of the current cycle stopped (skip flag of the 
        GI_NDONE,      // the case has left the Newton iteration (skip flag of everything)
        GI_STATUS,     // 0 running/converged, 1 non-finite, 2 iteration limit, 3 singular block
        GI_CONV,       // Newton converged
+       GI_REJECT,     // the last step was undone: out of this iteration (GI_NDONE set), back in the next
        GI_STRIDE };
 
 // Arguments of the fused residual kernels.  State-sized pointers are bases of the
@@ -217,6 +221,7 @@ struct Solver {
     double* d_gsu = nullptr;               // Gauss-Seidel work vectors [Ntot] x 2
     double* d_gst = nullptr;
     double f_ct = 0.0, f_idt = 0.0;        // time coefficients of the last context-level factor
+    bool reject_on = false;                // the running steady solve undoes steps that raise the residual
     // step workspace
     int kry_m = 0;
     double* d_q = nullptr;                 // Newton iterate

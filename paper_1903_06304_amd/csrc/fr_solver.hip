@@ -307,7 +307,8 @@ fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, f
     for (int c = 0; c < n; ++c) {
         const fr_steady_opts& x = o[c];
         if (!(x.dtau0 > 0.0) || !(x.dtau_min > 0.0) || !(x.dtau_max >= x.dtau_min) || !(x.r_ser >= 0.0) ||
-            !(x.tol_pseudo >= 0.0) || !(x.tol_res >= 0.0) || !(x.tol_abs >= 0.0) || x.krylov < 1 ||
+            !(x.tol_pseudo >= 0.0) || !(x.tol_res >= 0.0) || !(x.tol_abs >= 0.0) || !(x.reject_growth >= 0.0) ||
+            !std::isfinite(x.reject_growth) || x.krylov < 1 ||
             x.krylov > MAXV - 4 || x.max_lin_it < 1 || x.max_steps < 0 || x.jac_lag < 1 || x.prec < FR_FP64 ||
             x.prec > FR_BF16) {
             fr_set_error("invalid steady options");
@@ -321,6 +322,7 @@ fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, f
     }
     FR_TRY(solver_ensure_step(sv, o[0].krylov));
     CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
+    sv.reject_on = false;
     for (int c = 0; c < n; ++c) {
         CaseStep st{};   // no physical-time terms: c_time = inv_dt = a0 = a1 = a2 = 0
         st.dtau = o[c].dtau0;
@@ -333,6 +335,8 @@ fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, f
         st.tol_abs = o[c].tol_abs;
         st.max_newton = o[c].max_steps;
         st.ser = 1;
+        st.reject_growth = o[c].reject_growth;
+        sv.reject_on = sv.reject_on || o[c].reject_growth > 0.0;
         hst[c] = st;
     }
     fr_step_opts common{};
@@ -341,7 +345,9 @@ fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, f
     common.max_newton = o[0].max_steps;
     common.jac_lag = o[0].jac_lag;
     common.prec = o[0].prec;
-    FR_TRY(run_newton(sv, q, nullptr, common, caller));
+    const fr_status rs = run_newton(sv, q, nullptr, common, caller);
+    sv.reject_on = false;
+    FR_TRY(rs);
     for (int c = 0; c < n && stats; ++c) {
         const double* x = sv.h_pin + (size_t)c * SUM_STRIDE;
         stats[c].steps = (int32_t)x[S_NEWTON];
@@ -350,6 +356,7 @@ fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, f
         stats[c].res0 = x[S_RES0];
         stats[c].res_final = x[S_RES];
         stats[c].dtau_final = x[S_DTAU] > 0.0 ? x[S_DTAU] : o[c].dtau0;
+        stats[c].rejected = (int32_t)x[S_REJ];
     }
     return case_status(sv);
 }

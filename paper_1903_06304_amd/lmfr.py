@@ -61,12 +61,14 @@ class fr_steady_opts(ctypes.Structure):
     _fields_ = [("dtau0", ctypes.c_double), ("dtau_min", ctypes.c_double), ("dtau_max", ctypes.c_double),
                 ("r_ser", ctypes.c_double), ("tol_pseudo", ctypes.c_double), ("tol_res", ctypes.c_double),
                 ("tol_abs", ctypes.c_double), ("krylov", ctypes.c_int32), ("max_lin_it", ctypes.c_int32),
-                ("max_steps", ctypes.c_int32), ("jac_lag", ctypes.c_int32), ("prec", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int32), ("jac_lag", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("reject_growth", ctypes.c_double)]
 
 
 class fr_steady_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("gmres_its", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("res0", ctypes.c_double), ("res_final", ctypes.c_double), ("dtau_final", ctypes.c_double)]
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double), ("dtau_final", ctypes.c_double),
+                ("rejected", ctypes.c_int32)]
 
 
 def load_library(path: str = LIB_PATH):
@@ -262,16 +264,17 @@ class Context:
 
 
 def steady_opts(dtau0=0.01, dtau_min=0.01, dtau_max=1e20, r_ser=2.0, tol_pseudo=1e-8, tol_res=1e-6, tol_abs=0.0,
-                krylov=30, max_lin_it=200, max_steps=100, jac_lag=1, prec="fp64"):
-    """Options of a steady pseudo-transient solve (paper defaults for the SER controls)."""
+                krylov=30, max_lin_it=200, max_steps=100, jac_lag=1, prec="fp64", reject_growth=0.0):
+    """Options of a steady pseudo-transient solve (paper defaults for the SER controls; step
+    rejection, which is not part of the paper's method, off unless reject_growth > 0)."""
     return fr_steady_opts(float(dtau0), float(dtau_min), float(dtau_max), float(r_ser), float(tol_pseudo),
                           float(tol_res), float(tol_abs), int(krylov), int(max_lin_it), int(max_steps), int(jac_lag),
-                          PREC[prec] if isinstance(prec, str) else int(prec))
+                          PREC[prec] if isinstance(prec, str) else int(prec), float(reject_growth))
 
 
 def _steady_dict(s):
     return dict(steps=s.steps, gmres_its=s.gmres_its, converged=s.converged, res0=s.res0, res_final=s.res_final,
-                dtau_final=s.dtau_final)
+                dtau_final=s.dtau_final, rejected=s.rejected)
 
 
 def step_opts(dt, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=100, max_newton=100, jac_lag=2,

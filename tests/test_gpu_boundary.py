@@ -299,3 +299,31 @@ def test_inviscid_cylinder_steady():
     print(f"[boundary] inviscid cylinder {st} Cd={cd:.3e} Cl={cl:.3e} Es={es:.3e}", flush=True)
     assert st["converged"] == 1 and st["steps"] <= 30
     assert abs(cd) < 5e-3 and abs(cl) < 1e-5 and es < 1e-10
+
+
+def test_inviscid_cylinder_step_rejection():
+    """The 3rd-order inviscid cylinder on 48 x 40 elements: with the paper's SER the
+    pseudo-transient iteration diverges; with step rejection (not in the paper) it converges."""
+    from paper_1903_06304_amd import lmfr
+    mesh = I.Mesh(48, 40, 2, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 100.0), pg=4, bc=(0, 0, SLIP, FAR))
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=1e-3, viscous=False, kappa=1.0, geom_order=4)
+    qinf = [prm.gas_constant, 1.0, 0.0, 1.0]
+    g = lmfr.Context(prm, *mesh.connectivity())
+    g.set_geometry(*mesh.nodes(0.0))
+    g.set_farfield(qinf)
+    g.set_option("preconditioner", 1)
+    kw = dict(dtau0=0.01, dtau_min=0.01, dtau_max=1e20, tol_pseudo=1e-9, tol_res=1e-6, krylov=150, max_lin_it=1500,
+              max_steps=60, check=False)
+    q0 = I.uniform_flow(mesh, prm, u=1.0, v=0.0)
+    q = _dev(q0)
+    plain = g.steady_solve(q, **kw)
+    q = _dev(q0)
+    guarded = g.steady_solve(q, reject_growth=10.0, **kw)
+    torch.cuda.synchronize()
+    print(f"[boundary] cylinder 48x40 p2: SER {plain}; with step rejection {guarded}", flush=True)
+    assert plain["converged"] == 0
+    assert guarded["converged"] == 1 and guarded["rejected"] >= 1
+    o = Oracle(prm, mesh)
+    o.set_farfield(qinf)
+    cd, cl, es = _wall_forces_and_entropy(o, mesh, prm, q.cpu().numpy())
+    assert abs(cd) < 1e-3 and abs(cl) < 1e-3 and es < 1e-10, (cd, cl, es)

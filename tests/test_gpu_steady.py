@@ -129,6 +129,28 @@ def test_steady_options_rejected():
     g = _ctx(mesh, prm)
     qg = _dev(q)
     for bad in (dict(dtau0=0.0), dict(dtau_min=0.0), dict(dtau_min=1.0, dtau_max=0.5), dict(r_ser=-1.0),
-                dict(krylov=0), dict(krylov=157), dict(max_steps=-1), dict(jac_lag=0), dict(prec=7)):
+                dict(krylov=0), dict(krylov=157), dict(max_steps=-1), dict(jac_lag=0), dict(prec=7),
+                dict(reject_growth=-1.0), dict(reject_growth=float("inf"))):
         with pytest.raises(lmfr.FRError):
             g.steady_solve(qg, **bad)
+
+
+def test_step_rejection_matches_oracle():
+    """Step rejection (not in the paper; off by default) on the GPU and in the oracle, with a
+    growth bound so small that every step after the first is undone: same step, rejection and
+    GMRES counts, same final dtau (dtau0 / 1000), and the state back where it started."""
+    mesh, prm, q = _case(4, 2, 0.1)
+    kw = dict(dtau0=0.5, dtau_min=0.5, tol_pseudo=1e-30, tol_res=1e-10, krylov=60, max_lin_it=600, max_steps=5,
+              reject_growth=1e-300)
+    g = _ctx(mesh, prm)
+    qg = _dev(q)
+    st = g.steady_solve(qg, **kw)
+    torch.cuda.synchronize()
+    qo, sto = Oracle(prm, mesh).steady_solve(q, **kw)
+    print(f"[steady] rejection GPU {st} oracle { {k: v for k, v in sto.items() if k != 'hist'} }", flush=True)
+    assert st["steps"] == sto["steps"] == 6 and st["rejected"] == sto["rejected"] == 3
+    assert st["gmres_its"] == sto["gmres_its"]
+    assert abs(st["dtau_final"] - 5e-4) <= 1e-15 and abs(sto["dtau_final"] - 5e-4) <= 1e-15
+    scale = np.max(np.abs(q), axis=(1, 2))[:, None, None]
+    assert np.max(np.abs(qg.cpu().numpy() - q) / scale) <= 1e-13
+    assert np.max(np.abs(qo - q) / scale) <= 1e-13

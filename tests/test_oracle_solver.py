@@ -12,6 +12,9 @@
   dtau Gamma^-1 R to first order; a perturbed uniform NS flow converges to a uniform state
   (R = 0 there) in a number of steps that does not depend on the Mach number (the purpose
   of the preconditioning, Sec. 2.2).
+* Step rejection of the steady solve (not in the paper; off by default): a step that
+  raises the residual is undone -- the state returns to what it was, to rounding -- and
+  retried with dtau / 10 from a residual equal to the one before the step.
 * Symmetric block Gauss-Seidel preconditioner in element colour order: P^-1 r equals the
   dense solve with P = (D + L) D^-1 (D + U) assembled from the pinned dense operator; the
   colouring is proper (no two face neighbours share a colour; a checkerboard on even
@@ -246,3 +249,26 @@ def test_block_gauss_seidel_cuts_gmres_iterations():
     assert s1["newton_its"] == s0["newton_its"]
     assert s1["gmres_its"] < 0.7 * s0["gmres_its"], (s0["gmres_its"], s1["gmres_its"])
     assert np.max(np.abs(q1 - q0)) <= 1e-8 * np.max(np.abs(q0))
+
+
+def test_steady_step_rejection_undoes_and_retries():
+    """reject_growth so small that every step after the first is undone: the history is
+    accepted (dtau0), undone, retry (dtau0/10) from the initial residual, undone, retry
+    (dtau0/100), undone; the final state is the initial one to rounding."""
+    o, q = _steady_case(mach=0.1, nx=4, p=2)
+    d0 = 0.5
+    qs, st = o.steady_solve(q, dtau0=d0, dtau_min=d0, tol_pseudo=1e-30, tol_res=1e-10, krylov=60, max_lin_it=600,
+                            max_steps=5, reject_growth=1e-300)
+    assert st["rc"] == -5 and st["converged"] == 0
+    assert st["steps"] == 6 and st["rejected"] == 3
+    res = [h[0] for h in st["hist"]]
+    dts = [h[1] for h in st["hist"]]
+    assert np.allclose(dts, [d0, -d0 / 10, d0 / 10, -d0 / 100, d0 / 100, -d0 / 1000], rtol=1e-14), dts
+    assert abs(res[2] - res[0]) <= 1e-9 * res[0] and abs(res[4] - res[0]) <= 1e-9 * res[0], res
+    assert abs(st["dtau_final"] - d0 / 1000) <= 1e-14 * d0
+    scale = np.max(np.abs(q), axis=(1, 2))[:, None, None]
+    assert np.max(np.abs(qs - q) / scale) <= 1e-13
+    # growth 0 is the paper's SER: same run as before the option existed
+    _, st0 = o.steady_solve(q, dtau0=d0, dtau_min=d0, tol_pseudo=1e-30, tol_res=1e-10, krylov=60, max_lin_it=600,
+                            max_steps=3)
+    assert st0["rejected"] == 0 and st0["steps"] == 3 and all(h[1] > 0 for h in st0["hist"])
