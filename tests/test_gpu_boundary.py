@@ -7,6 +7,10 @@ elements (no-slip wall inside, far field outside), a curved box with all three k
 slip channel (inviscid), a translating box with moving walls, a P1 annulus (inviscid).
 Bars as for periodic meshes: R per row <= 1e-12 S_c; JVP, VJP, Newton operator <= 1e-12
 normwise; blocks <= 1e-12 of their largest entry; BDF2 and steady states 1e-8 relative.
+The GPU path is also held to the invariants that pin the oracle's boundary faces, with no
+oracle in the loop: a slip wall is a mirror plane (curved and moving meshes), a far-field
+face is a neighbour holding the free stream, plane Poiseuille flow gives the exact residual,
+and a closed adiabatic box at rest conserves mass and energy.
 """
 import numpy as np
 import pytest
@@ -327,3 +331,97 @@ def test_inviscid_cylinder_step_rejection():
     o.set_farfield(qinf)
     cd, cl, es = _wall_forces_and_entropy(o, mesh, prm, q.cpu().numpy())
     assert abs(cd) < 1e-3 and abs(cl) < 1e-3 and es < 1e-10, (cd, cl, es)
+
+
+# ---- the oracle's boundary pins, evaluated with the GPU library (independent of the oracle)
+def _gpu_residual(prm, mesh, q, t=0.0, qinf=None):
+    from paper_1903_06304_amd import lmfr
+    g = lmfr.Context(prm, *mesh.connectivity())
+    g.set_geometry(*mesh.nodes(t))
+    if qinf is not None:
+        g.set_farfield(qinf)
+    return g.residual(_dev(q)).cpu().numpy()
+
+
+def _wavy(amp, Lx, Ly, moving):
+    def f(xr, yr, t):
+        s = np.sin(2 * np.pi * xr / Lx)
+        dx, dy = amp * s * np.cos(np.pi * yr / Ly), amp * s * np.sin(np.pi * yr / Ly)
+        a, da = (1 + np.sin(2 * np.pi * t), 2 * np.pi * np.cos(2 * np.pi * t)) if moving else (1.0, 0.0)
+        return xr + a * dx, yr + a * dy, da * dx, da * dy
+    return f
+
+
+@pytest.mark.parametrize("p,moving", [(3, False), (4, True)])
+def test_gpu_slip_wall_is_a_mirror_plane(p, moving):
+    """Curved (and moving) mesh mirrored across y = 0: the half domain with slip walls at
+    y = 0 and y = Ly gives the residual of the full periodic domain's upper half."""
+    nx, nh, Lx, Ly, t = 6, 5, 2.0, 1.0, 0.13
+    n = p + 1
+    mp = _wavy(0.08, Lx, Ly, moving)
+    half = I.Mesh(nx, nh, p, (0.0, Lx, 0.0, Ly), mp, moving=moving, bc=(0, 0, SLIP, SLIP))
+    full = I.Mesh(nx, 2 * nh, p, (0.0, Lx, -Ly, Ly), mp, moving=moving)
+    prm = I.Params(order=p, n_elem=half.E, mach_ref=0.1, reynolds=30.0, viscous=True, kappa=1.0, moving=moving)
+    qh = _state(half, prm, t)
+    Rh = _gpu_residual(prm, half, qh, t)
+    Np = n * n
+    qf = np.empty((4, full.E, Np))
+    jrev = np.array([i + n * (n - 1 - j) for j in range(n) for i in range(n)])
+    sgn = np.array([1.0, 1.0, -1.0, 1.0])[:, None]
+    for iyh in range(nh):
+        for ix in range(nx):
+            src = qh[:, ix + nx * iyh]
+            qf[:, ix + nx * (nh + iyh)] = src
+            qf[:, ix + nx * (nh - 1 - iyh)] = sgn * src[:, jrev]
+    prm.n_elem = full.E
+    Rf = _gpu_residual(prm, full, qf, t)
+    upper = np.arange(nx * nh, 2 * nx * nh)
+    d = np.max(np.abs(Rh - Rf[:, upper]), axis=(1, 2))
+    s = np.max(np.abs(Rh), axis=(1, 2))
+    assert np.all(d <= 1e-11 * s), (d, s)
+
+
+def test_gpu_far_field_is_a_free_stream_neighbour():
+    p, nx, ny, h = 3, 6, 5, 0.7
+    prm = I.Params(order=p, n_elem=(nx - 1) * ny, mach_ref=0.1, reynolds=20.0, viscous=True, kappa=1.0)
+    mf = I.Mesh(nx - 1, ny, p, (0.0, (nx - 1) * h, 0.0, ny * h), bc=(FAR, FAR, 0, 0))
+    mpm = I.Mesh(nx, ny, p, (0.0, nx * h, 0.0, ny * h))
+    qf = _state(mf, prm, 0.0)
+    qinf = np.array([prm.gas_constant * 1.02, 0.35, 0.1, 0.98])
+    qp = np.empty((4, mpm.E, mpm.Np))
+    for e in range(mpm.E):
+        ix, iy = e % nx, e // nx
+        qp[:, e] = qinf[:, None] if ix == nx - 1 else qf[:, ix + (nx - 1) * iy]
+    Rf = _gpu_residual(prm, mf, qf, qinf=qinf)
+    prm.n_elem = mpm.E
+    Rp = _gpu_residual(prm, mpm, qp)
+    keep = [ix + nx * iy for iy in range(ny) for ix in range(nx - 1)]
+    d = np.max(np.abs(Rf - Rp[:, keep]), axis=(1, 2))
+    assert np.all(d <= 1e-12 * np.max(np.abs(Rf), axis=(1, 2))), d
+
+
+def test_gpu_noslip_poiseuille_and_closed_box():
+    """Plane Poiseuille between walls at rest: the exact NS residual at p = 3; a closed
+    adiabatic box with the fluid at rest and any temperature field conserves mass and energy."""
+    p, H, U = 3, 1.0, 0.3
+    mesh = I.Mesh(4, 5, p, (0.0, 2.0, 0.0, H), bc=(0, 0, WALL, WALL))
+    prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.1, reynolds=7.0, viscous=True, kappa=1.0)
+    _, y = mesh.solution_points()
+    q = I.uniform_flow(mesh, prm, u=0.0, v=0.0)
+    q[1] = U * y * (H - y)
+    R = _gpu_residual(prm, mesh, q)
+    up, upp, k = U * (H - 2 * y), -2.0 * U, prm.mu / prm.reynolds
+    ex = np.stack([0 * y, k * upp + 0 * y, 0 * y, k * (up * up + q[1] * upp)])
+    assert np.max(np.abs(R - ex)) <= 1e-9 * prm.gas_constant, np.max(np.abs(R - ex), axis=(1, 2))
+    box = I.Mesh(5, 4, p, (0.0, 2.0, 0.0, 1.5), bc=(WALL,) * 4)
+    prm = I.Params(order=p, n_elem=box.E, mach_ref=0.2, reynolds=5.0, viscous=True, kappa=1.0)
+    x, y = box.solution_points()
+    q = I.uniform_flow(box, prm, u=0.0, v=0.0)
+    q[3] *= 1 + 0.1 * np.cos(2.0 * x + 0.5) * np.sin(3.0 * y + 0.2)
+    R = _gpu_residual(prm, box, q)
+    o = Oracle(prm, box)      # geometry (|J|) only
+    w = np.polynomial.legendre.leggauss(p + 1)[1]
+    W = np.outer(w, w).reshape(-1)[None, :] * o.geometry()["jac"]
+    tot = np.einsum("es,ves->v", W, R)
+    mag = np.einsum("es,ves->v", W, np.abs(R))
+    assert abs(tot[0]) <= 1e-13 * mag[0] and abs(tot[3]) <= 1e-13 * mag[3], (tot, mag)
