@@ -32,7 +32,8 @@ template <bool VISC>
 __device__ void point_flux_rev(const PhysConst& c, const double* q, const double* G, const double* af,
                                const double* ag, const double* aqc, double* aq, double* aG) {
     const double p = q[0], u = q[1], v = q[2], T = q[3];
-    const double rho = p * c.inv_Rg / T;
+    const double iT = 1.0 / T;   // one division; the quotients below multiply by it
+    const double rho = p * c.inv_Rg * iT;
     const double ru = rho * u, rv = rho * v, k2 = u * u + v * v;
     const double E = p * c.inv_gm1 + 0.5 * rho * k2;
     const double Ep = E + p;
@@ -66,7 +67,7 @@ __device__ void point_flux_rev(const PhysConst& c, const double* q, const double
     a_u += 2.0 * u * a_k2; a_v += 2.0 * v * a_k2;
     a_rho += a_ru * u; a_u += a_ru * rho;
     a_rho += a_rv * v; a_v += a_rv * rho;
-    a_p += a_rho * c.inv_Rg / T; a_T -= a_rho * rho / T;
+    a_p += a_rho * c.inv_Rg * iT; a_T -= a_rho * rho * iT;
     aq[0] = a_p; aq[1] = a_u; aq[2] = a_v; aq[3] = a_T;
     if (VISC) {
         // txx = mu_re (4/3 ux - 2/3 vy), tyy = mu_re (4/3 vy - 2/3 ux), txy = mu_re (uy + vx)
@@ -83,7 +84,8 @@ __device__ void point_flux_rev(const PhysConst& c, const double* q, const double
 __device__ void normal_flux_rev(const PhysConst& c, const double* q, double nx, double ny, double vgn,
                                 const double* a, double* aq) {
     const double p = q[0], u = q[1], v = q[2], T = q[3];
-    const double rho = p * c.inv_Rg / T;
+    const double iT = 1.0 / T;
+    const double rho = p * c.inv_Rg * iT;
     const double ru = rho * u, rv = rho * v;
     const double E = p * c.inv_gm1 + 0.5 * rho * (u * u + v * v);
     const double un = u * nx + v * ny, unr = un - vgn;
@@ -96,7 +98,7 @@ __device__ void normal_flux_rev(const PhysConst& c, const double* q, double nx, 
     a_p += a_E * c.inv_gm1; a_rho += a_E * 0.5 * (u * u + v * v); a_u += a_E * rho * u; a_v += a_E * rho * v;
     a_rho += a_ru * u; a_u += a_ru * rho;
     a_rho += a_rv * v; a_v += a_rv * rho;
-    a_p += a_rho * c.inv_Rg / T; a_T -= a_rho * rho / T;
+    a_p += a_rho * c.inv_Rg * iT; a_T -= a_rho * rho * iT;
     aq[0] += a_p; aq[1] += a_u; aq[2] += a_v; aq[3] += a_T;
 }
 
@@ -110,11 +112,14 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
     const double vgn = ug * nx + vg * ny;
     double qb[4], dq[4];
     for (int r = 0; r < 4; ++r) { qb[r] = 0.5 * (qm[r] + qp[r]); dq[r] = qp[r] - qm[r]; }
-    const double rho = qb[0] * c.inv_Rg / qb[3];
+    // reciprocals taken once: T, c, U_r^2 (and |v - v_g|, c' below)
+    const double iT = 1.0 / qb[3];
+    const double rho = qb[0] * c.inv_Rg * iT;
     const double cs = sqrt(c.gRg * qb[3]);
+    const double ics = 1.0 / cs;
     const double ur = qb[1] - ug, vr = qb[2] - vg;
     const double mg = sqrt(ur * ur + vr * vr);
-    const double Ma = mg / cs;
+    const double Ma = mg * ics;
     // eps = min(1, max(eps_min, Ma)) with the forward tie rules
     double eps;
     bool ma_branch = false;
@@ -125,8 +130,9 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
         ma_branch = took_ma && !(1.0 <= t);
     }
     const double Ur = eps * cs, Ur2 = Ur * Ur;
-    const double theta = 1.0 / Ur2 + c.inv_Cp / qb[3];
-    const double rhoT = -rho / qb[3];
+    const double iUr2 = 1.0 / Ur2;
+    const double theta = iUr2 + c.inv_Cp * iT;
+    const double rhoT = -rho * iT;
     const double h = c.Cp * qb[3] + 0.5 * (qb[1] * qb[1] + qb[2] * qb[2]);
     const double r0 = theta * dq[0] + rhoT * dq[3];
     double gd[4];
@@ -180,7 +186,7 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
     }
     const double a_unp = a_lam * (unp >= 0.0 ? 1.0 : -1.0);
     const double a_cp = a_lam;
-    const double a_X = a_cp / (2.0 * cp);
+    const double a_X = a_cp * (0.5 / cp);
     double a_alpha = a_X * 2.0 * alpha * un * un;
     double a_un = a_X * 2.0 * alpha * alpha * un;
     double a_Ur2 = a_X;
@@ -203,25 +209,26 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
     const double a_rhoT = a_r0 * dq[3];
     a_dq[3] += a_r0 * rhoT;
     a_qb[3] += a_h * c.Cp; a_qb[1] += a_h * qb[1]; a_qb[2] += a_h * qb[2];
-    a_rho -= a_rhoT / qb[3];
-    a_qb[3] += a_rhoT * rho / qb[3] / qb[3] * 1.0;   // d(-rho/T)/dT = rho/T^2
-    a_Ur2 -= a_theta / (Ur2 * Ur2);
-    a_qb[3] -= a_theta * c.inv_Cp / (qb[3] * qb[3]);
+    a_rho -= a_rhoT * iT;
+    a_qb[3] += a_rhoT * rho * iT * iT;   // d(-rho/T)/dT = rho/T^2
+    a_Ur2 -= a_theta * iUr2 * iUr2;
+    a_qb[3] -= a_theta * c.inv_Cp * iT * iT;
     const double a_Ur = 2.0 * Ur * a_Ur2;
     a_eps += a_Ur * cs;
     double a_cs = a_Ur * eps;
     if (ma_branch) {
         const double a_Ma = a_eps;
-        const double a_mg = a_Ma / cs;
-        a_cs -= a_Ma * Ma / cs;
-        a_ur += a_mg * ur / mg;
-        a_vr += a_mg * vr / mg;
+        const double a_mg = a_Ma * ics;
+        a_cs -= a_Ma * Ma * ics;
+        const double img = 1.0 / mg;   // Ma > eps_min >= 0 on this branch, so mg > 0
+        a_ur += a_mg * ur * img;
+        a_vr += a_mg * vr * img;
     }
     a_qb[1] += a_ur;
     a_qb[2] += a_vr;
-    a_qb[3] += a_cs * c.gRg / (2.0 * cs);
-    a_qb[0] += a_rho * c.inv_Rg / qb[3];
-    a_qb[3] -= a_rho * rho / qb[3];
+    a_qb[3] += a_cs * c.gRg * (0.5 * ics);
+    a_qb[0] += a_rho * c.inv_Rg * iT;
+    a_qb[3] -= a_rho * rho * iT;
     for (int r = 0; r < 4; ++r) {
         aqm[r] = 0.5 * a_qb[r] - a_dq[r];
         aqp[r] = 0.5 * a_qb[r] + a_dq[r];
