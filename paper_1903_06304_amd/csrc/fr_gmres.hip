@@ -101,6 +101,36 @@ __global__ void k_cycle_init(Ctl k, int m) {
 }
 
 // column j of each case's Hessenberg matrix, Givens rotations, convergence flag
+// Column j of H: the Gram-Schmidt coefficients h_0..h_j (one or two passes summed) through the
+// previous rotations.  Rows 0..j-1 are stored; the rotated row-j entry is returned.  The running
+// entry stays in a register and the inputs are read through pointers that alias nothing written,
+// so the loads of later rows need not wait for the stores of earlier ones.
+__device__ __forceinline__ double rotate_column(const double* __restrict__ h1, const double* __restrict__ h2,
+                                                const double* __restrict__ cs, const double* __restrict__ sn,
+                                                double* __restrict__ Hj, int j, int m, bool two) {
+    constexpr int CH = 8;   // rows whose inputs are loaded together
+    double a = two ? h1[0] + h2[0] : h1[0];
+    for (int i0 = 0; i0 < j; i0 += CH) {
+        double hb[CH], c8[CH], s8[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            const int i = i0 + t < j ? i0 + t : j - 1;   // rows past j - 1 load row j - 1 again, unused
+            const double x1 = h1[i + 1], x2 = h2[i + 1];
+            hb[t] = two ? x1 + x2 : x1;
+            c8[t] = cs[i];
+            s8[t] = sn[i];
+        }
+#pragma unroll
+        for (int t = 0; t < CH; ++t) {
+            if (i0 + t < j) {
+                Hj[(size_t)(i0 + t) * m] = c8[t] * a + s8[t] * hb[t];
+                a = -s8[t] * a + c8[t] * hb[t];
+            }
+        }
+    }
+    return a;
+}
+
 __global__ void k_givens(Ctl k, int j, int m, int passes) {
     const int c = case_index();
     if (c >= k.n) return;
@@ -112,15 +142,8 @@ __global__ void k_givens(Ctl k, int j, int m, int passes) {
     double* cs = gs + L.CS;
     double* sn = gs + L.SN;
     double* g = gs + L.G;
-    for (int i = 0; i <= j; ++i) H[i * m + j] = passes == 2 ? gs[L.H1 + i] + gs[L.H2 + i] : gs[L.H1 + i];
     const double hn = sqrt(gs[L.NRM]);
-    H[(j + 1) * m + j] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double a0 = H[i * m + j], a1 = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a0 + sn[i] * a1;
-        H[(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
-    }
-    const double a0 = H[j * m + j], a1 = H[(j + 1) * m + j];
+    const double a0 = rotate_column(gs + L.H1, gs + L.H2, cs, sn, H + j, j, m, passes == 2), a1 = hn;
     const double den = sqrt(a0 * a0 + a1 * a1);
     cs[j] = den == 0.0 ? 1.0 : a0 / den;
     sn[j] = den == 0.0 ? 0.0 : a1 / den;
