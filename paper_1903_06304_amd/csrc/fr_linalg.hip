@@ -336,9 +336,15 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const doubl
         double nacc = 0.0;
         for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
             const double wt = w[t];
+            if (cnt > 0) {
+                // all rows loaded before any is used (rows past cnt - 1 reload row cnt - 1, unused)
+                double x[DB];
 #pragma unroll
-            for (int i = 0; i < DB; ++i)
-                if (i < cnt) acc[i] += Vc[i * ldv + t] * wt;
+                for (int i = 0; i < DB; ++i) x[i] = Vc[(size_t)(i < cnt ? i : cnt - 1) * ldv + t];
+#pragma unroll
+                for (int i = 0; i < DB; ++i)
+                    if (i < cnt) acc[i] += x[i] * wt;
+            }
             if (nrm && t < lim) nacc += wt * wt;
         }
         __syncthreads();   // red[] of the previous chunk consumed
@@ -379,6 +385,15 @@ __global__ void __launch_bounds__(RED_THREADS) k_update(ChunkArgs ca, const doub
         for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
             double wt = w_in[t];
             int i = 0;
+            // 16 basis entries loaded before any is used, summed in the groups of four below
+            for (; i + 16 <= nv; i += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = V[(size_t)(i + u) * ldv + t];
+#pragma unroll
+                for (int u = 0; u < 16; u += 4)
+                    wt -= cf[i + u] * x[u] + cf[i + u + 1] * x[u + 1] + cf[i + u + 2] * x[u + 2] + cf[i + u + 3] * x[u + 3];
+            }
             for (; i + 4 <= nv; i += 4)
                 wt -= cf[i] * V[i * ldv + t] + cf[i + 1] * V[(i + 1) * ldv + t] + cf[i + 2] * V[(i + 2) * ldv + t] +
                       cf[i + 3] * V[(i + 3) * ldv + t];
