@@ -220,15 +220,22 @@ struct Vec {
         }                                                                                                  \
     }
 
-// out = s_c * in, s_c = gs[c * stride + field]
+// out = s_c * in, s_c = gs[c * stride + field]; launched with 256 threads
+static_assert(CHUNK % (4 * 256) == 0, "k_scale_case covers a chunk in passes of 4 x 256 entries");
 __global__ void k_scale_case(Vec vc, const double* __restrict__ in, double* __restrict__ out, const double* gs,
                              int stride, int field) {
     for (int ch = blockIdx.x; ch < vc.nchunks; ch += gridDim.x) {
         const int c = vc.chunk_case[ch];
         if (vc.gi[c * GI_STRIDE + vc.flag]) continue;
         const double a = gs[(size_t)c * stride + field];
-        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x)
-            out[t] = a * in[t];
+        // four entries a pass, loaded before the first store (CHUNK is a multiple of 4 blockDim)
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += 4 * blockDim.x) {
+            double x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = in[t + (size_t)k * blockDim.x];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[t + (size_t)k * blockDim.x] = a * x[k];
+        }
     }
 }
 

@@ -647,12 +647,39 @@ fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const
 }
 
 // u = z on the elements whose colour lies in [lo, hi], 0 elsewhere
+// u = z on the elements of colours lo..hi, 0 elsewhere.  A thread takes U points a pass and
+// issues all their loads (colour and state, unconditionally) before its first store.
 __global__ void k_color_mask(ChunkArgs ca, const double* __restrict__ z, double* __restrict__ u, int lo, int hi) {
-    FR_POINT_LOOP(ca, {
-        const int col = cd.g.color[t / cd.Np];
-        const bool keep = col >= lo && col <= hi;
-        for (int v = 0; v < 4; ++v) u[base + v * EN] = keep ? z[base + v * EN] : 0.0;
-    })
+    constexpr int U = 4;
+    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
+        const int c = ca.chunk_case[ch];
+        if (chunk_skipped(ca, c)) continue;
+        const CaseDev& cd = ca.cases[c];
+        const size_t EN = (size_t)cd.E * cd.Np;
+        const size_t r0 = (size_t)ch * CHUNK - cd.off;
+        if (r0 >= EN) continue;
+        const size_t r1 = r0 + CHUNK < EN ? r0 + CHUNK : EN;
+        for (size_t t0 = r0 + threadIdx.x; t0 < r1; t0 += U * blockDim.x) {
+            int col[U];
+            double zv[U][4];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                size_t t = t0 + (size_t)k * blockDim.x;
+                t = t < r1 ? t : t0;   // past the end: reload t0, unused
+                col[k] = cd.g.color[t / cd.Np];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) zv[k][v] = z[cd.off + t + v * EN];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const size_t t = t0 + (size_t)k * blockDim.x;
+                if (t >= r1) break;
+                const bool keep = col[k] >= lo && col[k] <= hi;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) u[cd.off + t + v * EN] = keep ? zv[k][v] : 0.0;
+            }
+        }
+    }
 }
 
 fr_status launch_color_mask(const Solver& sv, const double* z, double* u, int lo, int hi, const int* flags, int flag,
