@@ -171,7 +171,19 @@ __global__ void k_backsub(Ctl k, int m) {
     double* y = gs + L.Y;
     for (int i = jd - 1; i >= 0; --i) {
         double s = gs[L.G + i];
-        for (int q = i + 1; q < jd; ++q) s -= H[i * m + q] * y[q];
+        // eight terms' loads a pass, subtracted in order (past jd - 1: reload jd - 1, unused)
+        for (int q0 = i + 1; q0 < jd; q0 += 8) {
+            double h8[8], y8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + u < jd ? q0 + u : jd - 1;
+                h8[u] = H[i * m + q];
+                y8[u] = y[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u < jd) s -= h8[u] * y8[u];
+        }
         y[i] = s / H[i * m + i];
     }
     for (int i = jd; i < m; ++i) y[i] = 0.0;
@@ -253,7 +265,16 @@ __global__ void k_combine_case(Vec vc, const double* __restrict__ V, size_t ldv,
         __syncthreads();
         for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += blockDim.x) {
             double s = 0.0;
-            for (int i = 0; i < nv; ++i) s += y[i] * V[i * ldv + t];
+            int i = 0;
+            // 16 basis entries loaded before any is used, added in order
+            for (; i + 16 <= nv; i += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = V[(size_t)(i + u) * ldv + t];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) s += y[i + u] * x[u];
+            }
+            for (; i < nv; ++i) s += y[i] * V[i * ldv + t];
             out[t] = s;
         }
     }
