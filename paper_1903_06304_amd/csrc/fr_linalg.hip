@@ -308,6 +308,15 @@ __device__ __forceinline__ bool chunk_skipped(const ChunkArgs& ca, int c) {
     return ca.flags && ca.flags[c * GI_STRIDE + ca.flag];
 }
 
+// End of chunk ch within its case's entries: the padding after a case's 4 E Np entries is
+// neither read nor written by the reductions, so a non-finite value that arithmetic on the
+// padding once produced (a scaling by a non-finite coefficient) cannot reach a dot product
+// or norm of a later iteration, step or solve.
+__device__ __forceinline__ size_t case_end(const CaseDev& cd, int ch) {
+    const size_t e = cd.off + (size_t)4 * cd.E * cd.Np, ce = (size_t)(ch + 1) * CHUNK;
+    return e < ce ? e : ce;
+}
+
 // Dot products V_i . w for i in [DB*blockIdx.y, DB*blockIdx.y + DB) ∩ [0, nv), plus |w|^2 in
 // slot nv when want_norm (y-block 0 only; mass_only: first E Np entries of the case).
 // DB = 8 vectors per pass (16 measured slower: fewer workgroups, heavier reduction).
@@ -324,9 +333,10 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const doubl
     for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
         const int c = ca.chunk_case[ch];
         if (chunk_skipped(ca, c)) continue;
-        size_t lim = (size_t)ch * CHUNK + CHUNK;
+        const CaseDev& cd = ca.cases[c];
+        const size_t end = case_end(cd, ch);
+        size_t lim = end;
         if (mass_only) {
-            const CaseDev& cd = ca.cases[c];
             const size_t m = cd.off + (size_t)cd.E * cd.Np;
             lim = m < lim ? m : lim;
         }
@@ -334,7 +344,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const doubl
 #pragma unroll
         for (int i = 0; i < DB; ++i) acc[i] = 0.0;
         double nacc = 0.0;
-        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < end; t += RED_THREADS) {
             const double wt = w[t];
             if (cnt > 0) {
                 // all rows loaded before any is used (rows past cnt - 1 reload row cnt - 1, unused)
@@ -378,11 +388,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_update(ChunkArgs ca, const doub
     for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
         const int c = ca.chunk_case[ch];
         if (chunk_skipped(ca, c)) continue;
+        const size_t end = case_end(ca.cases[c], ch);
         __syncthreads();   // cf[] / red[] of the previous chunk consumed
         if ((int)threadIdx.x < MAXV) cf[threadIdx.x] = ((int)threadIdx.x < nv) ? coef[(size_t)c * cstride + threadIdx.x] : 0.0;
         __syncthreads();
         double nacc = 0.0;
-        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < (size_t)(ch + 1) * CHUNK; t += RED_THREADS) {
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < end; t += RED_THREADS) {
             double wt = w_in[t];
             int i = 0;
             // 16 basis entries loaded before any is used, summed in the groups of four below

@@ -307,7 +307,11 @@ def test_inviscid_cylinder_steady():
 
 def test_inviscid_cylinder_step_rejection():
     """The 3rd-order inviscid cylinder on 48 x 40 elements: with the paper's SER the
-    pseudo-transient iteration diverges; with step rejection (not in the paper) it converges."""
+    pseudo-transient iteration diverges; with step rejection (not in the paper) it converges.
+    The path is sensitive to rounding (with growth 10 it converged in 38 steps on one build
+    and stalled at 1e-3 on another whose reductions round differently); growth 2 converges
+    in 91 steps, so the bar allows 150.  Both solves run on one context, so the second also
+    checks that nothing non-finite left by the diverged first solve reaches the second."""
     from paper_1903_06304_amd import lmfr
     mesh = I.Mesh(48, 40, 2, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 100.0), pg=4, bc=(0, 0, SLIP, FAR))
     prm = I.Params(order=2, n_elem=mesh.E, mach_ref=1e-3, viscous=False, kappa=1.0, geom_order=4)
@@ -322,7 +326,7 @@ def test_inviscid_cylinder_step_rejection():
     q = _dev(q0)
     plain = g.steady_solve(q, **kw)
     q = _dev(q0)
-    guarded = g.steady_solve(q, reject_growth=10.0, **kw)
+    guarded = g.steady_solve(q, reject_growth=2.0, **dict(kw, max_steps=150))
     torch.cuda.synchronize()
     print(f"[boundary] cylinder 48x40 p2: SER {plain}; with step rejection {guarded}", flush=True)
     assert plain["converged"] == 0
