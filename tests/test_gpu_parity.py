@@ -325,3 +325,36 @@ def test_bdf_operator_packs_bitwise(case):
     torch.cuda.synchronize()
     err = normwise_rel(A1.cpu().numpy(), A0.cpu().numpy())
     assert np.all(err <= 1e-14), (name, err)
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_context_recovers_after_non_finite_step(precond):
+    """A step from a non-finite state (reported as FR_ENONFINITE) leaves nothing behind in the
+    context's solver buffers, chunk padding included: the next steps on the same context equal
+    those on a fresh context bit for bit."""
+    lmfr = _lmfr()
+    c = I.config_c1(nx=8)
+    kw = dict(tol_pseudo=1e-10, tol_res=1e-9, krylov=20, max_lin_it=200, max_newton=20)
+
+    def ctx():
+        g = lmfr.Context(c.prm, *c.mesh.connectivity())
+        g.set_geometry(*c.mesh.nodes(0.0))
+        g.set_option("preconditioner", precond)
+        return g
+
+    used = ctx()
+    bad = c.q.copy()
+    bad[3, 5, 2] = np.nan
+    st = used.bdf2_step(_dev(bad), _dev(c.q_nm1), c.dt, check=False, **kw)
+    torch.cuda.synchronize()
+    print("[parity] non-finite step", st, flush=True)
+    assert st["rc"] == lmfr.FR_ENONFINITE and st["converged"] == 0
+    out = {}
+    for name, g_ in (("used", used), ("fresh", ctx())):
+        q = _dev(c.q)
+        out[name] = (q, g_.bdf2_step(q, _dev(c.q_nm1), c.dt, **kw))
+    torch.cuda.synchronize()
+    print("[parity] after it", out["used"][1], "fresh", out["fresh"][1], flush=True)
+    assert out["used"][1]["converged"] == 1
+    assert out["used"][1]["gmres_its"] == out["fresh"][1]["gmres_its"]
+    assert torch.equal(out["used"][0], out["fresh"][0])
