@@ -185,3 +185,77 @@ def test_viscous_flux_special_cases():
     # Fourier heat flux: k = mu Cp / Pr
     f, g = o.phys_flux(q, np.array([0, 0, 0, 2.0]), z)
     assert np.allclose(f0 - f, [0, 0, 0, prm.mu * prm.cp / prm.prandtl * 2.0 / prm.reynolds], rtol=1e-13)
+
+
+def _cons(prm, q):
+    """q^c = (rho, rho u, rho v, E) of the Sec. 2.1 non-dimensionalisation, written out."""
+    rho = q[0] / (prm.gas_constant * q[3])
+    E = q[0] / (prm.gamma - 1.0) + 0.5 * rho * (q[1] ** 2 + q[2] ** 2)
+    return np.array([rho, rho * q[1], rho * q[2], E])
+
+
+def _inviscid_ctx(mach, kappa, moving=True):
+    return _ctx(mach=mach, kappa=kappa, viscous=False, moving=moving)
+
+
+def test_rusanov_dissipation_at_eps_one_is_scalar_jump_of_conserved_state():
+    """Eq. (Rosanov) at eps = 1 (kappa Ma_inf >= 1): Gamma~ = M at the averaged state and
+    |lambda|max = |u_n| + c (alpha = 0), so the dissipation is -1/2 (|u_n| + c) times the
+    jump of the conserved state up to O(delta^3): M at the midpoint integrates dq^c/dq^p
+    along the jump with a midpoint-rule error.  The relative deviation therefore falls
+    4x when the jump halves.  A dissipation with the wrong sign (relative deviation 2) or a
+    coefficient 1 instead of 1/2 (deviation 1) fails at once."""
+    o, prm = _inviscid_ctx(0.05, 30.0)
+    rng = np.random.default_rng(11)
+    z = np.zeros(4)
+    for _ in range(6):
+        q = _random_state(rng, prm)
+        d = np.array([0.05 * q[0], 0.3, 0.3, 0.02 * q[3]]) * rng.choice([-1.0, 1.0], 4)
+        th = rng.uniform(0, 2 * np.pi)
+        nx, ny = np.cos(th), np.sin(th)
+        ug, vg = 0.2 * rng.standard_normal(2)
+        c = np.sqrt(prm.gamma * prm.gas_constant * q[3])
+        lam = abs((q[1] - ug) * nx + (q[2] - vg) * ny) + c
+        rel = []
+        for s in (1.0, 0.5):
+            qL, qR = q - 0.5 * s * d, q + 0.5 * s * d
+            fn, _ = o.common_flux(qL, qR, z, z, z, z, nx, ny, 1.0, 1.0, 1.0, ug, vg)
+            avg = 0.5 * (o.point(qL, nx, ny, ug, vg)["fn"] + o.point(qR, nx, ny, ug, vg)["fn"])
+            expect = -0.5 * lam * (_cons(prm, qR) - _cons(prm, qL))
+            rel.append(np.linalg.norm((fn - avg) - expect) / np.linalg.norm(expect))
+        assert rel[0] < 5e-3, rel
+        assert 3.5 < rel[0] / rel[1] < 4.5, rel
+
+
+@pytest.mark.parametrize("mach,kappa,moving", [(0.05, 1.0, True), (0.01, 1.0, False), (0.2, 0.0, True)])
+def test_rusanov_dissipation_below_eps_one(mach, kappa, moving):
+    """Eq. (Rosanov) with eps < 1: f^com = (f_n(q+) + f_n(q-))/2 - |lambda|max Gamma~ (q+ - q-)/2,
+    Gamma~ at the averaged primitive state (pinned: Gamma = M at eps = 1 and the eigenvalues of
+    Gamma^-1 A_n against the closed form) and |lambda|max = |u_n'| + c' from the closed form of
+    Eqs. (eigenvalues_para), (eps_move) at the same state (pinned against an eigen-solve).  The
+    jumps are O(1), so the identity is exact, not asymptotic.  The acoustic |u_n| + c in place
+    of |u_n'| + c' (about 1/Ma times larger), Gamma~ at one side's state, a flipped sign or a
+    coefficient 1 each fail."""
+    o, prm = _inviscid_ctx(mach, kappa, moving)
+    rng = np.random.default_rng(12)
+    z = np.zeros(4)
+    for _ in range(6):
+        qL, qR = _random_state(rng, prm), _random_state(rng, prm)
+        th = rng.uniform(0, 2 * np.pi)
+        nx, ny = np.cos(th), np.sin(th)
+        ug, vg = (0.2 * rng.standard_normal(2)) if moving else (0.0, 0.0)
+        qb = 0.5 * (qL + qR)
+        c = np.sqrt(prm.gamma * prm.gas_constant * qb[3])
+        un = (qb[1] - ug) * nx + (qb[2] - vg) * ny
+        eps = min(1.0, max(kappa * prm.mach_inf, np.hypot(qb[1] - ug, qb[2] - vg) / c))
+        Ur = eps * c
+        alpha = 0.5 * (1.0 - Ur ** 2 / c ** 2)
+        lam = abs(un * (1 - alpha)) + np.sqrt(alpha ** 2 * un ** 2 + Ur ** 2)
+        G = o.point(qb, nx, ny, ug, vg)["Gamma"]
+        avg = 0.5 * (o.point(qL, nx, ny, ug, vg)["fn"] + o.point(qR, nx, ny, ug, vg)["fn"])
+        expect = avg - 0.5 * lam * (G @ (qR - qL))
+        fn, _ = o.common_flux(qL, qR, z, z, z, z, nx, ny, 1.0, 1.0, 1.0, ug, vg)
+        scale = np.abs(avg) + 0.5 * lam * (np.abs(G) @ np.abs(qR - qL))
+        assert np.all(np.abs(fn - expect) <= 1e-13 * scale), (fn - expect) / scale
+        # the dissipation is not negligible next to the average: a wrong term shows
+        assert np.linalg.norm(fn - avg) > 1e-3 * np.linalg.norm(avg)
