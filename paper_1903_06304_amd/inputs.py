@@ -194,6 +194,72 @@ class Mesh:
         return np.stack([x, y])
 
 
+def _local_rotation(m: int, k: int):
+    """Index map of a tensor grid of m x m points when an element's local frame turns by k
+    quarter turns: new index (a', b') -> old index (a, b), as an array over a' + m b'."""
+    ap, bp = np.meshgrid(np.arange(m), np.arange(m), indexing="xy")
+    ap, bp = ap.reshape(-1), bp.reshape(-1)
+    a, b = ap, bp
+    for _ in range(k % 4):
+        # one quarter turn: xi = -eta', eta = xi'
+        a, b = m - 1 - b, a
+    return a + m * b
+
+
+def _face_map(k: int):
+    """For each new local face F of an element turned by k quarter turns: the old face it
+    is and whether its points run in the opposite order ((old face, reversed) pairs)."""
+    m = 3
+    perm = _local_rotation(m, k)
+    out = []
+    for F in range(4):
+        new = [(0, j) if F == 0 else (m - 1, j) if F == 1 else (j, 0) if F == 2 else (j, m - 1) for j in range(m)]
+        old = [(perm[a + m * b] % m, perm[a + m * b] // m) for a, b in new]
+        for f in range(4):
+            on = [(a == 0) if f == 0 else (a == m - 1) if f == 1 else (b == 0) if f == 2 else (b == m - 1)
+                  for a, b in old]
+            if all(on):
+                along = [b if f < 2 else a for a, b in old]
+                out.append((f, along[0] > along[-1]))
+                break
+    return out
+
+
+def renumber_elements(nbr, nbr_face, flip, rot):
+    """The same mesh with element e's local frame turned by rot[e] quarter turns: the face
+    table (nbr, nbr_face, flip) of the new numbering, and a function that carries arrays
+    [k][E][m*m] of the old numbering (geometry nodes, states) to the new one.  Exercises
+    neighbour faces other than the opposite one and reversed face-point order."""
+    E = nbr.shape[0]
+    rot = np.asarray(rot, dtype=np.int64) % 4
+    maps = [_face_map(k) for k in range(4)]
+    inv = [{f: F for F, (f, _) in enumerate(mp)} for mp in maps]
+    nb2 = np.empty_like(nbr)
+    nf2 = np.empty_like(nbr_face)
+    fl2 = np.zeros_like(flip)
+    for e in range(E):
+        for F in range(4):
+            f, rev = maps[rot[e]][F]
+            m = nbr[e, f]
+            if m < 0:
+                nb2[e, F], nf2[e, F] = m, -1
+                continue
+            G = inv[rot[m]][nbr_face[e, f]]
+            nb2[e, F], nf2[e, F] = m, G
+            fl2[e, F] = int(flip[e, f]) ^ int(rev) ^ int(maps[rot[m]][G][1])
+
+    def carry(arr):
+        arr = np.asarray(arr)
+        npts = arr.shape[-1]
+        mm = int(round(math.sqrt(npts)))
+        out = np.empty_like(arr)
+        for e in range(E):
+            out[..., e, :] = arr[..., e, _local_rotation(mm, rot[e])]
+        return out
+
+    return nb2, nf2, fl2, carry
+
+
 # --------------------------------------------------------------------------
 # physical parameters
 # --------------------------------------------------------------------------
@@ -239,7 +305,7 @@ def uniform_flow(mesh: Mesh, prm: Params, u=math.sqrt(0.5), v=math.sqrt(0.5), rh
 
 def isentropic_vortex(mesh: Mesh, prm: Params, t=0.0, alpha=5.0, phi=0.5, center=(5.0, 5.0),
                       vinf=(math.sqrt(0.5), math.sqrt(0.5)), xy=None):
-    """Isentropic vortex (paper Eq. VP_Solution) in the P58 non-dimensionalisation.
+    """Isentropic vortex (paper Eq. VP_Solution) in the non-dimensionalisation of Sec. 2.1, Eq. (comp_ns).
 
     T_inf = rho_inf = 1, |v_inf| = 1, r the Euclidean distance to the (advected)
     centre; the temperature dip is written with Cp so that it holds for R = 1/(gamma Ma^2);

@@ -11,6 +11,9 @@
   -div(F) + v_g.grad(q^c), computed symbolically, on the curved static map and
   on the deforming map, at order >= p - 1/4 (catches dropped terms, wrong signs,
   transposed metrics).
+* Invariance under element renumbering: turning elements' local frames (so faces meet
+  faces other than the opposite one, with reversed point order) permutes R and J v and
+  changes nothing else.
 """
 import numpy as np
 import pytest
@@ -193,3 +196,85 @@ def test_consistency_euler_vortex(p):
     e = _errors(prm_fn, mesh_fn, fields, 0.0, [16, 32, 64], window=(2.0, 8.0, 2.0, 8.0))
     rate = np.log2(e[:-1] / e[1:])
     assert np.all(rate[-1] >= p - 0.25), (e, rate)
+
+
+def _renumbered_cases():
+    out = []
+    mesh = I.Mesh(5, 4, 3, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+    prm = I.Params(order=3, n_elem=mesh.E, mach_ref=0.2, reynolds=50.0, viscous=True, kappa=1.0)
+    out.append(("curved_p3", prm, mesh, 0.0, None))
+    mesh = I.Mesh(4, 5, 2, (0.0, 2.0, 0.0, 2.0), I.map_deforming(0.05), moving=True)
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, moving=True, kappa=1.0)
+    out.append(("deforming_p2", prm, mesh, 0.13, None))
+    mesh = I.Mesh(4, 4, 2, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_affine)
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.1, viscous=False, kappa=1.0)
+    out.append(("affine_euler_p2", prm, mesh, 0.0, None))
+    mesh = I.Mesh(4, 3, 2, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1),
+                  bc=(I.BC_FARFIELD, I.BC_FARFIELD, I.BC_NOSLIP_WALL, I.BC_SLIP_WALL))
+    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=0.1, reynolds=50.0, viscous=True, kappa=1.0)
+    out.append(("boundary_p2", prm, mesh, 0.0, [prm.gas_constant, 0.9, 0.1, 1.0]))
+    return out
+
+
+def _random_state(prm, mesh, seed):
+    rng = np.random.default_rng(seed)
+    q = I.uniform_flow(mesh, prm)
+    q[0] *= 1 + 0.05 * rng.standard_normal(q[0].shape)
+    q[1] += 0.3 * rng.standard_normal(q[1].shape)
+    q[2] += 0.3 * rng.standard_normal(q[2].shape)
+    q[3] *= 1 + 0.03 * rng.standard_normal(q[3].shape)
+    return q
+
+
+@pytest.mark.parametrize("case", _renumbered_cases(), ids=lambda c: c[0])
+def test_renumbered_elements_permute_residual_and_jvp(case):
+    """Turning the local frames of the elements by seeded quarter turns (each face then meets
+    an arbitrary face of its neighbour, with reversed point order on half of them) is a
+    relabelling of the same discretisation: R and J v come out permuted the same way, to
+    rounding.  Pins the oracle's use of the neighbour-face and reversal entries."""
+    name, prm, mesh, t, qinf = case
+    nbr, nbf, flip = mesh.connectivity()
+    rot = np.random.default_rng(7).integers(0, 4, mesh.E)
+    rot[0] = 1
+    rot[1] = 2
+    nb2, nf2, fl2, carry = I.renumber_elements(nbr, nbf, flip, rot)
+    assert np.any(fl2 != 0) and np.any(nf2[nb2 >= 0] != np.array([1, 0, 3, 2])[np.nonzero(nb2 >= 0)[1]])
+    xg, vg = mesh.nodes(t)
+    q = _random_state(prm, mesh, 3)
+    v = np.random.default_rng(4).standard_normal(q.shape)
+    o1 = Oracle(prm, mesh, xg, vg)
+
+    class Renumbered:
+        def __init__(self, m):
+            self.m = m
+            self.E = m.E
+
+        def connectivity(self):
+            return nb2, nf2, fl2
+
+    o2 = Oracle(prm, Renumbered(mesh), carry(xg), None if vg is None else carry(vg))
+    if qinf is not None:
+        o1.set_farfield(qinf)
+        o2.set_farfield(qinf)
+    R1, R2 = o1.residual(q), o2.residual(carry(q))
+    scale = np.max(np.abs(R1), axis=(1, 2))
+    d = np.max(np.abs(R2 - carry(R1)), axis=(1, 2)) / scale
+    print(name, "R", d)
+    assert np.all(d <= 1e-12), (name, d)
+    J1, J2 = o1.jvp(q, v), o2.jvp(carry(q), carry(v))
+    jscale = np.max(np.abs(J1), axis=(1, 2))
+    dj = np.max(np.abs(J2 - carry(J1)), axis=(1, 2)) / jscale
+    print(name, "Jv", dj)
+    assert np.all(dj <= 1e-12), (name, dj)
+    # a wrong reversal entry breaks the invariance
+    bad = fl2.copy()
+    e, F = np.argwhere(fl2 != 0)[0]
+    bad[e, F] = 0
+    m, G = nb2[e, F], nf2[e, F]
+    bad[m, G] = 0
+    o3 = Oracle(prm, type("M", (), {"E": mesh.E, "connectivity": lambda self: (nb2, nf2, bad)})(),
+                carry(xg), None if vg is None else carry(vg))
+    if qinf is not None:
+        o3.set_farfield(qinf)
+    R3 = o3.residual(carry(q))
+    assert np.max(np.abs(R3 - carry(R1)) / scale[:, None, None]) > 1e-6
