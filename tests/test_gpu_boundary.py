@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 from oracle.oracle import Oracle  # noqa: E402
 from paper_1903_06304_amd import inputs as I  # noqa: E402
 
-from helpers import flux_scale, normwise_rel, row_errors  # noqa: E402
+from helpers import flux_scale, residual_parity, normwise_rel, row_errors  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -97,10 +97,8 @@ def test_residual_parity(case):
     assert g.affine_elements() <= int(np.sum(np.all(nbr >= 0, axis=1)))
     R = g.residual(_dev(q)).cpu().numpy()
     Ro = o.residual(q)
-    S = flux_scale(o.geometry(), prm, q)
-    err = row_errors(R, Ro)
-    print("  err/S", err / S, flush=True)
-    assert np.all(err <= 1e-12 * S), err / S
+    err_s = residual_parity(o.geometry(), prm, q, R, Ro)
+    assert np.all(err_s <= 1e-12), err_s
 
 
 def test_channel_interior_row_is_affine():
@@ -248,93 +246,12 @@ def test_cylinder_full_size_parity():
     g.autotune(None)
     R = g.residual(_dev(q)).cpu().numpy()
     Ro = o.residual(q)
-    S = flux_scale(o.geometry(), prm, q)
-    err = row_errors(R, Ro)
-    print("  err/S", err / S, flush=True)
-    assert np.all(err <= 1e-12 * S), err / S
+    err_s = residual_parity(o.geometry(), prm, q, R, Ro)
+    assert np.all(err_s <= 1e-12), err_s
     v = np.random.default_rng(8).standard_normal(q.shape)
     errj = normwise_rel(g.jvp(_dev(q), _dev(v)).cpu().numpy(), o.jvp(q, v))
     print("  jvp", errj, flush=True)
     assert np.all(errj <= 1e-12), errj
-
-
-def _wall_forces_and_entropy(o, mesh, prm, q):
-    """C_d, C_l from the pressure on the wall faces (eta = -1 sides of the first row of the
-    O-grid; inviscid: pressure only), and the entropy error E_s over the domain (the paper's
-    definitions in Sec. 4, with rho_inf = U_inf = D = 1)."""
-    g = o.geometry()
-    n = mesh.n
-    x, w = np.polynomial.legendre.leggauss(n)
-    V = np.polynomial.legendre.legvander(x, n - 1)
-    lam_m = np.polynomial.legendre.legvander(np.array([-1.0]), n - 1)[0] @ np.linalg.inv(V)
-    F = np.zeros(2)
-    for e in range(mesh.nx):
-        pw = lam_m @ q[0, e].reshape(n, n)          # p at the eta = -1 face points
-        # |J| grad(eta) points into the fluid: the force on the body is -int p n_body dS
-        F -= np.array([np.sum(w * pw * g["Sx"][e, 2]), np.sum(w * pw * g["Sy"][e, 2])])
-    rho = q[0] / (prm.gas_constant * q[3])
-    s = q[0] / rho ** prm.gamma
-    s_inf = prm.gas_constant
-    W = np.outer(w, w).reshape(-1)[None, :] * g["jac"]
-    return F[0] / 0.5, F[1] / 0.5, np.sqrt(np.sum(W * (s - s_inf) ** 2) / np.sum(W * s_inf ** 2))
-
-
-def test_inviscid_cylinder_steady():
-    """The paper's inviscid cylinder setting (Sec. 4, Ma_inf = 1e-3, kappa = 1, slip wall, far
-    field beyond 100 diameters, 20 x 24 elements, 3rd order, P4 geometry, SER from dtau = 0.01,
-    GMRES(150), tol_res 1e-6) on a synthetic O-grid: the steady solve converges to 1e-9, the
-    flow stays symmetric (C_l ~ 0), and drag and entropy error are the discretisation's (the
-    exact inviscid values are 0)."""
-    from paper_1903_06304_amd import lmfr
-    mesh = I.Mesh(24, 20, 2, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 100.0), pg=4, bc=(0, 0, SLIP, FAR))
-    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=1e-3, viscous=False, kappa=1.0, geom_order=4)
-    qinf = [prm.gas_constant, 1.0, 0.0, 1.0]
-    g = lmfr.Context(prm, *mesh.connectivity())
-    g.set_geometry(*mesh.nodes(0.0))
-    g.set_farfield(qinf)
-    g.set_option("preconditioner", 1)
-    q = _dev(I.uniform_flow(mesh, prm, u=1.0, v=0.0))
-    st = g.steady_solve(q, dtau0=0.01, dtau_min=0.01, dtau_max=1e20, tol_pseudo=1e-9, tol_res=1e-6, krylov=150,
-                        max_lin_it=1500, max_steps=40)
-    torch.cuda.synchronize()
-    o = Oracle(prm, mesh)
-    o.set_farfield(qinf)
-    cd, cl, es = _wall_forces_and_entropy(o, mesh, prm, q.cpu().numpy())
-    print(f"[boundary] inviscid cylinder {st} Cd={cd:.3e} Cl={cl:.3e} Es={es:.3e}", flush=True)
-    assert st["converged"] == 1 and st["steps"] <= 30
-    assert abs(cd) < 5e-3 and abs(cl) < 1e-5 and es < 1e-10
-
-
-def test_inviscid_cylinder_step_rejection():
-    """The 3rd-order inviscid cylinder on 48 x 40 elements: with the paper's SER the
-    pseudo-transient iteration diverges; with step rejection (not in the paper) it converges.
-    The path is sensitive to rounding (with growth 10 it converged in 38 steps on one build
-    and stalled at 1e-3 on another whose reductions round differently); growth 2 converges
-    in 91 steps, so the bar allows 150.  Both solves run on one context, so the second also
-    checks that nothing non-finite left by the diverged first solve reaches the second."""
-    from paper_1903_06304_amd import lmfr
-    mesh = I.Mesh(48, 40, 2, (0.0, 1.0, 0.0, 1.0), I.map_annulus(0.5, 100.0), pg=4, bc=(0, 0, SLIP, FAR))
-    prm = I.Params(order=2, n_elem=mesh.E, mach_ref=1e-3, viscous=False, kappa=1.0, geom_order=4)
-    qinf = [prm.gas_constant, 1.0, 0.0, 1.0]
-    g = lmfr.Context(prm, *mesh.connectivity())
-    g.set_geometry(*mesh.nodes(0.0))
-    g.set_farfield(qinf)
-    g.set_option("preconditioner", 1)
-    kw = dict(dtau0=0.01, dtau_min=0.01, dtau_max=1e20, tol_pseudo=1e-9, tol_res=1e-6, krylov=150, max_lin_it=1500,
-              max_steps=60, check=False)
-    q0 = I.uniform_flow(mesh, prm, u=1.0, v=0.0)
-    q = _dev(q0)
-    plain = g.steady_solve(q, **kw)
-    q = _dev(q0)
-    guarded = g.steady_solve(q, reject_growth=2.0, **dict(kw, max_steps=150))
-    torch.cuda.synchronize()
-    print(f"[boundary] cylinder 48x40 p2: SER {plain}; with step rejection {guarded}", flush=True)
-    assert plain["converged"] == 0
-    assert guarded["converged"] == 1 and guarded["rejected"] >= 1
-    o = Oracle(prm, mesh)
-    o.set_farfield(qinf)
-    cd, cl, es = _wall_forces_and_entropy(o, mesh, prm, q.cpu().numpy())
-    assert abs(cd) < 1e-3 and abs(cl) < 1e-3 and es < 1e-10, (cd, cl, es)
 
 
 # ---- the oracle's boundary pins, evaluated with the GPU library (independent of the oracle)
