@@ -20,11 +20,14 @@
  *    asynchronous on it unless stated otherwise.
  *  - No exceptions cross the ABI: every call returns an fr_status; the text of
  *    the last failure on the calling thread is returned by fr_last_error().
- *  - Memory: a context allocates its tables and workspaces in fr_create, the
- *    element blocks in its first fr_block_jacobi_factor (or step), and the Krylov
- *    workspace in its first fr_bdf2_step with a given Krylov dimension; a batch does
- *    the same in fr_batch_create and its first step.  Residual, JVP, VJP, apply and
- *    repeated step calls allocate nothing.
+ *  - Memory: a context allocates its tables and the residual / JVP / VJP workspaces in
+ *    fr_create.  fr_reserve (fr_batch_reserve for a batch) allocates everything the
+ *    factor, apply, step and steady-solve paths use, for Krylov dimensions up to a stated
+ *    maximum and an inverse stored at up to a stated precision; after it those calls
+ *    allocate no device memory (a step that captures its GMRES cycle still builds the
+ *    graph on its first call, in the runtime's own memory).  Without fr_reserve the first
+ *    factor allocates the blocks and the inverse at its precision, and the first step with
+ *    a larger Krylov dimension its workspace; residual, JVP, VJP and apply never allocate.
  */
 #ifndef LMFR_H
 #define LMFR_H
@@ -175,10 +178,12 @@ fr_status fr_vjp(fr_ctx ctx, const double* q, const double* w, double* JTw, void
 fr_status fr_bdf_operator(fr_ctx ctx, const double* q, const double* v, double c_time,
                           double inv_dtau, double* Av, void* stream);
 
-/* Element-block-Jacobi preconditioner: P_e = inv_dtau Gamma_e + c_time M_e - dR_e/dq_e,
+/* Element-block-Jacobi preconditioner (paper Sec. 4, parallel set-up: block Jacobi over
+ * the element blocks): P_e = inv_dtau Gamma_e + c_time M_e - dR_e/dq_e,
  * the true diagonal block of the Newton operator (own-state dependence through the
- * faces included), assembled on the device, factored (partial pivoting) and stored
- * as an explicit inverse in precision `prec` (FP32/BF16 with FP32 accumulation).
+ * faces included), assembled on the device in FP64, inverted by Gauss-Jordan elimination
+ * with partial pivoting and stored as an explicit inverse in precision `prec`.  The apply
+ * reads the stored inverse and accumulates in FP64.
  * c_time = 3/(2 dt) for BDF2, 1/dt for BDF1.  Kept in the context for the apply. */
 fr_status fr_block_jacobi_factor(fr_ctx ctx, const double* q, double c_time, double inv_dtau,
                                  int32_t prec, void* stream);
@@ -188,6 +193,18 @@ fr_status fr_block_jacobi_factor(fr_ctx ctx, const double* q, double c_time, dou
  * operator the last fr_block_jacobi_factor linearised (its q, c_time and inv_dtau; a later
  * fr_bdf_operator with "operator_packs" replaces that linearisation). */
 fr_status fr_block_jacobi_apply(fr_ctx ctx, const double* r, double* z, void* stream);
+
+/* Copy the stored inverse of the last fr_block_jacobi_factor, widened exactly to FP64, to
+ * the DEVICE array inv [E][4Np][4Np], row-major (row = v*Np + s), so that z_e = inv_e r_e
+ * is what fr_block_jacobi_apply computes with block Jacobi.  FR_EINVAL before a factor. */
+fr_status fr_get_inverse(fr_ctx ctx, double* inv, void* stream);
+
+/* Allocate now every device workspace of fr_block_jacobi_factor, fr_block_jacobi_apply,
+ * fr_bdf_operator, fr_bdf2_step and fr_steady_solve for Krylov dimensions up to krylov_max
+ * (1..156) and an inverse stored at up to the width of `prec` (FR_FP64 covers every
+ * precision): those calls then allocate no device memory, which keeps them usable where
+ * allocation is not allowed.  FR_EINVAL for arguments out of range, FR_ENOMEM. */
+fr_status fr_reserve(fr_ctx ctx, int32_t krylov_max, int32_t prec);
 
 /* Copy the assembled (unfactored) FP64 blocks of the last fr_block_jacobi_factor to
  * the DEVICE array blk [E][4Np][4Np], row-major (row = v*Np + s).  Only available
@@ -282,6 +299,9 @@ fr_status fr_batch_bdf2_step(fr_batch batch, double* const* q, const double* con
  * keeps its own SER step and convergence.  h_stats: HOST [n] or NULL. */
 fr_status fr_batch_steady_solve(fr_batch batch, double* const* q, const fr_steady_opts* opts,
                                 fr_steady_stats* h_stats, void* stream);
+
+/* fr_reserve for a batch: every workspace of its step and steady-solve paths. */
+fr_status fr_batch_reserve(fr_batch batch, int32_t krylov_max, int32_t prec);
 
 /* Options: "graph", "gram_schmidt", "preconditioner" and the "tile_*" launch-shape
  * options, as for a context. */

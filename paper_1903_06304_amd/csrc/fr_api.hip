@@ -405,7 +405,7 @@ extern "C" fr_status fr_block_jacobi_factor(fr_ctx c, const double* q, double c_
     if (prec < FR_FP64 || prec > FR_BF16) return bad("fr_block_jacobi_factor: unknown precision");
     Solver& sv = *c->self;
     hipStream_t s = (hipStream_t)stream;
-    FR_TRY(solver_ensure_blocks(sv));
+    FR_TRY(solver_ensure_blocks(sv, prec));
     KArgs a{};
     a.c_time = c_time; a.inv_dtau = inv_dtau;
     sv.f_ct = c_time; sv.f_idt = inv_dtau;
@@ -478,6 +478,56 @@ extern "C" fr_status fr_get_blocks(fr_ctx c, double* blk, void* stream) {
                        (size_t)c->E, nb, sv.d_blk_keep, blk);
     FR_HIP(hipGetLastError());
     return FR_OK;
+}
+
+// stored inverse (precision of the last factor, column-major per element) -> caller's FP64
+// array, row-major per element, widened exactly
+namespace {
+template <class Tin> __device__ __forceinline__ double widen(Tin x);
+template <> __device__ __forceinline__ double widen<double>(double x) { return x; }
+template <> __device__ __forceinline__ double widen<float>(float x) { return (double)x; }
+template <> __device__ __forceinline__ double widen<uint16_t>(uint16_t x) {
+    return (double)__uint_as_float((uint32_t)x << 16);
+}
+template <class Tin>
+__global__ void k_widen_inverse(size_t E, int nb, const Tin* __restrict__ src, double* __restrict__ dst) {
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t nn = (size_t)nb * nb;
+    if (t >= E * nn) return;
+    const size_t e = t / nn, rc = t % nn, col = rc / nb, row = rc % nb;
+    dst[e * nn + row * nb + col] = widen<Tin>(src[t]);
+}
+}  // namespace
+
+extern "C" fr_status fr_get_inverse(fr_ctx c, double* inv, void* stream) {
+    FR_TRY(ready(c));
+    if (!inv) return bad("fr_get_inverse: null argument");
+    const Solver& sv = *c->self;
+    if (sv.inv_prec < 0 || !sv.d_inv) return bad("fr_get_inverse: no factored blocks");
+    const int nb = 4 * c->Np;
+    const size_t tot = (size_t)c->E * nb * nb;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    hipStream_t s = (hipStream_t)stream;
+    switch (sv.inv_prec) {
+        case FR_FP64:
+            hipLaunchKernelGGL(k_widen_inverse<double>, grid, dim3(256), 0, s, (size_t)c->E, nb,
+                               (const double*)sv.d_inv, inv);
+            break;
+        case FR_FP32:
+            hipLaunchKernelGGL(k_widen_inverse<float>, grid, dim3(256), 0, s, (size_t)c->E, nb,
+                               (const float*)sv.d_inv, inv);
+            break;
+        default:
+            hipLaunchKernelGGL(k_widen_inverse<uint16_t>, grid, dim3(256), 0, s, (size_t)c->E, nb,
+                               (const uint16_t*)sv.d_inv, inv);
+    }
+    FR_HIP(hipGetLastError());
+    return FR_OK;
+}
+
+extern "C" fr_status fr_reserve(fr_ctx c, int32_t krylov_max, int32_t prec) {
+    if (!c) return bad("fr_reserve: null context");
+    return solver_reserve(*c->self, krylov_max, prec);
 }
 
 extern "C" fr_status fr_bdf2_step(fr_ctx c, double* q_io, const double* q_nm1, const fr_step_opts* o,
@@ -567,6 +617,11 @@ extern "C" fr_status fr_batch_steady_solve(fr_batch b, double* const* q, const f
     FR_TRY(batch_ready(b));
     if (!q || !opts) return bad("fr_batch_steady_solve: null argument");
     return solver_steady(b->sv, q, opts, h_stats, (hipStream_t)stream);
+}
+
+extern "C" fr_status fr_batch_reserve(fr_batch b, int32_t krylov_max, int32_t prec) {
+    if (!b) return bad("fr_batch_reserve: null batch");
+    return solver_reserve(b->sv, krylov_max, prec);
 }
 
 extern "C" fr_status fr_batch_set_option(fr_batch b, const char* name, int64_t value) {

@@ -213,6 +213,7 @@ struct Solver {
     // preconditioner
     double* d_blk = nullptr;               // FP64 assembly buffer (column-major blocks)
     void* d_inv = nullptr;                 // inverse blocks in the stored precision
+    size_t inv_bytes = 0;                  // capacity of d_inv
     int inv_prec = -1;
     bool keep_blocks = false;
     double* d_blk_keep = nullptr;
@@ -308,8 +309,10 @@ std::vector<int> fused_tile_widths(int p);
 // solver set-up (fr_solver.hip)
 fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n);
 void solver_free(Solver& sv);
-fr_status solver_ensure_blocks(Solver& sv);
-fr_status solver_ensure_step(Solver& sv, int m);
+fr_status solver_ensure_blocks(Solver& sv, int prec);
+fr_status solver_ensure_step(Solver& sv, int m, int prec);
+fr_status solver_reserve(Solver& sv, int m, int prec);
+size_t prec_bytes(int prec);
 
 // preconditioner (fr_linalg.hip)
 fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s);

@@ -148,15 +148,42 @@ void solver_free(Solver& sv) {
     sv = Solver();
 }
 
-fr_status solver_ensure_blocks(Solver& sv) {
+size_t prec_bytes(int prec) { return prec == FR_FP64 ? 8 : prec == FR_FP32 ? 4 : 2; }
+
+fr_status solver_ensure_blocks(Solver& sv, int prec) {
     FR_TRY(dalloc(&sv.d_blk, sv.Btot));
-    if (!sv.d_inv) FR_TRY(dalloc((double**)&sv.d_inv, sv.Btot));   // sized for FP64, reused by any precision
+    // the inverse in the stored precision; a wider precision than the buffer was sized for
+    // replaces it (the inverse of the previous factor is then gone: inv_prec is reset)
+    const size_t need = sv.Btot * prec_bytes(prec);
+    if (sv.inv_bytes < need) {
+        gmres_release(sv);   // a captured cycle holds the old buffer's address
+        dfree(sv.d_inv);
+        sv.d_inv = nullptr;
+        sv.inv_bytes = 0;
+        sv.inv_prec = -1;
+        char* p = nullptr;
+        FR_TRY(dalloc(&p, need));
+        sv.d_inv = p;
+        sv.inv_bytes = need;
+    }
     if (sv.keep_blocks) FR_TRY(dalloc(&sv.d_blk_keep, sv.Btot));
     return FR_OK;
 }
 
-fr_status solver_ensure_step(Solver& sv, int m) {
-    FR_TRY(solver_ensure_blocks(sv));
+fr_status solver_reserve(Solver& sv, int m, int prec) {
+    if (m < 1 || m > MAXV - 4 || prec < FR_FP64 || prec > FR_BF16) {
+        fr_set_error("reserve: krylov must be in 1..156 and prec an fr_prec");
+        return FR_EINVAL;
+    }
+    FR_TRY(solver_ensure_step(sv, m, prec));
+    FR_TRY(dalloc(&sv.d_gsu, sv.Ntot));   // Gauss-Seidel sweeps
+    FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
+    FR_TRY(dalloc(&sv.d_rscratch, sv.Ntot));   // R of the two-pass Newton operator
+    return FR_OK;
+}
+
+fr_status solver_ensure_step(Solver& sv, int m, int prec) {
+    FR_TRY(solver_ensure_blocks(sv, prec));
     if (sv.kry_m < m || !sv.d_V) {
         gmres_release(sv);
         dfree(sv.d_V); sv.d_V = nullptr;
@@ -265,7 +292,7 @@ fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, 
             return FR_EINVAL;
         }
     }
-    FR_TRY(solver_ensure_step(sv, o[0].krylov));
+    FR_TRY(solver_ensure_step(sv, o[0].krylov, o[0].prec));
     // per-case step scalars through the pinned staging area (the previous step has synchronised)
     CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
     for (int c = 0; c < n; ++c) {
@@ -320,7 +347,7 @@ fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, f
             return FR_EINVAL;
         }
     }
-    FR_TRY(solver_ensure_step(sv, o[0].krylov));
+    FR_TRY(solver_ensure_step(sv, o[0].krylov, o[0].prec));
     CaseStep* hst = reinterpret_cast<CaseStep*>(sv.h_pin + (size_t)n * SUM_STRIDE);
     sv.reject_on = false;
     for (int c = 0; c < n; ++c) {

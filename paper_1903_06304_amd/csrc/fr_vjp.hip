@@ -580,44 +580,47 @@ k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, 
 }
 
 template <int P, bool VISC, bool MOV>
-fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
+fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, const double* trace, double* aside,
+                  hipStream_t s) {
     const Geo g = c->geo();
     const int grid = (c->E + Sz<P>::EPB - 1) / Sz<P>::EPB;
     if (g.bc)
         hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV, true>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w,
-                           c->d_trace, out, c->d_vj, c->op, c->pc, g);
+                           trace, out, aside, c->op, c->pc, g);
     else
         hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV, false>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w,
-                           c->d_trace, out, c->d_vj, c->op, c->pc, g);
+                           trace, out, aside, c->op, c->pc, g);
     FR_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_vjp_gather<P, VISC>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, c->d_vj, out, c->op, g);
+    hipLaunchKernelGGL((k_vjp_gather<P, VISC>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, aside, out, c->op, g);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
 
 template <int P>
-fr_status vjp_p(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
+fr_status vjp_p(fr_ctx c, const double* q, const double* w, double* out, const double* tr, double* as,
+                hipStream_t s) {
     const bool visc = c->prm.viscous != 0, mov = c->prm.moving != 0;
-    if (visc) return mov ? run_vjp<P, true, true>(c, q, w, out, s) : run_vjp<P, true, false>(c, q, w, out, s);
-    return mov ? run_vjp<P, false, true>(c, q, w, out, s) : run_vjp<P, false, false>(c, q, w, out, s);
+    if (visc) return mov ? run_vjp<P, true, true>(c, q, w, out, tr, as, s) : run_vjp<P, true, false>(c, q, w, out, tr, as, s);
+    return mov ? run_vjp<P, false, true>(c, q, w, out, tr, as, s) : run_vjp<P, false, false>(c, q, w, out, tr, as, s);
+}
+
+// Traces, element adjoints and the neighbour gather with the given side buffers: trace
+// and aside each hold E * 4 * 10 * (p+1) doubles.
+fr_status vjp_with(fr_ctx c, const double* q, const double* w, double* out, double* trace, double* aside,
+                   hipStream_t s) {
+    FR_TRY(launch_traces(c, q, trace, s));
+    switch (c->p) {
+        case 1: return vjp_p<1>(c, q, w, out, trace, aside, s);
+        case 2: return vjp_p<2>(c, q, w, out, trace, aside, s);
+        case 3: return vjp_p<3>(c, q, w, out, trace, aside, s);
+        case 4: return vjp_p<4>(c, q, w, out, trace, aside, s);
+    }
+    fr_set_error("order outside 1..4");
+    return FR_EUNSUPPORTED;
 }
 
 }  // namespace
 
 fr_status launch_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
-    fr_status st = launch_traces(c, q, c->d_trace, s);
-    if (st != FR_OK) return st;
-    if (!c->d_vj) {
-        const size_t sz = (size_t)c->E * 4 * 10 * c->n * sizeof(double);
-        hipError_t e = hipMalloc((void**)&c->d_vj, sz);
-        if (e != hipSuccess) { c->d_vj = nullptr; fr_set_error("hipMalloc of the VJP side buffer failed"); return FR_ENOMEM; }
-    }
-    switch (c->p) {
-        case 1: return vjp_p<1>(c, q, w, out, s);
-        case 2: return vjp_p<2>(c, q, w, out, s);
-        case 3: return vjp_p<3>(c, q, w, out, s);
-        case 4: return vjp_p<4>(c, q, w, out, s);
-    }
-    fr_set_error("order outside 1..4");
-    return FR_EUNSUPPORTED;
+    return vjp_with(c, q, w, out, c->d_trace, c->d_vj, s);
 }

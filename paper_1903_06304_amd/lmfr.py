@@ -28,7 +28,8 @@ EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "f
            "fr_affine_elements", "fr_steady_solve", "fr_batch_steady_solve", "fr_set_farfield",
            "fr_set_option", "fr_autotune", "fr_batch_create", "fr_batch_destroy", "fr_batch_layout",
            "fr_batch_residual", "fr_batch_jvp", "fr_batch_bdf2_step", "fr_batch_set_option",
-           "fr_batch_autotune", "fr_last_error", "fr_destroy"]
+           "fr_batch_autotune", "fr_last_error", "fr_destroy", "fr_get_inverse", "fr_reserve",
+           "fr_batch_reserve"]
 
 
 class FRError(RuntimeError):
@@ -89,6 +90,9 @@ def load_library(path: str = LIB_PATH):
     L.fr_block_jacobi_factor.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
     L.fr_block_jacobi_apply.argtypes = [vp, dp, dp, vp]
     L.fr_get_blocks.argtypes = [vp, dp, vp]
+    L.fr_get_inverse.argtypes = [vp, dp, vp]
+    L.fr_reserve.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.fr_batch_reserve.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.fr_affine_elements.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     L.fr_set_farfield.argtypes = [vp, dp]
     L.fr_steady_solve.argtypes = [vp, dp, ctypes.POINTER(fr_steady_opts), ctypes.POINTER(fr_steady_stats), vp]
@@ -235,6 +239,17 @@ class Context:
         _check(load_library().fr_get_blocks(self.h, _ptr(out), _stream()))
         return out
 
+    def get_inverse(self):
+        """The stored inverse blocks of the last factor, widened to FP64, [E][4Np][4Np] row-major."""
+        nb = 4 * self.Np
+        out = torch.empty((self.E, nb, nb), dtype=torch.float64, device=self.device)
+        _check(load_library().fr_get_inverse(self.h, _ptr(out), _stream()))
+        return out
+
+    def reserve(self, krylov_max, prec="fp64"):
+        """Allocate every workspace of the factor, apply and step paths now (fr_reserve)."""
+        _check(load_library().fr_reserve(self.h, int(krylov_max), PREC[prec] if isinstance(prec, str) else int(prec)))
+
     def autotune(self, cache_path=None):
         _check(load_library().fr_autotune(self.h, None if cache_path is None else str(cache_path).encode(),
                                           _stream()))
@@ -333,6 +348,10 @@ class Batch:
     def set_option(self, name: str, value: int):
         _check(load_library().fr_batch_set_option(self.h, name.encode(), int(value)))
 
+    def reserve(self, krylov_max, prec="fp64"):
+        _check(load_library().fr_batch_reserve(self.h, int(krylov_max),
+                                               PREC[prec] if isinstance(prec, str) else int(prec)))
+
     def autotune(self, cache_path=None):
         _check(load_library().fr_batch_autotune(self.h, None if cache_path is None else str(cache_path).encode(),
                                                 _stream()))
@@ -375,6 +394,15 @@ class Batch:
         return rc, [_steady_dict(s) for s in sarr]
 
 
+def _plain(t):
+    """The tensor under torch.func's wrappers (torch.func.jvp hands the jvp rule wrapped
+    tensors, which have no storage for the kernels to read)."""
+    from torch._C._functorch import get_unwrapped, is_functorch_wrapped_tensor
+    while is_functorch_wrapped_tensor(t):
+        t = get_unwrapped(t)
+    return t
+
+
 class FRResidual(torch.autograd.Function):
     """R(q) with exact derivatives: forward = fr_residual, backward = fr_vjp, jvp = fr_jvp."""
 
@@ -386,8 +414,8 @@ class FRResidual(torch.autograd.Function):
     def setup_context(ctx, inputs, output):
         q, ctx_fr = inputs
         ctx.save_for_backward(q)
+        ctx.save_for_forward(q)
         ctx.fr = ctx_fr
-        ctx.q_fwd = q
 
     @staticmethod
     def backward(ctx, w):
@@ -396,7 +424,8 @@ class FRResidual(torch.autograd.Function):
 
     @staticmethod
     def jvp(ctx, v, _):
-        return ctx.fr.jvp(ctx.q_fwd, v.contiguous())
+        (q,) = ctx.saved_tensors
+        return ctx.fr.jvp(_plain(q), _plain(v).contiguous())
 
 
 def residual(q, ctx_fr):
