@@ -425,7 +425,8 @@ class FRResidual(torch.autograd.Function):
     @staticmethod
     def jvp(ctx, v, _):
         (q,) = ctx.saved_tensors
-        return ctx.fr.jvp(_plain(q), _plain(v).contiguous())
+        with torch._C._DisableFuncTorch():   # the binding's own tensor ops stay unwrapped
+            return ctx.fr.jvp(_plain(q), _plain(v).contiguous())
 
 
 def residual(q, ctx_fr):
