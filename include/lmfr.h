@@ -173,6 +173,15 @@ fr_status fr_jvp(fr_ctx ctx, const double* q, const double* v, double* Jv, doubl
  * gather-formulated and deterministic.  All arrays [4][E][Np]. */
 fr_status fr_vjp(fr_ctx ctx, const double* q, const double* w, double* JTw, void* stream);
 
+/* fr_vjp for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): the same kernels and results, bit for
+ * bit, with the two side buffers of the adjoint (face traces and face adjoints,
+ * E * 4 * 10 * (order+1) doubles each) in a 32 MiB array that the library holds on each
+ * device for the life of the process, instead of context memory.  Meshes above that
+ * (E * (order+1) > 52428) get FR_EINVAL.  Calls that overlap on one device share the
+ * array and race; the current device must be the context's.  Allocates nothing. */
+fr_status fr_vjp_noalloc(fr_ctx ctx, const double* q, const double* w, double* JTw, void* stream);
+
 /* Operator of the BDF2 Newton system, paper Eq. (unsteady_pre_discretized_3):
  * Av = inv_dtau Gamma v + c_time M v - (dR/dq) v, pointwise Gamma and M at q. */
 fr_status fr_bdf_operator(fr_ctx ctx, const double* q, const double* v, double c_time,

@@ -15,6 +15,8 @@
 // eps_min < Ma < 1, d|x|/dx = +1 at x = 0.
 #include "fr_internal.hpp"
 
+#include <mutex>
+
 namespace {
 
 template <int P>
@@ -623,4 +625,59 @@ fr_status vjp_with(fr_ctx c, const double* q, const double* w, double* out, doub
 
 fr_status launch_vjp(fr_ctx c, const double* q, const double* w, double* out, hipStream_t s) {
     return vjp_with(c, q, w, out, c->d_trace, c->d_vj, s);
+}
+
+// ----------------------------------------------------------------------------- allocation-free VJP
+// The same three kernels with their two side buffers (face traces, face adjoints) in a
+// file-scope device array instead of context memory, for callers that cannot allocate.
+// Each device holds its own copy of the array until the process ends.  Host code never
+// uses the array's name as an address: its device address is looked up once per device
+// and kept in scratch_dev.  Calls that overlap on one device share the array and race.
+static constexpr size_t VJP_SCRATCH_BYTES = size_t(32) << 20;
+static __device__ __align__(256) double scratch[VJP_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mtx;
+double* scratch_dev[MAX_DEVICES] = {};
+
+fr_status scratch_address(int dev, double** out) {
+    std::lock_guard<std::mutex> lock(scratch_mtx);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fr_set_error(std::string("fr_vjp_noalloc: hipGetSymbolAddress of the scratch array: ") +
+                         hipGetErrorString(e));
+            return FR_EHIP;
+        }
+        scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_dev[dev];
+    return FR_OK;
+}
+
+}  // namespace
+
+extern "C" fr_status fr_vjp_noalloc(fr_ctx c, const double* q, const double* w, double* JTw, void* stream) {
+    if (!c) { fr_set_error("fr_vjp_noalloc: null context"); return FR_EINVAL; }
+    if (const char* m = ctx_not_ready(c)) { fr_set_error(m); return FR_EINVAL; }
+    if (!q || !w || !JTw) { fr_set_error("fr_vjp_noalloc: null argument"); return FR_EINVAL; }
+    const size_t side = (size_t)c->E * 4 * 10 * c->n;   // doubles per side buffer
+    if (2 * side * sizeof(double) > VJP_SCRATCH_BYTES) {
+        fr_set_error("fr_vjp_noalloc: the mesh needs " + std::to_string(2 * side * sizeof(double)) +
+                     " bytes of scratch, above the maximum of " + std::to_string(VJP_SCRATCH_BYTES) +
+                     " (E * 4 * 10 * (p+1) * 16 bytes); use fr_vjp");
+        return FR_EINVAL;
+    }
+    int dev = -1;
+    FR_HIP(hipGetDevice(&dev));
+    if (dev != c->device || dev < 0 || dev >= MAX_DEVICES) {
+        fr_set_error("fr_vjp_noalloc: the current device is not the context's");
+        return FR_EINVAL;
+    }
+    double* base = nullptr;
+    FR_TRY(scratch_address(dev, &base));
+    return vjp_with(c, q, w, JTw, base, base + side, (hipStream_t)stream);
 }

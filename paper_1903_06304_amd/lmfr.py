@@ -29,7 +29,7 @@ EXPORTS = ["fr_create", "fr_set_geometry", "fr_residual", "fr_jvp", "fr_vjp", "f
            "fr_set_option", "fr_autotune", "fr_batch_create", "fr_batch_destroy", "fr_batch_layout",
            "fr_batch_residual", "fr_batch_jvp", "fr_batch_bdf2_step", "fr_batch_set_option",
            "fr_batch_autotune", "fr_last_error", "fr_destroy", "fr_get_inverse", "fr_reserve",
-           "fr_batch_reserve"]
+           "fr_batch_reserve", "fr_vjp_noalloc"]
 
 
 class FRError(RuntimeError):
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.fr_residual.argtypes = [vp, dp, dp, vp]
     L.fr_jvp.argtypes = [vp, dp, dp, dp, dp, vp]
     L.fr_vjp.argtypes = [vp, dp, dp, dp, vp]
+    L.fr_vjp_noalloc.argtypes = [vp, dp, dp, dp, vp]
     L.fr_bdf_operator.argtypes = [vp, dp, dp, ctypes.c_double, ctypes.c_double, dp, vp]
     L.fr_block_jacobi_factor.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp]
     L.fr_block_jacobi_apply.argtypes = [vp, dp, dp, vp]
