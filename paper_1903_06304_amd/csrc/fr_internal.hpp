@@ -317,9 +317,9 @@ size_t prec_bytes(int prec);
 // preconditioner (fr_linalg.hip)
 fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s);
 fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s);
-// blocks of 100 rows (p = 4), two waves per element (fr_invert.hip)
-fr_status launch_block_invert_p4(Solver& sv, const Group& gr, const GroupArgs& ga, int prec, const int* flags,
-                                 hipStream_t s);
+// explicit inverses of one group's element blocks, Gauss-Jordan on the matrix cores (fr_invert.hip)
+fr_status launch_block_invert_group(Solver& sv, int p, const GroupArgs& ga, int prec, const int* flags,
+                                    hipStream_t s);
 fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const int* flags, int flag, hipStream_t s);
 // restricted to the elements of one colour (color >= 0; -1: all):
 //   sub = false: z_e = D_e^-1 (r_e - b_e) (b may be null);  sub = true: z_e -= D_e^-1 r_e

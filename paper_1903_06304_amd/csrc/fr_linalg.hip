@@ -28,184 +28,6 @@ __device__ __forceinline__ int tile_member(const GroupArgs& ga, int t) {
     return lo;
 }
 
-// ------------------------------------------------------------------ block inversion
-template <class Tout>
-__device__ __forceinline__ Tout to_store(double x);
-template <> __device__ __forceinline__ double to_store<double>(double x) { return x; }
-template <> __device__ __forceinline__ float to_store<float>(double x) { return (float)x; }
-template <> __device__ __forceinline__ uint16_t to_store<uint16_t>(double x) {
-    float f = (float)x;
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
-    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);                       // round to nearest even
-    return (uint16_t)(r >> 16);
-}
-__device__ __forceinline__ double from_store(double x) { return x; }
-__device__ __forceinline__ double from_store(float x) { return (double)x; }
-__device__ __forceinline__ double from_store(uint16_t x) { return (double)__uint_as_float(((uint32_t)x) << 16); }
-
-// A is column-major in global (a[col*nb + row]); LDS holds it row-major with a padded stride.
-// One workgroup per element of a group (tile width 1); a zero pivot marks the case's
-// status (plain vector store) and leaves its inverse unwritten.
-template <class Tout>
-__global__ void __launch_bounds__(256) k_block_invert(GroupArgs ga, int nb, const double* __restrict__ blk,
-                                                      Tout* __restrict__ inv, int* __restrict__ gi,
-                                                      const int* __restrict__ flags) {
-    extern __shared__ double lds[];
-    const int ld = nb + 1;
-    double* A = lds;                       // [nb][ld]
-    double* colk = lds + (size_t)nb * ld;  // [nb]
-    int* perm = (int*)(colk + nb);         // [nb]
-    __shared__ int s_piv;
-    __shared__ double s_pval;
-    const int t = blockIdx.x;
-    if (t >= ga.ntiles) return;
-    const int lo = tile_member(ga, t);
-    const int cid = ga.ids[lo];
-    if (flags && flags[cid * GI_STRIDE + GI_NDONE]) return;
-    const CaseDev& cd = ga.cases[cid];
-    const int e = t - ga.pfx[lo];
-    const double* src = blk + cd.boff + (size_t)e * nb * nb;
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-        const int c = t / nb, r = t % nb;
-        A[r * ld + c] = src[t];
-    }
-    __syncthreads();
-    for (int k = 0; k < nb; ++k) {
-        // pivot search over rows k..nb-1 by the first wave (ties -> smallest row)
-        if (threadIdx.x < 64) {
-            double best = -1.0;
-            int br = k;
-            for (int r = k + (int)threadIdx.x; r < nb; r += 64) {
-                const double a = fabs(A[r * ld + k]);
-                if (a > best) { best = a; br = r; }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_down(best, off, 64);
-                const int orr = __shfl_down(br, off, 64);
-                if (ob > best || (ob == best && orr < br)) { best = ob; br = orr; }
-            }
-            if (threadIdx.x == 0) { s_piv = br; s_pval = A[br * ld + k]; perm[k] = br; }
-        }
-        __syncthreads();
-        const int pr = s_piv;
-        const double pv = s_pval;
-        if (pv == 0.0) {
-            if (threadIdx.x == 0) gi[cid * GI_STRIDE + GI_STATUS] = 3;   // plain vector store
-            return;   // uniform across the workgroup
-        }
-        if (pr != k) {
-            for (int c = threadIdx.x; c < nb; c += blockDim.x) {
-                const double t0 = A[k * ld + c];
-                A[k * ld + c] = A[pr * ld + c];
-                A[pr * ld + c] = t0;
-            }
-        }
-        __syncthreads();
-        // scale the pivot row (A[k][k] := 1 first so the inverse accumulates in place)
-        const double ip = 1.0 / pv;
-        for (int c = threadIdx.x; c < nb; c += blockDim.x) {
-            const double a = (c == k) ? 1.0 : A[k * ld + c];
-            A[k * ld + c] = a * ip;
-        }
-        for (int r = threadIdx.x; r < nb; r += blockDim.x) colk[r] = (r == k) ? 0.0 : A[r * ld + k];
-        __syncthreads();
-        for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-            const int r = t / nb, c = t % nb;
-            if (r == k) continue;
-            const double a = (c == k) ? 0.0 : A[r * ld + c];
-            A[r * ld + c] = a - colk[r] * A[k * ld + c];
-        }
-        __syncthreads();
-    }
-    // undo the row interchanges as column interchanges, last first
-    for (int k = nb - 1; k >= 0; --k) {
-        const int pr = perm[k];
-        if (pr != k) {
-            for (int r = threadIdx.x; r < nb; r += blockDim.x) {
-                const double t0 = A[r * ld + k];
-                A[r * ld + k] = A[r * ld + pr];
-                A[r * ld + pr] = t0;
-            }
-        }
-        __syncthreads();
-    }
-    Tout* dst = inv + cd.boff + (size_t)e * nb * nb;
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-        const int c = t / nb, r = t % nb;
-        dst[t] = to_store<Tout>(A[r * ld + c]);   // column-major inverse
-    }
-}
-
-// Gauss-Jordan inversion with partial pivoting, one wave per element, the block held in
-// registers: lane r owns row r (NB <= 64).  Pivoting is implicit: the row chosen for
-// column k stays in its lane, which records k.  Step k broadcasts the pivot row with
-// readlane and eliminates column k from every other row (the in-place inverse trick:
-// column k is replaced by the corresponding column of the accumulated inverse).  With
-// piv[k] the lane chosen at step k and B the final array, the inverse is
-// A^-1[k'][piv[k]] = B[piv[k']][k] where k' is the step of the lane: lane L writes its
-// values a[k] to column piv[k], row step(L).  Same arithmetic per entry as the LDS
-// kernel; ties between equal pivot magnitudes go to the lowest lane.
-__device__ __forceinline__ double rdlane(double x, int lane) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-template <int NB, class Tout>
-__global__ void __launch_bounds__(256) k_block_invert_wave(GroupArgs ga, const double* __restrict__ blk,
-                                                           Tout* __restrict__ inv, int* __restrict__ gi,
-                                                           const int* __restrict__ flags) {
-    const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);   // element tile of this wave
-    if (t >= ga.ntiles) return;                                           // uniform per wave
-    const int lo = tile_member(ga, t);
-    const int cid = ga.ids[lo];
-    if (flags && flags[cid * GI_STRIDE + GI_NDONE]) return;
-    const CaseDev& cd = ga.cases[cid];
-    const int e = t - ga.pfx[lo];
-    const double* src = blk + cd.boff + (size_t)e * NB * NB;
-    const bool row = lane < NB;
-    double a[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] = row ? src[(size_t)c * NB + lane] : 0.0;
-    bool used = !row;
-    int mystep = 0;
-    __shared__ int s_piv[4][NB];   // pivot lane of each step, per wave of the workgroup
-    int* piv = s_piv[threadIdx.x >> 6];
-#pragma clang loop unroll(full)
-    for (int k = 0; k < NB; ++k) {
-        // pivot: largest |a[k]| over the rows not used yet, lowest lane on ties
-        double m = used ? -1.0 : fabs(a[k]);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-        const unsigned long long cand = __ballot(!used && fabs(a[k]) == m);
-        const int p = __builtin_amdgcn_readfirstlane(cand ? (int)__ffsll((long long)cand) - 1 : 0);
-        const double pv = rdlane(a[k], p);
-        if (!(pv != 0.0)) {
-            if (lane == 0) gi[cid * GI_STRIDE + GI_STATUS] = 3;   // plain vector store
-            return;                                                // uniform per wave
-        }
-        if (lane == 0) piv[k] = p;
-        const bool isp = lane == p;
-        if (isp) { used = true; mystep = k; }
-        const double ip = 1.0 / pv;
-        const double f = a[k];
-#pragma clang loop unroll(full)
-        for (int c = 0; c < NB; ++c) {
-            const double pc = ((c == k) ? 1.0 : rdlane(a[c], p)) * ip;   // normalised pivot row
-            const double ac = (c == k) ? 0.0 : a[c];
-            a[c] = isp ? pc : ac - f * pc;
-        }
-    }
-    __builtin_amdgcn_wave_barrier();   // the wave's own pivot list (LDS is in order within a wave)
-    if (!row) return;
-    Tout* dst = inv + cd.boff + (size_t)e * NB * NB;
-#pragma clang loop unroll(full)
-    for (int k = 0; k < NB; ++k) dst[(size_t)piv[k] * NB + mystep] = to_store<Tout>(a[k]);   // column-major
-}
-
 // z_e = Ainv_e r_e for the elements of one group; state layout [4][E][Np] per case,
 // block row/col index v*Np + s.  Each thread owns RPT consecutive rows and reads them
 // from every column of the column-major inverse with one 8-byte load (1 double, 2
@@ -543,58 +365,19 @@ fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, 
     return FR_OK;
 }
 
-template <int NB, class Tout>
-static fr_status invert_wave(Solver& sv, const Group& gr, const int* flags, hipStream_t s) {
-    GroupArgs ga = group_args(sv, gr, 1);
-    if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
-    if (ga.ntiles == 0) return FR_OK;
-    hipLaunchKernelGGL((k_block_invert_wave<NB, Tout>), dim3((ga.ntiles + 3) / 4), dim3(256), 0, s, ga, sv.d_blk,
-                       (Tout*)sv.d_inv, sv.d_gi, flags);
-    FR_HIP(hipGetLastError());
-    return FR_OK;
-}
-
-template <class Tout> constexpr int prec_of();
-template <> constexpr int prec_of<double>() { return FR_FP64; }
-template <> constexpr int prec_of<float>() { return FR_FP32; }
-template <> constexpr int prec_of<uint16_t>() { return FR_BF16; }
-
-template <class Tout>
-static fr_status invert_as(Solver& sv, const int* flags, hipStream_t s) {
+// explicit inverse of every element block, on the matrix cores (fr_invert.hip)
+static fr_status invert_all(Solver& sv, int prec, const int* flags, hipStream_t s) {
     for (const Group& gr : sv.groups) {
-        const int nb = 4 * (gr.p + 1) * (gr.p + 1);
-        // blocks up to 64 rows: one wave per element, block in registers
-        if (gr.p == 1) { FR_TRY((invert_wave<16, Tout>(sv, gr, flags, s))); continue; }
-        if (gr.p == 2) { FR_TRY((invert_wave<36, Tout>(sv, gr, flags, s))); continue; }
-        if (gr.p == 3) { FR_TRY((invert_wave<64, Tout>(sv, gr, flags, s))); continue; }
-        if (gr.p == 4) {
-            // 100 rows: two waves per element (fr_invert.hip)
-            GroupArgs ga = group_args(sv, gr, 1);
-            if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
-            if (ga.ntiles == 0) continue;
-            FR_TRY(launch_block_invert_p4(sv, gr, ga, prec_of<Tout>(), flags, s));
-            continue;
-        }
-        const size_t lds = ((size_t)nb * (nb + 1) + nb) * sizeof(double) + nb * sizeof(int);
         GroupArgs ga = group_args(sv, gr, 1);
         if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
-        if (ga.ntiles == 0) continue;
-        FR_HIP(hipFuncSetAttribute((const void*)k_block_invert<Tout>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
-        hipLaunchKernelGGL(k_block_invert<Tout>, dim3(ga.ntiles), dim3(256), lds, s, ga, nb, sv.d_blk,
-                           (Tout*)sv.d_inv, sv.d_gi, flags);
-        FR_HIP(hipGetLastError());
+        FR_TRY(launch_block_invert_group(sv, gr.p, ga, prec, flags, s));
     }
     return FR_OK;
 }
 
 fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s) {
-    switch (prec) {
-        case FR_FP64: FR_TRY(invert_as<double>(sv, flags, s)); break;
-        case FR_FP32: FR_TRY(invert_as<float>(sv, flags, s)); break;
-        case FR_BF16: FR_TRY(invert_as<uint16_t>(sv, flags, s)); break;
-        default: fr_set_error("unknown precision"); return FR_EINVAL;
-    }
+    if (prec < FR_FP64 || prec > FR_BF16) { fr_set_error("unknown precision"); return FR_EINVAL; }
+    FR_TRY(invert_all(sv, prec, flags, s));
     sv.inv_prec = prec;
     return FR_OK;
 }
