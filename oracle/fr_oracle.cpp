@@ -57,6 +57,29 @@ template <class T> inline T smin(const T& a, const T& b) { return re(a) <= re(b)
 inline double ssqrt(double x) { return std::sqrt(x); }
 inline cplx ssqrt(const cplx& x) { return std::sqrt(x); }
 
+// Op-counting scalar: a double that tallies every arithmetic operation applied to it
+// (additions and subtractions, multiplications, divisions, square roots).  Running the
+// residual on it counts the floating-point work one evaluation does on the state; pure
+// geometry and operator-table arithmetic (doubles) is set-up work and is not counted.
+struct OpTally { unsigned long long add = 0, mul = 0, div = 0, sqrt = 0; };
+static OpTally g_tally;
+struct Cnt {
+    double v;
+    Cnt() : v(0.0) {}
+    Cnt(double x) : v(x) {}
+    Cnt operator-() const { return Cnt(-v); }
+    Cnt& operator+=(const Cnt& b) { ++g_tally.add; v += b.v; return *this; }
+    Cnt& operator-=(const Cnt& b) { ++g_tally.add; v -= b.v; return *this; }
+    Cnt& operator*=(const Cnt& b) { ++g_tally.mul; v *= b.v; return *this; }
+    Cnt& operator/=(const Cnt& b) { ++g_tally.div; v /= b.v; return *this; }
+};
+inline Cnt operator+(const Cnt& a, const Cnt& b) { ++g_tally.add; return Cnt(a.v + b.v); }
+inline Cnt operator-(const Cnt& a, const Cnt& b) { ++g_tally.add; return Cnt(a.v - b.v); }
+inline Cnt operator*(const Cnt& a, const Cnt& b) { ++g_tally.mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(const Cnt& a, const Cnt& b) { ++g_tally.div; return Cnt(a.v / b.v); }
+inline double re(const Cnt& x) { return x.v; }
+inline Cnt ssqrt(const Cnt& x) { ++g_tally.sqrt; return Cnt(std::sqrt(x.v)); }
+
 // ---------------------------------------------------------------- 1-D operators
 // Legendre P_k and P_k' by the three-term recurrence.
 static void legendre(int k, double x, double& P, double& dP) {
@@ -163,6 +186,7 @@ struct Ctx {
     // or |J| grad(eta) (faces 2,3), |J| at the flux point, grid velocity at the flux point
     std::vector<double> Sx, Sy, Jf, ugf, vgf;
     std::vector<double> xg, vg;
+    int threads = 1;   // element-loop threads of the residual (OpenMP builds only)
 };
 
 static inline double face_sign(int f) { return (f == 1 || f == 3) ? 1.0 : -1.0; }
@@ -629,6 +653,7 @@ static void element_residual(const Ctx& c, const Phys& ph, int e, const T* q, Tr
 template <class Phys, class T>
 static void compute_traces(const Ctx& c, const Phys& ph, const T* q, Traces<T>& tr) {
     tr.init(c.E, Phys::NV, c.n);
+#pragma omp parallel for schedule(static) num_threads(c.threads) if (c.threads > 1)
     for (int e = 0; e < c.E; ++e) element_traces(c, ph, e, q, tr.pq(e), tr.pgx(e), tr.pgy(e));
 }
 
@@ -637,11 +662,17 @@ template <class Phys, class T>
 static void residual(const Ctx& c, const Phys& ph, const T* q, T* R) {
     const int NV = Phys::NV, Np = c.Np;
     Traces<T> tr; compute_traces(c, ph, q, tr);
-    std::vector<T> Re((size_t)NV * Np);
-    for (int e = 0; e < c.E; ++e) {
-        element_residual(c, ph, e, q, tr, Re.data());
-        for (int v = 0; v < NV; ++v)
-            for (int s = 0; s < Np; ++s) R[((size_t)v * c.E + e) * Np + s] = Re[(size_t)v * Np + s];
+    // elements are independent once the traces exist: an OpenMP build may split them over
+    // threads (each with its own element buffer); the arithmetic per element is unchanged
+#pragma omp parallel num_threads(c.threads) if (c.threads > 1)
+    {
+        std::vector<T> Re((size_t)NV * Np);
+#pragma omp for schedule(static)
+        for (int e = 0; e < c.E; ++e) {
+            element_residual(c, ph, e, q, tr, Re.data());
+            for (int v = 0; v < NV; ++v)
+                for (int s = 0; s < Np; ++s) R[((size_t)v * c.E + e) * Np + s] = Re[(size_t)v * Np + s];
+        }
     }
 }
 
@@ -1092,6 +1123,33 @@ int ora_geometry(void* h, double* out, double* fout) {
     for (int i = 0; i < 9; ++i) std::memcpy(out + i * M, a[i]->data(), M * sizeof(double));
     const std::vector<double>* b[5] = {&c.Sx, &c.Sy, &c.Jf, &c.ugf, &c.vgf};
     for (int i = 0; i < 5; ++i) std::memcpy(fout + i * F, b[i]->data(), F * sizeof(double));
+    return 0;
+}
+
+void ora_set_threads(void* h, int n) { ((Ctx*)h)->threads = n < 1 ? 1 : n; }
+
+int ora_openmp(void) {
+#ifdef _OPENMP
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+// R(q) on the op-counting scalar: R (equal to ora_residual's bit for bit) and the counts
+// {add/sub, mul, div, sqrt} of one evaluation.  Serial.
+int ora_count_residual(void* h, const double* q, double* R, unsigned long long* counts) {
+    Ctx& c = *(Ctx*)h;
+    const int keep = c.threads;
+    c.threads = 1;
+    NSPhys ph{&c};
+    const size_t N = (size_t)4 * c.E * c.Np;
+    std::vector<Cnt> qc(q, q + N), Rc(N);
+    g_tally = OpTally();
+    residual(c, ph, qc.data(), Rc.data());
+    for (size_t i = 0; i < N; ++i) R[i] = Rc[i].v;
+    counts[0] = g_tally.add; counts[1] = g_tally.mul; counts[2] = g_tally.div; counts[3] = g_tally.sqrt;
+    c.threads = keep;
     return 0;
 }
 

@@ -15,7 +15,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fr_oracle.cpp")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# a build of the same source with other flags (the CPU baseline's optimised OpenMP build)
+# may be named by LMFR_ORACLE_LIB
+_LIB = os.environ.get("LMFR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -32,6 +34,16 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_native(path: str) -> str:
+    """The same source at -O3 -march=native with OpenMP element loops (no fast-math): the
+    build the CPU baseline times, on the machine that runs it."""
+    cmd = ["g++", "-O3", "-march=native", "-fopenmp", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math",
+           "-o", path + ".tmp", _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(path + ".tmp", path)
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -40,6 +52,9 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.ora_create.restype = ctypes.c_void_p
         L.ora_destroy.argtypes = [ctypes.c_void_p]
+        L.ora_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.ora_count_residual.restype = ctypes.c_int
+        L.ora_openmp.restype = ctypes.c_int
         for name in ["ora_residual", "ora_jvp", "ora_dense_jacobian", "ora_vjp_dofs", "ora_blocks",
                      "ora_point", "ora_common_flux", "ora_phys_flux", "ora_bdf2_step", "ora_steady_solve", "ora_precond_apply",
                      "ora_geometry", "ora_scalar_residual", "ora_residual_cplx", "ora_cons_cplx"]:
@@ -148,6 +163,18 @@ class Oracle:
         R = np.zeros_like(q)
         lib().ora_residual(self.h, _p(q), _p(R))
         return R
+
+    def set_threads(self, n: int):
+        """Element-loop threads of the residual (effective in an OpenMP build only)."""
+        lib().ora_set_threads(self.h, int(n))
+
+    def count_residual(self, q):
+        """R on the op-counting scalar: (R, {add, mul, div, sqrt}) for one evaluation."""
+        q = self._state(q)
+        R = np.zeros_like(q)
+        cnt = np.zeros(4, dtype=np.uint64)
+        lib().ora_count_residual(self.h, _p(q), _p(R), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_ulonglong)))
+        return R, dict(zip(["add", "mul", "div", "sqrt"], (int(x) for x in cnt)))
 
     def residual_complex(self, q):
         qr = np.ascontiguousarray(q.real, dtype=np.float64)

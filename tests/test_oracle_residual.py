@@ -278,3 +278,22 @@ def test_renumbered_elements_permute_residual_and_jvp(case):
         o3.set_farfield(qinf)
     R3 = o3.residual(carry(q))
     assert np.max(np.abs(R3 - carry(R1)) / scale[:, None, None]) > 1e-6
+
+
+@pytest.mark.parametrize("p,viscous", [(2, False), (3, True), (4, True)])
+def test_op_counting_scalar(p, viscous):
+    """The op-counting scalar runs the same arithmetic: R is the double residual bit for bit,
+    and on periodic meshes (every element does the same work) the counts scale exactly with
+    the element count.  The per-DOF count is what the measurement quotes as algorithmic flops."""
+    counts = []
+    for nx in (3, 6):
+        mesh = I.Mesh(nx, nx, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+        prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=viscous, kappa=1.0)
+        q = _random_state(prm, mesh, 5)
+        o = Oracle(prm, mesh)
+        R, cnt = o.count_residual(q)
+        assert np.array_equal(R, o.residual(q))
+        assert all(v > 0 for v in cnt.values())
+        counts.append(cnt)
+    for k in counts[0]:
+        assert counts[1][k] == 4 * counts[0][k], (k, counts)
