@@ -10,6 +10,7 @@ One timed step = one pass of the hot path over that input:
   * one BDF2 dual-time step (Newton to Res_m/Res_0 <= 1e-8, GMRES(30), tol_res 1e-6)
     with FP64 element blocks ("plain"), and the same step with FP32 and BF16 blocks,
     and with the symmetric block Gauss-Seidel preconditioner (FP64 and BF16 blocks),
+    at p = 3 (64 x 64 blocks) and at p = 4 (100 x 100 blocks, 6.55M DOF),
   * the batched workload: 48 uneven cases (16^2..192^2 quads, p = 2..4, Ma 0.01..0.3,
     Re 100..5000, half deforming) -- batched residuals and one batched BDF2 step per
     block precision, also with block Gauss-Seidel; launch shapes from the autotuner.
@@ -28,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 
 def parse():
@@ -41,7 +43,15 @@ def parse():
                     help="residual evaluations per step (about 50 ms: long enough for the clocks to settle)")
     ap.add_argument("--nj", type=int, default=10, help="JVP evaluations per step")
     ap.add_argument("--nv", type=int, default=10, help="VJP evaluations per step")
-    ap.add_argument("--dt", type=float, default=1e-3, help="physical time step of the BDF2 step")
+    ap.add_argument("--dt", type=float, default=1e-3,
+                    help="physical time step of the BDF2 step (the workload's nominal 0.01 is an acoustic CFL "
+                         "number of about 34 (p=3) and 43 (p=4) on 256^2, where GMRES(30) with the element-block "
+                         "preconditioners stalls: measured, see the design notes)")
+    ap.add_argument("--no-p4", action="store_true", help="skip the p = 4 BDF2 steps")
+    ap.add_argument("--p4-precs", default="fp64,fp32,bf16")
+    ap.add_argument("--p4-gs-precs", default="fp64,bf16")
+    ap.add_argument("--no-curved", action="store_true", help="skip the curved-mesh residual figures")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0, help="oracle timing per leg (one core, all cores)")
     ap.add_argument("--max-lin-it", type=int, default=200)
     ap.add_argument("--precs", default="fp64,fp32,bf16")
     ap.add_argument("--gs-precs", default="fp64,bf16",
@@ -55,7 +65,6 @@ def parse():
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: reuse (and extend) launch shapes chosen by an earlier run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20, help="oracle residual evaluations timed")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-case batched workload")
     ap.add_argument("--batch-precs", default="fp64,bf16")
     ap.add_argument("--batch-gs-precs", default="fp64,bf16",
@@ -148,13 +157,30 @@ def main():
                   jac_lag=2, inv_dtau=1e-20)
     q_nm1 = q0.clone()
     q_n = q0.clone()
+    floor3 = 10.0 * residual_noise(ctx, q0, torch)   # Newton's round-off floor (absolute)
     if not args.no_bdf2:
-        st0 = ctx.bdf2_step(q_n, None, args.dt, **bdf_kw)
+        st0 = ctx.bdf2_step(q_n, None, args.dt, tol_abs=floor3, **bdf_kw)
         torch.cuda.synchronize()
         print(f"[bench] BDF1 start step {st0}", file=sys.stderr, flush=True)
 
     precs = args.precs.split(",")
     gprecs = [x for x in args.gs_precs.split(",") if x]
+    p4precs = [x for x in args.p4_precs.split(",") if x]
+    p4gprecs = [x for x in args.p4_gs_precs.split(",") if x]
+    p4 = None
+    if not args.no_bdf2 and not args.no_p4:
+        # the same workload at p = 4: 100 x 100 element blocks
+        c4 = I.config_c4(nx=args.nx, p=4)
+        ctx4 = lmfr.Context(c4.prm, *c4.mesh.connectivity())
+        ctx4.set_geometry(*c4.mesh.nodes())
+        ctx4.autotune(args.tune_cache)
+        q40 = torch.tensor(c4.q, device=dev)
+        q4n = q40.clone()
+        floor4 = 10.0 * residual_noise(ctx4, q40, torch)
+        st4 = ctx4.bdf2_step(q4n, None, args.dt, tol_abs=floor4, **bdf_kw)
+        torch.cuda.synchronize()
+        print(f"[bench] p=4 BDF1 start step {st4}", file=sys.stderr, flush=True)
+        p4 = dict(ctx=ctx4, q_n=q4n, q_nm1=q40, dof=4 * c4.mesh.E * c4.mesh.Np, floor=floor4)
     bprecs = args.batch_precs.split(",")
     bgprecs = [x for x in args.batch_gs_precs.split(",") if x]
     bt = None
@@ -186,25 +212,27 @@ def main():
         t5.record(stream)
         ev["vjp"] = (t4, t5)
         stats = {}
+
+        def variants(c_, qn, qm, tag, plist, glist, floor):
+            """The BDF2 step from (qn, qm) with each block precision, block Jacobi and block
+            Gauss-Seidel; events and stats under keys tag + "bdf2_" / "gs_" + precision."""
+            for pc, lst in ((0, plist), (1, glist)):
+                c_.set_option("preconditioner", pc)
+                for pr in lst:
+                    qw = qn.clone()
+                    a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    st = c_.bdf2_step(qw, qm, args.dt, prec=pr, tol_abs=floor, **bdf_kw)
+                    b.record(stream)
+                    key = tag + ("gs_" if pc else "bdf2_") + pr
+                    ev[key] = (a, b)
+                    stats[key] = (st, qw)
+            c_.set_option("preconditioner", 0)
+
         if not args.no_bdf2:
-            for pr in precs:
-                qw = q_n.clone()
-                a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                st = ctx.bdf2_step(qw, q_nm1, args.dt, prec=pr, **bdf_kw)
-                b.record(stream)
-                ev["bdf2_" + pr] = (a, b)
-                stats[pr] = (st, qw)
-            ctx.set_option("preconditioner", 1)
-            for pr in gprecs:
-                qw = q_n.clone()
-                a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                st = ctx.bdf2_step(qw, q_nm1, args.dt, prec=pr, **bdf_kw)
-                b.record(stream)
-                ev["gs_" + pr] = (a, b)
-                stats["gs_" + pr] = (st, qw)
-            ctx.set_option("preconditioner", 0)
+            variants(ctx, q_n, q_nm1, "", precs, gprecs, floor3)
+            if p4 is not None:
+                variants(p4["ctx"], p4["q_n"], p4["q_nm1"], "p4_", p4precs, p4gprecs, p4["floor"])
         if bt is not None:
             a = torch.cuda.Event(enable_timing=True); b_ = torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -282,7 +310,15 @@ def main():
         "data": "synthetic (seeded smooth random fields)",
         "config": {"workload": f"NS p={args.order} {args.nx}x{args.nx} affine periodic [0,2pi]^2, Ma=0.05, "
                                f"Re=1000, seeded random fields", "dof": dof, "elements": E,
-                   "residuals_per_step": args.nr, "jvps_per_step": args.nj, "buffer_sets": nsets},
+                   "residuals_per_step": args.nr, "jvps_per_step": args.nj, "buffer_sets": nsets,
+                   "bdf2": {"dt": args.dt, "krylov": bdf_kw["krylov"], "tol_res": bdf_kw["tol_res"],
+                            "tol_pseudo": bdf_kw["tol_pseudo"], "max_lin_it": bdf_kw["max_lin_it"],
+                            "jac_lag": bdf_kw["jac_lag"], "start": "one BDF1 step from the seeded fields",
+                            "tol_abs": "10 x the mass-row change of R under a one-ulp perturbation of q",
+                            "dt_note": "dt = 1e-3 (acoustic CFL about 3.4 at p=3): at the nominal 0.01 the "
+                                       "element-block preconditioners stall on 256^2 (block Jacobi exceeds 600 "
+                                       "GMRES iterations per Newton step at p=3 and p=4; block Gauss-Seidel "
+                                       "converges only at p=3 with FP64 or FP32 blocks)"}},
         "residual_ms": res_ms,
         "autotune_s": t_tune,
         "jvp_ms": jvp_ms,
@@ -295,27 +331,34 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.order, args.nx), "algorithmic_bytes": alg_b},
     }
+    def step_table(tag, plist, glist, order):
+        """Per precision and preconditioner: time, iterations, gap to the FP64 block-Jacobi
+        step's state, speedup over it (the plain path)."""
+        bd = {"order": order, "block_size": 4 * (order + 1) ** 2}
+        last = records[-1][1]
+        for pc, lst in ((0, plist), (1, glist)):
+            for pr in lst:
+                key = tag + ("gs_" if pc else "bdf2_") + pr
+                st, qw = last[key]
+                bd[("gauss_seidel_" if pc else "") + pr] = {
+                    "ms": mean_ms(key), "newton_its": st["newton_its"], "gmres_its": st["gmres_its"],
+                    "converged": st["converged"], "res_ratio": st["res_final"] / max(st["res0"], 1e-300)}
+        if "fp64" in plist:
+            ref = last[tag + "bdf2_fp64"][1]
+            for name, row in list(bd.items()):
+                if not isinstance(row, dict) or name == "fp64":
+                    continue
+                key = tag + ("gs_" + name[len("gauss_seidel_"):] if name.startswith("gauss_seidel_") else "bdf2_" + name)
+                d = (last[key][1] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
+                row["max_rel_diff_vs_fp64"] = float(d.max())
+                row["speedup_vs_fp64"] = bd["fp64"]["ms"] / row["ms"]
+        return bd
+
     if not args.no_bdf2:
-        bd = {}
-        for pr in precs:
-            st, qw = records[-1][1][pr]
-            bd[pr] = {"ms": mean_ms("bdf2_" + pr), "newton_its": st["newton_its"], "gmres_its": st["gmres_its"],
-                      "converged": st["converged"], "res_ratio": st["res_final"] / max(st["res0"], 1e-300)}
-        ref = records[-1][1]["fp64"][1]
-        for pr in [x for x in precs if x != "fp64"]:
-            d = (records[-1][1][pr][1] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
-            bd[pr]["max_rel_diff_vs_fp64"] = float(d.max())
-            bd[pr]["speedup_vs_fp64"] = bd["fp64"]["ms"] / bd[pr]["ms"]
-        # the same step with the symmetric block Gauss-Seidel preconditioner
-        for pr in gprecs:
-            st, qw = records[-1][1]["gs_" + pr]
-            d = (qw - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
-            bd["gauss_seidel_" + pr] = {"ms": mean_ms("gs_" + pr), "newton_its": st["newton_its"],
-                                        "gmres_its": st["gmres_its"], "converged": st["converged"],
-                                        "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
-                                        "max_rel_diff_vs_fp64": float(d.max()),
-                                        "speedup_vs_fp64": bd["fp64"]["ms"] / mean_ms("gs_" + pr)}
-        out["bdf2_step"] = bd
+        out["bdf2_step"] = step_table("", precs, gprecs, args.order)
+        if p4 is not None:
+            out["bdf2_step_p4"] = step_table("p4_", p4precs, p4gprecs, 4)
+            out["bdf2_step_p4"]["dof"] = p4["dof"]
     if bt is not None:
         bres_ms = mean_ms("bres") / args.nrb
         bd = {"cases": len(bt["cases"]), "dof": bt["dof"], "elements": sum(c.mesh.E for c in bt["cases"]),
@@ -351,8 +394,19 @@ def main():
         out["steady"] = steady_solve(torch, lmfr, I, dev)
     if not args.no_boundary:
         out["boundary"] = boundary_case(args, torch, lmfr, I, dev)
+    if not args.no_curved:
+        out["curved"] = curved_cases(args, torch, lmfr, I, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_sample)
+        cb = cpu_baseline(args, torch, lmfr, I, dev)
+        out["cpu_baseline"] = cb
+        # the oracle's exact operation count of one residual against the FP64 vector peak
+        fl = cb.get("flops_per_residual")
+        if fl:
+            f_alg = float(sum(fl.values()))
+            fp64_frac = f_alg / (res_ms * 1e-3) / 1e12 / FP64_PEAK_TFS
+            out["roofline"]["flops_per_residual"] = f_alg
+            out["roofline"]["fp64_frac"] = fp64_frac
+            out["roofline"]["combined_frac"] = max(out["roofline"]["frac"], fp64_frac)
     print(json.dumps(out), flush=True)
 
 
@@ -485,19 +539,84 @@ def residual_noise(ctx, q, torch):
     return float(torch.linalg.vector_norm(d[0]))
 
 
-def cpu_baseline(case, nsample):
-    """The serial FP64 oracle timed on this host on a bounded sample of the same workload."""
+def cpu_baseline(args, torch, lmfr, I, dev):
+    """The CPU baseline leg (the only part of the benchmark that runs the oracle):
+    * the oracle's residual on the full workload, rebuilt on this host at -O3 -march=native
+      with its OpenMP element loops, timed on one core and on every core (a bounded sample:
+      --cpu-seconds per leg), with nproc / lscpu and the oracle's exact operation count;
+    * the mixed-precision gap: BDF2 steps on the GPU with FP64, FP32 and BF16 blocks against
+      the oracle's FP64 step on meshes it steps in seconds (C4's fields on 8x8 at p=3 and 6x6
+      at p=4, dt = 0.01, GMRES(30), tol_res 1e-6, Newton to 1e-8), as the largest gap over
+      the variables relative to each variable's range."""
+    import subprocess
     import numpy as np
+    r = subprocess.run([sys.executable, "-m", "oracle.cpu_bench", str(args.nx), str(args.order),
+                        str(args.cpu_seconds), "--native"], capture_output=True, text=True, cwd=ROOT)
+    if r.returncode != 0:
+        return {"error": r.stderr[-2000:]}
+    cb = json.loads(r.stdout.strip().splitlines()[-1])
+    allc = cb["all_cores"]
+    out = {"value": allc["dof_per_s"], "unit": "DOF-residual evals/s", "cores": allc["threads"], "kind": "oracle",
+           "sample": f"{allc['evals']} residual evaluations of the full workload on {allc['threads']} threads "
+                     f"({allc['seconds']:.1f} s), oracle built with g++ -O3 -march=native -fopenmp",
+           "one_core": cb["one_core"], "openmp": cb["openmp"], "nproc": cb["nproc"], "affinity": cb["affinity"],
+           "lscpu": cb["lscpu"], "flops_per_residual": cb["flops_per_residual"], "flops_per_dof": cb["flops_per_dof"]}
     from oracle.oracle import Oracle
-    o = Oracle(case.prm, case.mesh)
-    o.residual(case.q)
-    t = time.perf_counter()
-    for _ in range(nsample):
-        o.residual(case.q)
-    dt = time.perf_counter() - t
-    dof = 4 * case.mesh.E * case.mesh.Np
-    return {"value": dof * nsample / dt, "unit": "DOF-residual evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsample} serial residual evaluations of the full workload ({dt:.1f} s)"}
+    gaps = {}
+    for nx, p in ((8, 3), (6, 4)):
+        c = I.config_c4(nx=nx, p=p)
+        o = Oracle(c.prm, c.mesh)
+        kw = dict(tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=300, max_newton=30)
+        q1, _ = o.bdf2_step(c.q, None, 0.01, **kw)
+        t0 = time.perf_counter()
+        q2, so = o.bdf2_step(q1, c.q, 0.01, **kw)
+        t_ora = time.perf_counter() - t0
+        span = np.max(q2, axis=(1, 2)) - np.min(q2, axis=(1, 2))
+        g = lmfr.Context(c.prm, *c.mesh.connectivity())
+        g.set_geometry(*c.mesh.nodes())
+        row = {"oracle_step_s": t_ora, "oracle_gmres_its": so["gmres_its"]}
+        for pr in ("fp64", "fp32", "bf16"):
+            qg = torch.tensor(q1, device=dev)
+            st = g.bdf2_step(qg, torch.tensor(c.q, device=dev), 0.01, prec=pr, **kw)
+            torch.cuda.synchronize()
+            gap = np.max(np.abs(qg.cpu().numpy() - q2), axis=(1, 2)) / span
+            row[pr] = {"gap_over_range": float(gap.max()), "gmres_its": st["gmres_its"], "converged": st["converged"]}
+        gaps[f"c4_{nx}x{nx}_p{p}"] = row
+    out["bdf2_gap_vs_fp64_oracle"] = gaps
+    return out
+
+
+def curved_cases(args, torch, lmfr, I, dev):
+    """Residual rate through the general (curved-element) kernel, once, outside the timed
+    steps: the curved map of the 64x64 Taylor-Green workload at its own size and on the
+    256 x 256 mesh of the main workload, over rotating buffers larger than the Infinity Cache."""
+    import numpy as np
+    out = {}
+    for nx in (64, args.nx):
+        c = I.config_c2(nx=nx)
+        g = lmfr.Context(c.prm, *c.mesh.connectivity())
+        g.set_geometry(*c.mesh.nodes())
+        g.autotune(args.tune_cache)
+        q0 = torch.tensor(c.q, device=dev)
+        nsets = max(2, int(np.ceil(512e6 / (2 * q0.numel() * 8))))
+        qs = [q0 * (1.0 + 1e-6 * k) for k in range(nsets)]
+        Rs = [torch.empty_like(q0) for _ in range(nsets)]
+        n = 200 if nx <= 64 else 100
+        for k in range(20):
+            g.residual(qs[k % nsets], out=Rs[k % nsets])
+        a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for k in range(n):
+            g.residual(qs[k % nsets], out=Rs[k % nsets])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / n
+        dof = 4 * c.mesh.E * c.mesh.Np
+        alg = algorithmic_bytes_residual(c.mesh.E, c.prm.order)
+        out[f"curved_{nx}x{nx}_p{c.prm.order}"] = {
+            "residual_ms": ms, "dof_per_s": dof / (ms * 1e-3),
+            "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "affine_elements": g.affine_elements()}
+    return out
 
 
 if __name__ == "__main__":
