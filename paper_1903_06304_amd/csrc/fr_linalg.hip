@@ -30,25 +30,27 @@ __device__ __forceinline__ int tile_member(const GroupArgs& ga, int t) {
 
 // z_e = Ainv_e r_e for the elements of one group; state layout [4][E][Np] per case,
 // block row/col index v*Np + s.  Each thread owns RPT consecutive rows and reads them
-// from every column of the column-major inverse with one 8-byte load (1 double, 2
-// floats or 4 bfloat16), so every precision streams its blocks with full-width loads;
+// from every column of the column-major inverse with one load (1 double, 4 floats in 16
+// bytes, or 4 bfloat16 in 8 bytes), so every precision streams its blocks with wide loads;
 // FP64 accumulation over the columns in ascending order.
 template <class Tin> struct Pack8;
-template <> struct Pack8<double> {
+template <> struct Pack8<double> {   // 8-byte loads: 1 row per thread
     static constexpr int R = 1;
-    __device__ static void ld(const double* p, double* x) { x[0] = *p; }
+    using Raw = double;
+    __device__ static Raw ld(const double* p) { return *p; }
+    __device__ static void expand(const Raw& v, double* x) { x[0] = v; }
 };
-template <> struct Pack8<float> {
-    static constexpr int R = 2;
-    __device__ static void ld(const float* p, double* x) {
-        const float2 v = *reinterpret_cast<const float2*>(p);
-        x[0] = v.x; x[1] = v.y;
-    }
-};
-template <> struct Pack8<uint16_t> {
+template <> struct Pack8<float> {    // 16-byte loads: 4 rows per thread
     static constexpr int R = 4;
-    __device__ static void ld(const uint16_t* p, double* x) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p);
+    using Raw = float4;
+    __device__ static Raw ld(const float* p) { return *reinterpret_cast<const float4*>(p); }
+    __device__ static void expand(const Raw& v, double* x) { x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w; }
+};
+template <> struct Pack8<uint16_t> { // 8-byte loads: 4 rows per thread
+    static constexpr int R = 4;
+    using Raw = uint2;
+    __device__ static Raw ld(const uint16_t* p) { return *reinterpret_cast<const uint2*>(p); }
+    __device__ static void expand(const Raw& v, double* x) {
         x[0] = (double)__uint_as_float(v.x << 16);
         x[1] = (double)__uint_as_float(v.x & 0xffff0000u);
         x[2] = (double)__uint_as_float(v.y << 16);
@@ -96,13 +98,34 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
     double acc[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) acc[k] = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < NB; ++c) {
-        double x[RPT];
-        Pack8<Tin>::ld(A + (size_t)c * NB, x);
-        const double rc = rs[el][c];
+    // columns in batches of U, every load of a batch issued before any is used (so that
+    // U loads per thread are in flight), summed in ascending column order
+    constexpr int U = 16, NBU = NB - NB % U;
+    for (int c0 = 0; c0 < NBU; c0 += U) {
+        typename Pack8<Tin>::Raw raw[U];
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) acc[k] += x[k] * rc;
+        for (int u = 0; u < U; ++u) raw[u] = Pack8<Tin>::ld(A + (size_t)(c0 + u) * NB);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double x[RPT];
+            Pack8<Tin>::expand(raw[u], x);
+            const double rc = rs[el][c0 + u];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) acc[k] += x[k] * rc;
+        }
+    }
+    if (NBU < NB) {
+        typename Pack8<Tin>::Raw raw[NB % U > 0 ? NB % U : 1];
+#pragma unroll
+        for (int u = 0; u < NB - NBU; ++u) raw[u] = Pack8<Tin>::ld(A + (size_t)(NBU + u) * NB);
+#pragma unroll
+        for (int u = 0; u < NB - NBU; ++u) {
+            double x[RPT];
+            Pack8<Tin>::expand(raw[u], x);
+            const double rc = rs[el][NBU + u];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) acc[k] += x[k] * rc;
+        }
     }
     if (sub) {
 #pragma unroll
@@ -382,10 +405,11 @@ fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_
     return FR_OK;
 }
 
-// tile widths (elements per workgroup) of the block apply, per stored precision
+// tile widths (elements per workgroup) of the block apply, per stored precision (FP32 and
+// BF16 both take 4 rows per thread)
 std::vector<int> block_apply_widths(int p) {
     const int nb = 4 * (p + 1) * (p + 1);
-    return {256 / nb, 512 / nb, 1024 / nb};
+    return {256 / nb, 1024 / nb};
 }
 
 struct ApplyArgs {
