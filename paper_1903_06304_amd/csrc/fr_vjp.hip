@@ -1,7 +1,10 @@
 // Vector-Jacobian products J^T w of the FR/CPR residual (reverse / adjoint mode).
 //
 // Gather formulation, three kernels, no atomics (bitwise deterministic):
-//   1. value traces of every element (k_traces of the forward path);
+//   1. value traces of every element (k_traces of the forward path); static meshes whose
+//      elements are all affine skip it: the element kernel forms the neighbour traces
+//      itself from the neighbour's line of states through each face point, with the
+//      neighbour's constant metrics, as the affine residual kernel does;
 //   2. k_vjp_elem: for each element e, recompute the forward stages in LDS and run
 //      them backwards with the adjoint seed w_e: Radau lift and chain-rule divergence
 //      (transposed), point fluxes (hand-derived adjoint), corrected gradient, the
@@ -240,12 +243,14 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
 }
 
 // ---------------------------------------------------------------- kernel 2: element reverse sweep
-template <int P, bool VISC, bool MOV, bool BC>
+template <int P, bool VISC, bool MOV, bool BC, bool AFF = false>
 __global__ void __launch_bounds__((Sz<P>::threads))
 k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, const double* __restrict__ tr,
            double* __restrict__ out, double* __restrict__ aside, OpTab op_in, PhysConst pc, Geo g) {
+    static_assert(!AFF || (!MOV && !BC), "neighbour traces from states: static meshes without boundary faces");
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT, EPB = Sz<P>::EPB;
     constexpr int NTV = VISC ? 10 : 4;
+    constexpr int NG = MOV ? NGSP : G_IJ + 1;   // static meshes have no grid velocity
     __shared__ double s_q[EPB][4][Np];
     constexpr int NA = MOV ? 24 : 20;       // moving meshes add the 4 grid-velocity products
     __shared__ double s_a[EPB][NA][Np];      // scratch fields at solution points
@@ -270,7 +275,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         #pragma unroll
         for (int v = 0; v < 4; ++v) { qs[v] = q[v * EN + id]; s_q[el][v][lt] = qs[v]; }
         #pragma unroll
-        for (int c = 0; c < NGSP; ++c) geo[c] = g.sp[c * EN + id];
+        for (int c = 0; c < NG; ++c) geo[c] = g.sp[c * EN + id];
     }
     __syncthreads();
     if (VISC && isS) {
@@ -310,11 +315,44 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         }
         const int pk = g.nbr[e * 4 + f];
         const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
-        const double* src = tr + ((size_t)(nb * 4 + nf) * NTV) * n;
+        if (AFF) {
+            // the neighbour's line through this face point: its trace and face-normal
+            // derivative; the neighbour traces of (u, v, T) go to slots 4..6 of their
+            // own face point for the tangential derivative below
+            const double* lamn = (nf == 0 || nf == 2) ? op.lamL : op.lamR;
+            const double* dlamn = (nf == 0 || nf == 2) ? op.dlamL : op.dlamR;
+            const size_t nbase = (size_t)nb * Np;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) qp[v] = src[(size_t)v * n + k2];
+            for (int c = 0; c < 6; ++c) gp[c] = 0.0;
+            double ln[4][n];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) gp[c] = VISC ? src[(size_t)(4 + c) * n + k2] : 0.0;
+            for (int b = 0; b < n; ++b) {
+                const int sp = line_pt(n, nf, k2, b);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ln[v][b] = q[v * EN + nbase + sp];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double sacc = 0;
+                for (int b = 0; b < n; ++b) sacc += lamn[b] * ln[v][b];
+                qp[v] = sacc;
+            }
+            if (VISC) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double sacc = 0;
+                    for (int b = 0; b < n; ++b) sacc += dlamn[b] * ln[c + 1][b];
+                    gp[2 * c] = sacc;   // face-normal derivative for now
+                    s_f[el][f * n + k2][4 + c] = qp[c + 1];
+                }
+            }
+        } else {
+            const double* src = tr + ((size_t)(nb * 4 + nf) * NTV) * n;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) qp[v] = src[(size_t)v * n + k2];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) gp[c] = VISC ? src[(size_t)(4 + c) * n + k2] : 0.0;
+        }
         const size_t sid = (size_t)e * NF + lt;
         nx = g.fp[F_NX * FE + sid]; ny = g.fp[F_NY * FE + sid];
         sc = g.fp[F_SC * FE + sid]; cc = g.fp[F_CC * FE + sid];
@@ -330,6 +368,27 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         s_S[el][lt][2] = MOV ? sc * (ugf * nx + vgf * ny) : 0.0;
         s_S[el][lt][3] = sc;
         if (VISC) for (int c = 0; c < 3; ++c) s_f[el][lt][c] = 0.5 * (qp[c + 1] - qm[c + 1]);   // dqh
+    }
+    if (AFF && VISC) {
+        // neighbour gradient trace: the tangential derivative is the 1-D derivative of the
+        // neighbour traces along the face; the chain rule takes the neighbour's constant metrics
+        __syncthreads();
+        if (isF) {
+            const int pk = g.nbr[e * 4 + f];
+            const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
+            const size_t gid = (size_t)nb * Np;
+            const double mxix = g.sp[G_XIX * EN + gid], mxiy = g.sp[G_XIY * EN + gid];
+            const double metx = g.sp[G_ETX * EN + gid], mety = g.sp[G_ETY * EN + gid];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double dtan = 0;
+                for (int m = 0; m < n; ++m) dtan += op.D[k2 * n + m] * s_f[el][f * n + m][4 + c];
+                const double dnor = gp[2 * c];
+                const double dxi = nf < 2 ? dnor : dtan, deta = nf < 2 ? dtan : dnor;
+                gp[2 * c] = mxix * dxi + metx * deta;
+                gp[2 * c + 1] = mxiy * dxi + mety * deta;
+            }
+        }
     }
     __syncthreads();
     // ---- forward: corrected gradient; reverse: volume seeds
@@ -586,7 +645,11 @@ fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, const
                   hipStream_t s) {
     const Geo g = c->geo();
     const int grid = (c->E + Sz<P>::EPB - 1) / Sz<P>::EPB;
-    if (g.bc)
+    if (!trace) {
+        if constexpr (!MOV)
+            hipLaunchKernelGGL((k_vjp_elem<P, VISC, false, false, true>), dim3(grid), dim3(Sz<P>::threads), 0, s,
+                               c->E, q, w, nullptr, out, aside, c->op, c->pc, g);
+    } else if (g.bc)
         hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV, true>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w,
                            trace, out, aside, c->op, c->pc, g);
     else
@@ -607,10 +670,14 @@ fr_status vjp_p(fr_ctx c, const double* q, const double* w, double* out, const d
 }
 
 // Traces, element adjoints and the neighbour gather with the given side buffers: trace
-// and aside each hold E * 4 * 10 * (p+1) doubles.
+// and aside each hold E * 4 * 10 * (p+1) doubles.  Static meshes of affine elements without
+// boundary faces need no trace buffer.
 fr_status vjp_with(fr_ctx c, const double* q, const double* w, double* out, double* trace, double* aside,
                    hipStream_t s) {
-    FR_TRY(launch_traces(c, q, trace, s));
+    if (c->prm.moving == 0 && !c->d_bc && c->all_affine)
+        trace = nullptr;
+    else
+        FR_TRY(launch_traces(c, q, trace, s));
     switch (c->p) {
         case 1: return vjp_p<1>(c, q, w, out, trace, aside, s);
         case 2: return vjp_p<2>(c, q, w, out, trace, aside, s);
