@@ -148,9 +148,13 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
     }
     if (prm->n_elem <= 0 || prm->n_elem >= (1 << 27)) return bad("fr_create: n_elem out of range");
     {
-        // kernels index state arrays with 32-bit offsets: 4 * n_elem * (p+1)^2 < 2^31
+        // kernels index state arrays with 32-bit offsets: 4 * n_elem * (p+1)^2 < 2^31; the fused
+        // kernels form the byte offset of a per-field point index (solution or flux point) in
+        // 32 bits: 8 * n_elem * max((p+1)^2, 4(p+1)) < 2^32
         const long long np1 = prm->order + 1;
         if (4LL * prm->n_elem * np1 * np1 >= (1LL << 31)) return bad("fr_create: state arrays above 2^31 entries");
+        const long long npt = np1 * np1 > 4 * np1 ? np1 * np1 : 4 * np1;
+        if (8LL * prm->n_elem * npt >= (1LL << 32)) return bad("fr_create: flux-point arrays above 2^32 bytes");
     }
     if (!(prm->gamma > 1.0) || !(prm->mach_ref > 0.0) || !(prm->prandtl > 0.0) || !(prm->mach_inf >= 0.0) ||
         !(prm->kappa >= 0.0))

@@ -43,6 +43,9 @@ __device__ __forceinline__ int line_pt(int n, int f, int k, int a) {
     return f < 2 ? a + n * k : k + n * a;
 }
 
+
+template <class T> __device__ __forceinline__ T ldo(const T* base, unsigned idx);
+
 template <int MODE, int K> struct ModeT { using T = Dual<K>; };
 template <int K> struct ModeT<MODE_R, K> { using T = double; };
 template <int K> struct ModeT<MODE_PREP, K> { using T = double; };
@@ -51,14 +54,14 @@ template <int K> struct ModeT<MODE_PREP, K> { using T = double; };
 // unit column seed0 (+k)
 template <class T> struct Seed;
 template <> struct Seed<double> {
-    __device__ static double load(const KArgs& a, const double* q, const double*, unsigned gid, int) { return q[gid]; }
+    __device__ static double load(const KArgs& a, const double* q, const double*, unsigned gid, int) { return ldo(q, gid); }
 };
 template <int K> struct Seed<Dual<K>> {
     __device__ static Dual<K> load(const KArgs& a, const double* q, const double* v, unsigned gid, int col) {
-        Dual<K> r; r.v = q[gid];
+        Dual<K> r; r.v = ldo(q, gid);
         if (v) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) r.d[k] = v[gid];
+            for (int k = 0; k < K; ++k) r.d[k] = ldo(v, gid);
         } else {
 #pragma unroll
             for (int k = 0; k < K; ++k) r.d[k] = (col == a.seed0 + k) ? 1.0 : 0.0;
@@ -71,14 +74,14 @@ template <int K> struct Seed<Dual<K>> {
 // (periodic single-element rows)
 template <class T> struct NbLoad;
 template <> struct NbLoad<double> {
-    __device__ static double load(const KArgs&, const double* q, const double*, unsigned gid, int, bool) { return q[gid]; }
+    __device__ static double load(const KArgs&, const double* q, const double*, unsigned gid, int, bool) { return ldo(q, gid); }
 };
 template <int K> struct NbLoad<Dual<K>> {
     __device__ static Dual<K> load(const KArgs& a, const double* q, const double* v, unsigned gid, int col, bool self) {
-        Dual<K> r; r.v = q[gid];
+        Dual<K> r; r.v = ldo(q, gid);
         if (v) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) r.d[k] = v[gid];
+            for (int k = 0; k < K; ++k) r.d[k] = ldo(v, gid);
         } else {
 #pragma unroll
             for (int k = 0; k < K; ++k) r.d[k] = (self && col == a.seed0 + k) ? 1.0 : 0.0;
@@ -111,6 +114,18 @@ template <class T> __device__ __forceinline__ T* rfl(T* p) {
     return reinterpret_cast<T*>(rfl((unsigned long long)reinterpret_cast<uintptr_t>(p)));
 }
 
+// base[idx] for a workgroup-uniform base: the byte offset is formed in 32 bits, so the load
+// takes the scalar-base + 32-bit vector-offset form instead of per-lane 64-bit address
+// arithmetic.  Needs idx * sizeof(T) < 2^32; every per-field index of a case (solution or flux
+// point, connectivity entry) satisfies it by the size limits that fr_create checks.  The base
+// goes through rfl (both 32-bit halves), so that the compiler does not fold a uniform part of
+// it (a field or variable offset) into the per-lane address.
+template <class T> __device__ __forceinline__ T ldo(const T* base, unsigned idx) {
+    const unsigned off = idx * (unsigned)sizeof(T);
+    const char* b = reinterpret_cast<const char*>(rfl(base));
+    return *(const __attribute__((address_space(1))) T*)(b + off);
+}
+
 // Read-only tables of a launch (case descriptors, case ids, tile prefixes: written once when
 // the solver is set up) are read through the scalar cache: the address is uniform, and a
 // pointer into the constant address space lets the compiler use scalar loads.
@@ -124,6 +139,7 @@ template <class T> __device__ __forceinline__ T sld(const T* p) {
 template <class T> __device__ __forceinline__ T gld(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
 }
+
 
 // the descriptor of a case, in scalar registers (read as 8-byte words)
 __device__ __forceinline__ CaseDev load_case(const CaseDev* p) {
@@ -196,23 +212,23 @@ __device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt
     const unsigned EN = (unsigned)E * Np, FE = (unsigned)E * NF;
     const int ls = lt % Np, lf = lt % NF, f = lf / n, k = lf % n;
     const unsigned id = (unsigned)e * Np + ls, sid = (unsigned)e * NF + lf;
-    lg.xix = gld(g.sp + G_XIX * EN + id); lg.xiy = gld(g.sp + G_XIY * EN + id);
-    lg.etx = gld(g.sp + G_ETX * EN + id); lg.ety = gld(g.sp + G_ETY * EN + id);
-    lg.ij = gld(g.sp + G_IJ * EN + id);
-    lg.ug = MOV ? gld(g.sp + G_UG * EN + id) : 0.0;
-    lg.vg = MOV ? gld(g.sp + G_VG * EN + id) : 0.0;
-    lg.nx = gld(g.fp + F_NX * FE + sid); lg.ny = gld(g.fp + F_NY * FE + sid); lg.sc = gld(g.fp + F_SC * FE + sid);
-    lg.cc = VISC ? gld(g.fp + F_CC * FE + sid) : 0.0;
-    lg.fug = MOV ? gld(g.fp + F_UG * FE + sid) : 0.0;
-    lg.fvg = MOV ? gld(g.fp + F_VG * FE + sid) : 0.0;
+    lg.xix = ldo(g.sp + G_XIX * EN, id); lg.xiy = ldo(g.sp + G_XIY * EN, id);
+    lg.etx = ldo(g.sp + G_ETX * EN, id); lg.ety = ldo(g.sp + G_ETY * EN, id);
+    lg.ij = ldo(g.sp + G_IJ * EN, id);
+    lg.ug = MOV ? ldo(g.sp + G_UG * EN, id) : 0.0;
+    lg.vg = MOV ? ldo(g.sp + G_VG * EN, id) : 0.0;
+    lg.nx = ldo(g.fp + F_NX * FE, sid); lg.ny = ldo(g.fp + F_NY * FE, sid); lg.sc = ldo(g.fp + F_SC * FE, sid);
+    lg.cc = VISC ? ldo(g.fp + F_CC * FE, sid) : 0.0;
+    lg.fug = MOV ? ldo(g.fp + F_UG * FE, sid) : 0.0;
+    lg.fvg = MOV ? ldo(g.fp + F_VG * FE, sid) : 0.0;
     const int pk = f == 0 ? pk4[0] : f == 1 ? pk4[1] : f == 2 ? pk4[2] : pk4[3];
     lg.nb = pk >> 3; lg.nf = (pk >> 1) & 3; lg.k2 = (pk & 1) ? n - 1 - k : k;
     lg.aff = 0; lg.mxix = lg.mxiy = lg.metx = lg.mety = 0.0;
     if (VISC) {
         const unsigned gid = (unsigned)lg.nb * Np;
-        lg.aff = gld(g.aff + lg.nb);
-        lg.mxix = gld(g.sp + G_XIX * EN + gid); lg.mxiy = gld(g.sp + G_XIY * EN + gid);
-        lg.metx = gld(g.sp + G_ETX * EN + gid); lg.mety = gld(g.sp + G_ETY * EN + gid);
+        lg.aff = ldo(g.aff, (unsigned)lg.nb);
+        lg.mxix = ldo(g.sp + G_XIX * EN, gid); lg.mxiy = ldo(g.sp + G_XIY * EN, gid);
+        lg.metx = ldo(g.sp + G_ETX * EN, gid); lg.mety = ldo(g.sp + G_ETY * EN, gid);
     }
 }
 
@@ -278,13 +294,13 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = ldo(g.nbr, (unsigned)(e * 4 + ff));
             if (BC && g.bc) bck = (gld(g.bc + e) >> (2 * ((lt % NF) / n))) & 3;
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             T qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + ls);
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q + vv * EN, v ? v + vv * EN : nullptr, id, vv * Np + ls);
             lane_geo_load<P, VISC, MOV>(g, E, e, lt, pk4, lg);
             if (lt < Np) {
 #pragma unroll
@@ -295,7 +311,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                     const unsigned nid = (unsigned)nb * Np + lt;
 #pragma unroll
                     for (int vv = 0; vv < 4; ++vv)
-                        s_n[NI(el, ff * 4 + vv, lt)] = NbLoad<T>::load(a, q, v, vv * EN + nid, vv * Np + lt, nb == e);
+                        s_n[NI(el, ff * 4 + vv, lt)] = NbLoad<T>::load(a, q + vv * EN, v ? v + vv * EN : nullptr, nid, vv * Np + lt, nb == e);
                 }
             }
         }
@@ -391,8 +407,8 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
                         const int sp = line_pt(n, nf, k2, b);
                         const int is = sp % n, js = sp / n;
                         const unsigned gid = (unsigned)nb * Np + sp;
-                        const double xix = gld(g.sp + G_XIX * EN + gid), xiy = gld(g.sp + G_XIY * EN + gid);
-                        const double etx = gld(g.sp + G_ETX * EN + gid), ety = gld(g.sp + G_ETY * EN + gid);
+                        const double xix = ldo(g.sp + G_XIX * EN, gid), xiy = ldo(g.sp + G_XIY * EN, gid);
+                        const double etx = ldo(g.sp + G_ETX * EN, gid), ety = ldo(g.sp + G_ETY * EN, gid);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             T dxi = cst<T>(0.0), deta = cst<T>(0.0);
@@ -650,12 +666,12 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : gld(g.nbr + e * 4 + ff);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : ldo(g.nbr, (unsigned)(e * 4 + ff));
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             T qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q, v, vv * EN + id, vv * Np + ls);
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q + vv * EN, v ? v + vv * EN : nullptr, id, vv * Np + ls);
             lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
             if (lt < NF) {
                 const unsigned nbase = (unsigned)lg.nb * Np;
@@ -665,7 +681,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
                     const int sp = line_pt(n, lg.nf, lg.k2, b);
 #pragma unroll
                     for (int vv = 0; vv < 4; ++vv)
-                        ln[vv][b] = NbLoad<T>::load(a, q, v, vv * EN + nbase + sp, vv * Np + sp, lg.nb == e);
+                        ln[vv][b] = NbLoad<T>::load(a, q + vv * EN, v ? v + vv * EN : nullptr, nbase + sp, vv * Np + sp, lg.nb == e);
                 }
                 const double* lamn = s_lam[lg.nf & 1];
                 const double* dlamn = s_dlam[lg.nf & 1];
@@ -699,7 +715,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
             if (pkn_tile >= 0 && en < E) {
 #pragma unroll
-                for (int ff = 0; ff < 4; ++ff) pkn[ff] = gld(g.nbr + en * 4 + ff);
+                for (int ff = 0; ff < 4; ++ff) pkn[ff] = ldo(g.nbr, (unsigned)(en * 4 + ff));
             }
         }
         __syncthreads();
@@ -936,13 +952,13 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = gld(g.nbr + e * 4 + ff);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = ldo(g.nbr, (unsigned)(e * 4 + ff));
             if (BC && g.bc) bck = (gld(g.bc + e) >> (2 * ((lt % NF) / n))) & 3;
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             double qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : v[vv * EN + id];
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, id);
             lane_geo_load<P, VISC, MOV>(g, E, e, lt, pk4, lg);
             if (lt < Np) {
 #pragma unroll
@@ -954,7 +970,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
                     for (int vv = 0; vv < 4; ++vv)
                         s_n[NI(el, ff * 4 + vv, lt)] =
-                            BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : v[vv * EN + nid];
+                            BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, nid);
                 }
             }
         }
@@ -1011,8 +1027,8 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             D fn[4], dq[4], qm[4], qp[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                qm[vv] = mk(fpk[(size_t)vv * FE + sid], qmt[vv]);
-                qp[vv] = mk(fpk[(size_t)(4 + vv) * FE + sid], qpt[vv]);
+                qm[vv] = mk(ldo(fpk + (size_t)vv * FE, sid), qmt[vv]);
+                qp[vv] = mk(ldo(fpk + (size_t)(4 + vv) * FE, sid), qpt[vv]);
             }
             fr_common_inviscid<D>(pc, qm, qp, nx, ny, ugf, vgf, fn, dq);
             if (VISC) {
@@ -1023,7 +1039,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                     double am = 0.0;
 #pragma unroll
                     for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
-                    gm[c] = mk(fpk[(size_t)(8 + c) * FE + sid], am);
+                    gm[c] = mk(ldo(fpk + (size_t)(8 + c) * FE, sid), am);
                     gmt[c] = am;
                 }
                 double gpt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -1048,8 +1064,8 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                         const int sp = line_pt(n, nf, k2, b);
                         const int is = sp % n, js = sp / n;
                         const unsigned gid = (unsigned)lg.nb * Np + sp;
-                        const double xix = gld(g.sp + G_XIX * EN + gid), xiy = gld(g.sp + G_XIY * EN + gid);
-                        const double etx = gld(g.sp + G_ETX * EN + gid), ety = gld(g.sp + G_ETY * EN + gid);
+                        const double xix = ldo(g.sp + G_XIX * EN, gid), xiy = ldo(g.sp + G_XIY * EN, gid);
+                        const double etx = ldo(g.sp + G_ETX * EN, gid), ety = ldo(g.sp + G_ETY * EN, gid);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             double dxi = 0.0, deta = 0.0;
@@ -1090,7 +1106,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             D qs[4], gu[2], gv[2], gT[2];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                qv[vv] = spk[(size_t)vv * EN + id];
+                qv[vv] = ldo(spk + (size_t)vv * EN, id);
                 qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
             }
             if (VISC) {
@@ -1110,9 +1126,9 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                 }
 #pragma unroll
                 for (int d = 0; d < 2; ++d) {
-                    gu[d] = mk(spk[(size_t)(4 + d) * EN + id], gt[d]);
-                    gv[d] = mk(spk[(size_t)(6 + d) * EN + id], gt[2 + d]);
-                    gT[d] = mk(spk[(size_t)(8 + d) * EN + id], gt[4 + d]);
+                    gu[d] = mk(ldo(spk + (size_t)(4 + d) * EN, id), gt[d]);
+                    gv[d] = mk(ldo(spk + (size_t)(6 + d) * EN, id), gt[2 + d]);
+                    gT[d] = mk(ldo(spk + (size_t)(8 + d) * EN, id), gt[4 + d]);
                 }
             }
             D fl[4], gl[4], qc[4];
@@ -1255,12 +1271,12 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
         if (act) {
             int pk4[4];
 #pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : gld(g.nbr + e * 4 + ff);
+            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : ldo(g.nbr, (unsigned)(e * 4 + ff));
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             double qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : v[vv * EN + id];
+            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, id);
             lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
             if (lt < NF) {
                 const unsigned nbase = (unsigned)lg.nb * Np;
@@ -1270,7 +1286,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                     const int sp = line_pt(n, lg.nf, lg.k2, b);
 #pragma unroll
                     for (int vv = 0; vv < 4; ++vv)
-                        ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == a.seed0) ? 1.0 : 0.0) : v[vv * EN + nbase + sp];
+                        ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, nbase + sp);
                 }
                 const double* lamn = s_lam[lg.nf & 1];
                 const double* dlamn = s_dlam[lg.nf & 1];
@@ -1304,7 +1320,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
             if (pkn_tile >= 0 && en < E) {
 #pragma unroll
-                for (int ff = 0; ff < 4; ++ff) pkn[ff] = gld(g.nbr + en * 4 + ff);
+                for (int ff = 0; ff < 4; ++ff) pkn[ff] = ldo(g.nbr, (unsigned)(en * 4 + ff));
             }
         }
         __syncthreads();
@@ -1336,8 +1352,8 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                 double acc = 0.0;
 #pragma unroll
                 for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
-                qm[vv] = mk(fpk[(size_t)vv * FE + sid], acc);
-                qp[vv] = mk(fpk[(size_t)(4 + vv) * FE + sid], qpt[vv]);
+                qm[vv] = mk(ldo(fpk + (size_t)vv * FE, sid), acc);
+                qp[vv] = mk(ldo(fpk + (size_t)(4 + vv) * FE, sid), qpt[vv]);
             }
             fr_common_inviscid<D>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
             if (VISC) {
@@ -1347,7 +1363,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                     double acc = 0.0;
 #pragma unroll
                     for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
-                    gm[c] = mk(fpk[(size_t)(8 + c) * FE + sid], acc);
+                    gm[c] = mk(ldo(fpk + (size_t)(8 + c) * FE, sid), acc);
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -1376,7 +1392,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             D qs[4], gu[2], gv[2], gT[2];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                qv[vv] = spk[(size_t)vv * EN + id];
+                qv[vv] = ldo(spk + (size_t)vv * EN, id);
                 qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
             }
             if (VISC) {
@@ -1394,9 +1410,9 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                 }
 #pragma unroll
                 for (int d = 0; d < 2; ++d) {
-                    gu[d] = mk(spk[(size_t)(4 + d) * EN + id], gt[d]);
-                    gv[d] = mk(spk[(size_t)(6 + d) * EN + id], gt[2 + d]);
-                    gT[d] = mk(spk[(size_t)(8 + d) * EN + id], gt[4 + d]);
+                    gu[d] = mk(ldo(spk + (size_t)(4 + d) * EN, id), gt[d]);
+                    gv[d] = mk(ldo(spk + (size_t)(6 + d) * EN, id), gt[2 + d]);
+                    gT[d] = mk(ldo(spk + (size_t)(8 + d) * EN, id), gt[4 + d]);
                 }
             }
             D fl[4], gl[4], qc[4];
