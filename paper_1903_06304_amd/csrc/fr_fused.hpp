@@ -207,7 +207,7 @@ struct LaneGeo {
 };
 
 template <int P, bool VISC, bool MOV>
-__device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt, const int (&pk4)[4], LaneGeo& lg) {
+__device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt, int pk, LaneGeo& lg) {
     constexpr int n = P + 1, Np = n * n, NF = 4 * n;
     const unsigned EN = (unsigned)E * Np, FE = (unsigned)E * NF;
     const int ls = lt % Np, lf = lt % NF, f = lf / n, k = lf % n;
@@ -221,7 +221,6 @@ __device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt
     lg.cc = VISC ? ldo(g.fp + F_CC * FE, sid) : 0.0;
     lg.fug = MOV ? ldo(g.fp + F_UG * FE, sid) : 0.0;
     lg.fvg = MOV ? ldo(g.fp + F_VG * FE, sid) : 0.0;
-    const int pk = f == 0 ? pk4[0] : f == 1 ? pk4[1] : f == 2 ? pk4[2] : pk4[3];
     lg.nb = pk >> 3; lg.nf = (pk >> 1) & 3; lg.k2 = (pk & 1) ? n - 1 - k : k;
     lg.aff = 0; lg.mxix = lg.mxiy = lg.metx = lg.mety = 0.0;
     if (VISC) {
@@ -301,7 +300,9 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
             T qo[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q + vv * EN, v ? v + vv * EN : nullptr, id, vv * Np + ls);
-            lane_geo_load<P, VISC, MOV>(g, E, e, lt, pk4, lg);
+            // the lane's own face entry is loaded on its own: selecting it from pk4 by the lane's
+            // face makes the compiler index a stack copy of pk4 (scratch memory)
+            lane_geo_load<P, VISC, MOV>(g, E, e, lt, ldo(g.nbr, (unsigned)(e * 4 + (lt % NF) / n)), lg);
             if (lt < Np) {
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
@@ -642,7 +643,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
     int tile, tend, tstride;
     tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
     // connectivity of the next tile of this workgroup, requested one tile ahead (persistent grids)
-    int pkn[4] = {0, 0, 0, 0};
+    int pkn = 0;
     int pkn_tile = -1;
     for (; tile < tend; tile += tstride) {
         const int lo = find_member(ga, tile);
@@ -664,15 +665,13 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         T qp[4], dnor[3];
         const bool pre = pkn_tile == tile;
         if (act) {
-            int pk4[4];
-#pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : ldo(g.nbr, (unsigned)(e * 4 + ff));
+            const int pk = pre ? pkn : ldo(g.nbr, (unsigned)(e * 4 + f));
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             T qo[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qo[vv] = Seed<T>::load(a, q + vv * EN, v ? v + vv * EN : nullptr, id, vv * Np + ls);
-            lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
+            lane_geo_load<P, VISC, false>(g, E, e, lt, pk, lg);
             if (lt < NF) {
                 const unsigned nbase = (unsigned)lg.nb * Np;
                 T ln[4][n];
@@ -714,8 +713,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
             const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
             if (pkn_tile >= 0 && en < E) {
-#pragma unroll
-                for (int ff = 0; ff < 4; ++ff) pkn[ff] = ldo(g.nbr, (unsigned)(en * 4 + ff));
+                pkn = ldo(g.nbr, (unsigned)(en * 4 + f));
             }
         }
         __syncthreads();
@@ -959,7 +957,9 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             double qo[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, id);
-            lane_geo_load<P, VISC, MOV>(g, E, e, lt, pk4, lg);
+            // the lane's own face entry is loaded on its own: selecting it from pk4 by the lane's
+            // face makes the compiler index a stack copy of pk4 (scratch memory)
+            lane_geo_load<P, VISC, MOV>(g, E, e, lt, ldo(g.nbr, (unsigned)(e * 4 + (lt % NF) / n)), lg);
             if (lt < Np) {
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
@@ -1247,7 +1247,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
     const int f = (lt % NF) / n, k = lt % n;
     int tile, tend, tstride;
     tile_range(ga.ntiles, ga.xcd, tile, tend, tstride);
-    int pkn[4] = {0, 0, 0, 0};   // connectivity of the next tile, requested one tile ahead
+    int pkn = 0;   // connectivity of the next tile, requested one tile ahead
     int pkn_tile = -1;
     for (; tile < tend; tile += tstride) {
         const int lo = find_member(ga, tile);
@@ -1269,15 +1269,13 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
         double qpt[4], dnort[3];
         const bool pre = pkn_tile == tile;
         if (act) {
-            int pk4[4];
-#pragma unroll
-            for (int ff = 0; ff < 4; ++ff) pk4[ff] = pre ? pkn[ff] : ldo(g.nbr, (unsigned)(e * 4 + ff));
+            const int pk = pre ? pkn : ldo(g.nbr, (unsigned)(e * 4 + f));
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
             double qo[4];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, id);
-            lane_geo_load<P, VISC, false>(g, E, e, lt, pk4, lg);
+            lane_geo_load<P, VISC, false>(g, E, e, lt, pk, lg);
             if (lt < NF) {
                 const unsigned nbase = (unsigned)lg.nb * Np;
                 double ln[4][n];
@@ -1319,8 +1317,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
             const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
             if (pkn_tile >= 0 && en < E) {
-#pragma unroll
-                for (int ff = 0; ff < 4; ++ff) pkn[ff] = ldo(g.nbr, (unsigned)(en * 4 + ff));
+                pkn = ldo(g.nbr, (unsigned)(en * 4 + f));
             }
         }
         __syncthreads();

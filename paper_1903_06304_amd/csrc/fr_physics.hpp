@@ -192,17 +192,21 @@ FR_DEV void fr_common_viscous(const PhysConst& c, const T* dq, const T& qcu, con
 //              temperature gradient mirrored (its average has no normal part).
 // The mirror of a gradient g is g - 2 (g.n) n; that of the velocity gradient
 // G (G[a][b] = d u_a / d x_b) is Rm G Rm with Rm = I - 2 n n^T.
+// qinf (4 doubles) is read whatever the kind, so it must always be readable (every context
+// holds one); the far-field values are then selected like the other kinds' values, which keeps
+// the compiler from turning the selection into a load through a stack copy of the candidates.
 template <class T>
 FR_DEV void fr_bc_state(int kind, const double* qinf, const T* qm, double nx, double ny, double wx, double wy,
                         T* qp) {
+    const double qi0 = qinf[0], qi1 = qinf[1], qi2 = qinf[2], qi3 = qinf[3];
     const bool far = kind == 1, slip = kind == 2;
     const T urn = (qm[1] - wx) * nx + (qm[2] - wy) * ny;
     const T s1 = qm[1] - (2.0 * nx) * urn, s2 = qm[2] - (2.0 * ny) * urn;   // slip
     const T w1 = 2.0 * wx - qm[1], w2 = 2.0 * wy - qm[2];                   // no-slip
-    qp[0] = far ? cst<T>(qinf[0]) : qm[0];
-    qp[1] = far ? cst<T>(qinf[1]) : slip ? s1 : w1;
-    qp[2] = far ? cst<T>(qinf[2]) : slip ? s2 : w2;
-    qp[3] = far ? cst<T>(qinf[3]) : qm[3];
+    qp[0] = far ? cst<T>(qi0) : qm[0];
+    qp[1] = far ? cst<T>(qi1) : slip ? s1 : w1;
+    qp[2] = far ? cst<T>(qi2) : slip ? s2 : w2;
+    qp[3] = far ? cst<T>(qi3) : qm[3];
 }
 
 // The same map on a tangent (its linear part; the wall velocity and q^inf drop out).
