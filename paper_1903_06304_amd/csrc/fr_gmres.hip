@@ -471,6 +471,7 @@ void gmres_release(Solver& sv) {
 
 // GMRES on every case still in the Newton iteration: A dq = b with b = WB, dq = WDQ
 fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
+    PhaseRange range("lmfr: GMRES solve");
     const GsLayout L(m);
     const Ctl k = ctl(sv);
     hipLaunchKernelGGL(k_gm_start, dim3(cgrid(sv)), dim3(64), 0, s, k, max_it);
@@ -541,6 +542,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
 // paper Sec. 3.2, Eq. (unsteady_pre_discretized_3): the iterate and Q^n, Q^{n-1} are in
 // the solver's vectors (WQN, WQNM1 hold the states on entry; converted here).
 fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
+    PhaseRange range("lmfr: BDF2 step (Newton loop)");
     const Ctl k = ctl(sv);
     const GsLayout L(o->krylov);
     hipLaunchKernelGGL(k_step_init, dim3(cgrid(sv)), dim3(64), 0, s, k);
@@ -549,6 +551,7 @@ fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
     FR_TRY(launch_cons_nm1(sv, wv(sv, WQNM1), s));
     double* hs = sv.h_pin;
     for (int it = 0;; ++it) {
+        PhaseRange it_range("lmfr: Newton iteration");
         if (sv.reject_on) {
             hipLaunchKernelGGL(k_retry, dim3(cgrid(sv)), dim3(64), 0, s, k);
             FR_HIP(hipGetLastError());
@@ -576,6 +579,7 @@ fr_status solver_newton(Solver& sv, const fr_step_opts* o, hipStream_t s) {
         for (int c = 0; c < sv.n; ++c) any |= hs[(size_t)c * SUM_STRIDE + S_NDONE] == 0.0;
         if (!any) break;
         if (it % o->jac_lag == 0) {
+            PhaseRange refresh_range("lmfr: preconditioner refresh (enqueue)");
             KArgs b{};
             b.cstep = sv.d_step; b.flags = sv.d_gi; b.flag = GI_NDONE;
             b.fpack = sv.d_fpack; b.spack = sv.d_spack;   // written by this iteration's residual pass

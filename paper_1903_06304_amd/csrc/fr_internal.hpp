@@ -5,8 +5,21 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/lmfr.h"
 #include "fr_physics.hpp"
+
+// Named host-side range (roctx) over a solver phase, shown by rocprofv3 --marker-trace.  The
+// ranges time the host thread: they bracket GPU work where the phase ends with a stream
+// synchronisation (a BDF2 step, a Newton iteration, a GMRES solve, a steady solve, the
+// autotuner); elsewhere they cover the enqueueing only.
+struct PhaseRange {
+    explicit PhaseRange(const char* name) { roctxRangePushA(name); }
+    ~PhaseRange() { roctxRangePop(); }
+    PhaseRange(const PhaseRange&) = delete;
+    PhaseRange& operator=(const PhaseRange&) = delete;
+};
 
 #define FR_MAXN 5   // up to p = 4
 

@@ -373,6 +373,7 @@ GroupArgs group_args(const Solver& sv, const Group& gr, int epb) {
 
 // ----------------------------------------------------------------------------- launchers
 fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s) {
+    PhaseRange range("lmfr: block assembly (enqueue)");
     // one seeded column of every element's block per launch and group; with the
     // linearisation packs of q in base (fpack/spack), tangents only
     KArgs a = base;
@@ -399,6 +400,7 @@ static fr_status invert_all(Solver& sv, int prec, const int* flags, hipStream_t 
 }
 
 fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s) {
+    PhaseRange range("lmfr: block inversion (enqueue)");
     if (prec < FR_FP64 || prec > FR_BF16) { fr_set_error("unknown precision"); return FR_EINVAL; }
     FR_TRY(invert_all(sv, prec, flags, s));
     sv.inv_prec = prec;

@@ -329,6 +329,7 @@ fr_status solver_step(Solver& sv, double* const* q, const double* const* q_nm1, 
 // pseudo-time step under SER control, Eq. (SER), updated per case on the device.
 fr_status solver_steady(Solver& sv, double* const* q, const fr_steady_opts* o, fr_steady_stats* stats,
                         hipStream_t caller) {
+    PhaseRange range("lmfr: steady solve");
     const int n = sv.n;
     FR_TRY(check_cases(sv, q));
     for (int c = 0; c < n; ++c) {
@@ -436,6 +437,7 @@ std::string tune_key(const std::string& arch, const Solver& sv, const Group& g, 
 }  // namespace
 
 fr_status solver_autotune(Solver& sv, const char* cache_path, hipStream_t s) {
+    PhaseRange range("lmfr: autotune");
     const std::string arch = arch_name(sv.device);
     // cached choices
     std::vector<std::pair<std::string, Tune>> cache;

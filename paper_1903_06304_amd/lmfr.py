@@ -432,3 +432,51 @@ class FRResidual(torch.autograd.Function):
 
 def residual(q, ctx_fr):
     return FRResidual.apply(q, ctx_fr)
+
+
+# ----------------------------------------------------------------------------- checkpoint / resume
+CHECKPOINT_FORMAT = "lmfr-bdf2-state-1"
+
+
+def save_checkpoint(path, q, q_nm1, t, dt, step=0):
+    """Write the state a BDF2 march needs to continue (paper Sec. 3.2: the step from t to t + dt
+    reads q^n and q^{n-1}) to a safetensors file: the states as float64 host copies, and t, dt and
+    the step count as metadata (exact decimal round trip).
+
+    q, q_nm1: one context's state tensors, or lists of them for a batch; q_nm1 may be None (the
+    next step is then a BDF1 start).  A step also depends on the geometry at t + dt and on the
+    step options, which the caller sets again when it resumes; the preconditioner is refreshed at
+    the first Newton iteration of every step, so no solver state has to be saved."""
+    from safetensors.torch import save_file
+    many = isinstance(q, (list, tuple))
+    qs = list(q) if many else [q]
+    if q_nm1 is None:
+        ms = [None] * len(qs)
+    else:
+        ms = list(q_nm1) if many else [q_nm1]
+    if len(ms) != len(qs):
+        raise ValueError("q and q_nm1 hold different numbers of states")
+    tensors = {}
+    for i, (a, b) in enumerate(zip(qs, ms)):
+        tensors[f"q.{i}"] = a.detach().to("cpu", torch.float64).contiguous()
+        if b is not None:
+            tensors[f"q_nm1.{i}"] = b.detach().to("cpu", torch.float64).contiguous()
+    meta = {"format": CHECKPOINT_FORMAT, "t": repr(float(t)), "dt": repr(float(dt)), "step": str(int(step)),
+            "count": str(len(qs)), "batch": "1" if many else "0", "has_nm1": "0" if q_nm1 is None else "1"}
+    save_file(tensors, str(path), metadata=meta)
+
+
+def load_checkpoint(path, device="cuda"):
+    """Read what save_checkpoint wrote: a dict with q, q_nm1 (tensors on `device`, lists for a
+    batch, q_nm1 None for a BDF1 start), t, dt and step."""
+    from safetensors import safe_open
+    with safe_open(str(path), framework="pt", device="cpu") as f:
+        meta = f.metadata() or {}
+        if meta.get("format") != CHECKPOINT_FORMAT:
+            raise ValueError(f"{path}: not an lmfr BDF2 checkpoint")
+        n = int(meta["count"])
+        qs = [f.get_tensor(f"q.{i}").to(device) for i in range(n)]
+        ms = [f.get_tensor(f"q_nm1.{i}").to(device) for i in range(n)] if meta["has_nm1"] == "1" else None
+    batch = meta["batch"] == "1"
+    return {"q": qs if batch else qs[0], "q_nm1": (ms if batch else ms[0]) if ms is not None else None,
+            "t": float(meta["t"]), "dt": float(meta["dt"]), "step": int(meta["step"])}

@@ -143,3 +143,24 @@ def test_create_rejects_sizes_beyond_32_bit_offsets():
     st, h = _create(prm, nbr, nbf)
     assert st == lmfr.FR_EINVAL and not h.value
     assert b"2^31" in _lib().fr_last_error()
+
+
+def test_library_marks_solver_phases_with_roctx_ranges():
+    """The solver phases (BDF2 step, Newton iteration, GMRES solve, refresh, steady solve,
+    autotuner) push named roctx ranges: the library imports the range calls from ROCm's
+    roctx library, so rocprofv3 --marker-trace shows them."""
+    import shutil
+    import subprocess
+    if not os.path.exists(lmfr.LIB_PATH):
+        pytest.skip("liblmfr.so not built")
+    if shutil.which("readelf") is None:
+        pytest.skip("readelf missing")
+    dyn = subprocess.run(["readelf", "-d", lmfr.LIB_PATH], capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in dyn
+    syms = subprocess.run(["readelf", "--dyn-syms", "-W", lmfr.LIB_PATH], capture_output=True, text=True).stdout
+    undefined = {ln.split()[-1].split("@")[0] for ln in syms.splitlines() if " UND " in ln}
+    assert {"roctxRangePushA", "roctxRangePop"} <= undefined
+    strings = open(lmfr.LIB_PATH, "rb").read()
+    for name in (b"lmfr: BDF2 step (Newton loop)", b"lmfr: Newton iteration", b"lmfr: GMRES solve",
+                 b"lmfr: steady solve", b"lmfr: autotune"):
+        assert name in strings
