@@ -132,7 +132,9 @@ typedef struct {
  * has an fr_bc code in h_nbr (its h_nbr_face and h_flip entries are ignored).  A mesh
  * with far-field faces needs fr_set_farfield before any evaluation.
  * Returns FR_EUNSUPPORTED for order or geom_order outside 1..4, FR_EINVAL for a
- * table that is out of range or not symmetric. */
+ * table that is out of range or not symmetric, and for meshes past the size limits of
+ * the kernels' 32-bit offsets: n_elem < 2^27, 4 n_elem (p+1)^2 < 2^31 state entries and
+ * 8 n_elem max((p+1)^2, 4(p+1)) < 2^32 bytes per solution- or flux-point field. */
 fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const int32_t* h_nbr_face,
                     const int8_t* h_flip, fr_ctx* out);
 
