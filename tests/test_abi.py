@@ -143,6 +143,13 @@ def test_create_rejects_sizes_beyond_32_bit_offsets():
     st, h = _create(prm, nbr, nbf)
     assert st == lmfr.FR_EINVAL and not h.value
     assert b"2^31" in _lib().fr_last_error()
+    # p = 1: 4 flux points per face pair outnumber the 4 solution points; 8 E * 8 >= 2^32 bytes
+    # per flux-point field would overflow the fused kernels' 32-bit byte offsets (the check
+    # comes before the tables are read, so the small table is never indexed past its end)
+    prm = _params(order=1, E=1 << 26)
+    st, h = _create(prm, nbr, nbf)
+    assert st == lmfr.FR_EINVAL and not h.value
+    assert b"2^32" in _lib().fr_last_error()
 
 
 def test_library_marks_solver_phases_with_roctx_ranges():
