@@ -107,13 +107,29 @@ __device__ void normal_flux_rev(const PhysConst& c, const double* q, double nx, 
     aq[0] += a_p; aq[1] += a_u; aq[2] += a_v; aq[3] += a_T;
 }
 
+// The adjoint of the BR2 common gradient's viscous flux with respect to either side's
+// gradient trace, (u_x, u_y, v_x, v_y, T_x, T_y), from three face values: the adjoints of the
+// normal stress components t_n = tau . n (a_tnx, a_tny) and of the heat-flux scale (a_T, with
+// a_(T_x, T_y) = a_T n).  Each side's gradient trace enters the common gradient with weight 1/2.
+__device__ __forceinline__ void grad_trace_adjoint(const PhysConst& c, double a_tnx, double a_tny, double a_T,
+                                                   double nx, double ny, double* ag) {
+    const double a_txx = a_tnx * nx, a_txy = a_tnx * ny + a_tny * nx, a_tyy = a_tny * ny;
+    ag[0] = 0.5 * (c.mu_re * ((4.0 / 3.0) * a_txx - (2.0 / 3.0) * a_tyy));
+    ag[1] = 0.5 * (c.mu_re * a_txy);
+    ag[2] = 0.5 * (c.mu_re * a_txy);
+    ag[3] = 0.5 * (c.mu_re * ((4.0 / 3.0) * a_tyy - (2.0 / 3.0) * a_txx));
+    ag[4] = 0.5 * (a_T * nx);
+    ag[5] = 0.5 * (a_T * ny);
+}
+
 // adjoint of the common flux (fr_common_flux): seeds afn[4] on fn and adqh[3] on dqh;
-// outputs the adjoints of qm, qp (4 each) and gm, gp (6 each)
+// outputs the adjoints of qm, qp (4 each) and gm, gp (6 each), and (ag3, when not null)
+// the three face values that determine gm's and gp's adjoints (grad_trace_adjoint)
 template <bool VISC>
 __device__ void common_flux_rev(const PhysConst& c, const double* qm, const double* qp, const double* gm,
                                 const double* gp, double nx, double ny, double cc,
                                 double ug, double vg, const double* afn, const double* adqh, double* aqm,
-                                double* aqp, double* agm, double* agp) {
+                                double* aqp, double* agm, double* agp, double* ag3 = nullptr) {
     const double vgn = ug * nx + vg * ny;
     double qb[4], dq[4];
     for (int r = 0; r < 4; ++r) { qb[r] = 0.5 * (qm[r] + qp[r]); dq[r] = qp[r] - qm[r]; }
@@ -174,6 +190,7 @@ __device__ void common_flux_rev(const PhysConst& c, const double* qm, const doub
         const double a_uy = c.mu_re * a_txy, a_vx = c.mu_re * a_txy;
         const double ag6[6] = {a_ux, a_uy, a_vx, a_vy, a_Tx, a_Ty};
         for (int r = 0; r < 6; ++r) { agm[r] = 0.5 * ag6[r]; agp[r] = 0.5 * ag6[r]; }
+        if (ag3) { ag3[0] = a_tnx; ag3[1] = a_tny; ag3[2] = -afn[3] * c.kc_re; }
         a_dq[1] += cc * (nx * a_ux + ny * a_uy);
         a_dq[2] += cc * (nx * a_vx + ny * a_vy);
         a_dq[3] += cc * (nx * a_Tx + ny * a_Ty);
@@ -521,8 +538,9 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         double afn[4];
         #pragma unroll
         for (int v = 0; v < 4; ++v) afn[v] = sc * aDF[v];
-        double aqm[4], aqp[4], agm[6], agp[6];
-        common_flux_rev<VISC>(pc, qm, qp, gm, gp, nx, ny, cc, ugf, vgf, afn, adqh, aqm, aqp, agm, agp);
+        double aqm[4], aqp[4], agm[6], agp[6], ag3[3] = {0.0, 0.0, 0.0};
+        common_flux_rev<VISC>(pc, qm, qp, gm, gp, nx, ny, cc, ugf, vgf, afn, adqh, aqm, aqp, agm, agp,
+                              AFF ? ag3 : nullptr);
         if (BC && bck) {
             // q^+ and g^+ depend on the own traces through symmetric linear maps: their
             // adjoints go back to the own side, and nothing to a neighbour
@@ -536,10 +554,20 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
                 for (int c = 0; c < 6; ++c) { agm[c] += t[c]; agp[c] = 0.0; }
             }
         }
-        double* dst = aside + ((size_t)(e * 4 + f) * NTV) * n;
-        #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[(size_t)v * n + k] = aqp[v];
-        if (VISC) for (int c = 0; c < 6; ++c) dst[(size_t)(4 + c) * n + k] = agp[c];
+        if (AFF) {
+            // the neighbour's gradient-trace adjoint travels as the three face values it is made
+            // of; the neighbour rebuilds it with its own face normal (minus this side's)
+            constexpr int NTA = VISC ? 7 : 4;
+            double* dst = aside + ((size_t)(e * 4 + f) * NTA) * n;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[(size_t)v * n + k] = aqp[v];
+            if (VISC) for (int c = 0; c < 3; ++c) dst[(size_t)(4 + c) * n + k] = ag3[c];
+        } else {
+            double* dst = aside + ((size_t)(e * 4 + f) * NTV) * n;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[(size_t)v * n + k] = aqp[v];
+            if (VISC) for (int c = 0; c < 6; ++c) dst[(size_t)(4 + c) * n + k] = agp[c];
+        }
         #pragma unroll
         for (int v = 0; v < 4; ++v) s_f[el][lt][v] = aqm[v];
         if (VISC) for (int c = 0; c < 6; ++c) s_f[el][lt][4 + c] = agm[c];
@@ -581,11 +609,14 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
 }
 
 // ---------------------------------------------------------------- kernel 3: gather from neighbours
-template <int P, bool VISC>
+// AFF: static affine meshes without boundary faces; the side buffer holds the compressed face
+// values (aqp, then a_tnx, a_tny, a_T), and the element's constant metrics are read once.
+template <int P, bool VISC, bool AFF = false>
 __global__ void __launch_bounds__((Sz<P>::threads))
-k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, OpTab op_in, Geo g) {
+k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, OpTab op_in, PhysConst pc,
+             Geo g) {
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT, EPB = Sz<P>::EPB;
-    constexpr int NTV = VISC ? 10 : 4;
+    constexpr int NTV = VISC ? (AFF ? 7 : 10) : 4;
     __shared__ double s_f[EPB][NF][10];
     __shared__ double s_d[EPB][6][Np];
     __shared__ OpTab sop;
@@ -603,7 +634,19 @@ k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, 
         const int pk = g.nbr[e * 4 + f];
         const int nb = pk >> 3, nf = (pk >> 1) & 3, k2 = (pk & 1) ? n - 1 - k : k;
         const double* src = aside + ((size_t)(nb * 4 + nf) * NTV) * n;
-        for (int v = 0; v < NTV; ++v) s_f[el][lt][v] = src[(size_t)v * n + k2];
+        if (AFF && VISC) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s_f[el][lt][v] = src[(size_t)v * n + k2];
+            const size_t sid = (size_t)e * NF + lt, FE = (size_t)E * NF;
+            const double nx = -g.fp[F_NX * FE + sid], ny = -g.fp[F_NY * FE + sid];   // the neighbour's normal
+            double ag[6];
+            grad_trace_adjoint(pc, src[(size_t)4 * n + k2], src[(size_t)5 * n + k2], src[(size_t)6 * n + k2], nx, ny,
+                               ag);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) s_f[el][lt][4 + c] = ag[c];
+        } else {
+            for (int v = 0; v < NTV; ++v) s_f[el][lt][v] = src[(size_t)v * n + k2];
+        }
     }
     __syncthreads();
     double aq[4] = {0, 0, 0, 0}, aG[6] = {0, 0, 0, 0, 0, 0};
@@ -616,7 +659,7 @@ k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, 
             if (VISC) for (int c = 0; c < 6; ++c) aG[c] += lams[t] * s_f[el][fps[t]][4 + c];
         }
         if (VISC) {
-            const size_t id = (size_t)e * Np + lt;
+            const size_t id = (size_t)e * Np + (AFF ? 0 : lt);   // affine: the element's constant metrics
             geo[0] = g.sp[G_XIX * EN + id]; geo[1] = g.sp[G_XIY * EN + id];
             geo[2] = g.sp[G_ETX * EN + id]; geo[3] = g.sp[G_ETY * EN + id];
             for (int c = 0; c < 3; ++c) {
@@ -656,7 +699,12 @@ fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, const
         hipLaunchKernelGGL((k_vjp_elem<P, VISC, MOV, false>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, q, w,
                            trace, out, aside, c->op, c->pc, g);
     FR_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_vjp_gather<P, VISC>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, aside, out, c->op, g);
+    if (!trace)
+        hipLaunchKernelGGL((k_vjp_gather<P, VISC, true>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, aside, out,
+                           c->op, c->pc, g);
+    else
+        hipLaunchKernelGGL((k_vjp_gather<P, VISC>), dim3(grid), dim3(Sz<P>::threads), 0, s, c->E, aside, out, c->op,
+                           c->pc, g);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }
