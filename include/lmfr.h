@@ -245,7 +245,9 @@ fr_status fr_steady_solve(fr_ctx ctx, double* q, const fr_steady_opts* opts, fr_
 /* Options: "keep_blocks" (0/1: keep the FP64 blocks for fr_get_blocks), "graph" (0/1:
  * replay each GMRES restart cycle from a captured hipGraph, default 1), "gram_schmidt"
  * (1: classical Gram-Schmidt, one orthogonalisation pass per Arnoldi step, the default;
- * 2: with one re-orthogonalisation pass), "operator_packs" (0/1: fr_bdf_operator first
+ * 2: with one re-orthogonalisation pass), "fused_gram_schmidt" (0/1, default 1: with two
+ * passes, the first pass's update and the second pass's dot products share one read of
+ * the basis, up to 32 basis vectors; same results bit for bit), "operator_packs" (0/1: fr_bdf_operator first
  * stores the values its nonlinear point functions need at q, then applies the operator
  * on tangents only -- the form the BDF2 step uses inside GMRES; fr_block_jacobi_factor
  * assembles its block columns the same way; same results to rounding), "preconditioner"

@@ -282,6 +282,7 @@ static fr_status solver_option(Solver& sv, const char* name, int64_t value) {
         gmres_release(sv);
         return FR_OK;
     }
+    if (!strcmp(name, "fused_gram_schmidt")) { sv.fuse_gs = value != 0; gmres_release(sv); return FR_OK; }
     if (!strcmp(name, "preconditioner")) {
         if (value != 0 && value != 1) return bad("preconditioner must be 0 (block Jacobi) or 1 (block Gauss-Seidel)");
         if (value == 1) {   // the sweeps apply the Newton operator through the linearisation packs

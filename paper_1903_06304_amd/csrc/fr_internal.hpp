@@ -261,6 +261,7 @@ struct Solver {
     int graph_m = 0, graph_prec = -1, graph_passes = 0, graph_precond = -1;
     std::vector<char> graph_aff;           // per group: all members affine when the cycle was captured
     int gs_passes = 1;                     // classical Gram-Schmidt passes per Arnoldi step (1 or 2)
+    bool fuse_gs = true;                   // two passes: update and re-orthogonalising dots in one read
     size_t N(int c) const { return (size_t)4 * cs[c]->E * cs[c]->Np; }
 };
 

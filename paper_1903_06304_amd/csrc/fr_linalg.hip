@@ -269,6 +269,64 @@ __global__ void __launch_bounds__(RED_THREADS) k_update(ChunkArgs ca, const doub
     }
 }
 
+// The re-orthogonalising pass of classical Gram-Schmidt applied twice, in one read of the basis:
+// w_out = w_in - sum_{i < nv} coef_c[i] V_i (as k_update) and the partial dots V_k . w_out,
+// k < nv, of each chunk (as k_dots8 on w_out), from the basis entries already loaded for the
+// update.  The update's grouping and the reductions' order are those of the two kernels, so the
+// results are theirs bit for bit.  NV bounds nv.
+template <int NV>
+__global__ void __launch_bounds__(RED_THREADS) k_update_dots(ChunkArgs ca, const double* __restrict__ V, size_t ldv,
+                                                             int nv, const double* __restrict__ coef, int cstride,
+                                                             const double* w_in, double* w_out,
+                                                             double* __restrict__ partial) {
+    __shared__ double cf[NV];
+    __shared__ double red[RED_THREADS / 64][NV];
+    const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
+        const int c = ca.chunk_case[ch];
+        if (chunk_skipped(ca, c)) continue;
+        const size_t end = case_end(ca.cases[c], ch);
+        __syncthreads();   // cf[] / red[] of the previous chunk consumed
+        if ((int)threadIdx.x < NV) cf[threadIdx.x] = ((int)threadIdx.x < nv) ? coef[(size_t)c * cstride + threadIdx.x] : 0.0;
+        __syncthreads();
+        double acc[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+        for (size_t t = (size_t)ch * CHUNK + threadIdx.x; t < end; t += RED_THREADS) {
+            // all rows loaded before any is used (rows past nv - 1 reload row nv - 1, unused)
+            double x[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) x[k] = V[(size_t)(k < nv ? k : nv - 1) * ldv + t];
+            double wt = w_in[t];
+            const int n4 = nv & ~3;
+#pragma unroll
+            for (int k = 0; k < NV; k += 4)
+                if (k < n4) wt -= cf[k] * x[k] + cf[k + 1] * x[k + 1] + cf[k + 2] * x[k + 2] + cf[k + 3] * x[k + 3];
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (k >= n4 && k < nv) wt -= cf[k] * x[k];
+            w_out[t] = wt;
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) acc[k] += x[k] * wt;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            if (k >= nv) continue;
+            double v = acc[k];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[wid][k] = v;
+        }
+        __syncthreads();
+        const int k = threadIdx.x;
+        if (k < nv) {
+            double v = 0.0;
+            for (int q = 0; q < RED_THREADS / 64; ++q) v += red[q][k];
+            partial[(size_t)ch * MAXV + k] = v;
+        }
+    }
+}
+
 // out_c[i] = sum over the chunks of case c of partial[chunk][i]; grid (ncase, nout)
 __global__ void __launch_bounds__(256) k_final(ChunkArgs ca, const double* __restrict__ partial,
                                                double* __restrict__ out, int ostride) {
@@ -551,6 +609,22 @@ fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, c
     double* partial = sv.d_part;
     const unsigned grid = chunk_grid(sv);
     const double* w = w_in;
+    if (sv.fuse_gs && nv_upd > 0 && nv_dot == nv_upd && w_out && !want_norm && !mass_only && nv_upd <= 32) {
+        // update and re-orthogonalising dots share one read of the basis
+        if (nv_upd <= 8)
+            hipLaunchKernelGGL(k_update_dots<8>, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef, cstride,
+                               w_in, w_out, partial);
+        else if (nv_upd <= 16)
+            hipLaunchKernelGGL(k_update_dots<16>, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef,
+                               cstride, w_in, w_out, partial);
+        else
+            hipLaunchKernelGGL(k_update_dots<32>, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef,
+                               cstride, w_in, w_out, partial);
+        FR_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_final, dim3(sv.n, nv_dot), dim3(256), 0, s, ca, partial, out, ostride);
+        FR_HIP(hipGetLastError());
+        return FR_OK;
+    }
     if (nv_upd > 0) {
         // the norm of the updated vector rides on the update pass when no dots follow
         const int nrm = (want_norm && nv_dot == 0) ? 1 : 0;

@@ -226,6 +226,31 @@ def test_bdf2_step_parity_c1(gram_schmidt):
     assert np.all(row_errors(qg, qo) <= 1e-8 * scale), row_errors(qg, qo) / scale
 
 
+@pytest.mark.parametrize("graph", [1, 0])
+def test_fused_gram_schmidt_equals_separate_passes(graph):
+    """With two Gram-Schmidt passes the first pass's update and the second pass's dot products
+    run in one read of the basis (up to 32 vectors, 8- / 16- / 32-wide variants); the step
+    equals the one with separate update and dot kernels bit for bit.  GMRES(40) also runs
+    Arnoldi steps past 32 vectors, where the separate kernels take over."""
+    from paper_1903_06304_amd import lmfr
+    c = I.config_c1()
+    kw = dict(tol_pseudo=1e-10, tol_res=1e-12, krylov=40, max_lin_it=120, max_newton=3)
+    out = {}
+    for fused in (1, 0):
+        g = lmfr.Context(c.prm, *c.mesh.connectivity())
+        g.set_geometry(*c.mesh.nodes())
+        g.set_option("gram_schmidt", 2)
+        g.set_option("graph", graph)
+        g.set_option("fused_gram_schmidt", fused)
+        q = _dev(c.q)
+        st = g.bdf2_step(q, _dev(c.q_nm1), c.dt, check=False, **kw)
+        torch.cuda.synchronize()
+        out[fused] = (q.cpu().numpy(), st)
+    print("[parity] fused / separate Gram-Schmidt", out[1][1], out[0][1], flush=True)
+    assert out[1][1]["gmres_its"] == out[0][1]["gmres_its"] and out[1][1]["gmres_its"] > 32
+    assert np.array_equal(out[1][0], out[0][0])
+
+
 def test_bdf2_step_deforming_free_stream():
     c = I.config_c3(nx=6, p=2, perturbed=False)
     o, g = _pair(c.prm, c.mesh, 0.05)
