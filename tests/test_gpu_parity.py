@@ -17,7 +17,8 @@ torch = pytest.importorskip("torch")
 from oracle.oracle import Oracle  # noqa: E402
 from paper_1903_06304_amd import inputs as I  # noqa: E402
 
-from helpers import flux_scale, residual_parity, normwise_rel, row_errors, small_cases  # noqa: E402
+from helpers import (affine_metric_noise, flux_scale, normwise_rel, residual_parity, row_errors,  # noqa: E402
+                     small_cases)
 
 pytestmark = pytest.mark.gpu
 
@@ -280,6 +281,33 @@ def test_vjp_parity(case):
     Jv = g.jvp(_dev(q), _dev(v)).cpu().numpy()
     lhs, rhs = np.dot(w.ravel(), Jv.ravel()), np.dot(JTw.ravel(), v.ravel())
     assert abs(lhs - rhs) <= 1e-12 * np.abs(w.ravel() * Jv.ravel()).sum()
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_vjp_parity_c4_sampled(p):
+    """The 256x256 affine workload at full size (the benchmark's VJP): J^T w at sampled DOFs
+    against the oracle's per-DOF complex-step adjoint.  This mesh takes the adjoint's affine
+    path (neighbour traces from neighbour states, 7-word face adjoints); the samples include
+    every DOF of a few elements at the mesh's periodic seams and at workgroup boundaries."""
+    c = I.config_c4(p=p)
+    o, g = _pair(c.prm, c.mesh)
+    assert g.affine_elements() == c.mesh.E
+    rng = np.random.default_rng(60 + p)
+    w = rng.standard_normal(c.q.shape)
+    JTw = g.vjp(_dev(c.q), _dev(w)).cpu().numpy()
+    E, Np = c.mesh.E, (p + 1) ** 2
+    els = np.unique(np.concatenate([[0, 255, 256, E - 256, E - 1], rng.choice(E, 6, replace=False),
+                                    np.arange(7, 10)]))
+    grid = np.stack(np.meshgrid(np.arange(4), els, np.arange(Np), indexing="ij"), -1).reshape(-1, 3)
+    dofs = np.concatenate([np.ravel_multi_index(grid.T, (4, E, Np)), rng.choice(c.q.size, 300, replace=False)])
+    ref = o.vjp_dofs(c.q, w, dofs)
+    got = JTw.ravel()[dofs]
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    # the GPU takes one metric value per affine element where the oracle keeps the per-point
+    # values; they differ by the rounding of the node coordinates (delta), as in residual_parity
+    delta = affine_metric_noise(o.geometry())
+    print(f"[parity] vjp C4 p={p} sampled ({dofs.size} DOFs) {err:.2e}, affine metric noise {delta:.1e}", flush=True)
+    assert err / (1.0 + 2.0 * delta / 1e-12) <= 1e-12, (err, delta)
 
 
 def test_vjp_parity_c2_sampled():
