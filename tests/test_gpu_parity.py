@@ -78,10 +78,12 @@ def test_residual_parity_c2_full():
     print("  plain rel", normwise_rel(R, Ro), flush=True)
 
 
-def test_residual_and_jvp_parity_c4_full():
-    """The 256x256 affine p=3 workload at full size, every row."""
-    c = I.config_c4()
-    print(f"[parity] residual + jvp C4 full E={c.mesh.E}", flush=True)
+@pytest.mark.parametrize("p", [3, 4])
+def test_residual_and_jvp_parity_c4_full(p):
+    """The 256x256 affine workload at full size (p = 3: the headline residual; p = 4: the
+    100 x 100-block steps), every row."""
+    c = I.config_c4(p=p)
+    print(f"[parity] residual + jvp C4 full p={p} E={c.mesh.E}", flush=True)
     o, g = _pair(c.prm, c.mesh)
     assert g.affine_elements() == c.mesh.E
     R = g.residual(_dev(c.q)).cpu().numpy()
