@@ -269,8 +269,11 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     constexpr int NTV = VISC ? 10 : 4;
     constexpr int NG = MOV ? NGSP : G_IJ + 1;   // static meshes have no grid velocity
     __shared__ double s_q[EPB][4][Np];
-    constexpr int NA = MOV ? 24 : 20;       // moving meshes add the 4 grid-velocity products
-    __shared__ double s_a[EPB][NA][Np];      // scratch fields at solution points
+    // scratch fields at solution points: the adjoint seed times each metric term (20; moving
+    // meshes add the 4 grid-velocity products); affine elements store the seed alone (4 fields,
+    // the metric terms being element constants), so 6 fields cover the other phases
+    constexpr int NA = AFF ? 6 : (MOV ? 24 : 20);
+    __shared__ double s_a[EPB][NA][Np];
     __shared__ double s_f[EPB][NF][10];      // per flux point scratch
     __shared__ double s_S[EPB][NF][4];       // Sx, Sy, S.vg, scale sg|S|
     __shared__ OpTab sop;                    // operator tables (lane-dependent indexing in LDS)
@@ -291,6 +294,10 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         const size_t id = (size_t)e * Np + lt;
         #pragma unroll
         for (int v = 0; v < 4; ++v) { qs[v] = q[v * EN + id]; s_q[el][v][lt] = qs[v]; }
+    }
+    if (AFF ? act : isS) {
+        // affine: every lane, face lanes past Np included, holds the element's constant metrics
+        const size_t id = (size_t)e * Np + lt % Np;
         #pragma unroll
         for (int c = 0; c < NG; ++c) geo[c] = g.sp[c * EN + id];
     }
@@ -430,7 +437,12 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     }
     __syncthreads();   // gradient fields in s_a are dead from here
     // store per point: rho*xix, rho*etx, rho*xiy, rho*ety (+ rho*axi, rho*aet), rho*ij
-    if (isS) {
+    if constexpr (AFF) {
+        if (isS) {
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) s_a[el][v][lt] = rho_w[v];
+        }
+    } else if (isS) {
         const double axi = MOV ? geo[G_UG] * geo[G_XIX] + geo[G_VG] * geo[G_XIY] : 0.0;
         const double aet = MOV ? geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY] : 0.0;
         #pragma unroll
@@ -440,7 +452,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
             s_a[el][8 + v][lt] = rho_w[v] * geo[G_XIY];
             s_a[el][12 + v][lt] = rho_w[v] * geo[G_ETY];
             s_a[el][16 + v][lt] = rho_w[v] * geo[G_IJ];
-            if (MOV) {
+            if constexpr (MOV) {
                 s_a[el][20 + v][lt] = rho_w[v] * axi;   // combined below with aet via a second pass
             }
         }
@@ -455,9 +467,9 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
             for (int b = 0; b < n; ++b) {
                 const int s = line_pt(n, f, k, b);
                 const double gm_ = (f == 0 || f == 2) ? op.gamL[b] : op.gamR[b];
-                sacc += gm_ * s_a[el][16 + v][s];
+                sacc += gm_ * s_a[el][AFF ? v : 16 + v][s];
             }
-            aDF[v] = sacc;
+            aDF[v] = AFF ? geo[G_IJ] * sacc : sacc;
         }
     }
     // solution points: adjoints of f, g (and q^c) from the divergence terms
@@ -466,20 +478,32 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         #pragma unroll
         for (int v = 0; v < 4; ++v) {
             double s1 = 0, s2 = 0, s3 = 0;
-            for (int b = 0; b < n; ++b) {
-                const double Dxi = op.D[b * n + i], Det = op.D[b * n + j];   // D^T
-                s1 += Dxi * s_a[el][0 + v][b + n * j] + Det * s_a[el][4 + v][i + n * b];
-                s2 += Dxi * s_a[el][8 + v][b + n * j] + Det * s_a[el][12 + v][i + n * b];
-                if (MOV) s3 += Dxi * s_a[el][20 + v][b + n * j];
+            if constexpr (AFF) {
+                // the transposed reference derivatives of the seed, then the constant metrics
+                for (int b = 0; b < n; ++b) {
+                    s1 += op.D[b * n + i] * s_a[el][v][b + n * j];
+                    s2 += op.D[b * n + j] * s_a[el][v][i + n * b];
+                }
+                af[v] = geo[G_XIX] * s1 + geo[G_ETX] * s2;
+                ag[v] = geo[G_XIY] * s1 + geo[G_ETY] * s2;
+            } else {
+                for (int b = 0; b < n; ++b) {
+                    const double Dxi = op.D[b * n + i], Det = op.D[b * n + j];   // D^T
+                    s1 += Dxi * s_a[el][0 + v][b + n * j] + Det * s_a[el][4 + v][i + n * b];
+                    s2 += Dxi * s_a[el][8 + v][b + n * j] + Det * s_a[el][12 + v][i + n * b];
+                    if constexpr (MOV) s3 += Dxi * s_a[el][20 + v][b + n * j];
+                }
+                af[v] = s1; ag[v] = s2; aqc[v] = -s3;
             }
-            af[v] = s1; ag[v] = s2; aqc[v] = -s3;
         }
     }
     __syncthreads();
-    if (MOV && isS) {
-        const double aet = geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY];
-        #pragma unroll
-        for (int v = 0; v < 4; ++v) s_a[el][20 + v][lt] = rho_w[v] * aet;
+    if constexpr (MOV) {
+        if (isS) {
+            const double aet = geo[G_UG] * geo[G_ETX] + geo[G_VG] * geo[G_ETY];
+            #pragma unroll
+            for (int v = 0; v < 4; ++v) s_a[el][20 + v][lt] = rho_w[v] * aet;
+        }
     }
     if (isF) {
         // store -aDF (adjoint of F^loc) for the solution-point gather
@@ -488,7 +512,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
     }
     __syncthreads();
     if (isS) {
-        if (MOV) {
+        if constexpr (MOV) {
             #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 double s3 = 0;
