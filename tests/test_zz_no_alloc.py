@@ -14,8 +14,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _case(nx, ny, p, kind, seed):
-    if kind == "curved":
-        mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+    if kind in ("curved", "affine"):
+        # affine static meshes take the adjoint's path without the trace buffer
+        mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi),
+                      I.map_curved(0.1) if kind == "curved" else I.map_affine)
         prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
         t = 0.0
     else:
@@ -37,11 +39,14 @@ def _dev(x):
 def test_vjp_noalloc_matches_vjp():
     from paper_1903_06304_amd import lmfr
     L = lmfr.load_library()
-    cases = [_case(64, 48, 3, "curved", 1), _case(9, 7, 2, "deforming", 2)]   # the second is smaller
+    # each later mesh is smaller than the first
+    cases = [_case(64, 48, 3, "curved", 1), _case(9, 7, 2, "deforming", 2), _case(20, 16, 3, "affine", 3)]
     ctxs, args = [], []
     for prm, mesh, t, q, w in cases:
         g = lmfr.Context(prm, *mesh.connectivity())
         g.set_geometry(*mesh.nodes(t))
+        if mesh.mapping is I.map_affine:
+            assert g.affine_elements() == mesh.E
         qd, wd = _dev(q), _dev(w)
         ctxs.append(g)
         args.append((qd, wd, torch.empty_like(qd), torch.empty_like(qd)))
