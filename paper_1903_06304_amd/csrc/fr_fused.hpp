@@ -231,9 +231,12 @@ __device__ __forceinline__ void lane_geo_load(const Geo& g, int E, int e, int lt
     }
 }
 
-template <int P, bool VISC, bool MOV, int MODE, int K, int LANES, bool BC>
+template <int P, bool VISC, bool MOV, int MODE, int K, int LANES, bool BC, bool TAN = false>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused(GroupArgs ga, KArgs a, OpTab op) {
+    // TAN: only the tangent is wanted from the point fluxes on (a JVP without R, the Newton
+    // operator); stages 4-6 then keep the tangent fluxes in LDS as plain doubles
+    static_assert(!TAN || ((MODE == MODE_JVP || MODE == MODE_AOP) && K == 1), "tangent-only stages need one tangent");
     using T = typename ModeT<MODE, K>::T;
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
     constexpr int EPB = Shape<P, LANES>::EPB;
@@ -259,6 +262,11 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
     auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
     auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
     auto SI = [](int el, int c, int fp) { return el * ESS + c * NF + fp; };
+    // tangent-only fluxes: each element's areas of s_n and s_F read as doubles
+    constexpr int ESND = ESN * Store<T>::W, ESFD = ESF * Store<T>::W;
+    auto FD = [](int el, int v, int fp) { return el * ESFD + v * NF + fp; };
+    double* s_nd = reinterpret_cast<double*>(s_n);
+    double* s_Fd = reinterpret_cast<double*>(s_F);
     __shared__ double s_D[n * n];       // operator tables (lane-dependent indexing goes to LDS)
     __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
 
@@ -448,6 +456,7 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 
         // ---- stage 4: corrected gradient, pointwise fluxes (into the staging area)
         auto WI = [&](int fld, int sp) { return NI(el, fld, sp); };   // fluxes alias the neighbour area
+        auto WD = [&](int fld, int sp) { return el * ESND + (fld >> 2) * FACE + (fld & 3) * FS + sp; };
         T qs[4];
         if (act && lt < Np) {
             const double ij = lg.ij;
@@ -487,9 +496,15 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
             fr_point_flux<T, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                s_n[WI(vv, lt)] = fl[vv];
-                s_n[WI(4 + vv, lt)] = gl[vv];
-                if (MOV) s_n[WI(8 + vv, lt)] = qc[vv];
+                if constexpr (TAN) {
+                    s_nd[WD(vv, lt)] = fl[vv].d[0];
+                    s_nd[WD(4 + vv, lt)] = gl[vv].d[0];
+                    if (MOV) s_nd[WD(8 + vv, lt)] = qc[vv].d[0];
+                } else {
+                    s_n[WI(vv, lt)] = fl[vv];
+                    s_n[WI(4 + vv, lt)] = gl[vv];
+                    if (MOV) s_n[WI(8 + vv, lt)] = qc[vv];
+                }
             }
         }
         __syncthreads();
@@ -500,15 +515,27 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
             const double Sx = s_S[SI(el, 0, lt)], Sy = s_S[SI(el, 1, lt)], Svg = s_S[SI(el, 2, lt)];
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                T acc = cst<T>(0.0);
+                if constexpr (TAN) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int b = 0; b < n; ++b) {
-                    const int sp = line_pt(n, f, k, b);
-                    T w = Sx * s_n[WI(vv, sp)] + Sy * s_n[WI(4 + vv, sp)];
-                    if (MOV) w = w - Svg * s_n[WI(8 + vv, sp)];
-                    acc = acc + lam[b] * w;
+                    for (int b = 0; b < n; ++b) {
+                        const int sp = line_pt(n, f, k, b);
+                        double w = Sx * s_nd[WD(vv, sp)] + Sy * s_nd[WD(4 + vv, sp)];
+                        if (MOV) w = w - Svg * s_nd[WD(8 + vv, sp)];
+                        acc = acc + lam[b] * w;
+                    }
+                    s_Fd[FD(el, vv, lt)] = fsc[vv].d[0] - acc;
+                } else {
+                    T acc = cst<T>(0.0);
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        const int sp = line_pt(n, f, k, b);
+                        T w = Sx * s_n[WI(vv, sp)] + Sy * s_n[WI(4 + vv, sp)];
+                        if (MOV) w = w - Svg * s_n[WI(8 + vv, sp)];
+                        acc = acc + lam[b] * w;
+                    }
+                    s_F[FI(el, vv, lt)] = fsc[vv] - acc;
                 }
-                s_F[FI(el, vv, lt)] = fsc[vv] - acc;
             }
         }
         __syncthreads();
@@ -531,6 +558,33 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
             double* out = a.out + ((MODE == MODE_BLK) ? cd.boff : cd.off);
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
+                if constexpr (TAN) {
+                    double dfx = 0.0, dfe = 0.0, dgx = 0.0, dge = 0.0, dqx = 0.0, dqe = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        const double Dx = s_D[i * n + b], De = s_D[j * n + b];
+                        dfx = dfx + Dx * s_nd[WD(vv, b + n * j)];
+                        dgx = dgx + Dx * s_nd[WD(4 + vv, b + n * j)];
+                        dfe = dfe + De * s_nd[WD(vv, i + n * b)];
+                        dge = dge + De * s_nd[WD(4 + vv, i + n * b)];
+                        if (MOV) {
+                            dqx = dqx + Dx * s_nd[WD(8 + vv, b + n * j)];
+                            dqe = dqe + De * s_nd[WD(8 + vv, i + n * b)];
+                        }
+                    }
+                    double vol = geo[G_XIX] * dfx + geo[G_ETX] * dfe + geo[G_XIY] * dgx + geo[G_ETY] * dge;
+                    if (MOV) vol = vol - axi * dqx - aet * dqe;
+                    const double cor = s_gam[0][i] * s_Fd[FD(el, vv, 0 * n + j)] + s_gam[1][i] * s_Fd[FD(el, vv, 1 * n + j)]
+                                     + s_gam[0][j] * s_Fd[FD(el, vv, 2 * n + i)] + s_gam[1][j] * s_Fd[FD(el, vv, 3 * n + i)];
+                    const double R = -(vol + geo[G_IJ] * cor);
+                    if constexpr (MODE == MODE_AOP) {
+                        const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                        out[vv * EN + id] = ttv - R;
+                    } else {
+                        out[vv * EN + id] = R;
+                    }
+                    continue;
+                }
                 T dfx = cst<T>(0.0), dfe = cst<T>(0.0), dgx = cst<T>(0.0), dge = cst<T>(0.0);
                 T dqx = cst<T>(0.0), dqe = cst<T>(0.0);
 #pragma unroll
@@ -604,11 +658,15 @@ k_fused(GroupArgs ga, KArgs a, OpTab op) {
 //    so the divergence is dF~/dxi + dG~/deta and S.(Pi f, Pi g) on a xi (eta) face is |J| Pi F~
 //    (|J| Pi G~): half the LDS reads of the last two stages.
 // Equal to k_fused's values up to rounding.
-template <int P, bool VISC, int MODE, int LANES>
+//  * TAN: only the tangent is wanted from the point fluxes on (a JVP without R, the Newton
+//    operator): stages 4-6 keep the tangent fluxes in LDS as plain doubles, and the value
+//    parts that only R would need are not computed.
+template <int P, bool VISC, int MODE, int LANES, bool TAN = false>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
     static_assert(MODE == MODE_R || MODE == MODE_PREP || MODE == MODE_JVP || MODE == MODE_AOP,
                   "residual, packs, JVP or Newton operator");
+    static_assert(!TAN || MODE == MODE_JVP || MODE == MODE_AOP, "tangent-only stages need a tangent");
     using T = typename ModeT<MODE, 1>::T;
     constexpr int n = P + 1, Np = n * n, NF = 4 * n, NT = Sz<P>::NT;
     constexpr int EPB = Shape<P, LANES>::EPB;
@@ -617,6 +675,11 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
     constexpr int ESQ = 4 * FS + PD::E;
     constexpr int ESW = 8 * FS + PD::E;      // own gradient (6 fields); later F~ of the 4 equations, then G~
     constexpr int ESF = 4 * NF + 1, ND = VISC ? 3 : 1, ESD = ND * NF + 1;
+    // tangent-only fluxes: each element's areas of s_w and s_F read as doubles
+    constexpr int ESWD = ESW * Store<T>::W, ESFD = ESF * Store<T>::W;
+    // an element whose lanes span two wavefronts: the gradient reads of stage 4 and its
+    // (differently placed) tangent flux writes are then separated by a barrier
+    constexpr bool SPLIT = TAN && (64 % NT != 0) && EPB * NT > 64;
     __shared__ T s_q[EPB * ESQ];       // own state [el][var][point]
     __shared__ T s_w[EPB * ESW];       // own uncorrected gradient [el][6][point]; then F~, G~ [el][8][point]
     __shared__ T s_F[EPB * ESF];       // neighbour traces of (u, v, T) by neighbour point; then F^num - F^loc
@@ -628,6 +691,10 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
     auto GI = [](int el, int c, int sp) { return el * ESW + c * FS + sp; };
     auto FI = [](int el, int v, int fp) { return el * ESF + v * NF + fp; };
     auto DI = [](int el, int c, int fp) { return el * ESD + c * NF + fp; };
+    auto WD = [](int el, int fld, int sp) { return el * ESWD + fld * FS + sp; };
+    auto FD = [](int el, int v, int fp) { return el * ESFD + v * NF + fp; };
+    double* s_wd = reinterpret_cast<double*>(s_w);
+    double* s_Fd = reinterpret_cast<double*>(s_F);
     __shared__ double s_D[n * n];
     __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
 
@@ -789,14 +856,19 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
         }
         __syncthreads();
         // ---- stage 4: corrected gradient, point fluxes in contravariant form
-        if (act && lt < Np) {
-            T qs[4];
+        const bool s4 = act && lt < Np;
+        T qs[4], gu[2], gv[2], gT[2];
+        if (s4) {
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) qs[vv] = s_q[QI(el, vv, lt)];
-            T gu[2], gv[2], gT[2];
             if (VISC) {
 #pragma unroll
                 for (int d = 0; d < 2; ++d) { gu[d] = s_w[GI(el, d, lt)]; gv[d] = s_w[GI(el, 2 + d, lt)]; gT[d] = s_w[GI(el, 4 + d, lt)]; }
+            }
+        }
+        if constexpr (SPLIT) __syncthreads();
+        if (s4) {
+            if (VISC) {
                 // lift of q^com - q^- through the Radau slopes; on an affine element the face
                 // vectors are |J| grad(xi) (faces 0, 1) and |J| grad(eta) (faces 2, 3), and |J| / |J| = 1
                 const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
@@ -827,8 +899,13 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             fr_point_flux<T, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                s_w[WI(el, vv, lt)] = lg.xix * fl[vv] + lg.xiy * gl[vv];
-                s_w[WI(el, 4 + vv, lt)] = lg.etx * fl[vv] + lg.ety * gl[vv];
+                if constexpr (TAN) {
+                    s_wd[WD(el, vv, lt)] = lg.xix * fl[vv].d[0] + lg.xiy * gl[vv].d[0];
+                    s_wd[WD(el, 4 + vv, lt)] = lg.etx * fl[vv].d[0] + lg.ety * gl[vv].d[0];
+                } else {
+                    s_w[WI(el, vv, lt)] = lg.xix * fl[vv] + lg.xiy * gl[vv];
+                    s_w[WI(el, 4 + vv, lt)] = lg.etx * fl[vv] + lg.ety * gl[vv];
+                }
             }
         }
         __syncthreads();
@@ -839,10 +916,17 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             const int base = f < 2 ? 0 : 4;
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                T acc = cst<T>(0.0);
+                if constexpr (TAN) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
-                s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_wd[WD(el, base + vv, line_pt(n, f, k, b))];
+                    s_Fd[FD(el, vv, lt)] = fsc[vv].d[0] - jac * acc;
+                } else {
+                    T acc = cst<T>(0.0);
+#pragma unroll
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
+                    s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
+                }
             }
         }
         __syncthreads();
@@ -861,6 +945,24 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
             }
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
+                if constexpr (TAN) {
+                    double dF = 0.0, dG = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        dF = dF + s_D[i * n + b] * s_wd[WD(el, vv, b + n * j)];
+                        dG = dG + s_D[j * n + b] * s_wd[WD(el, 4 + vv, i + n * b)];
+                    }
+                    const double cor = s_gam[0][i] * s_Fd[FD(el, vv, 0 * n + j)] + s_gam[1][i] * s_Fd[FD(el, vv, 1 * n + j)]
+                                     + s_gam[0][j] * s_Fd[FD(el, vv, 2 * n + i)] + s_gam[1][j] * s_Fd[FD(el, vv, 3 * n + i)];
+                    const double R = -(dF + dG + lg.ij * cor);
+                    if constexpr (MODE == MODE_AOP) {
+                        const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                        out[vv * EN + id] = ttv - R;
+                    } else {
+                        out[vv * EN + id] = R;
+                    }
+                    continue;
+                }
                 T dF = cst<T>(0.0), dG = cst<T>(0.0);
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
@@ -1524,18 +1626,43 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
         if constexpr (has_aff) aff = group_affine(sv, gr);
         if constexpr (has_aff) {
             if (aff) {
-                hipLaunchKernelGGL((k_fused_aff<P, VISC, MODE, LANES>), dim3(grid_of(ga.ntiles, grid)),
-                                   dim3(SH::threads), 0, s, ga, a, op);
+                // the tangent-only form whenever R is not wanted as well
+                if constexpr (MODE == MODE_JVP || MODE == MODE_AOP) {
+                    if (MODE == MODE_AOP || !a.out2)
+                        hipLaunchKernelGGL((k_fused_aff<P, VISC, MODE, LANES, true>), dim3(grid_of(ga.ntiles, grid)),
+                                           dim3(SH::threads), 0, s, ga, a, op);
+                    else
+                        hipLaunchKernelGGL((k_fused_aff<P, VISC, MODE, LANES>), dim3(grid_of(ga.ntiles, grid)),
+                                           dim3(SH::threads), 0, s, ga, a, op);
+                } else {
+                    hipLaunchKernelGGL((k_fused_aff<P, VISC, MODE, LANES>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
+                }
             }
         }
         if (!aff) {
+            constexpr bool dual1 = MODE == MODE_JVP || MODE == MODE_AOP;
+            const bool tan = dual1 && (MODE == MODE_AOP || !a.out2);
             if (gr.bnd) {
-                if constexpr (LANES <= 128)
-                    hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, true>), dim3(grid_of(ga.ntiles, grid)),
-                                       dim3(SH::threads), 0, s, ga, a, op);
+                if constexpr (LANES <= 128) {
+                    if constexpr (dual1) {
+                        if (tan)
+                            hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, true, true>),
+                                               dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s, ga, a, op);
+                    }
+                    if (!tan)
+                        hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, true>), dim3(grid_of(ga.ntiles, grid)),
+                                           dim3(SH::threads), 0, s, ga, a, op);
+                }
             } else {
-                hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, false>), dim3(grid_of(ga.ntiles, grid)),
-                                   dim3(SH::threads), 0, s, ga, a, op);
+                if constexpr (dual1) {
+                    if (tan)
+                        hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, false, true>),
+                                           dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads), 0, s, ga, a, op);
+                }
+                if (!tan)
+                    hipLaunchKernelGGL((k_fused<P, VISC, MOV, MODE, 1, LANES, false>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
             }
         }
     }

@@ -131,6 +131,20 @@ def test_jvp_parity(case):
     assert np.all(normwise_rel(Jv.cpu().numpy(), Jo) <= 1e-12), normwise_rel(Jv.cpu().numpy(), Jo)
     err_s = residual_parity(o.geometry(), prm, q, R.cpu().numpy(), o.residual(q), name)
     assert np.all(err_s <= 1e-12), err_s
+    # without R the kernels carry only the tangent from the point fluxes on; the same bits at
+    # both workgroup widths of the dual-number kernels (at 128 lanes an element of p = 2 or 4
+    # spans two wavefronts), for the JVP and for the Newton operator
+    Jt = g.jvp(_dev(q), _dev(v))
+    A64 = g.bdf_operator(_dev(q), _dev(v), 150.0, 0.37)
+    g.set_option("tile_lanes", 128)
+    Jt128 = g.jvp(_dev(q), _dev(v))
+    A128 = g.bdf_operator(_dev(q), _dev(v), 150.0, 0.37)
+    torch.cuda.synchronize()
+    err_t = normwise_rel(Jt.cpu().numpy(), Jo)
+    print(f"  tangent-only jvp {err_t}", flush=True)
+    assert np.all(err_t <= 1e-12), err_t
+    assert torch.equal(Jt, Jt128)
+    assert torch.equal(A64, A128)
 
 
 def test_jvp_parity_c2_full():
