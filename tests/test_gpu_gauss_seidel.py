@@ -39,6 +39,41 @@ def _state(mesh, prm, seed):
     return q
 
 
+def _operator_dense(o, q, c_time, inv_dtau):
+    """The Newton operator inv_dtau Gamma + c_time M - dR/dq as a dense matrix on the [4][E][Np]
+    layout: the oracle's point matrices (at each point's grid velocity) and dense Jacobian."""
+    _, E, Np = q.shape
+    geo = o.geometry()
+    T = np.zeros((q.size, q.size))
+    for e in range(E):
+        for s_ in range(Np):
+            pt = o.point(q[:, e, s_], ug=geo["ug"][e, s_], vg=geo["vg"][e, s_])
+            idx = [v * E * Np + e * Np + s_ for v in range(4)]
+            T[np.ix_(idx, idx)] = inv_dtau * pt["Gamma"] + c_time * pt["M"]
+    return T - o.dense_jacobian(q)
+
+
+def _sgs_sweep(A, X, col, gidx, r):
+    """Symmetric block Gauss-Seidel in colour order with the block inverses X (row-major per
+    element, rows and columns v*Np + s) and the couplings of A."""
+    E = X.shape[0]
+    y = np.zeros_like(r)
+    ncol = int(col.max()) + 1
+    for c in range(ncol):
+        for e in np.nonzero(col == c)[0]:
+            rows = gidx[e]
+            earlier = np.concatenate([gidx[f] for f in range(E) if col[f] < c]) if c > 0 else np.zeros(0, int)
+            rhs = r[rows] - (A[np.ix_(rows, earlier)] @ y[earlier] if earlier.size else 0.0)
+            y[rows] = X[e] @ rhs
+    z = y.copy()
+    for c in range(ncol - 2, -1, -1):
+        later = np.concatenate([gidx[f] for f in range(E) if col[f] > c])
+        for e in np.nonzero(col == c)[0]:
+            rows = gidx[e]
+            z[rows] = y[rows] - X[e] @ (A[np.ix_(rows, later)] @ z[later])
+    return z
+
+
 @pytest.mark.parametrize("nx,ny,p,kind", [(4, 4, 2, "curved"), (3, 3, 1, "curved"), (4, 2, 3, "deforming"),
                                           (5, 4, 2, "curved")])
 def test_gauss_seidel_apply_matches_oracle(nx, ny, p, kind):
@@ -59,12 +94,26 @@ def test_gauss_seidel_apply_matches_oracle(nx, ny, p, kind):
     ct, idt = 150.0, 1e-3
     zo, col = o.precond_apply(q, r, ct, idt, precond=1)
     print(f"  colours {col.max() + 1}", flush=True)
-    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-3), ("bf16", 5e-1)):
+    # FP64 blocks: the oracle's sweep.  Every stored precision: the same sweep written out here
+    # on the dense Newton operator with the GPU's stored inverse X~ in place of D^-1,
+    #   forward  y_c = X~_c (r_c - (L y)_c),  backward  z_c = y_c - X~_c (U z)_c,
+    # L (U) the couplings to earlier (later) colours, so only FP64 rounding separates the two
+    A = _operator_dense(o, q, ct, idt)
+    E, Np = mesh.E, q.shape[2]
+    nb = 4 * Np
+    gidx = np.array([[v * E * Np + e * Np + s_ for v in range(4) for s_ in range(Np)] for e in range(E)])
+    assert np.allclose(A[gidx[:, :, None], gidx[:, None, :]], o.blocks(q, ct, idt), rtol=0, atol=1e-12 * np.abs(A).max())
+    for prec in ("fp64", "fp32", "bf16"):
         g.block_jacobi_factor(_dev(q), ct, idt, prec)
         z = g.block_jacobi_apply(_dev(r)).cpu().numpy()
-        rel = np.linalg.norm(z - zo) / np.linalg.norm(zo)
-        print(f"  {prec}: rel {rel:.2e}", flush=True)
-        assert rel <= tol, (prec, rel)
+        X = g.get_inverse().cpu().numpy()
+        zs = _sgs_sweep(A, X, col, gidx, r.ravel()).reshape(q.shape)
+        rel = np.linalg.norm(z - zs) / np.linalg.norm(zs)
+        rel_o = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+        print(f"  {prec}: rel to the sweep with the stored inverse {rel:.2e}, to the oracle {rel_o:.2e}", flush=True)
+        assert rel <= 1e-10, (prec, rel)
+        if prec == "fp64":
+            assert rel_o <= 1e-10, rel_o
     # block Jacobi again after switching back
     g.set_option("preconditioner", 0)
     g.block_jacobi_factor(_dev(q), ct, idt, "fp64")

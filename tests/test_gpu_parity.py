@@ -6,7 +6,8 @@ Bars (written here, derived in the design notes):
     test also prints the error over S_c alone;
   * JVP / BDF operator: per-row normwise relative error <= 1e-12;
   * element blocks: max abs error <= 1e-12 * max |block|;
-  * block apply: FP64 1e-10 relative; FP32 / BF16 within their storage precision;
+  * block apply (every stored precision): within a bound derived from the storage rounding and
+    the factorisation error of the stored inverse;
   * BDF2 step (FP64 blocks): converged states agree to 1e-8 relative per variable.
 """
 import numpy as np
@@ -217,12 +218,26 @@ def test_blocks_parity(nx, ny, p, kind, packs):
     zref = np.zeros_like(r)
     for e in range(E):
         zref[:, e, :] = np.linalg.solve(Bo[e], r[:, e, :].reshape(-1)).reshape(4, Np)
-    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-3), ("bf16", 5e-1)):
+    # bar per precision, from the arithmetic: the stored inverse is X~ = X + dX, X = B^-1, with
+    # |dX| within half an ulp of storage, u_s |X|, plus the factorisation error, at most one unit
+    # u_a of the factoring precision times cond(B) ||X||_2 in norm; the apply is z~ = X~ r in
+    # FP64 (test_stored_inverse_and_apply checks both parts entry by entry), so per element
+    # ||z~ - z|| <= u_s || |X| |r| || + u_a cond(B) ||X||_2 ||r||
+    Xo = np.linalg.inv(Bo)
+    cond = np.array([np.linalg.cond(b) for b in Bo])
+    rE = r.transpose(1, 0, 2).reshape(E, -1)
+    n2 = np.linalg.norm(Xo, ord=2, axis=(1, 2))
+    unit = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+    for prec in ("fp64", "fp32", "bf16"):
+        arith = 2.0 ** -53 if prec == "fp64" else 2.0 ** -24
+        b_e = unit[prec] * np.linalg.norm(np.einsum("eij,ej->ei", np.abs(Xo), np.abs(rE)), axis=1) \
+            + arith * cond * n2 * np.linalg.norm(rE, axis=1)
+        bar = np.sqrt(np.sum(b_e ** 2)) + 1e-12 * np.linalg.norm(zref)
         g.block_jacobi_factor(_dev(q), ct, idt, prec)
         z = g.block_jacobi_apply(_dev(r)).cpu().numpy()
-        rel = np.linalg.norm(z - zref) / np.linalg.norm(zref)
-        print(f"  apply {prec}: rel {rel:.2e}", flush=True)
-        assert rel <= tol, (prec, rel)
+        err = np.linalg.norm(z - zref)
+        print(f"  apply {prec}: rel {err / np.linalg.norm(zref):.2e}, error / derived bar {err / bar:.2e}", flush=True)
+        assert err <= bar, (prec, err, bar)
 
 
 @pytest.mark.parametrize("gram_schmidt", [1, 2])
