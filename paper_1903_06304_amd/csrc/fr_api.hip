@@ -202,9 +202,20 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         colour[e] = k;
         ncol = k + 1 > ncol ? k + 1 : ncol;
     }
+    // the elements sorted by colour, for the coupling passes of the sweeps
+    std::vector<int32_t> corder;
+    corder.reserve((size_t)E);
+    std::array<int, 6> cofs{};
+    for (int k = 0; k < ncol; ++k) {
+        cofs[k] = (int)corder.size();
+        for (int e = 0; e < E; ++e)
+            if (colour[e] == k) corder.push_back(e);
+    }
+    for (int k = ncol; k < 6; ++k) cofs[k] = E;
     fr_ctx c = new fr_ctx_s();
     c->prm = *prm;
     c->ncolors = ncol;
+    c->cofs = cofs;
     c->p = prm->order; c->n = c->p + 1; c->Np = c->n * c->n;
     c->pg = prm->geom_order; c->m = c->pg + 1; c->E = E;
     const double g = prm->gamma, Ma = prm->mach_ref;
@@ -229,6 +240,7 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         (st = dalloc(&c->d_gfp, NGFP * FE)) != FR_OK ||
         (st = dalloc(&c->d_aff, (size_t)E)) != FR_OK ||
         (st = dalloc(&c->d_color, (size_t)E)) != FR_OK ||
+        (st = dalloc(&c->d_corder, (size_t)E)) != FR_OK ||
         (st = dalloc(&c->d_trace, FE * 10)) != FR_OK ||
         (st = dalloc(&c->d_vj, FE * 10)) != FR_OK ||
         (st = dalloc(&c->d_qinf, (size_t)4)) != FR_OK ||
@@ -243,7 +255,8 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         return FR_EHIP;
     }
     if (hipMemcpy(c->d_nbr, packed.data(), packed.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_color, colour.data(), colour.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(c->d_color, colour.data(), colour.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_corder, corder.data(), corder.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
         fr_destroy(c);
         fr_set_error("copy of the neighbour table failed");
         return FR_EHIP;
@@ -260,7 +273,7 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
 extern "C" void fr_destroy(fr_ctx c) {
     if (!c) return;
     if (c->self) { solver_free(*c->self); delete c->self; }
-    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_aff); dfree(c->d_color); dfree(c->d_trace);
+    dfree(c->d_nbr); dfree(c->d_gsp); dfree(c->d_gfp); dfree(c->d_aff); dfree(c->d_color); dfree(c->d_corder); dfree(c->d_trace);
     dfree(c->d_vj); dfree(c->d_bc); dfree(c->d_qinf);
     delete c;
 }

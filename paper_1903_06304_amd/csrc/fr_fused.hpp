@@ -164,6 +164,17 @@ __device__ __forceinline__ int find_member(const GroupArgs& ga, int t) {
     return lo;
 }
 
+// element of lane slot `el` of a tile of member lo (the tile's EPB consecutive elements), and
+// whether the slot holds one.  In a Gauss-Seidel coupling pass (ga.csel set) the tiles run over
+// the member's elements of one colour instead, taken from its colour-sorted element list.
+__device__ __forceinline__ int tile_elem(const GroupArgs& ga, const Geo& g, int lo, int tile, int epb, int el, int E,
+                                         bool& act) {
+    const int idx = (tile - sld(ga.pfx + lo)) * epb + el;
+    if (!ga.csel) { act = idx < E; return idx; }
+    act = idx < sld(ga.csel + 2 * lo + 1);
+    return act ? ldo(g.corder, (unsigned)(sld(ga.csel + 2 * lo) + idx)) : 0;
+}
+
 // first tile of the range walked by this workgroup, the end of that range and the
 // stride: XCD-contiguous ranges (workgroup b runs on XCD b % 8), or plain round robin
 __device__ __forceinline__ void tile_range(int ntiles, int xcd_order, int& t0, int& tend, int& stride) {
@@ -1038,8 +1049,8 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         const PhysConst& pc = cd.pc;
         const Geo g = cd.g;
         const int E = cd.E;
-        const int e = (tile - sld(ga.pfx + lo)) * EPB + el;
-        const bool act = e < E;
+        bool act;
+        const int e = tile_elem(ga, g, lo, tile, EPB, el, E, act);
         const unsigned EN = (unsigned)E * Np;
         const double* v = BLK ? nullptr : a.v + cd.off;
         const double* fpk = a.fpack + cd.fpoff;
@@ -1359,8 +1370,8 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
         const PhysConst& pc = cd.pc;
         const Geo g = cd.g;
         const int E = cd.E;
-        const int e = (tile - sld(ga.pfx + lo)) * EPB + el;
-        const bool act = e < E;
+        bool act;
+        const int e = tile_elem(ga, g, lo, tile, EPB, el, E, act);
         const unsigned EN = (unsigned)E * Np;
         const double* v = BLK ? nullptr : a.v + cd.off;
         const double* fpk = a.fpack + cd.fpoff;
@@ -1417,9 +1428,10 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             const int tn = tile + tstride;
             const int pfx_hi = lo + 1 < ga.nmem ? sld(ga.pfx + lo + 1) : ga.ntiles;
             pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
-            const int en = (tn - sld(ga.pfx + lo)) * EPB + el;
-            if (pkn_tile >= 0 && en < E) {
-                pkn = ldo(g.nbr, (unsigned)(en * 4 + f));
+            if (pkn_tile >= 0) {
+                bool actn;
+                const int en = tile_elem(ga, g, lo, tn, EPB, el, E, actn);
+                if (actn) pkn = ldo(g.nbr, (unsigned)(en * 4 + f));
             }
         }
         __syncthreads();
@@ -1596,6 +1608,14 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
     ga.nmem = (int)gr.ids.size();
     ga.ntiles = gr.ntiles(SH::EPB);
     ga.xcd = xcd;
+    if (MODE == MODE_LIN && a.csweep > 0) {
+        // a Gauss-Seidel coupling pass: only the rows of colour csweep - 1 are used
+        const Group::ColorTiles* ct = gr.color_tiles(SH::EPB, a.csweep - 1);
+        if (!ct) { fr_set_error("colour tiles missing for this workgroup shape"); return FR_EINVAL; }
+        ga.pfx = ct->d_pfx;
+        ga.ntiles = ct->ntiles;
+        ga.csel = ct->d_csel;
+    }
     if (!ga.pfx) { fr_set_error("tile prefix missing for this workgroup shape"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
     const OpTab& op = sv.cs[gr.ids[0]]->op;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <string>
+#include <array>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
@@ -52,6 +53,7 @@ struct Geo {
     const int32_t* nbr;   // [E][4]: nb*8 + nb_face*2 + flip
     const int32_t* aff;   // [E]: 1 when the element's metrics are constant (affine map)
     const int32_t* color; // [E]: element colour of the Gauss-Seidel sweeps (no face neighbour shares it)
+    const int32_t* corder;// [E]: the elements sorted by colour (ascending; element order within a colour)
     const int32_t* bc;    // [E]: boundary kind of face f in bits 2f..2f+1 (BC_*), 0 interior;
                           // null when the mesh has no boundary face.  A boundary face's
                           // entry in nbr names the element itself, same face, no reversal.
@@ -136,6 +138,8 @@ struct KArgs {
     int flag;             // which flag skips a case
     double* fpack;        // linearisation packs (MODE_PREP writes, MODE_LIN reads)
     double* spack;
+    int csweep;           // MODE_LIN: 1 + the colour whose rows a Gauss-Seidel coupling pass computes
+                          // (the elements of other colours are skipped); 0: every element
 };
 
 // tiles of one launch group (cases of one order / viscous / moving combination)
@@ -146,6 +150,10 @@ struct GroupArgs {
     int nmem;
     int ntiles;
     int xcd;              // tile order (Tune::xcd)
+    // a Gauss-Seidel coupling pass: per member, the first entry of its colour in Geo::corder and
+    // the colour's element count [nmem][2]; the tiles then cover that colour only.  null: every
+    // element, in element order
+    const int* csel = nullptr;
 };
 
 // launch shape of the fused kernel: workgroup width (lanes) and persistent grid size
@@ -163,9 +171,16 @@ struct Group {
     int* d_ids = nullptr;
     std::vector<std::pair<int, int*>> pfx;   // tile width (elements) -> device prefix
     std::vector<long long> elems;            // elements of each member
+    std::vector<std::array<int, 6>> cofs;    // per member: first entry of each colour in corder (6: end)
+    struct ColorTiles { int epb, color, ntiles; int* d_pfx; int* d_csel; };
+    std::vector<ColorTiles> ctiles;          // tile prefixes of the Gauss-Seidel coupling passes
     Tune tune[NMODES];                       // per mode
     const int* tile_pfx(int epb) const {
         for (auto& x : pfx) if (x.first == epb) return x.second;
+        return nullptr;
+    }
+    const ColorTiles* color_tiles(int epb, int color) const {
+        for (auto& x : ctiles) if (x.epb == epb && x.color == color) return &x;
         return nullptr;
     }
     int ntiles(int epb) const {
@@ -191,6 +206,8 @@ struct fr_ctx_s {
     double* d_gfp = nullptr;        // [NGFP][E][4n]
     int32_t* d_aff = nullptr;       // [E] affine-element flags
     int32_t* d_color = nullptr;     // [E] element colours
+    int32_t* d_corder = nullptr;    // [E] elements sorted by colour
+    std::array<int, 6> cofs{};      // first entry of each colour in d_corder (entry ncolors: E)
     int32_t* d_bc = nullptr;        // [E] boundary face codes (null: no boundary face)
     double* d_qinf = nullptr;       // [4] far-field state
     bool has_farfield = false, farfield_set = false;
@@ -200,7 +217,7 @@ struct fr_ctx_s {
     double* d_vj = nullptr;         // adjoint trace buffer
     Solver* self = nullptr;         // one-case solver of the context's own entry points
     size_t N() const { return (size_t)4 * E * Np; }
-    Geo geo() const { return Geo{d_gsp, d_gfp, d_nbr, d_aff, d_color, d_bc, d_qinf}; }
+    Geo geo() const { return Geo{d_gsp, d_gfp, d_nbr, d_aff, d_color, d_corder, d_bc, d_qinf}; }
 };
 
 // why a context cannot be evaluated yet, or null

@@ -585,15 +585,18 @@ fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op,
     a.out = sv.d_gst;
     a.flags = flags;
     a.flag = flag;
+    // each coupling pass computes the rows of the colour that its block apply updates only
     for (int k = 0; k < K; ++k) {
         if (k > 0) {
             FR_TRY(launch_color_mask(sv, z, sv.d_gsu, 0, k - 1, flags, flag, s));
+            a.csweep = 1 + k;
             FR_TRY(solver_fused(sv, MODE_LIN, a, s));
         }
         FR_TRY(launch_block_apply_ex(sv, r, k > 0 ? sv.d_gst : nullptr, z, k, false, flags, flag, s));
     }
     for (int k = K - 2; k >= 0; --k) {
         FR_TRY(launch_color_mask(sv, z, sv.d_gsu, k + 1, K - 1, flags, flag, s));
+        a.csweep = 1 + k;
         FR_TRY(solver_fused(sv, MODE_LIN, a, s));
         FR_TRY(launch_block_apply_ex(sv, sv.d_gst, nullptr, z, k, true, flags, flag, s));
     }

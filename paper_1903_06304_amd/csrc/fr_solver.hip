@@ -98,6 +98,7 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
         }
         g->ids.push_back(c);
         g->elems.push_back(x->E);
+        g->cofs.push_back(x->cofs);
     }
     for (Group& g : sv.groups) {
         FR_TRY(upload(&g.d_ids, g.ids));
@@ -111,6 +112,24 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
             int* d = nullptr;
             FR_TRY(upload(&d, pfx));
             g.pfx.emplace_back(w, d);
+        }
+        // the Gauss-Seidel coupling passes: per colour, tiles over each member's elements of it
+        for (int w : fused_tile_widths(g.p)) {
+            for (int k = 0; k < sv.ncolors; ++k) {
+                if (g.color_tiles(w, k)) continue;
+                std::vector<int> pfx(g.ids.size() + 1, 0), csel(2 * g.ids.size());
+                for (size_t m = 0; m < g.ids.size(); ++m) {
+                    const int cnt = g.cofs[m][k + 1] - g.cofs[m][k];
+                    csel[2 * m] = g.cofs[m][k];
+                    csel[2 * m + 1] = cnt;
+                    pfx[m + 1] = pfx[m] + (cnt + w - 1) / w;
+                }
+                Group::ColorTiles ct{w, k, pfx.back(), nullptr, nullptr};
+                FR_TRY(upload(&ct.d_pfx, pfx));
+                const fr_status st = upload(&ct.d_csel, csel);
+                if (st != FR_OK) { dfree(ct.d_pfx); return st; }
+                g.ctiles.push_back(ct);
+            }
         }
     }
     // per-case flags, step scalars, summary, reduction partials, pinned staging
@@ -134,6 +153,7 @@ void solver_free(Solver& sv) {
     for (Group& g : sv.groups) {
         dfree(g.d_ids);
         for (auto& x : g.pfx) dfree(x.second);
+        for (auto& x : g.ctiles) { dfree(x.d_pfx); dfree(x.d_csel); }
     }
     sv.groups.clear();
     dfree(sv.d_cases); dfree(sv.d_chunk_case); dfree(sv.d_case_chunk);
