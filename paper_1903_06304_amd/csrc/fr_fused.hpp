@@ -1004,7 +1004,7 @@ k_fused_aff(GroupArgs ga, KArgs a, OpTab op) {
 // values come from the packs.  The tangent arithmetic is the dual-number arithmetic of
 // the other modes term by term (same sums in the same order); the result matches MODE_AOP
 // to a few ulp, where the compiler contracts different products into fused multiply-adds.
-template <int P, bool VISC, bool MOV, int LANES, bool BLK, bool BC>
+template <int P, bool VISC, bool MOV, int LANES, bool BLK, bool BC, bool CS = false>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_lin(GroupArgs ga, KArgs a, OpTab op) {
     using D = Dual<1>;
@@ -1067,9 +1067,13 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             if (BC && g.bc) bck = (gld(g.bc + e) >> (2 * ((lt % NF) / n))) & 3;
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
+            // a Gauss-Seidel coupling pass takes v on elements of lower (higher) colours only, so
+            // never on the element itself
+            constexpr bool cs = CS && !BLK;
             double qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, id);
+            for (int vv = 0; vv < 4; ++vv)
+                qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : (cs ? 0.0 : ldo(v + vv * EN, id));
             // the lane's own face entry is loaded on its own: selecting it from pk4 by the lane's
             // face makes the compiler index a stack copy of pk4 (scratch memory)
             lane_geo_load<P, VISC, MOV>(g, E, e, lt, ldo(g.nbr, (unsigned)(e * 4 + (lt % NF) / n)), lg);
@@ -1080,10 +1084,15 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                 for (int ff = 0; ff < 4; ++ff) {
                     const int nb = pk4[ff] >> 3;
                     const unsigned nid = (unsigned)nb * Np + lt;
+                    bool take = true;
+                    if (cs) {
+                        const int cn = ldo(g.color, (unsigned)nb);
+                        take = a.cbelow ? cn < a.csweep - 1 : cn > a.csweep - 1;
+                    }
 #pragma unroll
                     for (int vv = 0; vv < 4; ++vv)
                         s_n[NI(el, ff * 4 + vv, lt)] =
-                            BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, nid);
+                            BLK ? ((nb == e && vv * Np + lt == a.seed0) ? 1.0 : 0.0) : (take ? ldo(v + vv * EN, nid) : 0.0);
                 }
             }
         }
@@ -1322,7 +1331,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
 // are all affine, with the changes of k_fused_aff: neighbour tangent lines read into
 // registers, the neighbour gradient trace from its traces, contravariant flux tangents, face
 // vectors from the constant metrics.  BLK: one seeded block column per launch.
-template <int P, bool VISC, int LANES, bool BLK>
+template <int P, bool VISC, int LANES, bool BLK, bool CS = false>
 __global__ void __launch_bounds__((Shape<P, LANES>::threads))
 k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
     using D = Dual<1>;
@@ -1385,19 +1394,29 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             const int pk = pre ? pkn : ldo(g.nbr, (unsigned)(e * 4 + f));
             const int ls = lt % Np;
             const unsigned id = (unsigned)e * Np + ls;
+            // a Gauss-Seidel coupling pass takes v on elements of lower (higher) colours only, so
+            // never on the element itself
+            constexpr bool cs = CS && !BLK;
             double qo[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, id);
+            for (int vv = 0; vv < 4; ++vv)
+                qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : (cs ? 0.0 : ldo(v + vv * EN, id));
             lane_geo_load<P, VISC, false>(g, E, e, lt, pk, lg);
             if (lt < NF) {
                 const unsigned nbase = (unsigned)lg.nb * Np;
+                bool take = true;
+                if (cs) {
+                    const int cn = ldo(g.color, (unsigned)lg.nb);
+                    take = a.cbelow ? cn < a.csweep - 1 : cn > a.csweep - 1;
+                }
                 double ln[4][n];
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
                     const int sp = line_pt(n, lg.nf, lg.k2, b);
 #pragma unroll
                     for (int vv = 0; vv < 4; ++vv)
-                        ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == a.seed0) ? 1.0 : 0.0) : ldo(v + vv * EN, nbase + sp);
+                        ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == a.seed0) ? 1.0 : 0.0)
+                                        : (take ? ldo(v + vv * EN, nbase + sp) : 0.0);
                 }
                 const double* lamn = s_lam[lg.nf & 1];
                 const double* dlamn = s_dlam[lg.nf & 1];
@@ -1623,20 +1642,36 @@ fr_status run(const Solver& sv, const Group& gr, const KArgs& a, int grid, int x
         constexpr bool B = MODE == MODE_LINBLK;
         if (!a.fpack || !a.spack || (!B && !a.v)) { fr_set_error("linearised operator without packs"); return FR_EINVAL; }
         bool aff = false;
+        // a Gauss-Seidel coupling pass: the variants that take v on lower or higher colours only
+        const bool cs = !B && a.csweep > 0;
         if constexpr (!MOV) {
             aff = group_affine(sv, gr);
-            if (aff)
-                hipLaunchKernelGGL((k_lin_aff<P, VISC, LANES, B>), dim3(grid_of(ga.ntiles, grid)), dim3(SH::threads),
-                                   0, s, ga, a, op);
+            if (aff) {
+                if (cs)
+                    hipLaunchKernelGGL((k_lin_aff<P, VISC, LANES, B, !B>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
+                else
+                    hipLaunchKernelGGL((k_lin_aff<P, VISC, LANES, B>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
+            }
         }
         if (!aff) {
             if (gr.bnd) {
-                if constexpr (LANES <= 128)
-                    hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, true>), dim3(grid_of(ga.ntiles, grid)),
-                                       dim3(SH::threads), 0, s, ga, a, op);
+                if constexpr (LANES <= 128) {
+                    if (cs)
+                        hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, true, !B>), dim3(grid_of(ga.ntiles, grid)),
+                                           dim3(SH::threads), 0, s, ga, a, op);
+                    else
+                        hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, true>), dim3(grid_of(ga.ntiles, grid)),
+                                           dim3(SH::threads), 0, s, ga, a, op);
+                }
             } else {
-                hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, false>), dim3(grid_of(ga.ntiles, grid)),
-                                   dim3(SH::threads), 0, s, ga, a, op);
+                if (cs)
+                    hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, false, !B>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
+                else
+                    hipLaunchKernelGGL((k_lin<P, VISC, MOV, LANES, B, false>), dim3(grid_of(ga.ntiles, grid)),
+                                       dim3(SH::threads), 0, s, ga, a, op);
             }
         }
     } else {

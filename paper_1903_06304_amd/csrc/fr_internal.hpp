@@ -140,6 +140,8 @@ struct KArgs {
     double* spack;
     int csweep;           // MODE_LIN: 1 + the colour whose rows a Gauss-Seidel coupling pass computes
                           // (the elements of other colours are skipped); 0: every element
+    int cbelow;           // coupling pass: the tangent v is taken on elements of lower colours (1) or
+                          // of higher colours (0), zero elsewhere (the element itself included)
 };
 
 // tiles of one launch group (cases of one order / viscous / moving combination)
@@ -249,8 +251,7 @@ struct Solver {
     double* d_blk_keep = nullptr;
     int precond = 0;                       // 0: element-block Jacobi, 1: symmetric block Gauss-Seidel
     int ncolors = 1;                       // colours of the sweeps (max over the cases)
-    double* d_gsu = nullptr;               // Gauss-Seidel work vectors [Ntot] x 2
-    double* d_gst = nullptr;
+    double* d_gst = nullptr;               // Gauss-Seidel couplings [Ntot]
     double f_ct = 0.0, f_idt = 0.0;        // time coefficients of the last context-level factor
     bool reject_on = false;                // the running steady solve undoes steps that raise the residual
     // step workspace
@@ -356,9 +357,6 @@ fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const
 //   sub = false: z_e = D_e^-1 (r_e - b_e) (b may be null);  sub = true: z_e -= D_e^-1 r_e
 fr_status launch_block_apply_ex(const Solver& sv, const double* r, const double* b, double* z, int color, bool sub,
                                 const int* flags, int flag, hipStream_t s);
-// u = z on the elements whose colour lies in [lo, hi], 0 elsewhere
-fr_status launch_color_mask(const Solver& sv, const double* z, double* u, int lo, int hi, const int* flags, int flag,
-                            hipStream_t s);
 // z = P^-1 r with the solver's preconditioner; the Gauss-Seidel sweeps apply the Newton
 // operator described by op (its v and out are set here)
 fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op, const int* flags, int flag,

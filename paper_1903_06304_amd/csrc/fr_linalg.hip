@@ -524,49 +524,6 @@ fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const
     return launch_block_apply_ex(sv, r, nullptr, z, -1, false, flags, flag, s);
 }
 
-// u = z on the elements whose colour lies in [lo, hi], 0 elsewhere
-// u = z on the elements of colours lo..hi, 0 elsewhere.  A thread takes U points a pass and
-// issues all their loads (colour and state, unconditionally) before its first store.
-__global__ void k_color_mask(ChunkArgs ca, const double* __restrict__ z, double* __restrict__ u, int lo, int hi) {
-    constexpr int U = 4;
-    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
-        const int c = ca.chunk_case[ch];
-        if (chunk_skipped(ca, c)) continue;
-        const CaseDev& cd = ca.cases[c];
-        const size_t EN = (size_t)cd.E * cd.Np;
-        const size_t r0 = (size_t)ch * CHUNK - cd.off;
-        if (r0 >= EN) continue;
-        const size_t r1 = r0 + CHUNK < EN ? r0 + CHUNK : EN;
-        for (size_t t0 = r0 + threadIdx.x; t0 < r1; t0 += U * blockDim.x) {
-            int col[U];
-            double zv[U][4];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                size_t t = t0 + (size_t)k * blockDim.x;
-                t = t < r1 ? t : t0;   // past the end: reload t0, unused
-                col[k] = cd.g.color[t / cd.Np];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) zv[k][v] = z[cd.off + t + v * EN];
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const size_t t = t0 + (size_t)k * blockDim.x;
-                if (t >= r1) break;
-                const bool keep = col[k] >= lo && col[k] <= hi;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) u[cd.off + t + v * EN] = keep ? zv[k][v] : 0.0;
-            }
-        }
-    }
-}
-
-fr_status launch_color_mask(const Solver& sv, const double* z, double* u, int lo, int hi, const int* flags, int flag,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_color_mask, dim3(chunk_grid(sv)), dim3(256), 0, s, chunk_args(sv, flags, flag), z, u, lo, hi);
-    FR_HIP(hipGetLastError());
-    return FR_OK;
-}
-
 // Symmetric block Gauss-Seidel over the elements in colour order, P = (D + L) D^-1 (D + U)
 // with L / U the couplings of the Newton operator A to elements of lower / higher colour
 // (elements of one colour never share a face, so A restricted to a colour is D):
@@ -577,26 +534,26 @@ fr_status launch_color_mask(const Solver& sv, const double* z, double* u, int lo
 fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op, const int* flags, int flag,
                         hipStream_t s) {
     if (sv.precond == 0) return launch_block_apply(sv, r, z, flags, flag, s);
-    FR_TRY(dalloc(&sv.d_gsu, sv.Ntot));
     FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
     const int K = sv.ncolors;
     KArgs a = op;
-    a.v = sv.d_gsu;
+    a.v = z;
     a.out = sv.d_gst;
     a.flags = flags;
     a.flag = flag;
-    // each coupling pass computes the rows of the colour that its block apply updates only
+    // each coupling pass computes the rows of the colour that its block apply updates, from z
+    // on the elements of lower colours (forward sweep) or of higher colours (backward sweep)
     for (int k = 0; k < K; ++k) {
         if (k > 0) {
-            FR_TRY(launch_color_mask(sv, z, sv.d_gsu, 0, k - 1, flags, flag, s));
             a.csweep = 1 + k;
+            a.cbelow = 1;
             FR_TRY(solver_fused(sv, MODE_LIN, a, s));
         }
         FR_TRY(launch_block_apply_ex(sv, r, k > 0 ? sv.d_gst : nullptr, z, k, false, flags, flag, s));
     }
     for (int k = K - 2; k >= 0; --k) {
-        FR_TRY(launch_color_mask(sv, z, sv.d_gsu, k + 1, K - 1, flags, flag, s));
         a.csweep = 1 + k;
+        a.cbelow = 0;
         FR_TRY(solver_fused(sv, MODE_LIN, a, s));
         FR_TRY(launch_block_apply_ex(sv, sv.d_gst, nullptr, z, k, true, flags, flag, s));
     }

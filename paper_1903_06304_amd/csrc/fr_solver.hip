@@ -160,7 +160,7 @@ void solver_free(Solver& sv) {
     dfree(sv.d_blk); dfree(sv.d_inv); dfree(sv.d_blk_keep);
     dfree(sv.d_q); dfree(sv.d_w); dfree(sv.d_V); dfree(sv.d_gs); dfree(sv.d_gi); dfree(sv.d_part);
     dfree(sv.d_step); dfree(sv.d_sum); dfree(sv.d_fpack); dfree(sv.d_spack); dfree(sv.d_rscratch);
-    dfree(sv.d_gsu); dfree(sv.d_gst);
+    dfree(sv.d_gst);
     if (sv.h_pin) (void)hipHostFree(sv.h_pin);
     if (sv.ws) (void)hipStreamDestroy(sv.ws);
     if (sv.ev_in) (void)hipEventDestroy(sv.ev_in);
@@ -196,8 +196,7 @@ fr_status solver_reserve(Solver& sv, int m, int prec) {
         return FR_EINVAL;
     }
     FR_TRY(solver_ensure_step(sv, m, prec));
-    FR_TRY(dalloc(&sv.d_gsu, sv.Ntot));   // Gauss-Seidel sweeps
-    FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
+    FR_TRY(dalloc(&sv.d_gst, sv.Ntot));   // Gauss-Seidel sweeps
     FR_TRY(dalloc(&sv.d_rscratch, sv.Ntot));   // R of the two-pass Newton operator
     return FR_OK;
 }
