@@ -65,12 +65,12 @@ struct ApplyShape {
 };
 
 // z_e = D_e^-1 r_e for every element, or, for the Gauss-Seidel sweeps, for the elements of
-// one colour only (color >= 0): z_e = D_e^-1 (r_e - b_e) (b may be null), or z_e -= D_e^-1 r_e
-// (sub).  Elements of other colours read no block.
+// one colour only (tiles over that colour, ga.csel): z_e = D_e^-1 (r_e - b_e) (b may be null),
+// or z_e -= D_e^-1 r_e (sub).
 template <class Tin, int NB>
 __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __restrict__ inv,
                                                      const double* __restrict__ r, const double* __restrict__ b,
-                                                     double* __restrict__ z, int color, int sub,
+                                                     double* __restrict__ z, int sub,
                                                      const int* __restrict__ flags, int flag) {
     using SH = ApplyShape<Tin, NB>;
     constexpr int Np = NB / 4, RPT = SH::RPT, TPE = SH::TPE, EPB = SH::EPB;
@@ -82,8 +82,14 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
     if (flags && flags[cid * GI_STRIDE + flag]) return;
     const CaseDev& cd = ga.cases[cid];
     const int el = threadIdx.x / TPE, r0 = (threadIdx.x % TPE) * RPT;
-    const int e = (t - ga.pfx[lo]) * EPB + el;
-    const bool act = (el < EPB) && (e < cd.E) && (color < 0 || cd.g.color[e] == color);
+    // one colour of the Gauss-Seidel sweeps (ga.csel set): the tiles run over the member's
+    // elements of that colour, taken from its colour-sorted element list
+    int e = (t - ga.pfx[lo]) * EPB + el;
+    bool act = (el < EPB) && (e < cd.E);
+    if (ga.csel) {
+        act = (el < EPB) && (e < ga.csel[2 * lo + 1]);
+        e = act ? cd.g.corder[ga.csel[2 * lo] + e] : 0;
+    }
     const size_t EN = (size_t)cd.E * Np;
     size_t gid[RPT];
 #pragma unroll
@@ -416,7 +422,9 @@ unsigned chunk_grid(const Solver& sv) {
     return (unsigned)(sv.nchunks < MAX_GRID ? sv.nchunks : MAX_GRID);
 }
 
-GroupArgs group_args(const Solver& sv, const Group& gr, int epb) {
+// the tiles of a group at a tile width; color >= 0: the tiles over the members' elements of
+// that colour (pfx null when a table is missing)
+GroupArgs group_args(const Solver& sv, const Group& gr, int epb, int color = -1) {
     GroupArgs ga;
     ga.cases = sv.d_cases;
     ga.ids = gr.d_ids;
@@ -424,6 +432,12 @@ GroupArgs group_args(const Solver& sv, const Group& gr, int epb) {
     ga.nmem = (int)gr.ids.size();
     ga.ntiles = gr.ntiles(epb);
     ga.xcd = 0;
+    if (color >= 0) {
+        const Group::ColorTiles* ct = gr.color_tiles(epb, color);
+        ga.pfx = ct ? ct->d_pfx : nullptr;
+        ga.ntiles = ct ? ct->ntiles : 0;
+        ga.csel = ct ? ct->d_csel : nullptr;
+    }
     return ga;
 }
 
@@ -485,11 +499,11 @@ struct ApplyArgs {
 template <class Tin, int NB>
 static fr_status apply_as(const Solver& sv, const Group& gr, const ApplyArgs& x, hipStream_t s) {
     using SH = ApplyShape<Tin, NB>;
-    GroupArgs ga = group_args(sv, gr, SH::EPB);
+    GroupArgs ga = group_args(sv, gr, SH::EPB, x.color);
     if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
     hipLaunchKernelGGL((k_block_apply<Tin, NB>), dim3(ga.ntiles), dim3(SH::threads), 0, s, ga, (const Tin*)sv.d_inv,
-                       x.r, x.b, x.z, x.color, x.sub, x.flags, x.flag);
+                       x.r, x.b, x.z, x.sub, x.flags, x.flag);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

@@ -113,8 +113,11 @@ fr_status solver_init(Solver& sv, const fr_ctx* ctxs, int n) {
             FR_TRY(upload(&d, pfx));
             g.pfx.emplace_back(w, d);
         }
-        // the Gauss-Seidel coupling passes: per colour, tiles over each member's elements of it
-        for (int w : fused_tile_widths(g.p)) {
+        // the Gauss-Seidel sweeps (coupling passes and block applies): per colour, tiles over
+        // each member's elements of it
+        std::vector<int> cwidths = fused_tile_widths(g.p);
+        for (int w : block_apply_widths(g.p)) cwidths.push_back(w);
+        for (int w : cwidths) {
             for (int k = 0; k < sv.ncolors; ++k) {
                 if (g.color_tiles(w, k)) continue;
                 std::vector<int> pfx(g.ids.size() + 1, 0), csel(2 * g.ids.size());
