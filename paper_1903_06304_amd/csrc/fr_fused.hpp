@@ -1386,217 +1386,239 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
         const double* fpk = a.fpack + cd.fpoff;
         const double* spk = a.spack + cd.spoff;
         __syncthreads();
-        // ---- stage 1: own tangent; the neighbour's tangent line through this face point
         LaneGeo lg;
-        double qpt[4], dnort[3];
         const bool pre = pkn_tile == tile;
-        if (act) {
-            const int pk = pre ? pkn : ldo(g.nbr, (unsigned)(e * 4 + f));
-            const int ls = lt % Np;
-            const unsigned id = (unsigned)e * Np + ls;
-            // a Gauss-Seidel coupling pass takes v on elements of lower (higher) colours only, so
-            // never on the element itself
-            constexpr bool cs = CS && !BLK;
-            double qo[4];
+        // block columns: the connectivity, the metric terms and the packs once per tile, for
+        // every column of the launch (a.ncols from seed0)
+        double fpv[14], spv[10];
+        if constexpr (BLK) {
+            if (act) {
+                lane_geo_load<P, VISC, false>(g, E, e, lt, pre ? pkn : ldo(g.nbr, (unsigned)(e * 4 + f)), lg);
+                if (lt < NF) {
+                    const unsigned FE = (unsigned)E * NF, sid = (unsigned)e * NF + lt;
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv)
-                qo[vv] = BLK ? ((vv * Np + ls == a.seed0) ? 1.0 : 0.0) : (cs ? 0.0 : ldo(v + vv * EN, id));
-            lane_geo_load<P, VISC, false>(g, E, e, lt, pk, lg);
-            if (lt < NF) {
-                const unsigned nbase = (unsigned)lg.nb * Np;
-                bool take = true;
-                if (cs) {
-                    const int cn = ldo(g.color, (unsigned)lg.nb);
-                    take = a.cbelow ? cn < a.csweep - 1 : cn > a.csweep - 1;
+                    for (int c = 0; c < (VISC ? 14 : 8); ++c) fpv[c] = ldo(fpk + (size_t)c * FE, sid);
                 }
-                double ln[4][n];
+                if (lt < Np) {
+                    const unsigned id = (unsigned)e * Np + lt;
 #pragma unroll
-                for (int b = 0; b < n; ++b) {
-                    const int sp = line_pt(n, lg.nf, lg.k2, b);
-#pragma unroll
-                    for (int vv = 0; vv < 4; ++vv)
-                        ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == a.seed0) ? 1.0 : 0.0)
-                                        : (take ? ldo(v + vv * EN, nbase + sp) : 0.0);
+                    for (int c = 0; c < (VISC ? 10 : 4); ++c) spv[c] = ldo(spk + (size_t)c * EN, id);
                 }
-                const double* lamn = s_lam[lg.nf & 1];
-                const double* dlamn = s_dlam[lg.nf & 1];
+            }
+        }
+        const int c0 = BLK ? a.seed0 : 0;
+        const int c1 = BLK ? min(a.seed0 + max(a.ncols, 1), 4 * Np) : 1;
+        for (int col = c0; col < c1; ++col) {
+            if (col > c0) __syncthreads();   // the previous column's readers of LDS are done
+            // ---- stage 1: own tangent; the neighbour's tangent line through this face point
+            double qpt[4], dnort[3];
+            if (act) {
+                const int ls = lt % Np;
+                const unsigned id = (unsigned)e * Np + ls;
+                // a Gauss-Seidel coupling pass takes v on elements of lower (higher) colours only, so
+                // never on the element itself
+                constexpr bool cs = CS && !BLK;
+                double qo[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv)
+                    qo[vv] = BLK ? ((vv * Np + ls == col) ? 1.0 : 0.0) : (cs ? 0.0 : ldo(v + vv * EN, id));
+                if constexpr (!BLK) lane_geo_load<P, VISC, false>(g, E, e, lt, pre ? pkn : ldo(g.nbr, (unsigned)(e * 4 + f)), lg);
+                if (lt < NF) {
+                    const unsigned nbase = (unsigned)lg.nb * Np;
+                    bool take = true;
+                    if (cs) {
+                        const int cn = ldo(g.color, (unsigned)lg.nb);
+                        take = a.cbelow ? cn < a.csweep - 1 : cn > a.csweep - 1;
+                    }
+                    double ln[4][n];
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        const int sp = line_pt(n, lg.nf, lg.k2, b);
+#pragma unroll
+                        for (int vv = 0; vv < 4; ++vv)
+                            ln[vv][b] = BLK ? ((lg.nb == e && vv * Np + sp == col) ? 1.0 : 0.0)
+                                            : (take ? ldo(v + vv * EN, nbase + sp) : 0.0);
+                    }
+                    const double* lamn = s_lam[lg.nf & 1];
+                    const double* dlamn = s_dlam[lg.nf & 1];
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int b = 0; b < n; ++b) acc = acc + lamn[b] * ln[vv][b];
+                        qpt[vv] = acc;
+                    }
+                    if (VISC) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int b = 0; b < n; ++b) acc = acc + dlamn[b] * ln[c + 1][b];
+                            dnort[c] = acc;
+                            s_F[FI(el, c, f * n + lg.k2)] = qpt[c + 1];
+                        }
+                    }
+                }
+                if (lt < Np) {
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+                }
+            }
+            if (col == c0) {
+                const int tn = tile + tstride;
+                const int pfx_hi = lo + 1 < ga.nmem ? sld(ga.pfx + lo + 1) : ga.ntiles;
+                pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
+                if (pkn_tile >= 0) {
+                    bool actn;
+                    const int en = tile_elem(ga, g, lo, tn, EPB, el, E, actn);
+                    if (actn) pkn = ldo(g.nbr, (unsigned)(en * 4 + f));
+                }
+            }
+            __syncthreads();
+            // ---- stage 2: uncorrected gradient tangent
+            if (VISC && act && lt < Np) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double dxi = 0.0, deta = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
+                        deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
+                    }
+                    s_g[GI(el, 2 * c, lt)] = lg.xix * dxi + lg.etx * deta;
+                    s_g[GI(el, 2 * c + 1, lt)] = lg.xiy * dxi + lg.ety * deta;
+                }
+            }
+            __syncthreads();
+            // ---- stage 3: common flux on dual numbers (values from the face pack)
+            double fsc[4];
+            if (act && lt < NF) {
+                const double* lam = s_lam[f & 1];
+                const unsigned FE = (unsigned)E * NF;
+                const unsigned sid = (unsigned)e * NF + lt;
+                const double nx = lg.nx, ny = lg.ny, sc = lg.sc;
+                D fn[4], dq[4], qm[4], qp[4];
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) {
                     double acc = 0.0;
 #pragma unroll
-                    for (int b = 0; b < n; ++b) acc = acc + lamn[b] * ln[vv][b];
-                    qpt[vv] = acc;
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                    qm[vv] = mk(BLK ? fpv[vv] : ldo(fpk + (size_t)vv * FE, sid), acc);
+                    qp[vv] = mk(BLK ? fpv[4 + vv] : ldo(fpk + (size_t)(4 + vv) * FE, sid), qpt[vv]);
                 }
+                fr_common_inviscid<D>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
                 if (VISC) {
+                    D gm[6], gp[6];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
+                    for (int c = 0; c < 6; ++c) {
                         double acc = 0.0;
 #pragma unroll
-                        for (int b = 0; b < n; ++b) acc = acc + dlamn[b] * ln[c + 1][b];
-                        dnort[c] = acc;
-                        s_F[FI(el, c, f * n + lg.k2)] = qpt[c + 1];
+                        for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                        gm[c] = mk(BLK ? fpv[8 + c] : ldo(fpk + (size_t)(8 + c) * FE, sid), acc);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        double dtan = 0.0;
+#pragma unroll
+                        for (int m = 0; m < n; ++m) dtan = dtan + s_D[lg.k2 * n + m] * s_F[FI(el, c, f * n + m)];
+                        const double dxi = lg.nf < 2 ? dnort[c] : dtan, deta = lg.nf < 2 ? dtan : dnort[c];
+                        gp[2 * c] = mk(0.0, lg.mxix * dxi + lg.metx * deta);   // the pack holds g^- + g^+ in gm
+                        gp[2 * c + 1] = mk(0.0, lg.mxiy * dxi + lg.mety * deta);
+                    }
+                    const D qcu = qm[1] + 0.5 * dq[1];
+                    const D qcv = qm[2] + 0.5 * dq[2];
+                    D dqh[3];
+                    fr_common_viscous<D>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c].d[0];
+                }
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) fsc[vv] = (sc * fn[vv]).d[0];
+            }
+            __syncthreads();
+            // ---- stage 4: corrected gradient tangent, point flux on dual numbers, contravariant tangents
+            double qv[4];
+            if (act && lt < Np) {
+                const unsigned id = (unsigned)e * Np + lt;
+                D qs[4], gu[2], gv[2], gT[2];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    qv[vv] = BLK ? spv[vv] : ldo(spk + (size_t)vv * EN, id);
+                    qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
+                }
+                if (VISC) {
+                    double gt[6];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) gt[c] = s_g[GI(el, c, lt)];
+                    const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
+                    const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double lx = gL_i * s_dq[DI(el, c, fp0)] + gR_i * s_dq[DI(el, c, fp1)];
+                        const double le = gL_j * s_dq[DI(el, c, fp2)] + gR_j * s_dq[DI(el, c, fp3)];
+                        gt[2 * c] = gt[2 * c] + (lg.xix * lx + lg.etx * le);
+                        gt[2 * c + 1] = gt[2 * c + 1] + (lg.xiy * lx + lg.ety * le);
+                    }
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        gu[d] = mk(BLK ? spv[4 + d] : ldo(spk + (size_t)(4 + d) * EN, id), gt[d]);
+                        gv[d] = mk(BLK ? spv[6 + d] : ldo(spk + (size_t)(6 + d) * EN, id), gt[2 + d]);
+                        gT[d] = mk(BLK ? spv[8 + d] : ldo(spk + (size_t)(8 + d) * EN, id), gt[4 + d]);
+                    }
+                }
+                D fl[4], gl[4], qc[4];
+                fr_point_flux<D, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    s_w[WI(el, vv, lt)] = lg.xix * fl[vv].d[0] + lg.xiy * gl[vv].d[0];
+                    s_w[WI(el, 4 + vv, lt)] = lg.etx * fl[vv].d[0] + lg.ety * gl[vv].d[0];
+                }
+            }
+            __syncthreads();
+            // ---- stage 5: F^num' - F^loc'
+            if (act && lt < NF) {
+                const double* lam = s_lam[f & 1];
+                const double jac = 1.0 / lg.ij;
+                const int base = f < 2 ? 0 : 4;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
+                    s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
+                }
+            }
+            __syncthreads();
+            // ---- stage 6: divergence and lift of the tangents; time terms
+            if (act && lt < Np) {
+                const unsigned id = (unsigned)e * Np + lt;
+                double ct = a.c_time, idt = a.inv_dtau;
+                if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
+                double tt[4], x[4];
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
+                fr_time_apply<double, double>(pc, qv, 0.0, 0.0, idt, ct, x, tt);
+                double* out = a.out + (BLK ? cd.boff + (size_t)e * (4 * Np) * (4 * Np) : cd.off);
+#pragma unroll 1
+                for (int vv = 0; vv < 4; ++vv) {
+                    double dF = 0.0, dG = 0.0;
+#pragma unroll
+                    for (int b = 0; b < n; ++b) {
+                        dF = dF + s_D[i * n + b] * s_w[WI(el, vv, b + n * j)];
+                        dG = dG + s_D[j * n + b] * s_w[WI(el, 4 + vv, i + n * b)];
+                    }
+                    const double cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
+                                     + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
+                    const double Rd = -(dF + dG + lg.ij * cor);
+                    const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
+                    if (BLK) {
+                        out[(size_t)col * (4 * Np) + vv * Np + lt] = ttv - Rd;
+                    } else {
+                        out[vv * EN + id] = ttv - Rd;
                     }
                 }
             }
-            if (lt < Np) {
-#pragma unroll
-                for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
-            }
-        }
-        {
-            const int tn = tile + tstride;
-            const int pfx_hi = lo + 1 < ga.nmem ? sld(ga.pfx + lo + 1) : ga.ntiles;
-            pkn_tile = (tn < tend && tn < pfx_hi) ? tn : -1;
-            if (pkn_tile >= 0) {
-                bool actn;
-                const int en = tile_elem(ga, g, lo, tn, EPB, el, E, actn);
-                if (actn) pkn = ldo(g.nbr, (unsigned)(en * 4 + f));
-            }
-        }
-        __syncthreads();
-        // ---- stage 2: uncorrected gradient tangent
-        if (VISC && act && lt < Np) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double dxi = 0.0, deta = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) {
-                    dxi = dxi + s_D[i * n + b] * s_q[QI(el, c + 1, b + n * j)];
-                    deta = deta + s_D[j * n + b] * s_q[QI(el, c + 1, i + n * b)];
-                }
-                s_g[GI(el, 2 * c, lt)] = lg.xix * dxi + lg.etx * deta;
-                s_g[GI(el, 2 * c + 1, lt)] = lg.xiy * dxi + lg.ety * deta;
-            }
-        }
-        __syncthreads();
-        // ---- stage 3: common flux on dual numbers (values from the face pack)
-        double fsc[4];
-        if (act && lt < NF) {
-            const double* lam = s_lam[f & 1];
-            const unsigned FE = (unsigned)E * NF;
-            const unsigned sid = (unsigned)e * NF + lt;
-            const double nx = lg.nx, ny = lg.ny, sc = lg.sc;
-            D fn[4], dq[4], qm[4], qp[4];
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) {
-                double acc = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
-                qm[vv] = mk(ldo(fpk + (size_t)vv * FE, sid), acc);
-                qp[vv] = mk(ldo(fpk + (size_t)(4 + vv) * FE, sid), qpt[vv]);
-            }
-            fr_common_inviscid<D>(pc, qm, qp, nx, ny, 0.0, 0.0, fn, dq);
-            if (VISC) {
-                D gm[6], gp[6];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
-                    gm[c] = mk(ldo(fpk + (size_t)(8 + c) * FE, sid), acc);
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double dtan = 0.0;
-#pragma unroll
-                    for (int m = 0; m < n; ++m) dtan = dtan + s_D[lg.k2 * n + m] * s_F[FI(el, c, f * n + m)];
-                    const double dxi = lg.nf < 2 ? dnort[c] : dtan, deta = lg.nf < 2 ? dtan : dnort[c];
-                    gp[2 * c] = mk(0.0, lg.mxix * dxi + lg.metx * deta);   // the pack holds g^- + g^+ in gm
-                    gp[2 * c + 1] = mk(0.0, lg.mxiy * dxi + lg.mety * deta);
-                }
-                const D qcu = qm[1] + 0.5 * dq[1];
-                const D qcv = qm[2] + 0.5 * dq[2];
-                D dqh[3];
-                fr_common_viscous<D>(pc, dq, qcu, qcv, gm, gp, nx, ny, lg.cc, fn, dqh);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) s_dq[DI(el, c, lt)] = dqh[c].d[0];
-            }
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) fsc[vv] = (sc * fn[vv]).d[0];
-        }
-        __syncthreads();
-        // ---- stage 4: corrected gradient tangent, point flux on dual numbers, contravariant tangents
-        double qv[4];
-        if (act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
-            D qs[4], gu[2], gv[2], gT[2];
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) {
-                qv[vv] = ldo(spk + (size_t)vv * EN, id);
-                qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
-            }
-            if (VISC) {
-                double gt[6];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) gt[c] = s_g[GI(el, c, lt)];
-                const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
-                const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const double lx = gL_i * s_dq[DI(el, c, fp0)] + gR_i * s_dq[DI(el, c, fp1)];
-                    const double le = gL_j * s_dq[DI(el, c, fp2)] + gR_j * s_dq[DI(el, c, fp3)];
-                    gt[2 * c] = gt[2 * c] + (lg.xix * lx + lg.etx * le);
-                    gt[2 * c + 1] = gt[2 * c + 1] + (lg.xiy * lx + lg.ety * le);
-                }
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    gu[d] = mk(ldo(spk + (size_t)(4 + d) * EN, id), gt[d]);
-                    gv[d] = mk(ldo(spk + (size_t)(6 + d) * EN, id), gt[2 + d]);
-                    gT[d] = mk(ldo(spk + (size_t)(8 + d) * EN, id), gt[4 + d]);
-                }
-            }
-            D fl[4], gl[4], qc[4];
-            fr_point_flux<D, VISC>(pc, qs, gu, gv, gT, fl, gl, qc);
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) {
-                s_w[WI(el, vv, lt)] = lg.xix * fl[vv].d[0] + lg.xiy * gl[vv].d[0];
-                s_w[WI(el, 4 + vv, lt)] = lg.etx * fl[vv].d[0] + lg.ety * gl[vv].d[0];
-            }
-        }
-        __syncthreads();
-        // ---- stage 5: F^num' - F^loc'
-        if (act && lt < NF) {
-            const double* lam = s_lam[f & 1];
-            const double jac = 1.0 / lg.ij;
-            const int base = f < 2 ? 0 : 4;
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) {
-                double acc = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_w[WI(el, base + vv, line_pt(n, f, k, b))];
-                s_F[FI(el, vv, lt)] = fsc[vv] - jac * acc;
-            }
-        }
-        __syncthreads();
-        // ---- stage 6: divergence and lift of the tangents; time terms
-        if (act && lt < Np) {
-            const unsigned id = (unsigned)e * Np + lt;
-            double ct = a.c_time, idt = a.inv_dtau;
-            if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
-            double tt[4], x[4];
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
-            fr_time_apply<double, double>(pc, qv, 0.0, 0.0, idt, ct, x, tt);
-            double* out = a.out + (BLK ? cd.boff + (size_t)e * (4 * Np) * (4 * Np) : cd.off);
-#pragma unroll 1
-            for (int vv = 0; vv < 4; ++vv) {
-                double dF = 0.0, dG = 0.0;
-#pragma unroll
-                for (int b = 0; b < n; ++b) {
-                    dF = dF + s_D[i * n + b] * s_w[WI(el, vv, b + n * j)];
-                    dG = dG + s_D[j * n + b] * s_w[WI(el, 4 + vv, i + n * b)];
-                }
-                const double cor = s_gam[0][i] * s_F[FI(el, vv, 0 * n + j)] + s_gam[1][i] * s_F[FI(el, vv, 1 * n + j)]
-                                 + s_gam[0][j] * s_F[FI(el, vv, 2 * n + i)] + s_gam[1][j] * s_F[FI(el, vv, 3 * n + i)];
-                const double Rd = -(dF + dG + lg.ij * cor);
-                const double ttv = (vv == 0) ? tt[0] : (vv == 1) ? tt[1] : (vv == 2) ? tt[2] : tt[3];
-                if (BLK) {
-                    out[(size_t)a.seed0 * (4 * Np) + vv * Np + lt] = ttv - Rd;
-                } else {
-                    out[vv * EN + id] = ttv - Rd;
-                }
-            }
-        }
+        }   // columns
     }
 }
 

@@ -134,6 +134,8 @@ struct KArgs {
     double c_time, inv_dtau;   // time-term coefficients when cstep is NULL
     const CaseStep* cstep;     // per-case coefficients (solver steps) or NULL
     int seed0;            // first seeded column (block mode)
+    int ncols;            // block columns from the packs (MODE_LINBLK) on affine static groups: the
+                          // columns seed0 .. seed0 + ncols - 1 in one launch (0: one column)
     const int* flags;     // per-case flags (gi layout) or NULL
     int flag;             // which flag skips a case
     double* fpack;        // linearisation packs (MODE_PREP writes, MODE_LIN reads)

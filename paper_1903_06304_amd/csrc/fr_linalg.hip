@@ -453,6 +453,17 @@ fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, 
     const int mode = (a.fpack && a.spack) ? MODE_LINBLK : MODE_BLK;
     for (const Group& gr : sv.groups) {
         const int nb = 4 * (gr.p + 1) * (gr.p + 1);
+        // the affine kernel over the packs (static groups whose elements are all affine)
+        // assembles every column in one launch, reading the packs of an element once
+        bool all_aff = !gr.mov;
+        for (int id : gr.ids) all_aff = all_aff && sv.cs[id]->all_affine;
+        if (mode == MODE_LINBLK && all_aff) {
+            a.seed0 = 0;
+            a.ncols = nb;
+            FR_TRY(launch_fused(sv, gr, mode, a, gr.tune[mode], s));
+            a.ncols = 0;
+            continue;
+        }
         for (int col = 0; col < nb; ++col) {
             a.seed0 = col;
             FR_TRY(launch_fused(sv, gr, mode, a, gr.tune[mode], s));

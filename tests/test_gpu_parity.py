@@ -183,13 +183,16 @@ def test_bdf_operator_parity():
 
 @pytest.mark.parametrize("packs", [0, 1])
 @pytest.mark.parametrize("nx,ny,p,kind", [(3, 3, 2, "curved"), (1, 3, 1, "curved"), (2, 3, 2, "deforming"),
-                                          (4, 3, 3, "curved"), (3, 2, 4, "curved")])
+                                          (4, 3, 3, "curved"), (3, 2, 4, "curved"), (5, 3, 3, "affine"),
+                                          (3, 4, 4, "affine")])
 def test_blocks_parity(nx, ny, p, kind, packs):
     """Blocks from dual-number columns (packs = 0) and from tangent-only columns over the
-    linearisation packs (packs = 1, the BDF2 step's path)."""
+    linearisation packs (packs = 1, the BDF2 step's path; on affine meshes every column of a
+    block in one launch)."""
     print(f"[parity] blocks {nx}x{ny} p={p} {kind} packs={packs}", flush=True)
-    if kind == "curved":
-        mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+    if kind in ("curved", "affine"):
+        mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi),
+                      I.map_curved(0.1) if kind == "curved" else I.map_affine)
         prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
         q = I.taylor_green(mesh, prm); q[1] += 0.05; q[2] -= 0.03
         t = 0.0
