@@ -31,6 +31,13 @@ struct Sz {
 
 __device__ __forceinline__ int line_pt(int n, int f, int k, int a) { return f < 2 ? a + n * k : k + n * a; }
 
+// tile of workgroup b of a grid of 8 * per workgroups: workgroups go to the 8 XCDs round robin
+// (b % 8), so XCD x takes the contiguous tiles x * per .. x * per + per - 1 and the face
+// neighbours of a tile (the next tile, the next row of tiles) mostly share its L2
+__device__ __forceinline__ int xcd_tile(int per) {
+    return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
 // ---------------------------------------------------------------- pointwise adjoints
 // adjoint of the total flux (f, g) and q^c at a point w.r.t. q and the corrected gradient
 template <bool VISC>
@@ -281,7 +288,7 @@ k_vjp_elem(int E, const double* __restrict__ q, const double* __restrict__ w, co
         reinterpret_cast<double*>(&sop)[t] = reinterpret_cast<const double*>(&op_in)[t];
     const OpTab& op = sop;
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
-    const int e = blockIdx.x * EPB + el;
+    const int e = xcd_tile(gridDim.x / 8) * EPB + el;
     const bool act = e < E;
     const bool isS = act && lt < Np, isF = act && lt < NF;
     const size_t EN = (size_t)E * Np, FE = (size_t)E * NF;
@@ -648,7 +655,7 @@ k_vjp_gather(int E, const double* __restrict__ aside, double* __restrict__ out, 
         reinterpret_cast<double*>(&sop)[t] = reinterpret_cast<const double*>(&op_in)[t];
     const OpTab& op = sop;
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
-    const int e = blockIdx.x * EPB + el;
+    const int e = xcd_tile(gridDim.x / 8) * EPB + el;
     const bool act = e < E;
     const bool isS = act && lt < Np, isF = act && lt < NF;
     const size_t EN = (size_t)E * Np;
@@ -711,7 +718,8 @@ template <int P, bool VISC, bool MOV>
 fr_status run_vjp(fr_ctx c, const double* q, const double* w, double* out, const double* trace, double* aside,
                   hipStream_t s) {
     const Geo g = c->geo();
-    const int grid = (c->E + Sz<P>::EPB - 1) / Sz<P>::EPB;
+    // tiles of EPB elements, the grid rounded up to a multiple of 8 for the XCD-contiguous order
+    const int grid = 8 * (((c->E + Sz<P>::EPB - 1) / Sz<P>::EPB + 7) / 8);
     if (!trace) {
         if constexpr (!MOV)
             hipLaunchKernelGGL((k_vjp_elem<P, VISC, false, false, true>), dim3(grid), dim3(Sz<P>::threads), 0, s,
