@@ -172,8 +172,10 @@ def test_gauss_seidel_graph_replay_matches_eager():
 
 
 def test_gauss_seidel_batch_matches_single_cases():
+    """A batch equals its cases stepped alone, bit for bit; the two p = 2 NS cases share a launch
+    group and its per-colour tiles with different colour counts (5 x 5: three colours, 6 x 6: two)."""
     from paper_1903_06304_amd import lmfr
-    cases = [I.config_c4(nx=8, p=3), I.config_c4(nx=5, p=2), I.config_c1(nx=6)]
+    cases = [I.config_c4(nx=8, p=3), I.config_c4(nx=5, p=2), I.config_c4(nx=6, p=2), I.config_c1(nx=6)]
     singles, ctxs = [], []
     opts = lmfr.step_opts(0.01, tol_pseudo=1e-8, tol_res=1e-6, krylov=20, max_lin_it=600, max_newton=10)
     for c in cases:
