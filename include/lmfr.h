@@ -255,8 +255,10 @@ fr_status fr_steady_solve(fr_ctx ctx, double* q, const fr_steady_opts* opts, fr_
  * elements in colour order, P = (D + L) D^-1 (D + U) with D the element blocks and L / U
  * the couplings of the Newton operator to elements of lower / higher colour -- colours
  * from fr_create, the smallest colour no face neighbour has, in element order; each
- * application costs 2 (K - 1) operator applications for K colours, 2 on even periodic
- * meshes; used by fr_block_jacobi_apply and the GMRES of the BDF2 and steady solves),
+ * application costs 2 (K - 1) operator passes for K colours, each over the elements of
+ * one colour (on even periodic meshes two passes over half the elements each), and
+ * 2 - 1/K block applies; used by fr_block_jacobi_apply and the GMRES of the BDF2 and
+ * steady solves),
  * and a manual launch shape of the fused kernels (what fr_autotune chooses): "tile_lanes" (0 =
  * default, 64, 128, 256; dual-number modes cap it at 128), "tile_grid" (0 = one
  * workgroup per tile, else the persistent grid size), "tile_xcd" (1 = each XCD walks a

@@ -202,7 +202,7 @@ extern "C" fr_status fr_create(const fr_params* prm, const int32_t* h_nbr, const
         colour[e] = k;
         ncol = k + 1 > ncol ? k + 1 : ncol;
     }
-    // the elements sorted by colour, for the coupling passes of the sweeps
+    // the elements sorted by colour: the Gauss-Seidel sweeps run over one colour at a time
     std::vector<int32_t> corder;
     corder.reserve((size_t)E);
     std::array<int, 6> cofs{};
