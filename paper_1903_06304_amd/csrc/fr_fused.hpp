@@ -1031,6 +1031,9 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
     __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
     auto mk = [](double v, double d) { D r; r.v = v; r.d[0] = d; return r; };
 
+    // a Gauss-Seidel coupling pass: the element's own tangent is zero, and so are its gradient,
+    // its traces and its time terms, which are therefore not formed
+    constexpr bool ZO = CS && !BLK;
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
     if (threadIdx.x < n) {
@@ -1079,7 +1082,8 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             lane_geo_load<P, VISC, MOV>(g, E, e, lt, ldo(g.nbr, (unsigned)(e * 4 + (lt % NF) / n)), lg);
             if (lt < Np) {
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+                for (int vv = 0; vv < 4; ++vv)
+                    if (!ZO) s_q[QI(el, vv, lt)] = qo[vv];
 #pragma unroll
                 for (int ff = 0; ff < 4; ++ff) {
                     const int nb = pk4[ff] >> 3;
@@ -1098,7 +1102,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
         }
         __syncthreads();
         // ---- stage 2: uncorrected gradient tangent
-        if (VISC && act && lt < Np) {
+        if (VISC && !ZO && act && lt < Np) {
             const double xix = lg.xix, xiy = lg.xiy, etx = lg.etx, ety = lg.ety;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -1126,7 +1130,7 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                 double am = 0.0, ap = 0.0;
 #pragma unroll
                 for (int b = 0; b < n; ++b) {
-                    am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                    if (!ZO) am = am + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
                     ap = ap + lamn[b] * s_n[NI(el, f * 4 + vv, line_pt(n, nf, k2, b))];
                 }
                 qmt[vv] = am;
@@ -1160,7 +1164,8 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
                 for (int c = 0; c < 6; ++c) {
                     double am = 0.0;
 #pragma unroll
-                    for (int b = 0; b < n; ++b) am = am + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                    for (int b = 0; b < n; ++b)
+                        if (!ZO) am = am + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
                     gm[c] = mk(ldo(fpk + (size_t)(8 + c) * FE, sid), am);
                     gmt[c] = am;
                 }
@@ -1229,12 +1234,12 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
                 qv[vv] = ldo(spk + (size_t)vv * EN, id);
-                qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
+                qs[vv] = mk(qv[vv], ZO ? 0.0 : s_q[QI(el, vv, lt)]);
             }
             if (VISC) {
                 double gt[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) gt[c] = s_g[GI(el, c, lt)];
+                for (int c = 0; c < 6; ++c) gt[c] = ZO ? 0.0 : s_g[GI(el, c, lt)];
                 const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
                 const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
 #pragma unroll
@@ -1291,8 +1296,13 @@ k_lin(GroupArgs ga, KArgs a, OpTab op) {
             if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
             double tt[4], x[4];
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
-            fr_time_apply<double, double>(pc, qv, geo[G_UG], geo[G_VG], idt, ct, x, tt);
+            for (int vv = 0; vv < 4; ++vv) x[vv] = ZO ? 0.0 : s_q[QI(el, vv, lt)];
+            if constexpr (ZO) {
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) tt[vv] = 0.0;
+            } else {
+                fr_time_apply<double, double>(pc, qv, geo[G_UG], geo[G_VG], idt, ct, x, tt);
+            }
             double* out = a.out + (BLK ? cd.boff + (size_t)e * (4 * Np) * (4 * Np) : cd.off);
 #pragma unroll 1
             for (int vv = 0; vv < 4; ++vv) {
@@ -1358,6 +1368,9 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
     __shared__ double s_lam[2][n], s_gam[2][n], s_dlam[2][n];
     auto mk = [](double v, double d) { D r; r.v = v; r.d[0] = d; return r; };
 
+    // a Gauss-Seidel coupling pass: the element's own tangent is zero, and so are its gradient,
+    // its traces and its time terms, which are therefore not formed
+    constexpr bool ZO = CS && !BLK;
     const int el = threadIdx.x / NT, lt = threadIdx.x % NT;
     for (int t = threadIdx.x; t < n * n; t += blockDim.x) s_D[t] = op.D[t];
     if (threadIdx.x < n) {
@@ -1461,7 +1474,8 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                 }
                 if (lt < Np) {
 #pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) s_q[QI(el, vv, lt)] = qo[vv];
+                    for (int vv = 0; vv < 4; ++vv)
+                        if (!ZO) s_q[QI(el, vv, lt)] = qo[vv];
                 }
             }
             if (col == c0) {
@@ -1476,7 +1490,7 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
             }
             __syncthreads();
             // ---- stage 2: uncorrected gradient tangent
-            if (VISC && act && lt < Np) {
+            if (VISC && !ZO && act && lt < Np) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     double dxi = 0.0, deta = 0.0;
@@ -1502,7 +1516,8 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                 for (int vv = 0; vv < 4; ++vv) {
                     double acc = 0.0;
 #pragma unroll
-                    for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
+                    for (int b = 0; b < n; ++b)
+                        if (!ZO) acc = acc + lam[b] * s_q[QI(el, vv, line_pt(n, f, k, b))];
                     qm[vv] = mk(BLK ? fpv[vv] : ldo(fpk + (size_t)vv * FE, sid), acc);
                     qp[vv] = mk(BLK ? fpv[4 + vv] : ldo(fpk + (size_t)(4 + vv) * FE, sid), qpt[vv]);
                 }
@@ -1513,7 +1528,8 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                     for (int c = 0; c < 6; ++c) {
                         double acc = 0.0;
 #pragma unroll
-                        for (int b = 0; b < n; ++b) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
+                        for (int b = 0; b < n; ++b)
+                            if (!ZO) acc = acc + lam[b] * s_g[GI(el, c, line_pt(n, f, k, b))];
                         gm[c] = mk(BLK ? fpv[8 + c] : ldo(fpk + (size_t)(8 + c) * FE, sid), acc);
                     }
 #pragma unroll
@@ -1544,12 +1560,12 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) {
                     qv[vv] = BLK ? spv[vv] : ldo(spk + (size_t)vv * EN, id);
-                    qs[vv] = mk(qv[vv], s_q[QI(el, vv, lt)]);
+                    qs[vv] = mk(qv[vv], ZO ? 0.0 : s_q[QI(el, vv, lt)]);
                 }
                 if (VISC) {
                     double gt[6];
 #pragma unroll
-                    for (int c = 0; c < 6; ++c) gt[c] = s_g[GI(el, c, lt)];
+                    for (int c = 0; c < 6; ++c) gt[c] = ZO ? 0.0 : s_g[GI(el, c, lt)];
                     const int fp0 = 0 * n + j, fp1 = 1 * n + j, fp2 = 2 * n + i, fp3 = 3 * n + i;
                     const double gL_i = s_gam[0][i], gR_i = s_gam[1][i], gL_j = s_gam[0][j], gR_j = s_gam[1][j];
 #pragma unroll
@@ -1596,8 +1612,13 @@ k_lin_aff(GroupArgs ga, KArgs a, OpTab op) {
                 if (a.cstep) { ct = rfl(a.cstep[cid].ct); idt = rfl(a.cstep[cid].idt); }
                 double tt[4], x[4];
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv) x[vv] = s_q[QI(el, vv, lt)];
-                fr_time_apply<double, double>(pc, qv, 0.0, 0.0, idt, ct, x, tt);
+                for (int vv = 0; vv < 4; ++vv) x[vv] = ZO ? 0.0 : s_q[QI(el, vv, lt)];
+                if constexpr (ZO) {
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) tt[vv] = 0.0;
+                } else {
+                    fr_time_apply<double, double>(pc, qv, 0.0, 0.0, idt, ct, x, tt);
+                }
                 double* out = a.out + (BLK ? cd.boff + (size_t)e * (4 * Np) * (4 * Np) : cd.off);
 #pragma unroll 1
                 for (int vv = 0; vv < 4; ++vv) {
