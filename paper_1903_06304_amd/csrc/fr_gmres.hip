@@ -333,14 +333,15 @@ fr_status enqueue_cycle(Solver& sv, int m, hipStream_t s) {
         FR_TRY(bdf_op(sv, q, z, w, GI_DONE, s));
         // classical Gram-Schmidt: h = V^T w, w -= V h (and once more when re-orthogonalising)
         FR_TRY(la_krylov(sv, V, N, 0, nullptr, 0, j + 1, w, nullptr, false, false, gs + L.H1, gst, sv.d_gi, GI_DONE, s));
+        // each pass over the basis walks its chunks the other way from the pass before it
         if (sv.gs_passes == 2) {
             FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, j + 1, w, w, false, false, gs + L.H2, gst, sv.d_gi,
-                             GI_DONE, s));
+                             GI_DONE, s, sv.fuse_gs));
             FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H2, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi,
-                             GI_DONE, s));
+                             GI_DONE, s, !sv.fuse_gs));
         } else {
             FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi,
-                             GI_DONE, s));
+                             GI_DONE, s, true));
         }
         hipLaunchKernelGGL(k_givens, dim3(cgrid(sv)), dim3(64), 0, s, k, j, m, sv.gs_passes);
         FR_HIP(hipGetLastError());

@@ -367,9 +367,11 @@ fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op,
 //   w_out = w_in - sum_{i<nv_upd} coef_c[i] V_i            (coef_c = coef + c * cstride)
 //   out_c[i] = V_i . w_out (i < nv_dot), out_c[nv_dot] = |w_out|^2 (want_norm)
 // (out_c = out + c * ostride); mass_only restricts the norm to the first E Np entries.
+// rev: the update passes walk the chunks from the last to the first, so that a pass that follows
+// one over the same basis starts on the chunks still in the Infinity Cache (same results)
 fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, const double* coef, int cstride,
                     int nv_dot, const double* w_in, double* w_out, bool want_norm, bool mass_only, double* out,
-                    int ostride, const int* flags, int flag, hipStream_t s);
+                    int ostride, const int* flags, int flag, hipStream_t s, bool rev = false);
 fr_status launch_bdf_rhs(const Solver& sv, const double* q, const double* Qn, const double* Qnm1, const double* R,
                          double* b, const int* flags, hipStream_t s);
 fr_status launch_cons(const Solver& sv, const double* q, double* Qc, const int* flags, hipStream_t s);

@@ -232,11 +232,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots8(ChunkArgs ca, const doubl
 __global__ void __launch_bounds__(RED_THREADS) k_update(ChunkArgs ca, const double* __restrict__ V, size_t ldv, int nv,
                                                         const double* __restrict__ coef, int cstride,
                                                         const double* w_in, double* w_out, int want_norm,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, int rev) {
     __shared__ double cf[MAXV];
     __shared__ double red[RED_THREADS / 64];
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
+    for (int ci = blockIdx.x; ci < ca.nchunks; ci += gridDim.x) {
+        const int ch = rev ? ca.nchunks - 1 - ci : ci;   // chunks last to first (partials by chunk)
         const int c = ca.chunk_case[ch];
         if (chunk_skipped(ca, c)) continue;
         const size_t end = case_end(ca.cases[c], ch);
@@ -284,11 +285,12 @@ template <int NV>
 __global__ void __launch_bounds__(RED_THREADS) k_update_dots(ChunkArgs ca, const double* __restrict__ V, size_t ldv,
                                                              int nv, const double* __restrict__ coef, int cstride,
                                                              const double* w_in, double* w_out,
-                                                             double* __restrict__ partial) {
+                                                             double* __restrict__ partial, int rev) {
     __shared__ double cf[NV];
     __shared__ double red[RED_THREADS / 64][NV];
     const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
-    for (int ch = blockIdx.x; ch < ca.nchunks; ch += gridDim.x) {
+    for (int ci = blockIdx.x; ci < ca.nchunks; ci += gridDim.x) {
+        const int ch = rev ? ca.nchunks - 1 - ci : ci;   // chunks last to first (partials by chunk)
         const int c = ca.chunk_case[ch];
         if (chunk_skipped(ca, c)) continue;
         const size_t end = case_end(ca.cases[c], ch);
@@ -587,7 +589,7 @@ fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op,
 
 fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, const double* coef, int cstride,
                     int nv_dot, const double* w_in, double* w_out, bool want_norm, bool mass_only, double* out,
-                    int ostride, const int* flags, int flag, hipStream_t s) {
+                    int ostride, const int* flags, int flag, hipStream_t s, bool rev) {
     if (nv_upd > MAXV - 1 || nv_dot > MAXV - 1) { fr_set_error("too many Krylov vectors"); return FR_EINVAL; }
     if (mass_only && nv_upd > 0) { fr_set_error("mass-row norm only on a plain norm pass"); return FR_EINVAL; }
     const ChunkArgs ca = chunk_args(sv, flags, flag);
@@ -598,13 +600,13 @@ fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, c
         // update and re-orthogonalising dots share one read of the basis
         if (nv_upd <= 8)
             hipLaunchKernelGGL(k_update_dots<8>, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef, cstride,
-                               w_in, w_out, partial);
+                               w_in, w_out, partial, rev ? 1 : 0);
         else if (nv_upd <= 16)
             hipLaunchKernelGGL(k_update_dots<16>, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef,
-                               cstride, w_in, w_out, partial);
+                               cstride, w_in, w_out, partial, rev ? 1 : 0);
         else
             hipLaunchKernelGGL(k_update_dots<32>, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef,
-                               cstride, w_in, w_out, partial);
+                               cstride, w_in, w_out, partial, rev ? 1 : 0);
         FR_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_final, dim3(sv.n, nv_dot), dim3(256), 0, s, ca, partial, out, ostride);
         FR_HIP(hipGetLastError());
@@ -614,7 +616,7 @@ fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, c
         // the norm of the updated vector rides on the update pass when no dots follow
         const int nrm = (want_norm && nv_dot == 0) ? 1 : 0;
         hipLaunchKernelGGL(k_update, dim3(grid), dim3(RED_THREADS), 0, s, ca, V, ldv, nv_upd, coef, cstride, w_in,
-                           w_out, nrm, partial);
+                           w_out, nrm, partial, rev ? 1 : 0);
         FR_HIP(hipGetLastError());
         w = w_out;
         if (nv_dot == 0) {
