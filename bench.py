@@ -74,6 +74,26 @@ def parse():
     return ap.parse_args()
 
 
+def mixed_vs_plain(out):
+    """The metric's second half in one place: per BDF2 workload, the plain step (FP64 blocks,
+    block Jacobi) against the fastest step with reduced-precision blocks (FP32 or BF16, block
+    Jacobi or block Gauss-Seidel), each to the same Newton tolerance."""
+    rows = {}
+    for key, plain_key, names in (("bdf2_step", "fp64", ("fp32", "bf16", "gauss_seidel_bf16")),
+                                  ("bdf2_step_p4", "fp64", ("fp32", "bf16", "gauss_seidel_bf16")),
+                                  ("batch", "bdf2_fp64", ("bdf2_bf16", "gauss_seidel_bf16"))):
+        bd = out.get(key)
+        if not bd or plain_key not in bd:
+            continue
+        mixed = {k: bd[k]["ms"] for k in names if isinstance(bd.get(k), dict) and "ms" in bd[k]}
+        if not mixed:
+            continue
+        best = min(mixed, key=mixed.get)
+        rows[key] = {"plain": "fp64 blocks, block Jacobi", "plain_ms": bd[plain_key]["ms"],
+                     "mixed": best, "mixed_ms": mixed[best], "ratio": bd[plain_key]["ms"] / mixed[best]}
+    return rows
+
+
 def algorithmic_bytes_residual(E, p, moving=False):
     """Minimal FP64 words of one residual: q in, R out, 5 Np metrics, 8 n face words
     (+2 Np, +4 n grid-velocity words on moving meshes) per element."""
@@ -407,6 +427,9 @@ def main():
             out["roofline"]["flops_per_residual"] = f_alg
             out["roofline"]["fp64_frac"] = fp64_frac
             out["roofline"]["combined_frac"] = max(out["roofline"]["frac"], fp64_frac)
+    mv = mixed_vs_plain(out)
+    if mv:
+        out["mixed_vs_plain"] = mv
     print(json.dumps(out), flush=True)
 
 
