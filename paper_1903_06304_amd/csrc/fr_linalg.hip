@@ -448,8 +448,9 @@ GroupArgs group_args(const Solver& sv, const Group& gr, int epb, int color = -1)
 // ----------------------------------------------------------------------------- launchers
 fr_status launch_block_assembly(Solver& sv, const double* q, const KArgs& base, hipStream_t s) {
     PhaseRange range("lmfr: block assembly (enqueue)");
-    // one seeded column of every element's block per launch and group; with the
-    // linearisation packs of q in base (fpack/spack), tangents only
+    // one seeded column of every element's block per launch and group (every column at once
+    // on affine static groups, below); with the linearisation packs of q in base
+    // (fpack/spack), tangents only
     KArgs a = base;
     a.q = q; a.v = nullptr; a.out = sv.d_blk; a.out2 = nullptr;
     const int mode = (a.fpack && a.spack) ? MODE_LINBLK : MODE_BLK;
