@@ -507,12 +507,16 @@ template <> __device__ __forceinline__ double widen<float>(float x) { return (do
 template <> __device__ __forceinline__ double widen<uint16_t>(uint16_t x) {
     return (double)__uint_as_float((uint32_t)x << 16);
 }
+// slot k of the stored inverse holds element corder[k]'s block in the colour layout (corder
+// set), element k's otherwise; the output is in element order
 template <class Tin>
-__global__ void k_widen_inverse(size_t E, int nb, const Tin* __restrict__ src, double* __restrict__ dst) {
+__global__ void k_widen_inverse(size_t E, int nb, const Tin* __restrict__ src, const int32_t* __restrict__ corder,
+                                double* __restrict__ dst) {
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t nn = (size_t)nb * nb;
     if (t >= E * nn) return;
-    const size_t e = t / nn, rc = t % nn, col = rc / nb, row = rc % nb;
+    const size_t k = t / nn, rc = t % nn, col = rc / nb, row = rc % nb;
+    const size_t e = corder ? (size_t)corder[k] : k;
     dst[e * nn + row * nb + col] = widen<Tin>(src[t]);
 }
 }  // namespace
@@ -526,18 +530,19 @@ extern "C" fr_status fr_get_inverse(fr_ctx c, double* inv, void* stream) {
     const size_t tot = (size_t)c->E * nb * nb;
     const dim3 grid((unsigned)((tot + 255) / 256));
     hipStream_t s = (hipStream_t)stream;
+    const int32_t* cl = sv.inv_colour ? c->d_corder : nullptr;
     switch (sv.inv_prec) {
         case FR_FP64:
             hipLaunchKernelGGL(k_widen_inverse<double>, grid, dim3(256), 0, s, (size_t)c->E, nb,
-                               (const double*)sv.d_inv, inv);
+                               (const double*)sv.d_inv, cl, inv);
             break;
         case FR_FP32:
             hipLaunchKernelGGL(k_widen_inverse<float>, grid, dim3(256), 0, s, (size_t)c->E, nb,
-                               (const float*)sv.d_inv, inv);
+                               (const float*)sv.d_inv, cl, inv);
             break;
         default:
             hipLaunchKernelGGL(k_widen_inverse<uint16_t>, grid, dim3(256), 0, s, (size_t)c->E, nb,
-                               (const uint16_t*)sv.d_inv, inv);
+                               (const uint16_t*)sv.d_inv, cl, inv);
     }
     FR_HIP(hipGetLastError());
     return FR_OK;

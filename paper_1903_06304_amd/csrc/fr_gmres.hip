@@ -498,11 +498,11 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
         aff[g] = all ? 1 : 0;
     }
     if (graph && (!sv.graph_exec || sv.graph_m != m || sv.graph_prec != prec || sv.graph_passes != sv.gs_passes ||
-                  sv.graph_precond != sv.precond || sv.graph_aff != aff)) {
+                  sv.graph_precond != sv.precond || sv.graph_cl != (int)sv.inv_colour || sv.graph_aff != aff)) {
         gmres_release(sv);
         // capture one cycle (all buffers are solver-owned; tolerances, time coefficients and
-        // caps are read on the device, so the graph depends on m, the block precision, the
-        // Gram-Schmidt passes and the preconditioner only)
+        // caps are read on the device, so the graph depends on m, the block precision and
+        // layout, the Gram-Schmidt passes and the preconditioner only)
         hipGraph_t gr;
         FR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         fr_status cst = enqueue_cycle(sv, m, s);
@@ -518,6 +518,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
         sv.graph_prec = prec;
         sv.graph_passes = sv.gs_passes;
         sv.graph_precond = sv.precond;
+        sv.graph_cl = (int)sv.inv_colour;
         sv.graph_aff = aff;
     }
     double* hs = sv.h_pin;

@@ -249,6 +249,10 @@ struct Solver {
     void* d_inv = nullptr;                 // inverse blocks in the stored precision
     size_t inv_bytes = 0;                  // capacity of d_inv
     int inv_prec = -1;
+    // inverse blocks in colour order (chosen at factor time with the Gauss-Seidel sweeps): slot
+    // k of a case holds the block of its element corder[k], so each colour's blocks are one
+    // contiguous range; otherwise slot e holds element e's block
+    bool inv_colour = false;
     bool keep_blocks = false;
     double* d_blk_keep = nullptr;
     int precond = 0;                       // 0: element-block Jacobi, 1: symmetric block Gauss-Seidel
@@ -278,7 +282,7 @@ struct Solver {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     bool use_graph = true;
     void* graph_exec = nullptr;
-    int graph_m = 0, graph_prec = -1, graph_passes = 0, graph_precond = -1;
+    int graph_m = 0, graph_prec = -1, graph_passes = 0, graph_precond = -1, graph_cl = -1;
     std::vector<char> graph_aff;           // per group: all members affine when the cycle was captured
     int gs_passes = 1;                     // classical Gram-Schmidt passes per Arnoldi step (1 or 2)
     bool fuse_gs = true;                   // two passes: update and re-orthogonalising dots in one read

@@ -100,7 +100,7 @@ __device__ __forceinline__ int case_of_tile(const GroupArgs& ga, int t) {
 template <int NB, class TC, class TO>
 __global__ void __launch_bounds__(256) k_block_invert_mfma(GroupArgs ga, const double* __restrict__ blk,
                                                            TO* __restrict__ inv, int* __restrict__ gi,
-                                                           const int* __restrict__ flags) {
+                                                           const int* __restrict__ flags, int cl) {
     constexpr int NBP = (NB + 15) / 16 * 16, NT = NBP / 16;
     // column stride: one element of padding against bank conflicts where LDS allows two
     // blocks per CU either way (an FP64 100 x 100 block takes LD = NB to fit twice)
@@ -118,7 +118,10 @@ __global__ void __launch_bounds__(256) k_block_invert_mfma(GroupArgs ga, const d
     const int cid = ga.ids[lo];
     if (flags && flags[cid * GI_STRIDE + GI_NDONE]) return;       // uniform per workgroup
     const CaseDev& cd = ga.cases[cid];
-    const int e = t - ga.pfx[lo];
+    // slot of the stored inverse; its element is the same index, or the slot's entry of the
+    // colour-sorted element list in the colour layout
+    const int slot = t - ga.pfx[lo];
+    const int e = cl ? cd.g.corder[slot] : slot;
     const double* src = blk + cd.boff + (size_t)e * NB * NB;
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int c = idx / NB, r = idx % NB;
@@ -243,7 +246,7 @@ __global__ void __launch_bounds__(256) k_block_invert_mfma(GroupArgs ga, const d
     }
     // inverse(row R, col C) = a(piv(R), pos(C)); written column-major, consecutive threads
     // on consecutive rows
-    TO* dst = inv + cd.boff + (size_t)e * NB * NB;
+    TO* dst = inv + cd.boff + (size_t)slot * NB * NB;
     for (int idx = tid; idx < NB * NB; idx += 256) {
         const int C = idx / NB, R = idx % NB;
         dst[idx] = store_as<TO, TC>(A[s_pos[C] * LD + s_piv[R]]);
@@ -253,7 +256,7 @@ __global__ void __launch_bounds__(256) k_block_invert_mfma(GroupArgs ga, const d
 template <int NB, class TC, class TO>
 fr_status launch_nb(Solver& sv, const GroupArgs& ga, const int* flags, hipStream_t s) {
     hipLaunchKernelGGL((k_block_invert_mfma<NB, TC, TO>), dim3(ga.ntiles), dim3(256), 0, s, ga, sv.d_blk,
-                       (TO*)sv.d_inv, sv.d_gi, flags);
+                       (TO*)sv.d_inv, sv.d_gi, flags, sv.inv_colour ? 1 : 0);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

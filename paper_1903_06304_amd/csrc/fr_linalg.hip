@@ -71,7 +71,7 @@ template <class Tin, int NB>
 __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __restrict__ inv,
                                                      const double* __restrict__ r, const double* __restrict__ b,
                                                      double* __restrict__ z, int sub,
-                                                     const int* __restrict__ flags, int flag) {
+                                                     const int* __restrict__ flags, int flag, int cl) {
     using SH = ApplyShape<Tin, NB>;
     constexpr int Np = NB / 4, RPT = SH::RPT, TPE = SH::TPE, EPB = SH::EPB;
     __shared__ double rs[EPB][NB + 1];
@@ -83,13 +83,17 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
     const CaseDev& cd = ga.cases[cid];
     const int el = threadIdx.x / TPE, r0 = (threadIdx.x % TPE) * RPT;
     // one colour of the Gauss-Seidel sweeps (ga.csel set): the tiles run over the member's
-    // elements of that colour, taken from its colour-sorted element list
-    int e = (t - ga.pfx[lo]) * EPB + el;
-    bool act = (el < EPB) && (e < cd.E);
+    // elements of that colour, taken from its colour-sorted element list.  slot: the
+    // element's block in the stored inverse (its position in that list in the colour layout)
+    int slot = (t - ga.pfx[lo]) * EPB + el;
+    bool act = (el < EPB) && (slot < cd.E);
     if (ga.csel) {
-        act = (el < EPB) && (e < ga.csel[2 * lo + 1]);
-        e = act ? cd.g.corder[ga.csel[2 * lo] + e] : 0;
+        act = (el < EPB) && (slot < ga.csel[2 * lo + 1]);
+        slot += ga.csel[2 * lo];
     }
+    int e = slot;
+    if (ga.csel || cl) e = act ? cd.g.corder[slot] : 0;
+    if (!cl) slot = e;
     const size_t EN = (size_t)cd.E * Np;
     size_t gid[RPT];
 #pragma unroll
@@ -100,7 +104,7 @@ __global__ void __launch_bounds__(256) k_block_apply(GroupArgs ga, const Tin* __
     }
     __syncthreads();
     if (!act) return;
-    const Tin* A = inv + cd.boff + (size_t)e * NB * NB + r0;
+    const Tin* A = inv + cd.boff + (size_t)slot * NB * NB + r0;
     double acc[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) acc[k] = 0.0;
@@ -488,6 +492,10 @@ static fr_status invert_all(Solver& sv, int prec, const int* flags, hipStream_t 
 fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_t s) {
     PhaseRange range("lmfr: block inversion (enqueue)");
     if (prec < FR_FP64 || prec > FR_BF16) { fr_set_error("unknown precision"); return FR_EINVAL; }
+    // the Gauss-Seidel sweeps apply one colour at a time: colour-sorted blocks keep each
+    // colour's reads contiguous (every other block of the element order reads at about half
+    // the bandwidth)
+    sv.inv_colour = sv.precond == 1;
     FR_TRY(invert_all(sv, prec, flags, s));
     sv.inv_prec = prec;
     return FR_OK;
@@ -517,7 +525,7 @@ static fr_status apply_as(const Solver& sv, const Group& gr, const ApplyArgs& x,
     if (!ga.pfx) { fr_set_error("tile prefix missing"); return FR_EINVAL; }
     if (ga.ntiles == 0) return FR_OK;
     hipLaunchKernelGGL((k_block_apply<Tin, NB>), dim3(ga.ntiles), dim3(SH::threads), 0, s, ga, (const Tin*)sv.d_inv,
-                       x.r, x.b, x.z, x.sub, x.flags, x.flag);
+                       x.r, x.b, x.z, x.sub, x.flags, x.flag, sv.inv_colour ? 1 : 0);
     FR_HIP(hipGetLastError());
     return FR_OK;
 }

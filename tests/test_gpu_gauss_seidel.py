@@ -122,6 +122,38 @@ def test_gauss_seidel_apply_matches_oracle(nx, ny, p, kind):
     assert np.linalg.norm(zj - zjo) <= 1e-10 * np.linalg.norm(zjo)
 
 
+@pytest.mark.parametrize("nx,ny,p", [(5, 4, 2), (4, 4, 3), (6, 3, 1)])
+def test_colour_ordered_inverse_equals_element_order(nx, ny, p):
+    """A factor with the Gauss-Seidel sweeps selected stores the inverse blocks in colour
+    order; one with block Jacobi in element order.  The read-back inverse, the block-Jacobi
+    application and the sweep give the same bits from either layout."""
+    print(f"[gs] inverse layouts {nx}x{ny} p={p}", flush=True)
+    mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
+    prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
+    q = _state(mesh, prm, 5)
+    _, g = _pair(prm, mesh)
+    g.set_option("operator_packs", 1)   # the block-Jacobi factor writes the sweeps' packs too
+    r = _dev(np.random.default_rng(6).standard_normal(q.shape))
+    ct, idt = 150.0, 1e-3
+    for prec in ("fp64", "bf16"):
+        g.set_option("preconditioner", 0)
+        g.block_jacobi_factor(_dev(q), ct, idt, prec)           # element order
+        X0 = g.get_inverse().cpu().numpy()
+        zj0 = g.block_jacobi_apply(r).cpu().numpy()
+        g.set_option("preconditioner", 1)
+        zg0 = g.block_jacobi_apply(r).cpu().numpy()             # sweep over element-ordered blocks
+        g.block_jacobi_factor(_dev(q), ct, idt, prec)           # colour order
+        X1 = g.get_inverse().cpu().numpy()
+        zg1 = g.block_jacobi_apply(r).cpu().numpy()
+        g.set_option("preconditioner", 0)
+        zj1 = g.block_jacobi_apply(r).cpu().numpy()             # block Jacobi over colour-ordered blocks
+        assert np.array_equal(X0, X1), prec
+        assert np.array_equal(zg0, zg1), prec
+        assert np.array_equal(zj0, zj1), prec
+        assert not np.array_equal(zg1, zj1)
+    g.set_option("preconditioner", 0)
+
+
 def _c4_small():
     return I.config_c4(nx=8, p=3)
 
