@@ -207,7 +207,9 @@ fr_status fr_block_jacobi_apply(fr_ctx ctx, const double* r, double* z, void* st
 
 /* Copy the stored inverse of the last fr_block_jacobi_factor, widened exactly to FP64, to
  * the DEVICE array inv [E][4Np][4Np], row-major (row = v*Np + s), so that z_e = inv_e r_e
- * is what fr_block_jacobi_apply computes with block Jacobi.  FR_EINVAL before a factor. */
+ * is what fr_block_jacobi_apply computes with block Jacobi.  Element order always (a factor
+ * under the Gauss-Seidel option stores the blocks in colour order internally; the values
+ * are the same).  FR_EINVAL before a factor. */
 fr_status fr_get_inverse(fr_ctx ctx, double* inv, void* stream);
 
 /* Allocate now every device workspace of fr_block_jacobi_factor, fr_block_jacobi_apply,
