@@ -829,6 +829,7 @@ static std::vector<int> colour_elements(const Ctx& c, int& ncol) {
 //   forward  y_k = D_k^-1 (r_k - sum_{k' < k} A_{k k'} y_{k'})   for k = 0 .. K-1,
 //   backward z_k = y_k - D_k^-1 sum_{k' > k} A_{k k'} z_{k'}      for k = K-2 .. 0,
 // with the off-diagonal products taken as A applied to y (z) restricted to those colours.
+// precond 2: forward block Gauss-Seidel, P = D + L: the forward sweep alone (z = y).
 static void precond_apply(const Ctx& c, int precond, const std::vector<int>& col, int ncol,
                           const std::vector<double>& blk, const std::vector<int>& piv,
                           const std::function<void(const double*, double*)>& A, const double* r, double* z) {
@@ -868,6 +869,7 @@ static void precond_apply(const Ctx& c, int precond, const std::vector<int>& col
         for (int e = 0; e < E; ++e)
             if (col[e] == k) dsolve(e, r, k > 0 ? t.data() : nullptr, false);
     }
+    if (precond != 1) return;
     for (int k = ncol - 2; k >= 0; --k) {
         restrict_to(k + 1, ncol - 1);
         A(u.data(), t.data());
@@ -1339,8 +1341,8 @@ int ora_steady_solve(void* h, double* q, const double* dopt, const int* iopt, in
 }
 
 // z = P^-1 r for the Newton operator A v = inv_dtau Gamma v + c_time M v - J v at q:
-// precond 0 block Jacobi, 1 symmetric block Gauss-Seidel in colour order.  colours (may be
-// null) receives the element colours.
+// precond 0 block Jacobi, 1 symmetric block Gauss-Seidel in colour order, 2 forward block
+// Gauss-Seidel in colour order.  colours (may be null) receives the element colours.
 int ora_precond_apply(void* h, const double* q, double c_time, double inv_dtau, int precond, const double* r,
                       double* z, int* colours) {
     Ctx& c = *(Ctx*)h;

@@ -282,7 +282,8 @@ class Oracle:
 
     def precond_apply(self, q, r, c_time, inv_dtau, precond=1):
         """z = P^-1 r for the Newton operator at q (precond 0: block Jacobi, 1: symmetric block
-        Gauss-Seidel in colour order); returns (z, element colours)."""
+        Gauss-Seidel in colour order, 2: forward block Gauss-Seidel in colour order); returns
+        (z, element colours)."""
         q = self._state(q)
         r = self._state(r)
         z = np.zeros_like(q)

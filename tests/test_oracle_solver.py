@@ -16,9 +16,10 @@
   raises the residual is undone -- the state returns to what it was, to rounding -- and
   retried with dtau / 10 from a residual equal to the one before the step.
 * Symmetric block Gauss-Seidel preconditioner in element colour order: P^-1 r equals the
-  dense solve with P = (D + L) D^-1 (D + U) assembled from the pinned dense operator; the
-  colouring is proper (no two face neighbours share a colour; a checkerboard on even
-  periodic meshes); it cuts the GMRES iterations of a BDF2 step.
+  dense solve with P = (D + L) D^-1 (D + U) assembled from the pinned dense operator, and the
+  forward sweep alone the dense solve with P = D + L; the colouring is proper (no two face
+  neighbours share a colour; a checkerboard on even periodic meshes); both cut the GMRES
+  iterations of a BDF2 step and reach the block-Jacobi step's state.
 """
 import numpy as np
 import pytest
@@ -221,6 +222,7 @@ def test_block_gauss_seidel_matches_dense_sgs(nx, ny, p):
     A = _operator_dense(o, q, c_time, inv_dtau)
     z1, col = o.precond_apply(q, r, c_time, inv_dtau, precond=1)
     z0, _ = o.precond_apply(q, r, c_time, inv_dtau, precond=0)
+    z2, _ = o.precond_apply(q, r, c_time, inv_dtau, precond=2)
     E, Np = mesh.E, q.shape[2]
     elem = (np.arange(q.size) // Np) % E          # element of each row / column
     ce = col[elem]
@@ -230,8 +232,13 @@ def test_block_gauss_seidel_matches_dense_sgs(nx, ny, p):
     P = (D + L) @ np.linalg.solve(D, D + U)
     ref1 = np.linalg.solve(P, r.ravel())
     ref0 = np.linalg.solve(D, r.ravel())
+    ref2 = np.linalg.solve(D + L, r.ravel())       # forward block Gauss-Seidel
     assert np.linalg.norm(z1.ravel() - ref1) <= 1e-10 * np.linalg.norm(ref1)
     assert np.linalg.norm(z0.ravel() - ref0) <= 1e-10 * np.linalg.norm(ref0)
+    assert np.linalg.norm(z2.ravel() - ref2) <= 1e-10 * np.linalg.norm(ref2)
+    # the three differ (a sweep that dropped its couplings, or ran backward, would not)
+    assert np.linalg.norm(ref2 - ref1) > 1e-3 * np.linalg.norm(ref1)
+    assert np.linalg.norm(ref2 - ref0) > 1e-3 * np.linalg.norm(ref0)
     # the colouring is proper; a checkerboard on even periodic meshes
     nbr, _, _ = mesh.connectivity()
     assert all(col[e] != col[n] for e in range(E) for n in nbr[e] if n != e)
@@ -245,10 +252,12 @@ def test_block_gauss_seidel_cuts_gmres_iterations():
     kw = dict(dt=0.01, tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=2000, max_newton=10)
     q0, s0 = o.bdf2_step(c.q, None, precond=0, **kw)
     q1, s1 = o.bdf2_step(c.q, None, precond=1, **kw)
-    assert s0["converged"] == 1 and s1["converged"] == 1
-    assert s1["newton_its"] == s0["newton_its"]
-    assert s1["gmres_its"] < 0.7 * s0["gmres_its"], (s0["gmres_its"], s1["gmres_its"])
-    assert np.max(np.abs(q1 - q0)) <= 1e-8 * np.max(np.abs(q0))
+    q2, s2 = o.bdf2_step(c.q, None, precond=2, **kw)
+    for qk, sk in ((q1, s1), (q2, s2)):
+        assert s0["converged"] == 1 and sk["converged"] == 1
+        assert sk["newton_its"] == s0["newton_its"]
+        assert sk["gmres_its"] < 0.7 * s0["gmres_its"], (s0["gmres_its"], sk["gmres_its"])
+        assert np.max(np.abs(qk - q0)) <= 1e-8 * np.max(np.abs(q0))
 
 
 def test_steady_step_rejection_undoes_and_retries():
