@@ -9,11 +9,13 @@ One timed step = one pass of the hot path over that input:
     Infinity Cache, so inputs and outputs stream from HBM), NJ JVPs and NV VJPs,
   * one BDF2 dual-time step (Newton to Res_m/Res_0 <= 1e-8, GMRES(30), tol_res 1e-6)
     with FP64 element blocks ("plain"), and the same step with FP32 and BF16 blocks,
-    and with the symmetric block Gauss-Seidel preconditioner (FP64 and BF16 blocks),
-    at p = 3 (64 x 64 blocks) and at p = 4 (100 x 100 blocks, 6.55M DOF),
+    and with the symmetric (FP64 and BF16 blocks) and forward (BF16 blocks) block
+    Gauss-Seidel preconditioners, at p = 3 (64 x 64 blocks) and at p = 4 (100 x 100
+    blocks, 6.55M DOF),
   * the batched workload: 48 uneven cases (16^2..192^2 quads, p = 2..4, Ma 0.01..0.3,
     Re 100..5000, half deforming) -- batched residuals and one batched BDF2 step per
-    block precision, also with block Gauss-Seidel; launch shapes from the autotuner.
+    block precision, also with both block Gauss-Seidel sweeps; launch shapes from the
+    autotuner.
 `value` = DOF-residual evaluations per second of the residual (the metric's first
 half); the BDF2 step times (second half) are reported beside it.
 """
@@ -29,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# preconditioner option values: event / stats key part and result-table name prefix
+PC_KEY = {0: "bdf2_", 1: "gs_", 2: "fgs_"}
+PC_NAME = {0: "", 1: "gauss_seidel_", 2: "forward_gauss_seidel_"}
 FP64_PEAK_TFS = 78.6
 
 
@@ -50,12 +55,15 @@ def parse():
     ap.add_argument("--no-p4", action="store_true", help="skip the p = 4 BDF2 steps")
     ap.add_argument("--p4-precs", default="fp64,fp32,bf16")
     ap.add_argument("--p4-gs-precs", default="fp64,bf16")
+    ap.add_argument("--p4-fgs-precs", default="bf16")
     ap.add_argument("--no-curved", action="store_true", help="skip the curved-mesh residual figures")
     ap.add_argument("--cpu-seconds", type=float, default=6.0, help="oracle timing per leg (one core, all cores)")
     ap.add_argument("--max-lin-it", type=int, default=200)
     ap.add_argument("--precs", default="fp64,fp32,bf16")
     ap.add_argument("--gs-precs", default="fp64,bf16",
-                    help="block precisions of the BDF2 step with the block Gauss-Seidel preconditioner")
+                    help="block precisions of the BDF2 step with the symmetric block Gauss-Seidel preconditioner")
+    ap.add_argument("--fgs-precs", default="bf16",
+                    help="block precisions of the BDF2 step with the forward block Gauss-Seidel preconditioner")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--no-bdf2", action="store_true")
@@ -68,7 +76,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-case batched workload")
     ap.add_argument("--batch-precs", default="fp64,bf16")
     ap.add_argument("--batch-gs-precs", default="fp64,bf16",
-                    help="block precisions of the batched step with the block Gauss-Seidel preconditioner")
+                    help="block precisions of the batched step with the symmetric block Gauss-Seidel preconditioner")
+    ap.add_argument("--batch-fgs-precs", default="bf16",
+                    help="block precisions of the batched step with the forward block Gauss-Seidel preconditioner")
     ap.add_argument("--batch-cfl", type=float, default=2.0, help="acoustic CFL of each batched case's dt")
     ap.add_argument("--nrb", type=int, default=10, help="batched residual evaluations per step")
     return ap.parse_args()
@@ -76,12 +86,13 @@ def parse():
 
 def mixed_vs_plain(out):
     """The metric's second half in one place: per BDF2 workload, the plain step (FP64 blocks,
-    block Jacobi) against the fastest step with reduced-precision blocks (FP32 or BF16, block
-    Jacobi or block Gauss-Seidel), each to the same Newton tolerance."""
+    block Jacobi) against the fastest step with reduced-precision blocks (FP32 or BF16; block
+    Jacobi, symmetric or forward block Gauss-Seidel), each to the same Newton tolerance."""
     rows = {}
-    for key, plain_key, names in (("bdf2_step", "fp64", ("fp32", "bf16", "gauss_seidel_bf16")),
-                                  ("bdf2_step_p4", "fp64", ("fp32", "bf16", "gauss_seidel_bf16")),
-                                  ("batch", "bdf2_fp64", ("bdf2_bf16", "gauss_seidel_bf16"))):
+    gs = ("gauss_seidel_bf16", "forward_gauss_seidel_bf16")
+    for key, plain_key, names in (("bdf2_step", "fp64", ("fp32", "bf16") + gs),
+                                  ("bdf2_step_p4", "fp64", ("fp32", "bf16") + gs),
+                                  ("batch", "bdf2_fp64", ("bdf2_bf16",) + gs)):
         bd = out.get(key)
         if not bd or plain_key not in bd:
             continue
@@ -185,8 +196,10 @@ def main():
 
     precs = args.precs.split(",")
     gprecs = [x for x in args.gs_precs.split(",") if x]
+    fprecs = [x for x in args.fgs_precs.split(",") if x]
     p4precs = [x for x in args.p4_precs.split(",") if x]
     p4gprecs = [x for x in args.p4_gs_precs.split(",") if x]
+    p4fprecs = [x for x in args.p4_fgs_precs.split(",") if x]
     p4 = None
     if not args.no_bdf2 and not args.no_p4:
         # the same workload at p = 4: 100 x 100 element blocks
@@ -203,6 +216,7 @@ def main():
         p4 = dict(ctx=ctx4, q_n=q4n, q_nm1=q40, dof=4 * c4.mesh.E * c4.mesh.Np, floor=floor4)
     bprecs = args.batch_precs.split(",")
     bgprecs = [x for x in args.batch_gs_precs.split(",") if x]
+    bfprecs = [x for x in args.batch_fgs_precs.split(",") if x]
     bt = None
     if not args.no_batch:
         bt = setup_batch(args, torch, lmfr, I, dev)
@@ -233,10 +247,11 @@ def main():
         ev["vjp"] = (t4, t5)
         stats = {}
 
-        def variants(c_, qn, qm, tag, plist, glist, floor):
-            """The BDF2 step from (qn, qm) with each block precision, block Jacobi and block
-            Gauss-Seidel; events and stats under keys tag + "bdf2_" / "gs_" + precision."""
-            for pc, lst in ((0, plist), (1, glist)):
+        def variants(c_, qn, qm, tag, plist, glist, flist, floor):
+            """The BDF2 step from (qn, qm) with each block precision, block Jacobi, symmetric and
+            forward block Gauss-Seidel; events and stats under keys tag + "bdf2_" / "gs_" /
+            "fgs_" + precision."""
+            for pc, lst in ((0, plist), (1, glist), (2, flist)):
                 c_.set_option("preconditioner", pc)
                 for pr in lst:
                     qw = qn.clone()
@@ -244,15 +259,15 @@ def main():
                     a.record(stream)
                     st = c_.bdf2_step(qw, qm, args.dt, prec=pr, tol_abs=floor, **bdf_kw)
                     b.record(stream)
-                    key = tag + ("gs_" if pc else "bdf2_") + pr
+                    key = tag + PC_KEY[pc] + pr
                     ev[key] = (a, b)
                     stats[key] = (st, qw)
             c_.set_option("preconditioner", 0)
 
         if not args.no_bdf2:
-            variants(ctx, q_n, q_nm1, "", precs, gprecs, floor3)
+            variants(ctx, q_n, q_nm1, "", precs, gprecs, fprecs, floor3)
             if p4 is not None:
-                variants(p4["ctx"], p4["q_n"], p4["q_nm1"], "p4_", p4precs, p4gprecs, p4["floor"])
+                variants(p4["ctx"], p4["q_n"], p4["q_nm1"], "p4_", p4precs, p4gprecs, p4fprecs, p4["floor"])
         if bt is not None:
             a = torch.cuda.Event(enable_timing=True); b_ = torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -270,17 +285,18 @@ def main():
                 b_.record(stream)
                 ev["bbdf_" + pr] = (a, b_)
                 stats["batch_" + pr] = (rc, sts, qw)
-            bt["batch"].set_option("preconditioner", 1)
-            for pr in bgprecs:
-                qw = [q.clone() for q in bt["qs"]]
-                opts = [lmfr.step_opts(dt, krylov=30, max_lin_it=args.max_lin_it, max_newton=20, jac_lag=2,
-                                       tol_abs=ta, prec=pr) for dt, ta in zip(bt["dts"], bt["tol_abs"])]
-                a = torch.cuda.Event(enable_timing=True); b_ = torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                rc, sts = bt["batch"].bdf2_step(qw, None, opts)
-                b_.record(stream)
-                ev["bgs_" + pr] = (a, b_)
-                stats["batch_gs_" + pr] = (rc, sts, qw)
+            for pc, lst in ((1, bgprecs), (2, bfprecs)):
+                bt["batch"].set_option("preconditioner", pc)
+                for pr in lst:
+                    qw = [q.clone() for q in bt["qs"]]
+                    opts = [lmfr.step_opts(dt, krylov=30, max_lin_it=args.max_lin_it, max_newton=20, jac_lag=2,
+                                           tol_abs=ta, prec=pr) for dt, ta in zip(bt["dts"], bt["tol_abs"])]
+                    a = torch.cuda.Event(enable_timing=True); b_ = torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    rc, sts = bt["batch"].bdf2_step(qw, None, opts)
+                    b_.record(stream)
+                    ev["b" + PC_KEY[pc] + pr] = (a, b_)
+                    stats["batch_" + PC_KEY[pc] + pr] = (rc, sts, qw)
             bt["batch"].set_option("preconditioner", 0)
         if record is not None:
             record.append((ev, stats))
@@ -351,16 +367,18 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.order, args.nx), "algorithmic_bytes": alg_b},
     }
-    def step_table(tag, plist, glist, order):
+    def step_table(tag, plist, glist, flist, order):
         """Per precision and preconditioner: time, iterations, gap to the FP64 block-Jacobi
         step's state, speedup over it (the plain path)."""
         bd = {"order": order, "block_size": 4 * (order + 1) ** 2}
         last = records[-1][1]
-        for pc, lst in ((0, plist), (1, glist)):
+        keys = {}
+        for pc, lst in ((0, plist), (1, glist), (2, flist)):
             for pr in lst:
-                key = tag + ("gs_" if pc else "bdf2_") + pr
+                key = tag + PC_KEY[pc] + pr
                 st, qw = last[key]
-                bd[("gauss_seidel_" if pc else "") + pr] = {
+                keys[PC_NAME[pc] + pr] = key
+                bd[PC_NAME[pc] + pr] = {
                     "ms": mean_ms(key), "newton_its": st["newton_its"], "gmres_its": st["gmres_its"],
                     "converged": st["converged"], "res_ratio": st["res_final"] / max(st["res0"], 1e-300)}
         if "fp64" in plist:
@@ -368,16 +386,15 @@ def main():
             for name, row in list(bd.items()):
                 if not isinstance(row, dict) or name == "fp64":
                     continue
-                key = tag + ("gs_" + name[len("gauss_seidel_"):] if name.startswith("gauss_seidel_") else "bdf2_" + name)
-                d = (last[key][1] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
+                d = (last[keys[name]][1] - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))
                 row["max_rel_diff_vs_fp64"] = float(d.max())
                 row["speedup_vs_fp64"] = bd["fp64"]["ms"] / row["ms"]
         return bd
 
     if not args.no_bdf2:
-        out["bdf2_step"] = step_table("", precs, gprecs, args.order)
+        out["bdf2_step"] = step_table("", precs, gprecs, fprecs, args.order)
         if p4 is not None:
-            out["bdf2_step_p4"] = step_table("p4_", p4precs, p4gprecs, 4)
+            out["bdf2_step_p4"] = step_table("p4_", p4precs, p4gprecs, p4fprecs, 4)
             out["bdf2_step_p4"]["dof"] = p4["dof"]
     if bt is not None:
         bres_ms = mean_ms("bres") / args.nrb
@@ -394,16 +411,18 @@ def main():
                                 "newton_its_max": max(x["newton_its"] for x in sts),
                                 "gmres_its_max": max(x["gmres_its"] for x in sts),
                                 "gmres_its_total": sum(x["gmres_its"] for x in sts)}
-        for pr in bgprecs:
-            rc, sts, qw = records[-1][1]["batch_gs_" + pr]
-            bd["gauss_seidel_" + pr] = {"ms": mean_ms("bgs_" + pr), "rc": rc,
+        skeys = {f"bdf2_{x}": "batch_" + x for x in bprecs if x != "fp64"}
+        for pc, lst in ((1, bgprecs), (2, bfprecs)):
+            for pr in lst:
+                rc, sts, qw = records[-1][1]["batch_" + PC_KEY[pc] + pr]
+                skeys[PC_NAME[pc] + pr] = "batch_" + PC_KEY[pc] + pr
+                bd[PC_NAME[pc] + pr] = {"ms": mean_ms("b" + PC_KEY[pc] + pr), "rc": rc,
                                         "converged": sum(x["converged"] for x in sts),
                                         "gmres_its_max": max(x["gmres_its"] for x in sts),
                                         "gmres_its_total": sum(x["gmres_its"] for x in sts)}
         if "fp64" in bprecs:
             ref = records[-1][1]["batch_fp64"][2]
-            for key in [f"bdf2_{x}" for x in bprecs if x != "fp64"] + [f"gauss_seidel_{x}" for x in bgprecs]:
-                skey = "batch_" + key[5:] if key.startswith("bdf2_") else "batch_gs_" + key[len("gauss_seidel_"):]
+            for key, skey in skeys.items():
                 qw = records[-1][1][skey][2]
                 d = max(float(((a - r).abs().amax(dim=(1, 2)) / r.abs().amax(dim=(1, 2))).max())
                         for a, r in zip(qw, ref))
@@ -567,7 +586,8 @@ def cpu_baseline(args, torch, lmfr, I, dev):
     * the oracle's residual on the full workload, rebuilt on this host at -O3 -march=native
       with its OpenMP element loops, timed on one core and on every core (a bounded sample:
       --cpu-seconds per leg), with nproc / lscpu and the oracle's exact operation count;
-    * the mixed-precision gap: BDF2 steps on the GPU with FP64, FP32 and BF16 blocks against
+    * the mixed-precision gap: BDF2 steps on the GPU with FP64, FP32 and BF16 blocks (and BF16
+      blocks under forward block Gauss-Seidel) against
       the oracle's FP64 step on meshes it steps in seconds (C4's fields on 8x8 at p=3 and 6x6
       at p=4, dt = 0.01, GMRES(30), tol_res 1e-6, Newton to 1e-8), as the largest gap over
       the variables relative to each variable's range."""
@@ -598,12 +618,15 @@ def cpu_baseline(args, torch, lmfr, I, dev):
         g = lmfr.Context(c.prm, *c.mesh.connectivity())
         g.set_geometry(*c.mesh.nodes())
         row = {"oracle_step_s": t_ora, "oracle_gmres_its": so["gmres_its"]}
-        for pr in ("fp64", "fp32", "bf16"):
+        for pc, pr in ((0, "fp64"), (0, "fp32"), (0, "bf16"), (2, "bf16")):
+            g.set_option("preconditioner", pc)
             qg = torch.tensor(q1, device=dev)
             st = g.bdf2_step(qg, torch.tensor(c.q, device=dev), 0.01, prec=pr, **kw)
             torch.cuda.synchronize()
             gap = np.max(np.abs(qg.cpu().numpy() - q2), axis=(1, 2)) / span
-            row[pr] = {"gap_over_range": float(gap.max()), "gmres_its": st["gmres_its"], "converged": st["converged"]}
+            row[PC_NAME[pc] + pr] = {"gap_over_range": float(gap.max()), "gmres_its": st["gmres_its"],
+                                     "converged": st["converged"]}
+        g.set_option("preconditioner", 0)
         gaps[f"c4_{nx}x{nx}_p{p}"] = row
     out["bdf2_gap_vs_fp64_oracle"] = gaps
     return out

@@ -200,8 +200,8 @@ fr_status fr_block_jacobi_factor(fr_ctx ctx, const double* q, double c_time, dou
                                  int32_t prec, void* stream);
 
 /* z = P^-1 r with the last factored blocks; r, z [4][E][Np] (may not alias).  With the
- * option "preconditioner" = 1, P is the symmetric block Gauss-Seidel preconditioner of the
- * operator the last fr_block_jacobi_factor linearised (its q, c_time and inv_dtau; a later
+ * option "preconditioner" = 1 (2), P is the symmetric (forward) block Gauss-Seidel
+ * preconditioner of the operator the last fr_block_jacobi_factor linearised (its q, c_time and inv_dtau; a later
  * fr_bdf_operator with "operator_packs" replaces that linearisation). */
 fr_status fr_block_jacobi_apply(fr_ctx ctx, const double* r, double* z, void* stream);
 
@@ -259,8 +259,9 @@ fr_status fr_steady_solve(fr_ctx ctx, double* q, const fr_steady_opts* opts, fr_
  * from fr_create, the smallest colour no face neighbour has, in element order; each
  * application costs 2 (K - 1) operator passes for K colours, each over the elements of
  * one colour (on even periodic meshes two passes over half the elements each), and
- * 2 - 1/K block applies; used by fr_block_jacobi_apply and the GMRES of the BDF2 and
- * steady solves),
+ * 2 - 1/K block applies; 2: forward block Gauss-Seidel in the same colour order, P = D + L,
+ * the forward half of that sweep: K - 1 operator passes over one colour each and one
+ * block apply; used by fr_block_jacobi_apply and the GMRES of the BDF2 and steady solves),
  * and a manual launch shape of the fused kernels (what fr_autotune chooses): "tile_lanes" (0 =
  * default, 64, 128, 256; dual-number modes cap it at 128), "tile_grid" (0 = one
  * workgroup per tile, else the persistent grid size), "tile_xcd" (1 = each XCD walks a

@@ -297,8 +297,9 @@ static fr_status solver_option(Solver& sv, const char* name, int64_t value) {
     }
     if (!strcmp(name, "fused_gram_schmidt")) { sv.fuse_gs = value != 0; gmres_release(sv); return FR_OK; }
     if (!strcmp(name, "preconditioner")) {
-        if (value != 0 && value != 1) return bad("preconditioner must be 0 (block Jacobi) or 1 (block Gauss-Seidel)");
-        if (value == 1) {   // the sweeps apply the Newton operator through the linearisation packs
+        if (value < 0 || value > 2)
+            return bad("preconditioner must be 0 (block Jacobi), 1 (symmetric block Gauss-Seidel) or 2 (forward block Gauss-Seidel)");
+        if (value != 0) {   // the sweeps apply the Newton operator through the linearisation packs
             FR_TRY(dalloc(&sv.d_fpack, sv.fpack_len));
             FR_TRY(dalloc(&sv.d_spack, sv.spack_len));
             FR_TRY(dalloc(&sv.d_rscratch, sv.Ntot));
@@ -427,7 +428,7 @@ extern "C" fr_status fr_block_jacobi_factor(fr_ctx c, const double* q, double c_
     KArgs a{};
     a.c_time = c_time; a.inv_dtau = inv_dtau;
     sv.f_ct = c_time; sv.f_idt = inv_dtau;
-    if (sv.op_packs || sv.precond == 1) {
+    if (sv.op_packs || sv.precond != 0) {
         // linearisation packs of q, then tangent-only block columns
         KArgs p = plain_args(q, nullptr, sv.d_rscratch, nullptr);
         p.fpack = sv.d_fpack; p.spack = sv.d_spack;

@@ -486,7 +486,7 @@ fr_status gmres_device(Solver& sv, int m, int prec, int max_it, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_norm0, dim3(cgrid(sv)), dim3(64), 0, s, k, m);
     FR_HIP(hipGetLastError());
 
-    if (sv.precond == 1) {   // the sweeps' work vector exists before any capture
+    if (sv.precond != 0) {   // the sweeps' work vector exists before any capture
         FR_TRY(dalloc(&sv.d_gst, sv.Ntot));
     }
     const bool graph = sv.use_graph;

@@ -495,7 +495,7 @@ fr_status launch_block_invert(Solver& sv, int prec, const int* flags, hipStream_
     // the Gauss-Seidel sweeps apply one colour at a time: colour-sorted blocks keep each
     // colour's reads contiguous (every other block of the element order reads at about half
     // the bandwidth)
-    sv.inv_colour = sv.precond == 1;
+    sv.inv_colour = sv.precond != 0;
     FR_TRY(invert_all(sv, prec, flags, s));
     sv.inv_prec = prec;
     return FR_OK;
@@ -567,6 +567,8 @@ fr_status launch_block_apply(const Solver& sv, const double* r, double* z, const
 //   backward  z_k -= D_k^-1 [A z_{>k}]_k,          k = K-2 .. 0
 // where z_{<k} (z_{>k}) is z on the colours below (above) k and zero elsewhere.  Costs
 // 2 (K - 1) operator applications and about 1.5 block-apply passes per application.
+// Forward block Gauss-Seidel (option value 2), P = D + L, is the forward sweep alone:
+// K - 1 operator applications over one colour each and one block-apply pass.
 fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op, const int* flags, int flag,
                         hipStream_t s) {
     if (sv.precond == 0) return launch_block_apply(sv, r, z, flags, flag, s);
@@ -587,7 +589,7 @@ fr_status precond_apply(Solver& sv, const double* r, double* z, const KArgs& op,
         }
         FR_TRY(launch_block_apply_ex(sv, r, k > 0 ? sv.d_gst : nullptr, z, k, false, flags, flag, s));
     }
-    for (int k = K - 2; k >= 0; --k) {
+    for (int k = K - 2; k >= 0 && sv.precond == 1; --k) {
         a.csweep = 1 + k;
         a.cbelow = 0;
         FR_TRY(solver_fused(sv, MODE_LIN, a, s));

@@ -1,9 +1,10 @@
-"""Symmetric block Gauss-Seidel preconditioner in element colour order on the GPU path,
-against the oracle's (itself pinned against the dense (D + L) D^-1 (D + U) solve).
+"""Block Gauss-Seidel preconditioners in element colour order on the GPU path, symmetric
+(option value 1) and forward (2), against the oracle's (itself pinned against the dense
+(D + L) D^-1 (D + U) and D + L solves).
 
 Checked: one application after a factor (several meshes, 2 and 3 colours, curved and
-deforming, every stored precision of the blocks); a BDF2 step with it reaches the state the
-block-Jacobi step reaches with fewer GMRES iterations and the oracle's Newton count; graph
+deforming, every stored precision of the blocks); a BDF2 step with either reaches the state
+the block-Jacobi step reaches with fewer GMRES iterations and the oracle's Newton count; graph
 replay of the cycle equals eager launches; a batch equals its cases solved one by one.
 """
 import numpy as np
@@ -53,9 +54,9 @@ def _operator_dense(o, q, c_time, inv_dtau):
     return T - o.dense_jacobian(q)
 
 
-def _sgs_sweep(A, X, col, gidx, r):
-    """Symmetric block Gauss-Seidel in colour order with the block inverses X (row-major per
-    element, rows and columns v*Np + s) and the couplings of A."""
+def _sgs_sweep(A, X, col, gidx, r, symmetric=True):
+    """Symmetric (or forward only) block Gauss-Seidel in colour order with the block inverses
+    X (row-major per element, rows and columns v*Np + s) and the couplings of A."""
     E = X.shape[0]
     y = np.zeros_like(r)
     ncol = int(col.max()) + 1
@@ -66,6 +67,8 @@ def _sgs_sweep(A, X, col, gidx, r):
             rhs = r[rows] - (A[np.ix_(rows, earlier)] @ y[earlier] if earlier.size else 0.0)
             y[rows] = X[e] @ rhs
     z = y.copy()
+    if not symmetric:
+        return z
     for c in range(ncol - 2, -1, -1):
         later = np.concatenate([gidx[f] for f in range(E) if col[f] > c])
         for e in np.nonzero(col == c)[0]:
@@ -89,31 +92,34 @@ def test_gauss_seidel_apply_matches_oracle(nx, ny, p, kind):
         t = 0.1
     q = _state(mesh, prm, 3)
     o, g = _pair(prm, mesh, t)
-    g.set_option("preconditioner", 1)
     r = np.random.default_rng(4).standard_normal(q.shape)
     ct, idt = 150.0, 1e-3
-    zo, col = o.precond_apply(q, r, ct, idt, precond=1)
-    print(f"  colours {col.max() + 1}", flush=True)
-    # FP64 blocks: the oracle's sweep.  Every stored precision: the same sweep written out here
-    # on the dense Newton operator with the GPU's stored inverse X~ in place of D^-1,
-    #   forward  y_c = X~_c (r_c - (L y)_c),  backward  z_c = y_c - X~_c (U z)_c,
-    # L (U) the couplings to earlier (later) colours, so only FP64 rounding separates the two
-    A = _operator_dense(o, q, ct, idt)
-    E, Np = mesh.E, q.shape[2]
-    nb = 4 * Np
-    gidx = np.array([[v * E * Np + e * Np + s_ for v in range(4) for s_ in range(Np)] for e in range(E)])
-    assert np.allclose(A[gidx[:, :, None], gidx[:, None, :]], o.blocks(q, ct, idt), rtol=0, atol=1e-12 * np.abs(A).max())
-    for prec in ("fp64", "fp32", "bf16"):
-        g.block_jacobi_factor(_dev(q), ct, idt, prec)
-        z = g.block_jacobi_apply(_dev(r)).cpu().numpy()
-        X = g.get_inverse().cpu().numpy()
-        zs = _sgs_sweep(A, X, col, gidx, r.ravel()).reshape(q.shape)
-        rel = np.linalg.norm(z - zs) / np.linalg.norm(zs)
-        rel_o = np.linalg.norm(z - zo) / np.linalg.norm(zo)
-        print(f"  {prec}: rel to the sweep with the stored inverse {rel:.2e}, to the oracle {rel_o:.2e}", flush=True)
-        assert rel <= 1e-10, (prec, rel)
-        if prec == "fp64":
-            assert rel_o <= 1e-10, rel_o
+    A = None
+    for pc in (1, 2):
+        g.set_option("preconditioner", pc)
+        zo, col = o.precond_apply(q, r, ct, idt, precond=pc)
+        print(f"  sweep {pc}: colours {col.max() + 1}", flush=True)
+        # FP64 blocks: the oracle's sweep.  Every stored precision: the same sweep written out
+        # here on the dense Newton operator with the GPU's stored inverse X~ in place of D^-1,
+        #   forward  y_c = X~_c (r_c - (L y)_c),  backward  z_c = y_c - X~_c (U z)_c,
+        # L (U) the couplings to earlier (later) colours, so only FP64 rounding separates the two
+        if A is None:
+            A = _operator_dense(o, q, ct, idt)
+            E, Np = mesh.E, q.shape[2]
+            gidx = np.array([[v * E * Np + e * Np + s_ for v in range(4) for s_ in range(Np)] for e in range(E)])
+            assert np.allclose(A[gidx[:, :, None], gidx[:, None, :]], o.blocks(q, ct, idt), rtol=0,
+                               atol=1e-12 * np.abs(A).max())
+        for prec in ("fp64", "fp32", "bf16"):
+            g.block_jacobi_factor(_dev(q), ct, idt, prec)
+            z = g.block_jacobi_apply(_dev(r)).cpu().numpy()
+            X = g.get_inverse().cpu().numpy()
+            zs = _sgs_sweep(A, X, col, gidx, r.ravel(), symmetric=pc == 1).reshape(q.shape)
+            rel = np.linalg.norm(z - zs) / np.linalg.norm(zs)
+            rel_o = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+            print(f"  {prec}: rel to the sweep with the stored inverse {rel:.2e}, to the oracle {rel_o:.2e}", flush=True)
+            assert rel <= 1e-10, (pc, prec, rel)
+            if prec == "fp64":
+                assert rel_o <= 1e-10, (pc, rel_o)
     # block Jacobi again after switching back
     g.set_option("preconditioner", 0)
     g.block_jacobi_factor(_dev(q), ct, idt, "fp64")
@@ -122,12 +128,12 @@ def test_gauss_seidel_apply_matches_oracle(nx, ny, p, kind):
     assert np.linalg.norm(zj - zjo) <= 1e-10 * np.linalg.norm(zjo)
 
 
-@pytest.mark.parametrize("nx,ny,p", [(5, 4, 2), (4, 4, 3), (6, 3, 1)])
-def test_colour_ordered_inverse_equals_element_order(nx, ny, p):
+@pytest.mark.parametrize("nx,ny,p,pc", [(5, 4, 2, 1), (4, 4, 3, 1), (6, 3, 1, 1), (4, 4, 3, 2)])
+def test_colour_ordered_inverse_equals_element_order(nx, ny, p, pc):
     """A factor with the Gauss-Seidel sweeps selected stores the inverse blocks in colour
     order; one with block Jacobi in element order.  The read-back inverse, the block-Jacobi
     application and the sweep give the same bits from either layout."""
-    print(f"[gs] inverse layouts {nx}x{ny} p={p}", flush=True)
+    print(f"[gs] inverse layouts {nx}x{ny} p={p} sweep {pc}", flush=True)
     mesh = I.Mesh(nx, ny, p, (0.0, 2 * np.pi, 0.0, 2 * np.pi), I.map_curved(0.1))
     prm = I.Params(order=p, n_elem=mesh.E, mach_ref=0.05, reynolds=100.0, viscous=True, kappa=1.0)
     q = _state(mesh, prm, 5)
@@ -140,7 +146,7 @@ def test_colour_ordered_inverse_equals_element_order(nx, ny, p):
         g.block_jacobi_factor(_dev(q), ct, idt, prec)           # element order
         X0 = g.get_inverse().cpu().numpy()
         zj0 = g.block_jacobi_apply(r).cpu().numpy()
-        g.set_option("preconditioner", 1)
+        g.set_option("preconditioner", pc)
         zg0 = g.block_jacobi_apply(r).cpu().numpy()             # sweep over element-ordered blocks
         g.block_jacobi_factor(_dev(q), ct, idt, prec)           # colour order
         X1 = g.get_inverse().cpu().numpy()
@@ -163,7 +169,7 @@ def test_bdf2_step_with_gauss_seidel():
     o, g = _pair(c.prm, c.mesh)
     kw = dict(tol_pseudo=1e-8, tol_res=1e-6, krylov=30, max_lin_it=2000, max_newton=10)
     res = {}
-    for pc in (0, 1):
+    for pc in (0, 1, 2):
         g.set_option("preconditioner", pc)
         qg = _dev(c.q)
         st = g.bdf2_step(qg, None, 0.01, **kw)
@@ -171,20 +177,23 @@ def test_bdf2_step_with_gauss_seidel():
         res[pc] = (qg.cpu().numpy(), st)
         print(f"[gs] bdf2 precond={pc}: {st}", flush=True)
         assert st["converged"] == 1
-    qo, sto = o.bdf2_step(c.q, None, dt=0.01, precond=1, **kw)
-    print(f"[gs] oracle precond=1: {sto}", flush=True)
-    (q0, s0), (q1, s1) = res[0], res[1]
-    assert s1["newton_its"] == s0["newton_its"] == sto["newton_its"]
-    assert s1["gmres_its"] < 0.7 * s0["gmres_its"]
-    assert abs(s1["gmres_its"] - sto["gmres_its"]) <= 2 * s1["newton_its"]
-    assert np.max(np.abs(q1 - q0)) <= 1e-8 * np.max(np.abs(q0))
-    assert np.max(np.abs(q1 - qo)) <= 1e-8 * np.max(np.abs(qo))
+    q0, s0 = res[0]
+    for pc in (1, 2):
+        qo, sto = o.bdf2_step(c.q, None, dt=0.01, precond=pc, **kw)
+        print(f"[gs] oracle precond={pc}: {sto}", flush=True)
+        q1, s1 = res[pc]
+        assert s1["newton_its"] == s0["newton_its"] == sto["newton_its"]
+        assert s1["gmres_its"] < 0.7 * s0["gmres_its"]
+        assert abs(s1["gmres_its"] - sto["gmres_its"]) <= 2 * s1["newton_its"]
+        assert np.max(np.abs(q1 - q0)) <= 1e-8 * np.max(np.abs(q0))
+        assert np.max(np.abs(q1 - qo)) <= 1e-8 * np.max(np.abs(qo))
 
 
-def test_gauss_seidel_graph_replay_matches_eager():
+@pytest.mark.parametrize("pc", [1, 2])
+def test_gauss_seidel_graph_replay_matches_eager(pc):
     c = _c4_small()
     _, g = _pair(c.prm, c.mesh)
-    g.set_option("preconditioner", 1)
+    g.set_option("preconditioner", pc)
     out = []
     for graph in (0, 1):
         g.set_option("graph", graph)
@@ -203,7 +212,8 @@ def test_gauss_seidel_graph_replay_matches_eager():
         assert torch.equal(qa, qb)
 
 
-def test_gauss_seidel_batch_matches_single_cases():
+@pytest.mark.parametrize("pc", [1, 2])
+def test_gauss_seidel_batch_matches_single_cases(pc):
     """A batch equals its cases stepped alone, bit for bit; the two p = 2 NS cases share a launch
     group and its per-colour tiles with different colour counts (5 x 5: three colours, 6 x 6: two)."""
     from paper_1903_06304_amd import lmfr
@@ -212,13 +222,13 @@ def test_gauss_seidel_batch_matches_single_cases():
     opts = lmfr.step_opts(0.01, tol_pseudo=1e-8, tol_res=1e-6, krylov=20, max_lin_it=600, max_newton=10)
     for c in cases:
         _, g = _pair(c.prm, c.mesh)
-        g.set_option("preconditioner", 1)
+        g.set_option("preconditioner", pc)
         qg = _dev(c.q)
         st = g.bdf2_step(qg, None, 0.01, tol_pseudo=1e-8, tol_res=1e-6, krylov=20, max_lin_it=600, max_newton=10)
         singles.append((qg, st))
         ctxs.append(_pair(c.prm, c.mesh)[1])
     b = lmfr.Batch(ctxs)
-    b.set_option("preconditioner", 1)
+    b.set_option("preconditioner", pc)
     qs = [_dev(c.q) for c in cases]
     rc, sts = b.bdf2_step(qs, None, opts)
     torch.cuda.synchronize()

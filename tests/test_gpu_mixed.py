@@ -1,8 +1,8 @@
 """Mixed-precision preconditioner against the FP64 oracle, and the allocation-free hot path.
 
 Bars (written here, derived in the design notes):
-  * converged state of a BDF2 step with FP32 or BF16 blocks (block Jacobi or block
-    Gauss-Seidel) against the oracle's FP64 step: per variable, max |q_gpu - q_oracle| <=
+  * converged state of a BDF2 step with FP32 or BF16 blocks (block Jacobi, symmetric or
+    forward block Gauss-Seidel) against the oracle's FP64 step: per variable, max |q_gpu - q_oracle| <=
     1e-5 x the variable's range over the field (the stated mixed-precision bar); FP64 blocks
     1e-8.  The preconditioner does not change the solution of the Newton system, so the gap
     is the Newton and GMRES tolerances times the conditioning, not the storage precision.
@@ -62,7 +62,7 @@ def _oracle_steps(name, prm, mesh, q0):
     return _ORACLE_STEPS[name]
 
 
-@pytest.mark.parametrize("precond", [0, 1], ids=["block_jacobi", "gauss_seidel"])
+@pytest.mark.parametrize("precond", [0, 1, 2], ids=["block_jacobi", "gauss_seidel", "forward_gauss_seidel"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("case", _CASES, ids=[c[0] for c in _CASES])
 def test_step_converged_state_matches_fp64_oracle(case, prec, precond):
@@ -154,7 +154,7 @@ def test_reserve_then_hot_path_allocates_nothing():
     L = lmfr.load_library()
     torch.cuda.synchronize()
     free0, res0 = torch.cuda.mem_get_info()[0], torch.cuda.memory_reserved()
-    for precond in (0, 1):
+    for precond in (0, 1, 2):
         g.set_option("preconditioner", precond)
         for prec in ("fp64", "fp32", "bf16"):
             g.block_jacobi_factor(q, 150.0, 0.0, prec)
