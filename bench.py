@@ -194,7 +194,7 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] BDF1 start step {st0}", file=sys.stderr, flush=True)
 
-    precs = args.precs.split(",")
+    precs = [x for x in args.precs.split(",") if x]
     gprecs = [x for x in args.gs_precs.split(",") if x]
     fprecs = [x for x in args.fgs_precs.split(",") if x]
     p4precs = [x for x in args.p4_precs.split(",") if x]
@@ -214,7 +214,7 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] p=4 BDF1 start step {st4}", file=sys.stderr, flush=True)
         p4 = dict(ctx=ctx4, q_n=q4n, q_nm1=q40, dof=4 * c4.mesh.E * c4.mesh.Np, floor=floor4)
-    bprecs = args.batch_precs.split(",")
+    bprecs = [x for x in args.batch_precs.split(",") if x]
     bgprecs = [x for x in args.batch_gs_precs.split(",") if x]
     bfprecs = [x for x in args.batch_fgs_precs.split(",") if x]
     bt = None
