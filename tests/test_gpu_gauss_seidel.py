@@ -160,6 +160,20 @@ def test_colour_ordered_inverse_equals_element_order(nx, ny, p, pc):
     g.set_option("preconditioner", 0)
 
 
+def test_preconditioner_option_values():
+    """0, 1 and 2 are accepted; anything else is rejected with FR_EINVAL and leaves the choice."""
+    from paper_1903_06304_amd import lmfr
+    c = _c4_small()
+    _, g = _pair(c.prm, c.mesh)
+    for pc in (0, 1, 2):
+        g.set_option("preconditioner", pc)
+    for bad in (-1, 3):
+        with pytest.raises(lmfr.FRError) as ei:
+            g.set_option("preconditioner", bad)
+        assert ei.value.status == lmfr.FR_EINVAL
+        assert "preconditioner" in str(ei.value)
+
+
 def _c4_small():
     return I.config_c4(nx=8, p=3)
 
