@@ -52,14 +52,16 @@ def _dev(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
-def test_steady_first_steps_match_oracle():
+@pytest.mark.parametrize("pc", [0, 1, 2], ids=["block_jacobi", "gauss_seidel", "forward_gauss_seidel"])
+def test_steady_first_steps_match_oracle(pc):
     mesh, prm, q = _case(4, 2, 0.1)
     kw = dict(tol_pseudo=1e-30, tol_res=1e-12, krylov=60, max_lin_it=2000, max_steps=6)
     g = _ctx(mesh, prm)
+    g.set_option("preconditioner", pc)
     qg = _dev(q)
     st = g.steady_solve(qg, **kw)
     torch.cuda.synchronize()
-    qo, sto = Oracle(prm, mesh).steady_solve(q, **kw)
+    qo, sto = Oracle(prm, mesh).steady_solve(q, precond=pc, **kw)
     print(f"[steady] GPU {st}\n[steady] oracle { {k: v for k, v in sto.items() if k != 'hist'} }", flush=True)
     assert st["steps"] == sto["steps"] == 6
     assert abs(st["res_final"] - sto["res_final"]) <= 1e-8 * sto["res0"]
