@@ -131,13 +131,30 @@ __device__ __forceinline__ double rotate_column(const double* __restrict__ h1, c
     return a;
 }
 
-__global__ void k_givens(Ctl k, int j, int m, int passes) {
-    const int c = case_index();
-    if (c >= k.n) return;
+// One workgroup of 256 threads per case: the second stage of |w|^2 (the update pass's chunk
+// partials in slot 0, summed in the order of the solver's other second stages), then the Givens
+// update on thread 0.
+__global__ void __launch_bounds__(256) k_norm_givens(Ctl k, const int* __restrict__ case_chunk,
+                                                     const double* __restrict__ partial, int j, int m, int passes) {
+    __shared__ double red[256];
+    const int c = blockIdx.x;
     int* gi = k.gi + c * GI_STRIDE;
-    if (gi[GI_DONE]) return;
+    if (gi[GI_DONE]) return;   // uniform per workgroup
     const GsLayout L(m);
     double* gs = k.gs + (size_t)c * k.gs_stride;
+    {
+        const int c0 = case_chunk[c], c1 = case_chunk[c + 1];
+        double v = 0.0;
+        for (int b = c0 + threadIdx.x; b < c1; b += blockDim.x) v += partial[(size_t)b * MAXV];
+        red[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x != 0) return;
+        gs[L.NRM] = red[0];
+    }
     double* H = gs + L.H;
     double* cs = gs + L.CS;
     double* sn = gs + L.SN;
@@ -337,13 +354,15 @@ fr_status enqueue_cycle(Solver& sv, int m, hipStream_t s) {
         if (sv.gs_passes == 2) {
             FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, j + 1, w, w, false, false, gs + L.H2, gst, sv.d_gi,
                              GI_DONE, s, sv.fuse_gs));
-            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H2, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi,
+            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H2, gst, 0, w, w, true, false, nullptr, gst, sv.d_gi,
                              GI_DONE, s, !sv.fuse_gs));
         } else {
-            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, 0, w, w, true, false, gs + L.NRM, gst, sv.d_gi,
+            FR_TRY(la_krylov(sv, V, N, j + 1, gs + L.H1, gst, 0, w, w, true, false, nullptr, gst, sv.d_gi,
                              GI_DONE, s, true));
         }
-        hipLaunchKernelGGL(k_givens, dim3(cgrid(sv)), dim3(64), 0, s, k, j, m, sv.gs_passes);
+        // |w|^2's second stage and the Givens update in one launch
+        hipLaunchKernelGGL(k_norm_givens, dim3(sv.n), dim3(256), 0, s, k, sv.d_case_chunk, sv.d_part, j, m,
+                           sv.gs_passes);
         FR_HIP(hipGetLastError());
         if (j + 1 < m) {
             hipLaunchKernelGGL(k_scale_case, dim3(vgrid(sv)), dim3(256), 0, s, vec(sv, GI_DONE), w,

@@ -631,7 +631,7 @@ fr_status la_krylov(const Solver& sv, const double* V, size_t ldv, int nv_upd, c
         FR_HIP(hipGetLastError());
         w = w_out;
         if (nv_dot == 0) {
-            if (nrm) {
+            if (nrm && out) {   // (no out: the caller reduces the partials in slot 0 itself)
                 hipLaunchKernelGGL(k_final, dim3(sv.n, 1), dim3(256), 0, s, ca, partial, out, ostride);
                 FR_HIP(hipGetLastError());
             }
